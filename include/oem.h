@@ -1,0 +1,200 @@
+/*
+ * oem.h - C ABI of the MI355X (gfx950) OEM library for penalized least
+ * squares on tall data.
+ *
+ * Method: orthogonalizing EM (OEM) as reviewed in Huling & Qian, "Fast
+ * Penalized Regression and Cross Validation for Tall Data with the oem
+ * Package", Section 2.  The problem (Section 2.1, eq. (eqn:pen_loss), with
+ * the 1/n scaling of the precomputed-statistics interface of Section 5.6) is
+ *
+ *     minimise_beta  1/(2n) ||y - X beta||^2 + P_lambda(beta)
+ *
+ * for X n x p (n >> p).  Everything the iteration needs is in the sufficient
+ * statistics G = X^T X, X^T y, y^T y and n; for K-fold cross validation the
+ * per-fold statistics are summed to give each training Gram (Section 3).
+ *
+ * Library flow:
+ *   oem_gram_create      one handle per (p, K, precision)
+ *   oem_gram             one streaming pass over a block of rows (may be
+ *                        repeated on successive row blocks; sums accumulate)
+ *   oem_fit_path         warm-started lambda path(s) on all rows or on the
+ *                        training rows of one fold
+ *   oem_cv               paths on every fold plus the full data, held-out
+ *                        error and model selection
+ *   oem_gram_free
+ *
+ * Conventions shared by every entry point
+ *   - Return value: OEM_OK (0), OEM_NOT_CONVERGED (1, a warning: outputs are
+ *     valid) or a negative error code; oem_last_error() gives a message for
+ *     the calling thread's last non-OK return.
+ *   - "device pointer": memory the GPU can read or write (hipMalloc'd, or
+ *     pinned host memory from hipHostMalloc).  "host pointer": ordinary CPU
+ *     memory, read during the call only.
+ *   - The caller owns every pointer it passes; the library never keeps one
+ *     after the call returns.  The handle owns its own device buffers.
+ *   - stream: a hipStream_t passed as void* (NULL = the null stream).  Work
+ *     is enqueued on it; device outputs are valid after the stream is
+ *     synchronised.  A handle must not be used from two threads at once.
+ *   - Matrices are row-major.  Sizes are element counts.
+ */
+#ifndef OEM_H
+#define OEM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+enum {
+    OEM_OK = 0,
+    OEM_NOT_CONVERGED = 1, /* some (path, lambda) hit maxit; iters < 0 there */
+    OEM_E_INVAL = -1,      /* invalid argument */
+    OEM_E_NOMEM = -2,      /* device allocation failed */
+    OEM_E_HIP = -3,        /* a HIP runtime call failed */
+    OEM_E_STATE = -4       /* handle not in a state that allows the call */
+};
+
+/* Arithmetic of the Gram pass and of the path iterations.
+ *   OEM_FP64        X widened to FP64, FP64 matrix-core products, FP64 paths.
+ *   OEM_SPLIT_BF16  x = hi + lo (two BF16 parts), three BF16 products
+ *                   (hi*hi + hi*lo + lo*hi) accumulated in FP32 on the matrix
+ *                   cores, flushed to FP64; the diagonal, X^T y and y^T y in
+ *                   FP64.  Paths iterate in FP32 with an FP64 finish.
+ *   OEM_BF16        as SPLIT_BF16 with the hi part only (reported variant). */
+enum { OEM_FP64 = 0, OEM_SPLIT_BF16 = 1, OEM_BF16 = 2 };
+
+/* Element type of X. */
+enum { OEM_X_F32 = 0, OEM_X_F64 = 1 };
+
+/* Penalties (Section 2.2, penalty table). */
+enum {
+    OEM_LASSO = 0,     /* lambda sum_j w_j |beta_j|                         */
+    OEM_ENET = 1,      /* alpha lambda sum w|b| + (1-alpha)/2 lambda sum w b^2 */
+    OEM_MCP = 2,       /* minimax concave penalty, gamma > 1                */
+    OEM_SCAD = 3,      /* smoothly clipped absolute deviation, gamma > 2    */
+    OEM_GRP_LASSO = 4  /* lambda sum_k c_k ||beta_{g_k}||                   */
+};
+
+typedef struct {
+    int32_t kind;  /* OEM_LASSO .. OEM_GRP_LASSO */
+    double alpha;  /* elastic net mixing, 0 < alpha <= 1 (ignored otherwise) */
+    double gamma;  /* MCP / SCAD concavity (ignored otherwise) */
+    double tau;    /* reserved, must be 0 */
+} oem_penalty;
+
+/* Options of a path fit.  Every pointer here is a HOST pointer. */
+typedef struct {
+    int32_t nlambda;          /* L >= 1 values per penalty                        */
+    double lambda_min_ratio;  /* lambda_L / lambda_1 in (0, 1] when lambda == NULL */
+    const double *lambda;     /* npen x L explicit sequences, or NULL: log grid
+                                 from lambda_max of the full-data statistics      */
+    double tol;               /* stop when max|delta beta| <= tol * max|beta|     */
+    int32_t maxit;            /* OEM updates per lambda, >= 1                     */
+    int32_t standardize;      /* 1: columns scaled to unit norm (Section 2.1)     */
+    const int32_t *groups;    /* p group ids in [0, ngroups), every id used; NULL
+                                 allowed unless a group penalty is requested      */
+    const double *w;          /* p variable weights >= 0, NULL = all 1            */
+    const double *cg;         /* ngroups group weights > 0, NULL = sqrt(size)     */
+    int32_t sync;             /* 1: wait for the stream and return
+                                 OEM_NOT_CONVERGED when some lambda hit maxit     */
+} oem_path_opts;
+
+typedef struct oem_gram_s *oem_handle;
+
+/* Create a handle for p columns and nfolds folds (1 = no cross validation).
+ * precision: OEM_FP64 | OEM_SPLIT_BF16 | OEM_BF16.  x_dtype: OEM_X_F32 |
+ * OEM_X_F64.  fold_seed: seed of the fold hash (Section 3 partitions the rows
+ * at random): row i (global index) is in fold floor(nfolds * h_i / 2^32),
+ * h_i = high 32 bits of the (i+1)-th SplitMix64 output from state fold_seed.
+ * Uses the current HIP device.  Errors: OEM_E_INVAL (p < 1, p > 4096,
+ * nfolds < 1 or > 64, bad enum), OEM_E_NOMEM, OEM_E_HIP. */
+int oem_gram_create(int32_t p, int32_t nfolds, int32_t precision, int32_t x_dtype,
+                    uint64_t fold_seed, oem_handle *out);
+
+/* Release the handle and its device memory (NULL is ignored).  Waits for
+ * work already enqueued with the handle. */
+void oem_gram_free(oem_handle g);
+
+/* Set every accumulated statistic back to zero. */
+int oem_gram_reset(oem_handle g, void *stream);
+
+/* One streaming pass over rows 0..n-1 of X (device pointer, n x p, row
+ * stride ldx >= p elements of the handle's x_dtype) and y (device pointer,
+ * n FP64 values), adding to the per-fold sums (Section 3):
+ *     G_k += sum_{i in fold k} x_i x_i^T,  b_k += sum x_i y_i,
+ *     yy_k += sum y_i^2,                   n_k += |{i in fold k}|.
+ * row_offset: global index of row 0 (the fold hash uses global indices, so
+ * successive blocks of one data set keep their folds).  foldid: NULL (use
+ * the hash) or a device array of n fold ids < nfolds.  n = 0 is a no-op.
+ * X and y are not referenced after the work completes.  Errors: OEM_E_INVAL
+ * (NULL X or y with n > 0, ldx < p, n < 0), OEM_E_HIP. */
+int oem_gram(oem_handle g, const void *X, int64_t n, int64_t ldx, const double *y,
+             int64_t row_offset, const uint8_t *foldid, void *stream);
+
+/* Load sufficient statistics computed elsewhere into fold slot `fold`
+ * (precomputed X^T X and X^T y, Section 5.6).  XtX (p x p), Xty (p): device
+ * pointers.  scaled = 1: the inputs are X^T X / n, X^T y / n, y^T y / n (the
+ * scaling used in Section 5.6) and are multiplied by n; scaled = 0: raw sums.
+ * Replaces the slot's previous contents.  Errors: OEM_E_INVAL. */
+int oem_gram_import(oem_handle g, int32_t fold, const double *XtX, const double *Xty,
+                    double yty, int64_t n, int32_t scaled, void *stream);
+
+/* Copy the raw per-fold sums out: G (nfolds x p x p), b (nfolds x p), yy
+ * (nfolds), nk (nfolds).  Device pointers; any may be NULL. */
+int oem_gram_export(oem_handle g, double *G, double *b, double *yy, int64_t *nk, void *stream);
+
+/* Warm-started OEM paths (Section 2.1 iteration, Section 2.2 updates) for
+ * npen penalties (host array) on the full data (fold = -1) or on the rows
+ * outside fold `fold` (its training rows, Section 3).
+ * Per penalty: beta = 0, then for each lambda in order repeat
+ *     u = c + (d I - G) beta,   beta <- update_penalty(u, lambda, d)
+ * until max_j |delta beta_j| <= tol * max_j |beta_j| or maxit updates, with G,
+ * c the (standardised) Gram and X^T y scaled by 1/n and d = lambda_1(G) *
+ * (1 + 1e-10) from a Lanczos eigen-solve.
+ * Device outputs (any may be NULL except beta):
+ *     beta    npen x L x p   coefficients on the original scale of X
+ *     lambda  npen x L       the lambda sequence used
+ *     iters   npen x L       updates used; -maxit where maxit was reached
+ *     kkt     npen x L       max stationarity violation (standardised scale)
+ *     obj     npen x L       objective value
+ *     d_out   1              the d used
+ * Errors: OEM_E_INVAL (fold out of range, n of the selected rows = 0, bad
+ * penalty parameters: alpha not in (0,1], MCP gamma <= 1 or gamma d <= 1,
+ * SCAD gamma <= 2 or (gamma-1) d <= 1, bad groups, L < 1, maxit < 1),
+ * OEM_E_STATE (no rows accumulated), OEM_E_HIP. */
+int oem_fit_path(oem_handle g, int32_t fold, const oem_penalty *pen, int32_t npen,
+                 const oem_path_opts *opts, double *beta, double *lambda, int32_t *iters,
+                 double *kkt, double *obj, double *d_out, void *stream);
+
+/* K-fold cross validation from the fold statistics (Section 3; outputs as in
+ * Section 5.5): paths on the full data and on each fold's training rows with
+ * the full-data lambda sequence, held-out mean squared error of each fold
+ *     MSE_{k,l} = (yy_k - 2 beta_l^T b_k + beta_l^T G_k beta_l) / n_k,
+ * cvm_l = sum_k n_k MSE_{k,l} / n,
+ * cvsd_l = sqrt(sum_k n_k (MSE_{k,l} - cvm_l)^2 / (n (K - 1))),
+ * i_min = first argmin of cvm, i_1se = first l with cvm_l <= cvm_min + cvsd at
+ * i_min, best = penalty with the smallest minimum cvm (first on ties).
+ * Device outputs (NULL allowed except beta_full, cvm):
+ *     beta_full  npen x L x p        full-data coefficients
+ *     beta_folds K x npen x L x p    training-row coefficients of each fold
+ *     lambda     npen x L
+ *     cvm, cvsd  npen x L
+ *     i_min, i_1se npen;  best 1
+ *     iters      (K + 1) x npen x L  (slot 0 = full data)
+ * Requires nfolds >= 2.  Errors as oem_fit_path. */
+int oem_cv(oem_handle g, const oem_penalty *pen, int32_t npen, const oem_path_opts *opts,
+           double *beta_full, double *beta_folds, double *lambda, double *cvm, double *cvsd,
+           int32_t *i_min, int32_t *i_1se, int32_t *best, int32_t *iters, void *stream);
+
+/* Message for the calling thread's last non-OK return ("" if none). */
+const char *oem_last_error(void);
+
+/* Library version string. */
+const char *oem_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* OEM_H */

@@ -1,0 +1,313 @@
+"""MI355X (gfx950) OEM library for penalized least squares on tall data.
+
+Thin Python binding over the C ABI of ``liboem.so`` (declared in
+``include/oem.h``): argument marshalling only.  Every step of the method (the
+Gram pass, standardisation, d, lambda grids, OEM paths, CV error and
+selection) runs in the library's HIP kernels.  PyTorch supplies device memory
+and streams.  There is no CPU fallback: without the built library, or without
+a GPU, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboem.so")
+
+OEM_OK, OEM_NOT_CONVERGED = 0, 1
+OEM_E_INVAL, OEM_E_NOMEM, OEM_E_HIP, OEM_E_STATE = -1, -2, -3, -4
+OEM_FP64, OEM_SPLIT_BF16, OEM_BF16 = 0, 1, 2
+OEM_X_F32, OEM_X_F64 = 0, 1
+OEM_LASSO, OEM_ENET, OEM_MCP, OEM_SCAD, OEM_GRP_LASSO = 0, 1, 2, 3, 4
+
+PENALTY_KIND = {"lasso": OEM_LASSO, "enet": OEM_ENET, "elastic_net": OEM_ENET, "mcp": OEM_MCP,
+                "scad": OEM_SCAD, "grp_lasso": OEM_GRP_LASSO, "group_lasso": OEM_GRP_LASSO}
+PRECISION = {"fp64": OEM_FP64, "split_bf16": OEM_SPLIT_BF16, "bf16": OEM_BF16}
+
+EXPORTED = ["oem_gram_create", "oem_gram_free", "oem_gram_reset", "oem_gram", "oem_gram_import",
+            "oem_gram_export", "oem_fit_path", "oem_cv", "oem_last_error", "oem_version"]
+
+
+class OemError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"oem error {code}: {msg}")
+        self.code = code
+
+
+class oem_penalty(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("alpha", C.c_double), ("gamma", C.c_double),
+                ("tau", C.c_double)]
+
+
+class oem_path_opts(C.Structure):
+    _fields_ = [("nlambda", C.c_int32), ("lambda_min_ratio", C.c_double),
+                ("lambda_", C.POINTER(C.c_double)), ("tol", C.c_double), ("maxit", C.c_int32),
+                ("standardize", C.c_int32), ("groups", C.POINTER(C.c_int32)),
+                ("w", C.POINTER(C.c_double)), ("cg", C.POINTER(C.c_double)),
+                ("sync", C.c_int32)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH) -> C.CDLL:
+    """Load liboem.so; raise if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise OemError(OEM_E_STATE, f"{path} is missing: build it with "
+                                    "`python -c 'import __graft_entry__ as g; g.build()'`")
+    L = C.CDLL(path)
+    vp, dp, ip, i64p = C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int32), C.POINTER(C.c_int64)
+    L.oem_gram_create.restype = C.c_int
+    L.oem_gram_create.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_uint64,
+                                  C.POINTER(C.c_void_p)]
+    L.oem_gram_free.restype = None
+    L.oem_gram_free.argtypes = [vp]
+    L.oem_gram_reset.restype = C.c_int
+    L.oem_gram_reset.argtypes = [vp, vp]
+    L.oem_gram.restype = C.c_int
+    L.oem_gram.argtypes = [vp, vp, C.c_int64, C.c_int64, vp, C.c_int64, vp, vp]
+    L.oem_gram_import.restype = C.c_int
+    L.oem_gram_import.argtypes = [vp, C.c_int32, vp, vp, C.c_double, C.c_int64, C.c_int32, vp]
+    L.oem_gram_export.restype = C.c_int
+    L.oem_gram_export.argtypes = [vp, vp, vp, vp, vp, vp]
+    L.oem_fit_path.restype = C.c_int
+    L.oem_fit_path.argtypes = [vp, C.c_int32, C.POINTER(oem_penalty), C.c_int32,
+                               C.POINTER(oem_path_opts), vp, vp, vp, vp, vp, vp, vp]
+    L.oem_cv.restype = C.c_int
+    L.oem_cv.argtypes = [vp, C.POINTER(oem_penalty), C.c_int32, C.POINTER(oem_path_opts), vp, vp,
+                         vp, vp, vp, vp, vp, vp, vp, vp]
+    L.oem_last_error.restype = C.c_char_p
+    L.oem_last_error.argtypes = []
+    L.oem_version.restype = C.c_char_p
+    L.oem_version.argtypes = []
+    _lib = L
+    return L
+
+
+def _check(rc: int, allow_not_converged: bool = True) -> int:
+    if rc == OEM_OK or (rc == OEM_NOT_CONVERGED and allow_not_converged):
+        return rc
+    msg = load_library().oem_last_error().decode()
+    raise OemError(rc, msg)
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise OemError(OEM_E_STATE, "no GPU: the OEM library runs on the GPU only")
+    return torch
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+@dataclass
+class Penalty:
+    kind: str = "lasso"
+    alpha: float = 1.0
+    gamma: float = 3.0
+
+    def c(self) -> oem_penalty:
+        return oem_penalty(PENALTY_KIND[self.kind], float(self.alpha), float(self.gamma), 0.0)
+
+
+def _penalties(pens: Sequence) -> list:
+    out = []
+    for p in pens:
+        if isinstance(p, Penalty):
+            out.append(p)
+        elif isinstance(p, str):
+            out.append(Penalty(p))
+        else:
+            out.append(Penalty(**p))
+    return out
+
+
+# ------------------------------------------------------------------ C-ABI names
+
+def oem_gram_create(p: int, nfolds: int = 1, precision: int = OEM_FP64, x_dtype: int = OEM_X_F32,
+                    fold_seed: int = 0) -> C.c_void_p:
+    _torch()
+    h = C.c_void_p()
+    _check(load_library().oem_gram_create(p, nfolds, precision, x_dtype,
+                                          C.c_uint64(fold_seed & (2**64 - 1)), C.byref(h)))
+    return h
+
+
+def oem_gram_free(h) -> None:
+    if h:
+        load_library().oem_gram_free(h)
+
+
+def oem_gram_reset(h, stream=None) -> None:
+    _check(load_library().oem_gram_reset(h, _stream(stream)))
+
+
+def oem_gram(h, X, y, row_offset: int = 0, foldid=None, stream=None) -> None:
+    """Accumulate the statistics of the rows of X (cuda, row-major) and y."""
+    torch = _torch()
+    if X.dim() != 2 or X.stride(1) != 1:
+        raise OemError(OEM_E_INVAL, "X must be a 2-D tensor with unit column stride")
+    if not (X.is_cuda and y.is_cuda and y.dtype == torch.float64 and y.is_contiguous()):
+        raise OemError(OEM_E_INVAL, "X, y must be cuda tensors; y contiguous float64")
+    if foldid is not None and not (foldid.is_cuda and foldid.dtype == torch.uint8):
+        raise OemError(OEM_E_INVAL, "foldid must be a cuda uint8 tensor")
+    _check(load_library().oem_gram(h, _ptr(X), X.shape[0], X.stride(0), _ptr(y), row_offset,
+                                   _ptr(foldid), _stream(stream)))
+
+
+def oem_gram_import(h, fold: int, XtX, Xty, yty: float, n: int, scaled: bool = True,
+                    stream=None) -> None:
+    _check(load_library().oem_gram_import(h, fold, _ptr(XtX), _ptr(Xty), float(yty), int(n),
+                                          int(scaled), _stream(stream)))
+
+
+def oem_gram_export(h, p: int, nfolds: int, stream=None):
+    torch = _torch()
+    G = torch.empty((nfolds, p, p), dtype=torch.float64, device="cuda")
+    b = torch.empty((nfolds, p), dtype=torch.float64, device="cuda")
+    yy = torch.empty(nfolds, dtype=torch.float64, device="cuda")
+    nk = torch.empty(nfolds, dtype=torch.int64, device="cuda")
+    _check(load_library().oem_gram_export(h, _ptr(G), _ptr(b), _ptr(yy), _ptr(nk), _stream(stream)))
+    return G, b, yy, nk
+
+
+class _Opts:
+    """Keeps the host arrays referenced by an oem_path_opts alive."""
+
+    def __init__(self, nlambda, lambda_min_ratio, lambdas, tol, maxit, standardize, groups, w, cg,
+                 sync):
+        self.lam = None if lambdas is None else np.ascontiguousarray(lambdas, dtype=np.float64)
+        self.groups = None if groups is None else np.ascontiguousarray(groups, dtype=np.int32)
+        self.w = None if w is None else np.ascontiguousarray(w, dtype=np.float64)
+        self.cg = None if cg is None else np.ascontiguousarray(cg, dtype=np.float64)
+        dp = lambda a: None if a is None else a.ctypes.data_as(C.POINTER(C.c_double))
+        self.c = oem_path_opts(int(nlambda), float(lambda_min_ratio), dp(self.lam), float(tol),
+                               int(maxit), int(standardize),
+                               None if self.groups is None else
+                               self.groups.ctypes.data_as(C.POINTER(C.c_int32)),
+                               dp(self.w), dp(self.cg), int(sync))
+
+
+def oem_fit_path(h, p: int, penalties: Sequence, fold: int = -1, nlambda: int = 100,
+                 lambda_min_ratio: float = 1e-3, lambdas=None, tol: float = 1e-10,
+                 maxit: int = 100000, standardize: bool = True, groups=None, w=None, cg=None,
+                 sync: bool = True, stream=None) -> dict:
+    """Warm-started OEM paths; returns cuda tensors and the status code."""
+    torch = _torch()
+    pens = _penalties(penalties)
+    npen = len(pens)
+    arr = (oem_penalty * npen)(*[q.c() for q in pens])
+    o = _Opts(nlambda, lambda_min_ratio, lambdas, tol, maxit, standardize, groups, w, cg, sync)
+    f64 = dict(dtype=torch.float64, device="cuda")
+    beta = torch.empty((npen, nlambda, p), **f64)
+    lam = torch.empty((npen, nlambda), **f64)
+    iters = torch.empty((npen, nlambda), dtype=torch.int32, device="cuda")
+    kkt = torch.empty((npen, nlambda), **f64)
+    obj = torch.empty((npen, nlambda), **f64)
+    d = torch.empty(1, **f64)
+    rc = _check(load_library().oem_fit_path(h, fold, arr, npen, C.byref(o.c), _ptr(beta), _ptr(lam),
+                                            _ptr(iters), _ptr(kkt), _ptr(obj), _ptr(d),
+                                            _stream(stream)))
+    return dict(beta=beta, lambda_=lam, iters=iters, kkt=kkt, obj=obj, d=d, status=rc)
+
+
+def oem_cv(h, p: int, nfolds: int, penalties: Sequence, nlambda: int = 100,
+           lambda_min_ratio: float = 1e-3, lambdas=None, tol: float = 1e-10, maxit: int = 100000,
+           standardize: bool = True, groups=None, w=None, cg=None, sync: bool = True,
+           stream=None) -> dict:
+    """K-fold cross validation from the fold statistics; cuda tensors out."""
+    torch = _torch()
+    pens = _penalties(penalties)
+    npen = len(pens)
+    arr = (oem_penalty * npen)(*[q.c() for q in pens])
+    o = _Opts(nlambda, lambda_min_ratio, lambdas, tol, maxit, standardize, groups, w, cg, sync)
+    f64 = dict(dtype=torch.float64, device="cuda")
+    i32 = dict(dtype=torch.int32, device="cuda")
+    beta_full = torch.empty((npen, nlambda, p), **f64)
+    beta_folds = torch.empty((nfolds, npen, nlambda, p), **f64)
+    lam = torch.empty((npen, nlambda), **f64)
+    cvm = torch.empty((npen, nlambda), **f64)
+    cvsd = torch.empty((npen, nlambda), **f64)
+    i_min = torch.empty(npen, **i32)
+    i_1se = torch.empty(npen, **i32)
+    best = torch.empty(1, **i32)
+    iters = torch.empty((nfolds + 1, npen, nlambda), **i32)
+    rc = _check(load_library().oem_cv(h, arr, npen, C.byref(o.c), _ptr(beta_full), _ptr(beta_folds),
+                                      _ptr(lam), _ptr(cvm), _ptr(cvsd), _ptr(i_min), _ptr(i_1se),
+                                      _ptr(best), _ptr(iters), _stream(stream)))
+    return dict(beta=beta_full, beta_folds=beta_folds, lambda_=lam, cvm=cvm, cvsd=cvsd,
+                i_min=i_min, i_1se=i_1se, best=best, iters=iters, status=rc)
+
+
+# ------------------------------------------------------------------ convenience
+
+class Gram:
+    """Owning wrapper of a library handle (statistics of one data set)."""
+
+    def __init__(self, p: int, nfolds: int = 1, precision: str = "fp64", x_dtype=None,
+                 fold_seed: int = 0):
+        torch = _torch()
+        xd = OEM_X_F64 if x_dtype in (torch.float64, "f64", OEM_X_F64) else OEM_X_F32
+        self.p, self.nfolds, self.precision = p, nfolds, precision
+        self.h = oem_gram_create(p, nfolds, PRECISION[precision], xd, fold_seed)
+
+    def close(self):
+        oem_gram_free(self.h)
+        self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None):
+                self.close()
+        except Exception:
+            pass
+
+    def add(self, X, y, row_offset: int = 0, foldid=None, stream=None):
+        oem_gram(self.h, X, y, row_offset, foldid, stream)
+        return self
+
+    def export(self, stream=None):
+        return oem_gram_export(self.h, self.p, self.nfolds, stream)
+
+    def fit_path(self, penalties, fold: int = -1, **kw) -> dict:
+        return oem_fit_path(self.h, self.p, penalties, fold=fold, **kw)
+
+    def cv(self, penalties, **kw) -> dict:
+        return oem_cv(self.h, self.p, self.nfolds, penalties, **kw)
+
+
+def fit(X, y, penalties, precision: str = "fp64", **kw) -> dict:
+    """Gram pass then full-data paths (the oem() call of Section 5.1)."""
+    with Gram(X.shape[1], 1, precision, X.dtype) as g:
+        g.add(X, y)
+        return g.fit_path(penalties, **kw)
+
+
+def cv(X, y, nfolds: int, fold_seed: int, penalties, precision: str = "fp64", foldid=None,
+       **kw) -> dict:
+    """Gram pass with fold statistics then K-fold CV (xval.oem of Section 5.5)."""
+    with Gram(X.shape[1], nfolds, precision, X.dtype, fold_seed) as g:
+        g.add(X, y, foldid=foldid)
+        return g.cv(penalties, **kw)

@@ -1,0 +1,521 @@
+// C ABI of liboem (declared in include/oem.h): argument checks, device
+// buffer management and the order of kernel launches.  No arithmetic of the
+// method happens here; every step runs in the kernels of gram.hip,
+// derive.hip and path.hip.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+#include "oem_internal.h"
+
+namespace oem {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+int fail(int code, const std::string &msg)
+{
+    set_error(msg);
+    return code;
+}
+
+int DevBuf::ensure(size_t need)
+{
+    if (need <= bytes && ptr) return OEM_OK;
+    release();
+    if (need == 0) need = 8;
+    if (hipMalloc(&ptr, need) != hipSuccess) {
+        ptr = nullptr;
+        bytes = 0;
+        (void)hipGetLastError();
+        return fail(OEM_E_NOMEM, "device allocation of " + std::to_string(need) + " bytes failed");
+    }
+    bytes = need;
+    return OEM_OK;
+}
+
+void DevBuf::release()
+{
+    if (ptr) (void)hipFree(ptr);
+    ptr = nullptr;
+    bytes = 0;
+}
+
+static inline hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+static int num_problems(const oem_gram_s *h) { return h->K == 1 ? 1 : h->K + 1; }
+
+// Group structure of one fit: CSR member lists (ascending variable index
+// within each group), weights; all in one device buffer.
+struct GroupPlan {
+    int ngroups = 0;
+    std::vector<int32_t> gstart, gidx;
+    std::vector<double> w, cg;
+    const int32_t *d_gstart = nullptr, *d_gidx = nullptr;
+    const double *d_w = nullptr, *d_cg = nullptr;
+};
+
+static int build_groups(oem_gram_s *h, const oem_path_opts *o, bool need_groups, GroupPlan &gp,
+                        hipStream_t s)
+{
+    const int p = h->p;
+    if (o->groups) {
+        int ng = 0;
+        for (int j = 0; j < p; ++j) {
+            if (o->groups[j] < 0) return fail(OEM_E_INVAL, "negative group id");
+            ng = std::max(ng, o->groups[j] + 1);
+        }
+        gp.ngroups = ng;
+        std::vector<int32_t> cnt(ng + 1, 0);
+        for (int j = 0; j < p; ++j) cnt[o->groups[j] + 1]++;
+        for (int g = 0; g < ng; ++g)
+            if (cnt[g + 1] == 0) return fail(OEM_E_INVAL, "group ids must use every id in [0, ngroups)");
+        gp.gstart.assign(ng + 1, 0);
+        for (int g = 0; g < ng; ++g) gp.gstart[g + 1] = gp.gstart[g] + cnt[g + 1];
+        gp.gidx.assign(p, 0);
+        std::vector<int32_t> fill(ng, 0);
+        for (int j = 0; j < p; ++j) {
+            const int g = o->groups[j];
+            gp.gidx[gp.gstart[g] + fill[g]++] = j;
+        }
+        gp.cg.resize(ng);
+        for (int g = 0; g < ng; ++g) {
+            const double c = o->cg ? o->cg[g] : std::sqrt((double)(gp.gstart[g + 1] - gp.gstart[g]));
+            if (!(c > 0.0)) return fail(OEM_E_INVAL, "group weights must be > 0");
+            gp.cg[g] = c;
+        }
+    } else if (need_groups) {
+        return fail(OEM_E_INVAL, "a group penalty needs opts->groups");
+    }
+    if (o->w) {
+        gp.w.assign(o->w, o->w + p);
+        for (double v : gp.w)
+            if (!(v >= 0.0)) return fail(OEM_E_INVAL, "variable weights must be >= 0");
+    }
+    const size_t bytes = (gp.gstart.size() + gp.gidx.size()) * sizeof(int32_t) + 16 +
+                         (gp.w.size() + gp.cg.size()) * sizeof(double);
+    int rc = h->groupbuf.ensure(bytes);
+    if (rc) return rc;
+    std::vector<char> host(bytes, 0);
+    size_t off = 0;
+    auto put = [&](const void *src, size_t nb) {
+        size_t at = off;
+        if (nb) std::memcpy(host.data() + at, src, nb);
+        off += nb;
+        off = (off + 7) & ~size_t(7);
+        return at;
+    };
+    const size_t o_gs = put(gp.gstart.data(), gp.gstart.size() * sizeof(int32_t));
+    const size_t o_gi = put(gp.gidx.data(), gp.gidx.size() * sizeof(int32_t));
+    const size_t o_w = put(gp.w.data(), gp.w.size() * sizeof(double));
+    const size_t o_cg = put(gp.cg.data(), gp.cg.size() * sizeof(double));
+    OEM_HIP_CHECK(hipMemcpyAsync(h->groupbuf.ptr, host.data(), bytes, hipMemcpyHostToDevice, s));
+    OEM_HIP_CHECK(hipStreamSynchronize(s));   // host staging buffer is released on return
+    char *base = static_cast<char *>(h->groupbuf.ptr);
+    if (!gp.gstart.empty()) {
+        gp.d_gstart = reinterpret_cast<const int32_t *>(base + o_gs);
+        gp.d_gidx = reinterpret_cast<const int32_t *>(base + o_gi);
+        gp.d_cg = reinterpret_cast<const double *>(base + o_cg);
+    }
+    if (!gp.w.empty()) gp.d_w = reinterpret_cast<const double *>(base + o_w);
+    return OEM_OK;
+}
+
+// Combine, standardise and compute d for every problem, once per change of
+// the accumulated statistics; copies d and the row counts to the host.
+static int ensure_derived(oem_gram_s *h, int standardize, hipStream_t s)
+{
+    if (h->derived_valid && h->derived_std == standardize) return OEM_OK;
+    if (h->rows_seen <= 0) return fail(OEM_E_STATE, "no rows accumulated");
+    int rc = launch_combine(h, standardize, s);
+    if (rc) return rc;
+    rc = launch_lanczos(h, s);
+    if (rc) return rc;
+    const int nq = num_problems(h);
+    h->d_host.assign(nq, 0.0);
+    h->n_host.assign(nq, 0);
+    h->lz_host.assign(nq, 0);
+    OEM_HIP_CHECK(hipMemcpyAsync(h->d_host.data(), h->dq.ptr, nq * sizeof(double),
+                                 hipMemcpyDeviceToHost, s));
+    OEM_HIP_CHECK(hipMemcpyAsync(h->n_host.data(), h->ntrain.ptr, nq * sizeof(int64_t),
+                                 hipMemcpyDeviceToHost, s));
+    OEM_HIP_CHECK(hipMemcpyAsync(h->lz_host.data(), h->lzsteps.ptr, nq * sizeof(int32_t),
+                                 hipMemcpyDeviceToHost, s));
+    OEM_HIP_CHECK(hipStreamSynchronize(s));
+    h->derived_valid = true;
+    h->derived_std = standardize;
+    return OEM_OK;
+}
+
+static int check_opts(const oem_path_opts *o)
+{
+    if (!o) return fail(OEM_E_INVAL, "opts is NULL");
+    if (o->nlambda < 1) return fail(OEM_E_INVAL, "nlambda must be >= 1");
+    if (o->maxit < 1) return fail(OEM_E_INVAL, "maxit must be >= 1");
+    if (!(o->tol >= 0.0)) return fail(OEM_E_INVAL, "tol must be >= 0");
+    if (!o->lambda && !(o->lambda_min_ratio > 0.0 && o->lambda_min_ratio <= 1.0))
+        return fail(OEM_E_INVAL, "lambda_min_ratio must be in (0, 1]");
+    return OEM_OK;
+}
+
+static int check_penalty(const oem_penalty &pn, double d)
+{
+    switch (pn.kind) {
+    case OEM_LASSO:
+    case OEM_GRP_LASSO:
+        break;
+    case OEM_ENET:
+        if (!(pn.alpha > 0.0 && pn.alpha <= 1.0)) return fail(OEM_E_INVAL, "elastic net alpha must be in (0, 1]");
+        break;
+    case OEM_MCP:
+        if (!(pn.gamma > 1.0)) return fail(OEM_E_INVAL, "MCP needs gamma > 1");
+        if (!(pn.gamma * d > 1.0)) return fail(OEM_E_INVAL, "MCP needs gamma * d > 1");
+        break;
+    case OEM_SCAD:
+        if (!(pn.gamma > 2.0)) return fail(OEM_E_INVAL, "SCAD needs gamma > 2");
+        if (!((pn.gamma - 1.0) * d > 1.0)) return fail(OEM_E_INVAL, "SCAD needs (gamma - 1) d > 1");
+        break;
+    default:
+        return fail(OEM_E_INVAL, "unknown penalty kind");
+    }
+    if (pn.tau != 0.0) return fail(OEM_E_INVAL, "penalty tau is reserved and must be 0");
+    return OEM_OK;
+}
+
+// lambda sequences (npen x L) into h->lam: explicit, or grids from the
+// full-data problem's standardised X^T y.
+static int prepare_lambda(oem_gram_s *h, const oem_penalty *pen, int npen,
+                          const oem_path_opts *o, const GroupPlan &gp, hipStream_t s)
+{
+    const int L = o->nlambda;
+    const size_t nl = (size_t)npen * L;
+    int rc = h->lam.ensure(nl * sizeof(double) + npen * sizeof(oem_penalty) + 64);
+    if (rc) return rc;
+    double *dl = h->lam.as<double>();
+    if (o->lambda) {
+        for (size_t i = 0; i < nl; ++i)
+            if (!(o->lambda[i] >= 0.0)) return fail(OEM_E_INVAL, "lambda values must be >= 0");
+        OEM_HIP_CHECK(hipMemcpyAsync(dl, o->lambda, nl * sizeof(double), hipMemcpyHostToDevice, s));
+        OEM_HIP_CHECK(hipStreamSynchronize(s));
+        return OEM_OK;
+    }
+    oem_penalty *dpen = reinterpret_cast<oem_penalty *>(dl + nl);
+    OEM_HIP_CHECK(hipMemcpyAsync(dpen, pen, npen * sizeof(oem_penalty), hipMemcpyHostToDevice, s));
+    OEM_HIP_CHECK(hipStreamSynchronize(s));
+    return launch_lambda_grid(h->cs.as<double>(), h->p, gp.d_gstart, gp.d_gidx, gp.ngroups, gp.d_w,
+                              gp.d_cg, dpen, npen, L, o->lambda_min_ratio, dl, s);
+}
+
+static PathDesc make_desc(oem_gram_s *h, int q, const oem_penalty &pn, const oem_path_opts *o,
+                          const GroupPlan &gp, const double *lam, double *beta, int32_t *iters,
+                          double *kkt, double *obj)
+{
+    const size_t pp = (size_t)h->p * h->p;
+    PathDesc d{};
+    d.G = h->Gs.as<double>() + q * pp;
+    d.G32 = nullptr;
+    d.c = h->cs.as<double>() + (size_t)q * h->p;
+    d.s = h->sc.as<double>() + (size_t)q * h->p;
+    d.yyn = h->yyn.as<double>() + q;
+    d.d = h->dq.as<double>() + q;
+    d.lambda = lam;
+    d.beta = beta;
+    d.beta_std = nullptr;
+    d.iters = iters;
+    d.kkt = kkt;
+    d.obj = obj;
+    d.gstart = gp.d_gstart;
+    d.gidx = gp.d_gidx;
+    d.w = gp.d_w;
+    d.cg = gp.d_cg;
+    d.p = h->p;
+    d.L = o->nlambda;
+    d.kind = pn.kind;
+    d.ngroups = gp.ngroups;
+    d.alpha = pn.alpha;
+    d.gamma = pn.gamma;
+    d.tol = o->tol;
+    d.maxit = o->maxit;
+    d.prec = PATH_FP64;
+    return d;
+}
+
+static int upload_descs(oem_gram_s *h, const std::vector<PathDesc> &descs, hipStream_t s)
+{
+    int rc = h->paths.ensure(descs.size() * sizeof(PathDesc));
+    if (rc) return rc;
+    OEM_HIP_CHECK(hipMemcpyAsync(h->paths.ptr, descs.data(), descs.size() * sizeof(PathDesc),
+                                 hipMemcpyHostToDevice, s));
+    OEM_HIP_CHECK(hipStreamSynchronize(s));
+    return OEM_OK;
+}
+
+static int finish_sync(const int32_t *d_iters, size_t count, hipStream_t s)
+{
+    std::vector<int32_t> it(count);
+    OEM_HIP_CHECK(hipMemcpyAsync(it.data(), d_iters, count * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    OEM_HIP_CHECK(hipStreamSynchronize(s));
+    for (int32_t v : it)
+        if (v < 0) {
+            set_error("some lambda reached maxit before the convergence test held");
+            return OEM_NOT_CONVERGED;
+        }
+    return OEM_OK;
+}
+
+} // namespace oem
+
+using namespace oem;
+
+extern "C" {
+
+const char *oem_last_error(void) { return g_last_error.c_str(); }
+
+const char *oem_version(void) { return "oem-mi355x 0.1 (gfx950)"; }
+
+int oem_gram_create(int32_t p, int32_t nfolds, int32_t precision, int32_t x_dtype,
+                    uint64_t fold_seed, oem_handle *out)
+{
+    if (!out) return fail(OEM_E_INVAL, "out is NULL");
+    *out = nullptr;
+    if (p < 1 || p > 4096) return fail(OEM_E_INVAL, "p must be in [1, 4096]");
+    if (nfolds < 1 || nfolds > 64) return fail(OEM_E_INVAL, "nfolds must be in [1, 64]");
+    if (precision != OEM_FP64 && precision != OEM_SPLIT_BF16 && precision != OEM_BF16)
+        return fail(OEM_E_INVAL, "unknown precision");
+    if (x_dtype != OEM_X_F32 && x_dtype != OEM_X_F64) return fail(OEM_E_INVAL, "unknown x_dtype");
+    oem_gram_s *h = new oem_gram_s();
+    h->p = p;
+    h->K = nfolds;
+    h->prec = precision;
+    h->xdt = x_dtype;
+    h->seed = fold_seed;
+    if (hipGetDevice(&h->device) != hipSuccess) {
+        delete h;
+        return fail(OEM_E_HIP, "hipGetDevice failed");
+    }
+    const size_t pp = (size_t)p * p, K = nfolds, nq = (nfolds == 1) ? 1 : nfolds + 1;
+    int rc = OEM_OK;
+    rc = rc ? rc : h->Gk.ensure(K * pp * sizeof(double));
+    rc = rc ? rc : h->bk.ensure(K * p * sizeof(double));
+    rc = rc ? rc : h->yyk.ensure(K * sizeof(double));
+    rc = rc ? rc : h->nk.ensure(K * sizeof(int64_t));
+    rc = rc ? rc : h->Gs.ensure(nq * pp * sizeof(double));
+    rc = rc ? rc : h->cs.ensure(nq * p * sizeof(double));
+    rc = rc ? rc : h->sc.ensure(nq * p * sizeof(double));
+    rc = rc ? rc : h->yyn.ensure(nq * sizeof(double));
+    rc = rc ? rc : h->dq.ensure(nq * sizeof(double));
+    rc = rc ? rc : h->ntrain.ensure(nq * sizeof(int64_t));
+    rc = rc ? rc : h->lzsteps.ensure(nq * sizeof(int32_t));
+    if (rc) {
+        oem_gram_free(h);
+        return rc;
+    }
+    rc = oem_gram_reset(h, nullptr);
+    if (rc == OEM_OK) rc = (hipStreamSynchronize(nullptr) == hipSuccess) ? OEM_OK : OEM_E_HIP;
+    if (rc) {
+        oem_gram_free(h);
+        return rc == OEM_E_HIP ? fail(OEM_E_HIP, "initialisation failed") : rc;
+    }
+    *out = h;
+    return OEM_OK;
+}
+
+void oem_gram_free(oem_handle h)
+{
+    if (!h) return;
+    (void)hipDeviceSynchronize();
+    for (DevBuf *b : {&h->Gk, &h->bk, &h->yyk, &h->nk, &h->Gs, &h->Gs32, &h->cs, &h->sc, &h->yyn,
+                      &h->dq, &h->ntrain, &h->lzsteps, &h->partial, &h->partial_n, &h->lanczos,
+                      &h->paths, &h->lam, &h->betaw, &h->groupbuf, &h->cvw, &h->flag})
+        b->release();
+    delete h;
+}
+
+int oem_gram_reset(oem_handle h, void *stream)
+{
+    if (!h) return fail(OEM_E_INVAL, "handle is NULL");
+    hipStream_t s = as_stream(stream);
+    const size_t pp = (size_t)h->p * h->p, K = h->K;
+    int rc = launch_fill_f64(h->Gk.as<double>(), K * pp, 0.0, s);
+    rc = rc ? rc : launch_fill_f64(h->bk.as<double>(), K * h->p, 0.0, s);
+    rc = rc ? rc : launch_fill_f64(h->yyk.as<double>(), K, 0.0, s);
+    rc = rc ? rc : launch_fill_i64(h->nk.as<int64_t>(), K, 0, s);
+    h->derived_valid = false;
+    h->rows_seen = 0;
+    return rc;
+}
+
+int oem_gram(oem_handle h, const void *X, int64_t n, int64_t ldx, const double *y,
+             int64_t row_offset, const uint8_t *foldid, void *stream)
+{
+    if (!h) return fail(OEM_E_INVAL, "handle is NULL");
+    if (n < 0) return fail(OEM_E_INVAL, "n must be >= 0");
+    if (n == 0) return OEM_OK;
+    if (!X || !y) return fail(OEM_E_INVAL, "X and y must not be NULL");
+    if (ldx < h->p) return fail(OEM_E_INVAL, "ldx must be >= p");
+    if (row_offset < 0) return fail(OEM_E_INVAL, "row_offset must be >= 0");
+    int rc = launch_gram(h, X, n, ldx, y, row_offset, foldid, as_stream(stream));
+    if (rc) return rc;
+    h->rows_seen += n;
+    h->derived_valid = false;
+    return OEM_OK;
+}
+
+int oem_gram_import(oem_handle h, int32_t fold, const double *XtX, const double *Xty, double yty,
+                    int64_t n, int32_t scaled, void *stream)
+{
+    if (!h) return fail(OEM_E_INVAL, "handle is NULL");
+    if (fold < 0 || fold >= h->K) return fail(OEM_E_INVAL, "fold out of range");
+    if (!XtX || !Xty || n <= 0) return fail(OEM_E_INVAL, "XtX, Xty must be set and n > 0");
+    hipStream_t s = as_stream(stream);
+    const size_t pp = (size_t)h->p * h->p;
+    double *G = h->Gk.as<double>() + fold * pp;
+    double *b = h->bk.as<double>() + (size_t)fold * h->p;
+    OEM_HIP_CHECK(hipMemcpyAsync(G, XtX, pp * sizeof(double), hipMemcpyDeviceToDevice, s));
+    OEM_HIP_CHECK(hipMemcpyAsync(b, Xty, h->p * sizeof(double), hipMemcpyDeviceToDevice, s));
+    const double yv = scaled ? yty * (double)n : yty;
+    int rc = launch_fill_f64(h->yyk.as<double>() + fold, 1, yv, s);
+    rc = rc ? rc : launch_fill_i64(h->nk.as<int64_t>() + fold, 1, n, s);
+    if (rc) return rc;
+    if (scaled) {
+        rc = launch_scale_f64(G, pp, (double)n, s);
+        rc = rc ? rc : launch_scale_f64(b, h->p, (double)n, s);
+        if (rc) return rc;
+    }
+    h->rows_seen += n;
+    h->derived_valid = false;
+    return OEM_OK;
+}
+
+int oem_gram_export(oem_handle h, double *G, double *b, double *yy, int64_t *nk, void *stream)
+{
+    if (!h) return fail(OEM_E_INVAL, "handle is NULL");
+    hipStream_t s = as_stream(stream);
+    const size_t pp = (size_t)h->p * h->p, K = h->K;
+    if (G) OEM_HIP_CHECK(hipMemcpyAsync(G, h->Gk.ptr, K * pp * sizeof(double), hipMemcpyDeviceToDevice, s));
+    if (b) OEM_HIP_CHECK(hipMemcpyAsync(b, h->bk.ptr, K * h->p * sizeof(double), hipMemcpyDeviceToDevice, s));
+    if (yy) OEM_HIP_CHECK(hipMemcpyAsync(yy, h->yyk.ptr, K * sizeof(double), hipMemcpyDeviceToDevice, s));
+    if (nk) OEM_HIP_CHECK(hipMemcpyAsync(nk, h->nk.ptr, K * sizeof(int64_t), hipMemcpyDeviceToDevice, s));
+    return OEM_OK;
+}
+
+int oem_fit_path(oem_handle h, int32_t fold, const oem_penalty *pen, int32_t npen,
+                 const oem_path_opts *opts, double *beta, double *lambda, int32_t *iters,
+                 double *kkt, double *obj, double *d_out, void *stream)
+{
+    if (!h) return fail(OEM_E_INVAL, "handle is NULL");
+    if (!pen || npen < 1) return fail(OEM_E_INVAL, "need at least one penalty");
+    if (!beta) return fail(OEM_E_INVAL, "beta must not be NULL");
+    int rc = check_opts(opts);
+    if (rc) return rc;
+    if (fold < -1 || fold >= h->K || (h->K == 1 && fold != -1))
+        return fail(OEM_E_INVAL, "fold out of range");
+    hipStream_t s = as_stream(stream);
+    rc = ensure_derived(h, opts->standardize ? 1 : 0, s);
+    if (rc) return rc;
+    const int q = (fold < 0) ? 0 : 1 + fold;
+    if (h->n_host[q] <= 0) return fail(OEM_E_INVAL, "the selected rows are empty");
+    if (h->n_host[0] <= 0) return fail(OEM_E_INVAL, "no rows in the full data");
+    bool need_groups = false;
+    for (int i = 0; i < npen; ++i) {
+        rc = check_penalty(pen[i], h->d_host[q]);
+        if (rc) return rc;
+        need_groups |= pen[i].kind == OEM_GRP_LASSO;
+    }
+    GroupPlan gp;
+    rc = build_groups(h, opts, need_groups, gp, s);
+    if (rc) return rc;
+    rc = prepare_lambda(h, pen, npen, opts, gp, s);
+    if (rc) return rc;
+    const int L = opts->nlambda;
+    const size_t nl = (size_t)npen * L;
+    rc = h->flag.ensure(nl * sizeof(int32_t));
+    if (rc) return rc;
+    int32_t *it = iters ? iters : h->flag.as<int32_t>();
+    std::vector<PathDesc> descs;
+    for (int i = 0; i < npen; ++i)
+        descs.push_back(make_desc(h, q, pen[i], opts, gp, h->lam.as<double>() + (size_t)i * L,
+                                  beta + (size_t)i * L * h->p, it + (size_t)i * L,
+                                  kkt ? kkt + (size_t)i * L : nullptr,
+                                  obj ? obj + (size_t)i * L : nullptr));
+    rc = upload_descs(h, descs, s);
+    if (rc) return rc;
+    rc = launch_paths(h->paths.as<PathDesc>(), npen, h->p, s);
+    if (rc) return rc;
+    if (lambda)
+        OEM_HIP_CHECK(hipMemcpyAsync(lambda, h->lam.ptr, nl * sizeof(double), hipMemcpyDeviceToDevice, s));
+    if (d_out)
+        OEM_HIP_CHECK(hipMemcpyAsync(d_out, h->dq.as<double>() + q, sizeof(double), hipMemcpyDeviceToDevice, s));
+    if (opts->sync) return finish_sync(it, nl, s);
+    return OEM_OK;
+}
+
+int oem_cv(oem_handle h, const oem_penalty *pen, int32_t npen, const oem_path_opts *opts,
+           double *beta_full, double *beta_folds, double *lambda, double *cvm, double *cvsd,
+           int32_t *i_min, int32_t *i_1se, int32_t *best, int32_t *iters, void *stream)
+{
+    if (!h) return fail(OEM_E_INVAL, "handle is NULL");
+    if (h->K < 2) return fail(OEM_E_INVAL, "cross validation needs nfolds >= 2");
+    if (!pen || npen < 1) return fail(OEM_E_INVAL, "need at least one penalty");
+    if (!beta_full || !cvm) return fail(OEM_E_INVAL, "beta_full and cvm must not be NULL");
+    int rc = check_opts(opts);
+    if (rc) return rc;
+    hipStream_t s = as_stream(stream);
+    rc = ensure_derived(h, opts->standardize ? 1 : 0, s);
+    if (rc) return rc;
+    const int K = h->K, p = h->p, L = opts->nlambda;
+    for (int q = 0; q <= K; ++q)
+        if (h->n_host[q] <= 0) return fail(OEM_E_INVAL, "a fold leaves no training rows");
+    bool need_groups = false;
+    for (int i = 0; i < npen; ++i) {
+        for (int q = 0; q <= K; ++q) {
+            rc = check_penalty(pen[i], h->d_host[q]);
+            if (rc) return rc;
+        }
+        need_groups |= pen[i].kind == OEM_GRP_LASSO;
+    }
+    GroupPlan gp;
+    rc = build_groups(h, opts, need_groups, gp, s);
+    if (rc) return rc;
+    rc = prepare_lambda(h, pen, npen, opts, gp, s);
+    if (rc) return rc;
+    const size_t nl = (size_t)npen * L;
+    const size_t fold_beta = (size_t)K * nl * p;
+    double *bf = beta_folds;
+    if (!bf) {
+        rc = h->betaw.ensure(fold_beta * sizeof(double));
+        if (rc) return rc;
+        bf = h->betaw.as<double>();
+    }
+    rc = h->flag.ensure((size_t)(K + 1) * nl * sizeof(int32_t));
+    if (rc) return rc;
+    int32_t *it = iters ? iters : h->flag.as<int32_t>();
+    // scratch: per-fold MSE (npen x K x L), cvm/cvsd if not requested, selection
+    rc = h->cvw.ensure((nl * K + 2 * nl) * sizeof(double) + 4 * npen * sizeof(int32_t) + 64);
+    if (rc) return rc;
+    double *mse = h->cvw.as<double>();
+    double *cvsd_w = cvsd ? cvsd : mse + nl * K;
+    std::vector<PathDesc> descs;
+    for (int q = 0; q <= K; ++q)
+        for (int i = 0; i < npen; ++i) {
+            double *b = (q == 0) ? beta_full + (size_t)i * L * p
+                                 : bf + ((size_t)(q - 1) * npen + i) * L * p;
+            descs.push_back(make_desc(h, q, pen[i], opts, gp, h->lam.as<double>() + (size_t)i * L, b,
+                                      it + ((size_t)q * npen + i) * L, nullptr, nullptr));
+        }
+    rc = upload_descs(h, descs, s);
+    if (rc) return rc;
+    rc = launch_paths(h->paths.as<PathDesc>(), (int)descs.size(), p, s);
+    if (rc) return rc;
+    rc = launch_cv(h->Gk.as<double>(), h->bk.as<double>(), h->yyk.as<double>(), h->nk.as<int64_t>(),
+                   K, p, npen, L, bf, mse, cvm, cvsd_w, i_min, i_1se, best, s);
+    if (rc) return rc;
+    if (lambda)
+        OEM_HIP_CHECK(hipMemcpyAsync(lambda, h->lam.ptr, nl * sizeof(double), hipMemcpyDeviceToDevice, s));
+    if (opts->sync) return finish_sync(it, (size_t)(K + 1) * nl, s);
+    return OEM_OK;
+}
+
+} // extern "C"

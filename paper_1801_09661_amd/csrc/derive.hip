@@ -1,0 +1,346 @@
+// From per-fold sums to the problems the paths solve.
+//
+// Problem q = 0 is the full data, q = 1 + k the training rows of fold k
+// (Section 3): G_(k) = sum_{c != k} G_c, X_(k)^T y_(k) = sum_{c != k} b_c,
+// summed as written (no subtraction).  Each is scaled by 1/n_q and
+// standardised to unit column norms (Section 2.1): s_j = sqrt(G_jj),
+// Gs = S^-1 G S^-1, cs = S^-1 c.
+//
+// d per problem (Section 2.1: d >= lambda_1, d = lambda_1 converges fastest,
+// found by the Lanczos algorithm): FP64 Lanczos with full
+// reorthogonalisation, stopped when the top Ritz pair's residual is below
+// 1e-12 of the Ritz value, or the Krylov space is invariant, or it spans
+// every dimension; d = theta * (1 + 1e-10).
+#include <algorithm>
+
+#include "oem_internal.h"
+
+namespace oem {
+
+__device__ inline void problem_rows(int q, int K, int *skip)
+{
+    *skip = (q == 0) ? -1 : q - 1;
+}
+
+// phase 1: per problem, the scaled diagonal gives s; c, yy/n, n_q
+__global__ void combine_scale_kernel(int p, int K, int standardize, const double *__restrict__ Gk,
+                                     const double *__restrict__ bk,
+                                     const double *__restrict__ yyk,
+                                     const int64_t *__restrict__ nk, double *__restrict__ cs,
+                                     double *__restrict__ sc, double *__restrict__ yyn,
+                                     int64_t *__restrict__ ntrain)
+{
+    const int q = blockIdx.y;
+    int skip;
+    problem_rows(q, K, &skip);
+    int64_t nq = 0;
+    double yy = 0.0;
+    for (int c = 0; c < K; ++c) {
+        if (c == skip) continue;
+        nq += nk[c];
+        yy += yyk[c];
+    }
+    const double dn = (double)nq;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        yyn[q] = yy / dn;
+        ntrain[q] = nq;
+    }
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < p; j += gridDim.x * blockDim.x) {
+        double gjj = 0.0, bj = 0.0;
+        for (int c = 0; c < K; ++c) {
+            if (c == skip) continue;
+            gjj += Gk[(size_t)c * p * p + (size_t)j * p + j];
+            bj += bk[(size_t)c * p + j];
+        }
+        gjj = gjj / dn;
+        const double cj = bj / dn;
+        double s = 1.0;
+        if (standardize) s = gjj > 0.0 ? sqrt(gjj) : 1.0;
+        sc[(size_t)q * p + j] = s;
+        cs[(size_t)q * p + j] = cj / s;
+    }
+}
+
+// phase 2: Gs = (G / n) / (s_i s_j); also an FP32 copy for mixed paths
+__global__ void combine_gram_kernel(int p, int K, const double *__restrict__ Gk,
+                                    const int64_t *__restrict__ ntrain,
+                                    const double *__restrict__ sc, double *__restrict__ Gs,
+                                    float *__restrict__ Gs32)
+{
+    const int q = blockIdx.y;
+    int skip;
+    problem_rows(q, K, &skip);
+    const double dn = (double)ntrain[q];
+    const size_t pp = (size_t)p * p;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < pp;
+         e += (size_t)gridDim.x * blockDim.x) {
+        const int i = (int)(e / p), j = (int)(e % p);
+        double v = 0.0;
+        for (int c = 0; c < K; ++c) {
+            if (c == skip) continue;
+            v += Gk[(size_t)c * pp + e];
+        }
+        v = v / dn;
+        const double r = v / (sc[(size_t)q * p + i] * sc[(size_t)q * p + j]);
+        Gs[(size_t)q * pp + e] = r;
+        if (Gs32) Gs32[(size_t)q * pp + e] = (float)r;
+    }
+}
+
+int launch_combine(oem_gram_s *h, int standardize, hipStream_t s)
+{
+    const int p = h->p, K = h->K, nq = (K == 1) ? 1 : K + 1;
+    dim3 g1((p + 255) / 256, nq);
+    hipLaunchKernelGGL(combine_scale_kernel, g1, dim3(256), 0, s, p, K, standardize,
+                       h->Gk.as<double>(), h->bk.as<double>(), h->yyk.as<double>(),
+                       h->nk.as<int64_t>(), h->cs.as<double>(), h->sc.as<double>(),
+                       h->yyn.as<double>(), h->ntrain.as<int64_t>());
+    OEM_HIP_CHECK(hipGetLastError());
+    const size_t pp = (size_t)p * p;
+    dim3 g2((unsigned)std::min<size_t>((pp + 255) / 256, 2048), nq);
+    hipLaunchKernelGGL(combine_gram_kernel, g2, dim3(256), 0, s, p, K, h->Gk.as<double>(),
+                       h->ntrain.as<int64_t>(), h->sc.as<double>(), h->Gs.as<double>(),
+                       h->Gs32.as<float>());
+    OEM_HIP_CHECK(hipGetLastError());
+    return OEM_OK;
+}
+
+// ---------------------------------------------------------------- Lanczos
+
+constexpr int kLzThreads = 256;
+constexpr int kLzWaves = kLzThreads / kWave;
+
+__device__ inline double block_sum(double v, double *red)
+{
+    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+    __syncthreads();
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    double t = 0.0;
+    for (int w = 0; w < kLzWaves; ++w) t += red[w];
+    return t;
+}
+
+// Number of eigenvalues of the symmetric tridiagonal (a, b) that are < x
+// (Sturm sequence count of the LDL^T pivots).
+__device__ inline int sturm_below(const double *a, const double *b, int m, double x)
+{
+    int cnt = 0;
+    double q = 1.0;
+    for (int i = 0; i < m; ++i) {
+        double bb = (i > 0) ? b[i - 1] * b[i - 1] : 0.0;
+        q = (a[i] - x) - (i > 0 ? bb / q : 0.0);
+        if (q == 0.0) q = -1e-300;
+        if (q < 0.0) ++cnt;
+    }
+    return cnt;
+}
+
+// Top eigenvalue of T (m x m) by multisection on one wave; returns [lo, hi].
+__device__ inline void tri_top(const double *a, const double *b, int m, double *lo_out,
+                               double *hi_out)
+{
+    const int lane = threadIdx.x % kWave;
+    double lo = -INFINITY, hi = -INFINITY;
+    for (int i = 0; i < m; ++i) {
+        double r = fabs(i > 0 ? b[i - 1] : 0.0) + fabs(i < m - 1 ? b[i] : 0.0);
+        lo = fmax(lo, a[i]);
+        hi = fmax(hi, a[i] + r);
+    }
+    // invariant: count(< lo) <= m - 1 (top eigenvalue >= lo), count(< hi') = m for hi' > hi
+    hi = hi + fabs(hi) * 1e-15 + 1e-300;
+    lo = lo - fabs(lo) * 1e-15 - 1e-300;
+    for (int round = 0; round < 24; ++round) {
+        if (hi - lo <= 2e-16 * fmax(fabs(lo), fabs(hi))) break;
+        const double x = lo + (hi - lo) * (double)(lane + 1) / (double)(kWave + 1);
+        const int below = sturm_below(a, b, m, x);
+        // first lane whose point is above every eigenvalue
+        const uint64_t above = __ballot(below == m);
+        double nlo = lo, nhi = hi;
+        if (above) {
+            const int f = __ffsll((long long)above) - 1;
+            nhi = lo + (hi - lo) * (double)(f + 1) / (double)(kWave + 1);
+            if (f > 0) nlo = lo + (hi - lo) * (double)f / (double)(kWave + 1);
+        } else {
+            nlo = lo + (hi - lo) * (double)kWave / (double)(kWave + 1);
+        }
+        lo = nlo;
+        hi = nhi;
+    }
+    *lo_out = lo;
+    *hi_out = hi;
+}
+
+// Residual of the top Ritz pair: beta_m * |last component| of the unit
+// eigenvector of T, by two steps of inverse iteration with a shift just above
+// the top eigenvalue (theta' I - T is then positive definite, so the
+// tridiagonal solve needs no pivoting).
+__device__ inline double tri_residual(const double *a, const double *b, int m, double shift,
+                                      double beta_m, double *x, double *work)
+{
+    for (int i = 0; i < m; ++i) x[i] = 1.0;
+    for (int it = 0; it < 2; ++it) {
+        // solve (shift I - T) z = x ; diag: shift - a_i ; off: -b_i
+        double dprev = 0.0;
+        for (int i = 0; i < m; ++i) {
+            double di = shift - a[i];
+            double rhs = x[i];
+            if (i > 0) {
+                const double l = -b[i - 1] / dprev;
+                di -= l * (-b[i - 1]);
+                rhs -= l * work[i - 1];
+            }
+            work[i] = rhs;
+            x[i] = di;  // store pivot
+            dprev = di;
+        }
+        // back substitution into x (pivots currently in x)
+        double znext = 0.0;
+        for (int i = m - 1; i >= 0; --i) {
+            const double piv = x[i];
+            const double z = (work[i] - (i < m - 1 ? -b[i] * znext : 0.0)) / piv;
+            work[i] = z;
+            znext = z;
+        }
+        double nrm = 0.0;
+        for (int i = 0; i < m; ++i) nrm += work[i] * work[i];
+        nrm = sqrt(nrm);
+        for (int i = 0; i < m; ++i) x[i] = work[i] / nrm;
+    }
+    return fabs(beta_m * x[m - 1]);
+}
+
+__device__ inline double start_component(int i)
+{
+    uint64_t z = 0x243F6A8885A308D3ULL + (uint64_t)(i + 1) * 0x9E3779B97F4A7C15ULL;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    z ^= z >> 31;
+    return (double)(z >> 11) * (1.0 / 9007199254740992.0) + 0.5;  // in [0.5, 1.5)
+}
+
+// One workgroup per problem.  V: (mmax + 1) x p workspace per problem.
+// LDS: v (p), w (p), alpha/beta/coef (mmax each), tridiagonal scratch.
+__global__ __launch_bounds__(kLzThreads) void lanczos_kernel(int p, int mmax,
+                                                             const double *__restrict__ Gs_all,
+                                                             double *__restrict__ V_all,
+                                                             double *__restrict__ d_out,
+                                                             int32_t *__restrict__ steps_out)
+{
+    extern __shared__ double sm[];
+    const int q = blockIdx.x;
+    const double *G = Gs_all + (size_t)q * p * p;
+    double *V = V_all + (size_t)q * (mmax + 1) * p;
+    double *w = sm;                 // p
+    double *al = w + p;             // mmax
+    double *be = al + mmax;         // mmax
+    double *coef = be + mmax;       // mmax + 1
+    double *tx = coef + mmax + 1;   // mmax
+    double *tw = tx + mmax;         // mmax
+    double *red = tw + mmax;        // kLzWaves + 4
+    __shared__ int s_flag;
+    __shared__ double s_theta;
+
+    // v0 = pseudo-random positive start vector, normalised
+    double ss = 0.0;
+    for (int i = threadIdx.x; i < p; i += kLzThreads) {
+        const double v = start_component(i);
+        V[i] = v;
+        ss += v * v;
+    }
+    double nrm = sqrt(block_sum(ss, red));
+    for (int i = threadIdx.x; i < p; i += kLzThreads) V[i] /= nrm;
+    __syncthreads();
+
+    double gnorm = 0.0;
+    int m = 0;
+    double theta = 0.0;
+    for (int j = 0; j < mmax; ++j) {
+        const double *vj = V + (size_t)j * p;
+        // w = G v_j (G symmetric: column reads are coalesced across threads)
+        for (int i = threadIdx.x; i < p; i += kLzThreads) {
+            double acc = 0.0;
+            for (int c = 0; c < p; ++c) acc += G[(size_t)c * p + i] * vj[c];
+            w[i] = acc;
+        }
+        __syncthreads();
+        double part = 0.0;
+        for (int i = threadIdx.x; i < p; i += kLzThreads) part += w[i] * vj[i];
+        const double a = block_sum(part, red);
+        if (threadIdx.x == 0) al[j] = a;
+        gnorm = fmax(gnorm, fabs(a));
+        // full reorthogonalisation against v_0..v_j (classical Gram-Schmidt,
+        // repeated once when it removed most of w)
+        double before = 0.0;
+        for (int i = threadIdx.x; i < p; i += kLzThreads) before += w[i] * w[i];
+        before = block_sum(before, red);
+        for (int pass = 0; pass < 2; ++pass) {
+            const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+            for (int mm = wave; mm <= j; mm += kLzWaves) {
+                const double *vm = V + (size_t)mm * p;
+                double t = 0.0;
+                for (int i = lane; i < p; i += kWave) t += vm[i] * w[i];
+                for (int o = kWave / 2; o > 0; o >>= 1) t += __shfl_xor(t, o);
+                if (lane == 0) coef[mm] = t;
+            }
+            __syncthreads();
+            for (int i = threadIdx.x; i < p; i += kLzThreads) {
+                double t = w[i];
+                for (int mm = 0; mm <= j; ++mm) t -= coef[mm] * V[(size_t)mm * p + i];
+                w[i] = t;
+            }
+            __syncthreads();
+            double after = 0.0;
+            for (int i = threadIdx.x; i < p; i += kLzThreads) after += w[i] * w[i];
+            after = block_sum(after, red);
+            if (after > 0.5 * before) break;   // little cancellation: one pass suffices
+            before = after;
+        }
+        double bsq = 0.0;
+        for (int i = threadIdx.x; i < p; i += kLzThreads) bsq += w[i] * w[i];
+        const double b = sqrt(block_sum(bsq, red));
+        if (threadIdx.x == 0) be[j] = b;
+        m = j + 1;
+        const bool invariant = (b <= 1e-14 * fmax(gnorm, 1e-300)) || (m == p);
+        // convergence test on the wave 0
+        __syncthreads();
+        if (threadIdx.x < kWave) {
+            double lo, hi;
+            tri_top(al, be, m, &lo, &hi);
+            if (threadIdx.x == 0) {
+                const double th = 0.5 * (lo + hi);
+                const double shift = hi + (hi - lo) + 1e-13 * fabs(hi) + 1e-300;
+                const double res = invariant ? 0.0 : tri_residual(al, be, m, shift, b, tx, tw);
+                s_theta = th;
+                s_flag = invariant || (res <= 1e-12 * fabs(th));
+            }
+        }
+        __syncthreads();
+        theta = s_theta;
+        if (s_flag) break;
+        double *vn = V + (size_t)(j + 1) * p;
+        for (int i = threadIdx.x; i < p; i += kLzThreads) vn[i] = w[i] / b;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        d_out[q] = theta * (1.0 + 1e-10);
+        if (steps_out) steps_out[q] = s_flag ? m : -m;
+    }
+}
+
+int launch_lanczos(oem_gram_s *h, hipStream_t s)
+{
+    const int p = h->p, nq = (h->K == 1) ? 1 : h->K + 1;
+    const int mmax = std::min(p, 512);
+    int rc = h->lanczos.ensure((size_t)nq * (mmax + 1) * p * sizeof(double));
+    if (rc) return rc;
+    const size_t lds = (size_t)(p + 5 * mmax + 1 + kLzWaves + 4) * sizeof(double);
+    hipLaunchKernelGGL(lanczos_kernel, dim3(nq), dim3(kLzThreads), lds, s, p, mmax,
+                       h->Gs.as<double>(), h->lanczos.as<double>(), h->dq.as<double>(),
+                       h->lzsteps.as<int32_t>());
+    OEM_HIP_CHECK(hipGetLastError());
+    return OEM_OK;
+}
+
+} // namespace oem

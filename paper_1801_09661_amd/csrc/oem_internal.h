@@ -1,0 +1,140 @@
+// Internal declarations shared by the HIP translation units of liboem.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/oem.h"
+
+namespace oem {
+
+constexpr int kWave = 64;
+
+// ------------------------------------------------------------------ errors
+void set_error(const std::string &msg);
+int fail(int code, const std::string &msg);
+
+#define OEM_HIP_CHECK(expr)                                                        \
+    do {                                                                           \
+        hipError_t e_ = (expr);                                                    \
+        if (e_ != hipSuccess)                                                      \
+            return ::oem::fail(OEM_E_HIP, std::string(#expr) + ": " +              \
+                                              hipGetErrorString(e_));              \
+    } while (0)
+
+// ------------------------------------------------------------------ fold hash
+// SplitMix64 (Steele, Lea & Flood 2014): the (i+1)-th output from state seed
+// is mix64(seed + (i+1) * 0x9E3779B97F4A7C15).  The fold is the high word
+// scaled to [0, K).
+__host__ __device__ inline uint32_t fold_hash(uint64_t seed, int64_t row, uint32_t K)
+{
+    uint64_t z = seed + (uint64_t)(row + 1) * 0x9E3779B97F4A7C15ULL;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    z ^= z >> 31;
+    return (uint32_t)(((z >> 32) * (uint64_t)K) >> 32);
+}
+
+// ------------------------------------------------------------------ Gram geometry
+// The Gram pass computes the upper triangle of the augmented Gram
+// [X y]^T [X y] in square tiles.  Tiles are grouped into super-blocks of W
+// tiles; one workgroup owns one (fold, row split, super-block pair).
+struct GramGeom {
+    int p;            // columns of X
+    int pa;           // columns carried through the matrix cores (p + 1 in FP64: y appended)
+    int tile;         // 16 (FP64 MFMA) or 32 (BF16 MFMA)
+    int T;            // tiles per side
+    int W;            // tiles per super-block side
+    int nsb;          // super-blocks per side
+    int npsb;         // super-block pairs (upper triangle)
+    int ntp;          // tile pairs (upper triangle) = T (T + 1) / 2
+    int K;            // folds
+    int nsplit;       // row splits
+    int64_t rows_per_split;
+    int rk;           // rows per LDS stage
+};
+
+// ------------------------------------------------------------------ paths
+enum PathPrec : int32_t { PATH_FP64 = 0, PATH_MIXED = 1 };
+
+// One warm-started lambda path: a (problem, penalty) pair.
+struct PathDesc {
+    const double *G;      // p x p standardised Gram (scaled by 1/n)
+    const float *G32;     // FP32 copy (mixed paths) or null
+    const double *c;      // p
+    const double *s;      // p column scales (beta = beta_std / s)
+    const double *yyn;    // 1
+    const double *d;      // 1
+    const double *lambda; // L
+    double *beta;         // L x p original scale
+    double *beta_std;     // L x p standardised scale or null
+    int32_t *iters;       // L or null
+    double *kkt;          // L or null
+    double *obj;          // L or null
+    const int32_t *gstart;  // ngroups + 1 (group penalties)
+    const int32_t *gidx;    // p
+    const double *w;        // p or null
+    const double *cg;       // ngroups
+    int32_t p;
+    int32_t L;
+    int32_t kind;
+    int32_t ngroups;
+    double alpha;
+    double gamma;
+    double tol;
+    int32_t maxit;
+    int32_t prec;
+};
+
+// ------------------------------------------------------------------ handle
+struct DevBuf {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+    int ensure(size_t need);   // grow (contents not kept); OEM_OK / OEM_E_NOMEM
+    void release();
+    template <typename T> T *as() const { return static_cast<T *>(ptr); }
+};
+
+} // namespace oem
+
+struct oem_gram_s {
+    int32_t p = 0, K = 1, prec = OEM_FP64, xdt = OEM_X_F32;
+    uint64_t seed = 0;
+    int device = 0;
+    // raw per-fold sums
+    oem::DevBuf Gk, bk, yyk, nk;       // K p^2, K p, K, K (int64)
+    // derived problems: q = 0 full data, q = 1 + k training rows of fold k
+    oem::DevBuf Gs, Gs32, cs, sc, yyn, dq, ntrain, lzsteps;  // (K+1) p^2, (K+1) p^2 f32, (K+1) p, ...
+    bool derived_valid = false;
+    int derived_std = -1;
+    std::vector<double> d_host;        // d per problem (valid with derived_valid)
+    std::vector<int64_t> n_host;       // rows per problem
+    std::vector<int32_t> lz_host;      // Lanczos steps (negative: not converged)
+    int64_t rows_seen = 0;
+    // workspaces
+    oem::DevBuf partial, partial_n, lanczos, paths, lam, betaw, groupbuf, cvw, flag;
+};
+
+namespace oem {
+
+// ------------------------------------------------------------------ launchers
+int launch_fill_f64(double *p, size_t n, double v, hipStream_t s);
+int launch_fill_i64(int64_t *p, size_t n, int64_t v, hipStream_t s);
+int launch_scale_f64(double *p, size_t n, double v, hipStream_t s);
+int launch_gram(oem_gram_s *g, const void *X, int64_t n, int64_t ldx, const double *y,
+                int64_t row_offset, const uint8_t *foldid, hipStream_t s);
+int launch_combine(oem_gram_s *g, int standardize, hipStream_t s);
+int launch_lanczos(oem_gram_s *g, hipStream_t s);
+int launch_lambda_grid(const double *cs_full, int p, const int32_t *gstart, const int32_t *gidx,
+                       int ngroups, const double *w, const double *cg, const oem_penalty *d_pens,
+                       int npen, int L, double ratio, double *lambda_out, hipStream_t s);
+int launch_paths(const PathDesc *d_desc, int npaths, int max_p, hipStream_t s);
+int launch_cv(const double *Gk, const double *bk, const double *yyk, const int64_t *nk,
+              int K, int p, int npen, int L, const double *beta_folds, double *mse,
+              double *cvm, double *cvsd, int32_t *i_min, int32_t *i_1se, int32_t *best,
+              hipStream_t s);
+
+} // namespace oem

@@ -1,0 +1,500 @@
+// OEM lambda paths (Section 2.1 iteration, Section 2.2 updates), lambda grids
+// and cross-validation error (Section 3).
+//
+// One workgroup runs one whole warm-started path: for each lambda it repeats
+//     u = c + (d I - G) beta          (only columns with beta_j != 0 are read)
+//     beta <- update(u)               (thresholding operator of the penalty)
+// until max|delta beta| <= tol * max|beta|.  G is kept in LDS when it fits,
+// otherwise it streams from L2.  Every (problem, fold, penalty) path is
+// independent, so paths of different problems and sizes share one launch.
+#include <algorithm>
+
+#include "oem_internal.h"
+
+namespace oem {
+
+constexpr int kPathThreads = 256;
+constexpr int kPathWaves = kPathThreads / kWave;
+
+// ---------------------------------------------------------------- updates
+
+__device__ inline double sgn(double v) { return v > 0.0 ? 1.0 : (v < 0.0 ? -1.0 : 0.0); }
+__device__ inline double pos(double v) { return v > 0.0 ? v : 0.0; }
+
+// Scalar thresholding operators of Section 2.2 (lam_w = w_j * lambda).
+__device__ inline double update1(int kind, double u, double lam_w, double d, double alpha,
+                                 double gamma)
+{
+    const double au = fabs(u);
+    switch (kind) {
+    case OEM_LASSO:  // S(u, w lambda, d)
+        return sgn(u) * pos(au - lam_w) / d;
+    case OEM_ENET:
+        return sgn(u) * pos(au - lam_w * alpha) / (d + lam_w * (1.0 - alpha));
+    case OEM_MCP:    // M(u, w lambda, gamma, d)
+        if (au <= lam_w * gamma * d) return sgn(u) * gamma * pos(au - lam_w) / (gamma * d - 1.0);
+        return u / d;
+    case OEM_SCAD:   // C(u, w lambda, gamma, d)
+        if (au <= (d + 1.0) * lam_w) return sgn(u) * pos(au - lam_w) / d;
+        if (au <= lam_w * gamma * d)
+            return sgn(u) * ((gamma - 1.0) * au - lam_w * gamma) / ((gamma - 1.0) * d - 1.0);
+        return u / d;
+    default:
+        return 0.0;
+    }
+}
+
+// derivative of the penalty at |b| > 0 (for the stationarity check)
+__device__ inline double pen_deriv(int kind, double ab, double lw, double alpha, double gamma)
+{
+    switch (kind) {
+    case OEM_LASSO: return lw;
+    case OEM_ENET: return alpha * lw + (1.0 - alpha) * lw * ab;
+    case OEM_MCP: return pos(lw - ab / gamma);
+    case OEM_SCAD:
+        if (ab <= lw) return lw;
+        if (ab <= gamma * lw) return (gamma * lw - ab) / (gamma - 1.0);
+        return 0.0;
+    default: return 0.0;
+    }
+}
+
+__device__ inline double pen_value(int kind, double b, double lw, double alpha, double gamma)
+{
+    const double ab = fabs(b);
+    switch (kind) {
+    case OEM_LASSO: return lw * ab;
+    case OEM_ENET: return alpha * lw * ab + 0.5 * (1.0 - alpha) * lw * b * b;
+    case OEM_MCP: return ab <= gamma * lw ? lw * ab - b * b / (2.0 * gamma) : 0.5 * gamma * lw * lw;
+    case OEM_SCAD:
+        if (ab <= lw) return lw * ab;
+        if (ab <= gamma * lw) return -(ab * ab - 2.0 * gamma * lw * ab + lw * lw) / (2.0 * (gamma - 1.0));
+        return 0.5 * (gamma + 1.0) * lw * lw;
+    default: return 0.0;
+    }
+}
+
+// ---------------------------------------------------------------- reductions
+
+__device__ inline double wave_max(double v)
+{
+    for (int o = kWave / 2; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    return v;
+}
+
+__device__ inline double wave_sum(double v)
+{
+    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// ---------------------------------------------------------------- lambda grid
+
+// lambda_max of penalty `pen` from the full-data standardised X^T y: the
+// smallest value at which the update maps beta = 0 to 0 (each candidate is
+// raised by ulps until the update's own zero test holds), then a log grid.
+__global__ __launch_bounds__(kPathThreads) void lambda_grid_kernel(
+    const double *__restrict__ cs, int p, const int32_t *__restrict__ gstart,
+    const int32_t *__restrict__ gidx, int ngroups, const double *__restrict__ w,
+    const double *__restrict__ cg, const oem_penalty *__restrict__ pens, int L, double ratio,
+    double *__restrict__ lambda_out)
+{
+    __shared__ double red[kPathWaves];
+    const oem_penalty pen = pens[blockIdx.x];
+    double m = 0.0;
+    if (pen.kind == OEM_GRP_LASSO) {
+        for (int gi = threadIdx.x; gi < ngroups; gi += kPathThreads) {
+            double ss = 0.0;
+            for (int t = gstart[gi]; t < gstart[gi + 1]; ++t) ss += cs[gidx[t]] * cs[gidx[t]];
+            const double nrm = sqrt(ss), c = cg[gi];
+            double lg = nrm / c;
+            while (nrm > 0.0 && 1.0 - c * lg / nrm > 0.0) lg = nextafter(lg, INFINITY);
+            m = fmax(m, lg);
+        }
+    } else {
+        const double a = pen.kind == OEM_ENET ? pen.alpha : 1.0;
+        for (int j = threadIdx.x; j < p; j += kPathThreads) {
+            const double wj = w ? w[j] : 1.0;
+            if (wj <= 0.0) continue;
+            const double ac = fabs(cs[j]);
+            double lj = ac / (wj * a);
+            if (pen.kind == OEM_ENET) {
+                while (ac - wj * lj * a > 0.0) lj = nextafter(lj, INFINITY);
+            } else {
+                while (ac - wj * lj > 0.0) lj = nextafter(lj, INFINITY);
+            }
+            m = fmax(m, lj);
+        }
+    }
+    m = wave_max(m);
+    if (threadIdx.x % kWave == 0) red[threadIdx.x / kWave] = m;
+    __syncthreads();
+    double lmax = red[0];
+    for (int i = 1; i < kPathWaves; ++i) lmax = fmax(lmax, red[i]);
+    for (int l = threadIdx.x; l < L; l += kPathThreads)
+        lambda_out[(size_t)blockIdx.x * L + l] =
+            (L == 1) ? lmax : lmax * pow(ratio, (double)l / (double)(L - 1));
+}
+
+// ---------------------------------------------------------------- path kernel
+
+struct PathLds {
+    double *beta, *u, *Gl;
+    int *act;
+    double *red;
+    int *iscan;
+};
+
+// u = c + (d beta - G beta) over the active columns; also returns nothing.
+__device__ inline void oem_u(const PathDesc &P, const double *G, int ldg, const PathLds &S,
+                             int nact, double d)
+{
+    const int p = P.p;
+    for (int i = threadIdx.x; i < p; i += kPathThreads) {
+        double acc = 0.0;
+        int a = 0;
+        for (; a + 4 <= nact; a += 4) {
+            const int j0 = S.act[a], j1 = S.act[a + 1], j2 = S.act[a + 2], j3 = S.act[a + 3];
+            acc += G[(size_t)j0 * ldg + i] * S.beta[j0];
+            acc += G[(size_t)j1 * ldg + i] * S.beta[j1];
+            acc += G[(size_t)j2 * ldg + i] * S.beta[j2];
+            acc += G[(size_t)j3 * ldg + i] * S.beta[j3];
+        }
+        for (; a < nact; ++a) {
+            const int j = S.act[a];
+            acc += G[(size_t)j * ldg + i] * S.beta[j];
+        }
+        S.u[i] = P.c[i] + (d * S.beta[i] - acc);
+    }
+}
+
+// ordered list of nonzero coordinates; returns the count (uniform)
+__device__ inline int rebuild_active(const PathLds &S, int p)
+{
+    const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+    int base = 0;
+    for (int i0 = 0; i0 < p; i0 += kPathThreads) {
+        const int i = i0 + threadIdx.x;
+        const int nz = (i < p) && (S.beta[i] != 0.0);
+        const uint64_t ball = __ballot(nz);
+        const int before = __popcll(ball & ((1ull << lane) - 1ull));
+        if (lane == 0) S.iscan[wave] = __popcll(ball);
+        __syncthreads();
+        int off = 0, tot = 0;
+        for (int w = 0; w < kPathWaves; ++w) {
+            if (w < wave) off += S.iscan[w];
+            tot += S.iscan[w];
+        }
+        if (nz) S.act[base + off + before] = i;
+        __syncthreads();
+        base += tot;
+    }
+    return base;
+}
+
+__global__ __launch_bounds__(kPathThreads) void path_kernel(const PathDesc *__restrict__ descs,
+                                                            int lds_g_max_p)
+{
+    extern __shared__ double sm[];
+    const PathDesc P = descs[blockIdx.x];
+    const int p = P.p;
+    const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+    PathLds S;
+    S.beta = sm;
+    S.u = S.beta + p;
+    S.red = S.u + p;                               // 4 * kPathWaves + 2
+    S.act = reinterpret_cast<int *>(S.red + 4 * kPathWaves + 2);
+    S.iscan = S.act + p + 1;                       // kPathWaves
+    double *after_ints = sm + 2 * p + 4 * kPathWaves + 2 + (p + 1 + kPathWaves + 1) / 2 + 1;
+    const bool g_in_lds = p <= lds_g_max_p;
+    const double *G = P.G;
+    if (g_in_lds) {
+        S.Gl = after_ints;
+        for (size_t e = threadIdx.x; e < (size_t)p * p; e += kPathThreads) S.Gl[e] = P.G[e];
+        G = S.Gl;
+    }
+    const double d = *P.d;
+    const double yyn = *P.yyn;
+    const bool grp = (P.kind == OEM_GRP_LASSO);
+    for (int i = threadIdx.x; i < p; i += kPathThreads) S.beta[i] = 0.0;
+    __syncthreads();
+    int nact = 0;
+
+    for (int l = 0; l < P.L; ++l) {
+        const double lam = P.lambda[l];
+        int it = 0;
+        bool conv = false;
+        while (it < P.maxit) {
+            oem_u(P, G, p, S, nact, d);
+            __syncthreads();
+            // update, change and size
+            double dl = 0.0, mx = 0.0;
+            if (grp) {
+                for (int gi = threadIdx.x; gi < P.ngroups; gi += kPathThreads) {
+                    double ss = 0.0;
+                    const int t0 = P.gstart[gi], t1 = P.gstart[gi + 1];
+                    for (int t = t0; t < t1; ++t) ss += S.u[P.gidx[t]] * S.u[P.gidx[t]];
+                    const double nrm = sqrt(ss);
+                    const double lam_c = P.cg[gi] * lam;
+                    const double f = nrm > 0.0 ? 1.0 - lam_c / nrm : 0.0;
+                    for (int t = t0; t < t1; ++t) {
+                        const int j = P.gidx[t];
+                        const double bn = f > 0.0 ? (S.u[j] / d) * f : 0.0;
+                        dl = fmax(dl, fabs(bn - S.beta[j]));
+                        mx = fmax(mx, fabs(bn));
+                        S.beta[j] = bn;
+                    }
+                }
+            } else {
+                for (int i = threadIdx.x; i < p; i += kPathThreads) {
+                    const double lw = (P.w ? P.w[i] : 1.0) * lam;
+                    const double bn = update1(P.kind, S.u[i], lw, d, P.alpha, P.gamma);
+                    dl = fmax(dl, fabs(bn - S.beta[i]));
+                    mx = fmax(mx, fabs(bn));
+                    S.beta[i] = bn;
+                }
+            }
+            dl = wave_max(dl);
+            mx = wave_max(mx);
+            if (lane == 0) {
+                S.red[wave] = dl;
+                S.red[kPathWaves + wave] = mx;
+            }
+            __syncthreads();
+            dl = S.red[0];
+            mx = S.red[kPathWaves];
+            for (int wv = 1; wv < kPathWaves; ++wv) {
+                dl = fmax(dl, S.red[wv]);
+                mx = fmax(mx, S.red[kPathWaves + wv]);
+            }
+            nact = rebuild_active(S, p);
+            ++it;
+            if (dl <= P.tol * mx) {
+                conv = true;
+                break;
+            }
+        }
+        // gradient g = G beta - c, stationarity and objective (FP64)
+        double kv = 0.0, quad = 0.0, lin = 0.0, penv = 0.0;
+        for (int i = threadIdx.x; i < p; i += kPathThreads) {
+            double acc = 0.0;
+            for (int a = 0; a < nact; ++a) {
+                const int j = S.act[a];
+                acc += G[(size_t)j * p + i] * S.beta[j];
+            }
+            S.u[i] = acc - P.c[i];   // gradient
+            quad += S.beta[i] * acc;
+            lin += P.c[i] * S.beta[i];
+            if (!grp) {
+                const double lw = (P.w ? P.w[i] : 1.0) * lam;
+                const double b = S.beta[i];
+                double v;
+                if (b == 0.0) {
+                    v = pos(fabs(S.u[i]) - (P.kind == OEM_ENET ? P.alpha * lw : lw));
+                } else {
+                    v = fabs(S.u[i] + sgn(b) * pen_deriv(P.kind, fabs(b), lw, P.alpha, P.gamma));
+                }
+                kv = fmax(kv, v);
+                penv += pen_value(P.kind, b, lw, P.alpha, P.gamma);
+            }
+        }
+        __syncthreads();
+        if (grp) {
+            for (int gi = threadIdx.x; gi < P.ngroups; gi += kPathThreads) {
+                const double lc = lam * P.cg[gi];
+                double bn = 0.0, gn = 0.0;
+                const int t0 = P.gstart[gi], t1 = P.gstart[gi + 1];
+                for (int t = t0; t < t1; ++t) {
+                    const int j = P.gidx[t];
+                    bn += S.beta[j] * S.beta[j];
+                    gn += S.u[j] * S.u[j];
+                }
+                bn = sqrt(bn);
+                gn = sqrt(gn);
+                double v;
+                if (bn > 0.0) {
+                    double ss = 0.0;
+                    for (int t = t0; t < t1; ++t) {
+                        const int j = P.gidx[t];
+                        const double r = S.u[j] + lc * S.beta[j] / bn;
+                        ss += r * r;
+                    }
+                    v = sqrt(ss);
+                } else {
+                    v = pos(gn - lc);
+                }
+                kv = fmax(kv, v);
+                penv += lc * bn;
+            }
+        }
+        kv = wave_max(kv);
+        quad = wave_sum(quad);
+        lin = wave_sum(lin);
+        penv = wave_sum(penv);
+        __syncthreads();
+        if (lane == 0) {
+            S.red[wave] = kv;
+            S.red[kPathWaves + wave] = quad;
+            S.red[2 * kPathWaves + wave] = lin;
+            S.red[3 * kPathWaves + wave] = penv;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double k2 = 0.0, q2 = 0.0, l2 = 0.0, p2 = 0.0;
+            for (int wv = 0; wv < kPathWaves; ++wv) {
+                k2 = fmax(k2, S.red[wv]);
+                q2 += S.red[kPathWaves + wv];
+                l2 += S.red[2 * kPathWaves + wv];
+                p2 += S.red[3 * kPathWaves + wv];
+            }
+            if (P.kkt) P.kkt[l] = k2;
+            if (P.obj) P.obj[l] = 0.5 * q2 - l2 + 0.5 * yyn + p2;
+            if (P.iters) P.iters[l] = conv ? it : -it;
+        }
+        for (int i = threadIdx.x; i < p; i += kPathThreads) {
+            P.beta[(size_t)l * p + i] = S.beta[i] / P.s[i];
+            if (P.beta_std) P.beta_std[(size_t)l * p + i] = S.beta[i];
+        }
+        __syncthreads();
+    }
+}
+
+size_t path_lds_bytes(int p, bool g_in_lds)
+{
+    size_t doubles = 2 * (size_t)p + 4 * kPathWaves + 2 + ((size_t)p + 1 + kPathWaves + 1) / 2 + 1;
+    if (g_in_lds) doubles += (size_t)p * p;
+    return doubles * sizeof(double);
+}
+
+int launch_paths(const PathDesc *d_desc, int npaths, int max_p, hipStream_t s)
+{
+    if (npaths == 0) return OEM_OK;
+    // keep G in LDS when the largest path's matrix fits next to its vectors
+    const size_t limit = 150 * 1024;
+    int lds_g_max_p = 0;
+    size_t lds = path_lds_bytes(max_p, false);
+    if (path_lds_bytes(max_p, true) <= limit) {
+        lds_g_max_p = max_p;
+        lds = path_lds_bytes(max_p, true);
+    }
+    if (lds > 64 * 1024)
+        OEM_HIP_CHECK(hipFuncSetAttribute((const void *)path_kernel,
+                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL(path_kernel, dim3(npaths), dim3(kPathThreads), lds, s, d_desc, lds_g_max_p);
+    OEM_HIP_CHECK(hipGetLastError());
+    return OEM_OK;
+}
+
+int launch_lambda_grid(const double *cs_full, int p, const int32_t *gstart, const int32_t *gidx,
+                       int ngroups, const double *w, const double *cg, const oem_penalty *d_pens,
+                       int npen, int L, double ratio, double *lambda_out, hipStream_t s)
+{
+    hipLaunchKernelGGL(lambda_grid_kernel, dim3(npen), dim3(kPathThreads), 0, s, cs_full, p, gstart,
+                       gidx, ngroups, w, cg, d_pens, L, ratio, lambda_out);
+    OEM_HIP_CHECK(hipGetLastError());
+    return OEM_OK;
+}
+
+// ---------------------------------------------------------------- CV error
+
+// MSE_{k,l} = (yy_k - 2 beta^T b_k + beta^T G_k beta) / n_k from held-out
+// sums; one workgroup per (fold, penalty, lambda).
+__global__ __launch_bounds__(kPathThreads) void cv_mse_kernel(
+    const double *__restrict__ Gk, const double *__restrict__ bk, const double *__restrict__ yyk,
+    const int64_t *__restrict__ nk, int K, int p, int npen, int L,
+    const double *__restrict__ beta_folds, double *__restrict__ mse)
+{
+    __shared__ double red[2 * kPathWaves];
+    const int l = blockIdx.x % L;
+    const int pen = (blockIdx.x / L) % npen;
+    const int k = blockIdx.x / (L * npen);
+    const double *beta = beta_folds + (((size_t)k * npen + pen) * L + l) * p;
+    const double *G = Gk + (size_t)k * p * p;
+    double quad = 0.0, lin = 0.0;
+    for (int i = threadIdx.x; i < p; i += kPathThreads) {
+        double acc = 0.0;
+        for (int j = 0; j < p; ++j) {
+            const double bj = beta[j];
+            if (bj != 0.0) acc += G[(size_t)j * p + i] * bj;
+        }
+        quad += beta[i] * acc;
+        lin += beta[i] * bk[(size_t)k * p + i];
+    }
+    quad = wave_sum(quad);
+    lin = wave_sum(lin);
+    if (threadIdx.x % kWave == 0) {
+        red[threadIdx.x / kWave] = quad;
+        red[kPathWaves + threadIdx.x / kWave] = lin;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double q2 = 0.0, l2 = 0.0;
+        for (int w = 0; w < kPathWaves; ++w) {
+            q2 += red[w];
+            l2 += red[kPathWaves + w];
+        }
+        mse[((size_t)pen * K + k) * L + l] = (yyk[k] - 2.0 * l2 + q2) / (double)nk[k];
+    }
+}
+
+// cvm, cvsd per (penalty, lambda); i_min, i_1se per penalty; best penalty.
+__global__ void cv_select_kernel(const double *__restrict__ mse, const int64_t *__restrict__ nk,
+                                 int K, int npen, int L, double *__restrict__ cvm,
+                                 double *__restrict__ cvsd, int32_t *__restrict__ i_min,
+                                 int32_t *__restrict__ i_1se, int32_t *__restrict__ best)
+{
+    int64_t ntot = 0;
+    for (int k = 0; k < K; ++k) ntot += nk[k];
+    const double n = (double)ntot;
+    for (int e = threadIdx.x; e < npen * L; e += blockDim.x) {
+        const int pen = e / L, l = e % L;
+        double m = 0.0;
+        for (int k = 0; k < K; ++k) m += (double)nk[k] * mse[((size_t)pen * K + k) * L + l];
+        m /= n;
+        double v = 0.0;
+        for (int k = 0; k < K; ++k) {
+            const double dv = mse[((size_t)pen * K + k) * L + l] - m;
+            v += (double)nk[k] * dv * dv;
+        }
+        cvm[e] = m;
+        cvsd[e] = sqrt(v / (n * (K - 1)));
+    }
+    __syncthreads();
+    for (int pen = threadIdx.x; pen < npen; pen += blockDim.x) {
+        int im = 0;
+        for (int l = 1; l < L; ++l)
+            if (cvm[(size_t)pen * L + l] < cvm[(size_t)pen * L + im]) im = l;
+        const double thr = cvm[(size_t)pen * L + im] + cvsd[(size_t)pen * L + im];
+        int i1 = im;
+        for (int l = 0; l < L; ++l)
+            if (cvm[(size_t)pen * L + l] <= thr) { i1 = l; break; }
+        if (i_min) i_min[pen] = im;
+        if (i_1se) i_1se[pen] = i1;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && best) {
+        int b = 0;
+        double bv = INFINITY;
+        for (int pen = 0; pen < npen; ++pen) {
+            double mn = cvm[(size_t)pen * L];
+            for (int l = 1; l < L; ++l) mn = fmin(mn, cvm[(size_t)pen * L + l]);
+            if (mn < bv) { bv = mn; b = pen; }
+        }
+        *best = b;
+    }
+}
+
+int launch_cv(const double *Gk, const double *bk, const double *yyk, const int64_t *nk, int K,
+              int p, int npen, int L, const double *beta_folds, double *mse, double *cvm,
+              double *cvsd, int32_t *i_min, int32_t *i_1se, int32_t *best, hipStream_t s)
+{
+    hipLaunchKernelGGL(cv_mse_kernel, dim3(K * npen * L), dim3(kPathThreads), 0, s, Gk, bk, yyk, nk,
+                       K, p, npen, L, beta_folds, mse);
+    OEM_HIP_CHECK(hipGetLastError());
+    hipLaunchKernelGGL(cv_select_kernel, dim3(1), dim3(256), 0, s, mse, nk, K, npen, L, cvm, cvsd,
+                       i_min, i_1se, best);
+    OEM_HIP_CHECK(hipGetLastError());
+    return OEM_OK;
+}
+
+} // namespace oem

@@ -1,0 +1,63 @@
+"""CPU-side checks of the C ABI: the built library loads and exports every
+function that include/oem.h declares; host-side argument checks."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1801_09661_amd as oem
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "oem.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(oem_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(oem.LIB_PATH):
+        pytest.fail("liboem.so is not built; run __graft_entry__.build()")
+    return oem.load_library()
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for required in ["oem_gram_create", "oem_gram", "oem_fit_path", "oem_cv", "oem_gram_free",
+                     "oem_last_error"]:
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in _declared():
+        assert hasattr(lib, name), name
+    assert set(oem.EXPORTED) <= set(_declared())
+
+
+def test_version_string(lib):
+    assert b"gfx950" in lib.oem_version()
+
+
+def test_invalid_arguments_rejected_without_gpu(lib):
+    h = ctypes.c_void_p()
+    assert lib.oem_gram_create(0, 1, 0, 0, 0, ctypes.byref(h)) == oem.OEM_E_INVAL
+    assert b"p must be" in lib.oem_last_error()
+    assert lib.oem_gram_create(10, 0, 0, 0, 0, ctypes.byref(h)) == oem.OEM_E_INVAL
+    assert lib.oem_gram_create(10, 2, 7, 0, 0, ctypes.byref(h)) == oem.OEM_E_INVAL
+    assert lib.oem_gram_create(10, 2, 0, 9, 0, ctypes.byref(h)) == oem.OEM_E_INVAL
+    assert lib.oem_gram(None, None, 0, 0, None, 0, None, None) == oem.OEM_E_INVAL
+    assert lib.oem_fit_path(None, -1, None, 0, None, None, None, None, None, None, None,
+                            None) == oem.OEM_E_INVAL
+    assert lib.oem_cv(None, None, 0, None, None, None, None, None, None, None, None, None, None,
+                      None) == oem.OEM_E_INVAL
+
+
+def test_no_cpu_fallback_without_gpu():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("GPU present")
+    with pytest.raises(oem.OemError):
+        oem.oem_gram_create(10)

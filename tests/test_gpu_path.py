@@ -1,0 +1,175 @@
+"""GPU parity of the OEM paths and cross validation (FP64 form) against the
+oracle.
+
+Tolerance (coefficients, FP64): both sides stop when the last update moved
+beta by at most tol * max|beta| (tol = 1e-10), from the same warm start, the
+same d (to ~1e-12) and the same lambda grid; a stopping decision that differs
+by one update moves beta by at most tol * max|beta|.  Hence, per (penalty,
+lambda): max|beta_gpu - beta_oracle| <= 1e-10 * max|beta_oracle|.  Active sets
+(nonzero patterns) must match exactly.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+def _oem():
+    import paper_1801_09661_amd as oem
+    return oem
+
+
+def _cuda(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _assert_paths(b_gpu, b_or, tol=TOL, skip_first=False, what=""):
+    """b_*: (npen, L, p).  Per (penalty, lambda) relative inf-norm error."""
+    for q in range(b_or.shape[0]):
+        for l in range(b_or.shape[1]):
+            ref = b_or[q, l]
+            got = b_gpu[q, l]
+            scale = np.abs(ref).max()
+            if scale == 0.0:
+                assert np.all(got == 0.0), f"{what} pen {q} lambda {l}: expected all-zero"
+                continue
+            err = np.abs(got - ref).max() / scale
+            assert err <= tol, f"{what} pen {q} lambda {l}: rel err {err:.3e}"
+            assert np.array_equal(got != 0, ref != 0), f"{what} pen {q} lambda {l}: active set"
+
+
+def _fit_both(pr, pens, L, ratio=1e-3, groups=None, **kw):
+    oem = _oem()
+    res = oem.fit(_cuda(pr.X), _cuda(pr.y), pens, nlambda=L, lambda_min_ratio=ratio, tol=TOL,
+                  groups=groups, **kw)
+    torch.cuda.synchronize()
+    ref = oracle.fit(pr.X, pr.y, pens, groups=groups, nlambda=L, lambda_min_ratio=ratio, tol=TOL,
+                     **{k: v for k, v in kw.items() if k in ("w", "cg", "standardize", "maxit")})
+    return res, ref
+
+
+def test_small_lasso_workload_parity():
+    """n=1e4, p=20, iid FP64 X, lasso, 50 lambdas, tol 1e-10 (full size)."""
+    print("case: small_lasso full size", flush=True)
+    pr = workloads.small_lasso()
+    res, ref = _fit_both(pr, ["lasso"], 50)
+    d = res["d"].item()
+    assert abs(d - ref["d"]) <= 1e-12 * ref["d"]
+    lam = res["lambda_"].cpu().numpy()
+    assert np.allclose(lam, ref["lambda"], rtol=1e-14, atol=0)
+    _assert_paths(res["beta"].cpu().numpy(), ref["beta"], what="lasso")
+    it = res["iters"].cpu().numpy()
+    assert np.all(it > 0)
+    assert np.all(np.abs(it - ref["iters"]) <= 1)
+    assert np.allclose(res["obj"].cpu().numpy(), ref["obj"], rtol=1e-12)
+
+
+@pytest.mark.parametrize("p", [1, 2, 30, 64, 65, 150])
+def test_four_penalties_parity(p):
+    print(f"case: tall_multi scaled n=20000 p={p}", flush=True)
+    pr = workloads.tall_multi(n=20_000, p=p, seed_tag=200 + p)
+    pens = [dict(kind="lasso"), dict(kind="enet", alpha=0.5), dict(kind="mcp", gamma=3.0),
+            dict(kind="scad", gamma=3.7)]
+    res, ref = _fit_both(pr, pens, 30)
+    _assert_paths(res["beta"].cpu().numpy(), ref["beta"], what=f"p={p}")
+    k = res["kkt"].cpu().numpy()
+    assert np.all(k <= 1e-8)
+
+
+def test_group_lasso_parity_noncontiguous_groups():
+    print("case: group lasso, shuffled group ids", flush=True)
+    pr = workloads.cv_grouped(n=20_000, p=40, group_size=5, active_groups=3, seed_tag=210)
+    rng = np.random.default_rng(0)
+    groups = rng.permutation(pr.groups).astype(np.int32)
+    res, ref = _fit_both(pr, ["grp_lasso"], 25, groups=groups)
+    _assert_paths(res["beta"].cpu().numpy(), ref["beta"], what="grp")
+
+
+def test_weights_and_unstandardized():
+    print("case: weights + standardize=0", flush=True)
+    pr = workloads.small_lasso(n=5000, p=12, seed_tag=211)
+    w = np.linspace(0.5, 2.0, 12)
+    res, ref = _fit_both(pr, ["lasso", dict(kind="mcp", gamma=4.0)], 20, w=w, standardize=False)
+    _assert_paths(res["beta"].cpu().numpy(), ref["beta"], what="weighted")
+
+
+def test_explicit_lambda_and_lambda_zero():
+    oem = _oem()
+    pr = workloads.tall_multi(n=8000, p=10, seed_tag=212)
+    lam = np.array([[0.2, 0.05, 0.0]])
+    res = oem.fit(_cuda(pr.X), _cuda(pr.y), ["lasso"], nlambda=3, lambdas=lam, tol=1e-13)
+    ref = oracle.fit(pr.X, pr.y, ["lasso"], lambdas=lam, tol=1e-13)
+    _assert_paths(res["beta"].cpu().numpy(), ref["beta"], tol=1e-12, what="explicit")
+    ols = np.linalg.lstsq(pr.X.astype(np.float64), pr.y, rcond=None)[0]
+    assert np.abs(res["beta"].cpu().numpy()[0, 2] - ols).max() <= 1e-8 * np.abs(ols).max()
+
+
+def test_maxit_reports_nonconvergence():
+    oem = _oem()
+    pr = workloads.tall_multi(n=8000, p=10, seed_tag=213)
+    res = oem.fit(_cuda(pr.X), _cuda(pr.y), ["lasso"], nlambda=5, maxit=2)
+    assert res["status"] == oem.OEM_NOT_CONVERGED
+    it = res["iters"].cpu().numpy()[0]
+    assert it[0] == 1 and np.all(it[1:] == -2)
+
+
+def test_invalid_inputs_raise():
+    oem = _oem()
+    pr = workloads.small_lasso(n=500, p=5, seed_tag=214)
+    X, y = _cuda(pr.X), _cuda(pr.y)
+    with pytest.raises(oem.OemError):
+        oem.fit(X, y, [dict(kind="mcp", gamma=0.5)], nlambda=3)
+    with pytest.raises(oem.OemError):
+        oem.fit(X, y, ["grp_lasso"], nlambda=3)          # no groups
+    with pytest.raises(oem.OemError):
+        oem.fit(X, y, [dict(kind="enet", alpha=0.0)], nlambda=3)
+    with oem.Gram(5, 1, "fp64", X.dtype) as g:
+        with pytest.raises(oem.OemError):
+            g.fit_path(["lasso"], nlambda=3)             # no rows yet
+
+
+def test_cv_parity_grouped_workload_scaled():
+    """Scaled-down CV workload: K=5 hashed folds, group lasso + lasso + MCP."""
+    oem = _oem()
+    K, seed = 5, 12345
+    print("case: cv_grouped scaled n=30000 p=60 K=5", flush=True)
+    pr = workloads.cv_grouped(n=30_000, p=60, group_size=10, active_groups=2, seed_tag=215)
+    pens = ["grp_lasso", "lasso", dict(kind="mcp", gamma=3.0)]
+    res = oem.cv(_cuda(pr.X), _cuda(pr.y), K, seed, pens, nlambda=20, tol=TOL, groups=pr.groups)
+    torch.cuda.synchronize()
+    ref = oracle.cv(pr.X, pr.y, K, seed, pens, groups=pr.groups, nlambda=20, tol=TOL)
+    _assert_paths(res["beta"].cpu().numpy(), ref["full"]["beta"], what="cv full")
+    bf = res["beta_folds"].cpu().numpy()
+    for k in range(K):
+        _assert_paths(bf[k], ref["folds"][k]["beta"], what=f"cv fold {k}")
+    cvm = res["cvm"].cpu().numpy()
+    assert np.allclose(cvm, ref["cvm"], rtol=1e-9, atol=0)
+    assert np.allclose(res["cvsd"].cpu().numpy(), ref["cvsd"], rtol=1e-6, atol=1e-14)
+    im = res["i_min"].cpu().numpy()
+    for q in range(3):
+        # either index is correct when the two curve values agree to 1e-9
+        a, b = im[q], ref["i_min"][q]
+        assert a == b or abs(ref["cvm"][q, a] - ref["cvm"][q, b]) <= 1e-9 * ref["cvm"][q, b]
+    assert res["best"].item() == ref["best"] or abs(
+        ref["cvm"][res["best"].item()].min() - ref["cvm"][ref["best"]].min()) <= 1e-9
+
+
+def test_cv_equals_naive_refits():
+    """oem_cv on fold statistics == separate fits on the physically split rows."""
+    oem = _oem()
+    K, seed = 4, 99
+    pr = workloads.tall_multi(n=12_000, p=16, seed_tag=216)
+    res = oem.cv(_cuda(pr.X), _cuda(pr.y), K, seed, ["lasso"], nlambda=15, tol=TOL)
+    lam = res["lambda_"].cpu().numpy()
+    f = oracle.fold_ids(seed, pr.X.shape[0], K)
+    for k in range(K):
+        Xt = np.ascontiguousarray(pr.X[f != k])
+        r = oem.fit(_cuda(Xt), _cuda(pr.y[f != k]), ["lasso"], nlambda=15, lambdas=lam, tol=TOL)
+        _assert_paths(res["beta_folds"].cpu().numpy()[k], r["beta"].cpu().numpy(), tol=1e-9,
+                      what=f"naive fold {k}")
