@@ -17,7 +17,7 @@ from typing import Optional, Sequence
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "liboem.so")
+LIB_PATH = os.environ.get("OEM_LIBRARY", os.path.join(HERE, "liboem.so"))
 
 OEM_OK, OEM_NOT_CONVERGED = 0, 1
 OEM_E_INVAL, OEM_E_NOMEM, OEM_E_HIP, OEM_E_STATE = -1, -2, -3, -4

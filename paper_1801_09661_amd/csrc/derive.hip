@@ -13,7 +13,7 @@
 // every dimension; d = theta * (1 + 1e-10).
 #include <algorithm>
 
-#include "oem_internal.h"
+#include "path_common.h"
 
 namespace oem {
 
@@ -303,8 +303,16 @@ __global__ __launch_bounds__(kLzThreads) void lanczos_kernel(int p, int mmax,
         if (threadIdx.x == 0) be[j] = b;
         m = j + 1;
         const bool invariant = (b <= 1e-14 * fmax(gnorm, 1e-300)) || (m == p);
-        // convergence test on the wave 0
+        // convergence test on wave 0, every 8 steps (the Ritz values only
+        // grow with m, so testing less often never accepts an earlier one)
         __syncthreads();
+        const bool test_now = invariant || (m % 8 == 0) || (m == mmax);
+        if (!test_now) {
+            double *vn = V + (size_t)(j + 1) * p;
+            for (int i = threadIdx.x; i < p; i += kLzThreads) vn[i] = w[i] / b;
+            __syncthreads();
+            continue;
+        }
         if (threadIdx.x < kWave) {
             double lo, hi;
             tri_top(al, be, m, &lo, &hi);
@@ -323,16 +331,205 @@ __global__ __launch_bounds__(kLzThreads) void lanczos_kernel(int p, int mmax,
         for (int i = threadIdx.x; i < p; i += kLzThreads) vn[i] = w[i] / b;
         __syncthreads();
     }
+    // Lanczos did not settle within mmax steps: fall back to the Gershgorin
+    // bound max_i sum_j |G_ij| >= lambda_1, which keeps the iteration a
+    // majorisation (slower, but never divergent).
+    double dval = theta * (1.0 + 1e-10);
+    if (!s_flag) {
+        double gm = 0.0;
+        for (int i = threadIdx.x; i < p; i += kLzThreads) {
+            double r = 0.0;
+            for (int c = 0; c < p; ++c) r += fabs(G[(size_t)c * p + i]);
+            gm = fmax(gm, r);
+        }
+        for (int o = kWave / 2; o > 0; o >>= 1) gm = fmax(gm, __shfl_xor(gm, o));
+        __syncthreads();
+        if (threadIdx.x % kWave == 0) red[threadIdx.x / kWave] = gm;
+        __syncthreads();
+        gm = red[0];
+        for (int w = 1; w < kLzWaves; ++w) gm = fmax(gm, red[w]);
+        dval = fmax(dval, gm);
+    }
     if (threadIdx.x == 0) {
-        d_out[q] = theta * (1.0 + 1e-10);
+        d_out[q] = dval;
         if (steps_out) steps_out[q] = s_flag ? m : -m;
+    }
+}
+
+// Lanczos for p <= 128: G spread over the registers of 64 NW threads (thread
+// (wave w, lane l) holds G[l + 64 r][NW c + w]), the Krylov basis V in LDS.
+// Same recurrence, reorthogonalisation and stopping rule as lanczos_kernel.
+template <int NW, int R, int CPW>
+__global__ __launch_bounds__(64 * NW) void lanczos_reg_kernel(int p, int mmax,
+                                                              const double *__restrict__ Gs_all,
+                                                              double *__restrict__ d_out,
+                                                              int32_t *__restrict__ steps_out)
+{
+    constexpr int NT = 64 * NW;
+    extern __shared__ double sm[];
+    const int q = blockIdx.x;
+    const double *G = Gs_all + (size_t)q * p * p;
+    const int t = threadIdx.x, lane = t % kWave, wave = t / kWave;
+    const int ldv = p + 1;                    // padded row pitch of V
+    double *V = sm;                           // (mmax + 1) x ldv
+    double *ws = V + (size_t)(mmax + 1) * ldv;  // p
+    double *part = ws + p;                    // NW x 64 R
+    double *al = part + NW * 64 * R;          // mmax
+    double *be = al + mmax;                   // mmax
+    double *coef = be + mmax;                 // mmax + 1
+    double *tx = coef + mmax + 1;             // mmax
+    double *tw = tx + mmax;                   // mmax
+    double *red = tw + mmax;                  // NW
+    __shared__ int s_flag;
+    __shared__ double s_theta;
+
+    double Gr[R][CPW];
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int c = 0; c < CPW; ++c) {
+            const int i = lane + 64 * r, j = NW * c + wave;
+            Gr[r][c] = (i < p && j < p) ? G[(size_t)i * p + j] : 0.0;
+        }
+    const bool mine = t < p;
+
+    auto bsum = [&](double v) -> double {
+        v = wave_sum(v);
+        __syncthreads();
+        if (lane == 0) red[wave] = v;
+        __syncthreads();
+        double a = 0.0;
+        for (int w = 0; w < NW; ++w) a += red[w];
+        return a;
+    };
+
+    // start vector
+    double v0 = mine ? start_component(t) : 0.0;
+    const double nrm0 = sqrt(bsum(v0 * v0));
+    if (mine) V[t] = v0 / nrm0;
+    __syncthreads();
+
+    double gnorm = 0.0, theta = 0.0;
+    int m = 0;
+    for (int j = 0; j < mmax; ++j) {
+        const double *vj = V + (size_t)j * ldv;
+        // w = G v_j
+        double acc[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) acc[r] = 0.0;
+#pragma unroll
+        for (int c = 0; c < CPW; ++c) {
+            const int col = NW * c + wave;
+            const double vc = col < p ? vj[col] : 0.0;
+#pragma unroll
+            for (int r = 0; r < R; ++r) acc[r] += Gr[r][c] * vc;
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) part[wave * 64 * R + lane + 64 * r] = acc[r];
+        __syncthreads();
+        double wt = 0.0;
+        if (mine)
+            for (int w = 0; w < NW; ++w) wt += part[w * 64 * R + t];
+        const double a = bsum(mine ? wt * vj[t] : 0.0);
+        if (t == 0) al[j] = a;
+        gnorm = fmax(gnorm, fabs(a));
+        // full reorthogonalisation against v_0..v_j, repeated once when it
+        // removed most of w
+        double before = bsum(wt * wt);
+        for (int pass = 0; pass < 2; ++pass) {
+            if (mine) ws[t] = wt;
+            __syncthreads();
+            for (int mm = t; mm <= j; mm += NT) {
+                const double *vm = V + (size_t)mm * ldv;
+                double c0 = 0.0, c1 = 0.0;
+                int i = 0;
+                for (; i + 1 < p; i += 2) {
+                    c0 += vm[i] * ws[i];
+                    c1 += vm[i + 1] * ws[i + 1];
+                }
+                if (i < p) c0 += vm[i] * ws[i];
+                coef[mm] = c0 + c1;
+            }
+            __syncthreads();
+            if (mine) {
+                double tv = wt;
+                for (int mm = 0; mm <= j; ++mm) tv -= coef[mm] * V[(size_t)mm * ldv + t];
+                wt = tv;
+            }
+            const double after = bsum(wt * wt);
+            if (after > 0.5 * before) break;
+            before = after;
+        }
+        const double b = sqrt(bsum(wt * wt));
+        if (t == 0) be[j] = b;
+        m = j + 1;
+        const bool invariant = (b <= 1e-14 * fmax(gnorm, 1e-300)) || (m == p);
+        const bool test_now = invariant || (m % 8 == 0) || (m == mmax);
+        if (test_now) {
+            __syncthreads();
+            if (t < kWave) {
+                double lo, hi;
+                tri_top(al, be, m, &lo, &hi);
+                if (t == 0) {
+                    const double th = 0.5 * (lo + hi);
+                    const double shift = hi + (hi - lo) + 1e-13 * fabs(hi) + 1e-300;
+                    const double res = invariant ? 0.0 : tri_residual(al, be, m, shift, b, tx, tw);
+                    s_theta = th;
+                    s_flag = invariant || (res <= 1e-12 * fabs(th));
+                }
+            }
+            __syncthreads();
+            theta = s_theta;
+            if (s_flag) break;
+        }
+        if (mine) V[(size_t)(j + 1) * ldv + t] = wt / b;
+        __syncthreads();
+    }
+    double dval = theta * (1.0 + 1e-10);
+    const bool settled = s_flag;
+    if (!settled) {
+        double gm = 0.0;
+        if (mine)
+            for (int c = 0; c < p; ++c) gm += fabs(G[(size_t)c * p + t]);
+        gm = wave_max(gm);
+        __syncthreads();
+        if (lane == 0) red[wave] = gm;
+        __syncthreads();
+        gm = red[0];
+        for (int w = 1; w < NW; ++w) gm = fmax(gm, red[w]);
+        dval = fmax(dval, gm);
+    }
+    if (t == 0) {
+        d_out[q] = dval;
+        if (steps_out) steps_out[q] = settled ? m : -m;
     }
 }
 
 int launch_lanczos(oem_gram_s *h, hipStream_t s)
 {
     const int p = h->p, nq = (h->K == 1) ? 1 : h->K + 1;
-    const int mmax = std::min(p, 512);
+    if (p <= 128) {
+        const int mmax = p;
+        const int NW = p <= 64 ? 4 : 8, R = p <= 64 ? 1 : 2;
+        const size_t lds = ((size_t)(mmax + 1) * (p + 1) + p + NW * 64 * R + 5 * mmax + 1 + NW) *
+                           sizeof(double);
+        if (p <= 64) {
+            if (lds > 64 * 1024)
+                OEM_HIP_CHECK(hipFuncSetAttribute((const void *)lanczos_reg_kernel<4, 1, 16>,
+                                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+            hipLaunchKernelGGL((lanczos_reg_kernel<4, 1, 16>), dim3(nq), dim3(256), lds, s, p, mmax,
+                               h->Gs.as<double>(), h->dq.as<double>(), h->lzsteps.as<int32_t>());
+        } else {
+            if (lds > 64 * 1024)
+                OEM_HIP_CHECK(hipFuncSetAttribute((const void *)lanczos_reg_kernel<8, 2, 16>,
+                                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+            hipLaunchKernelGGL((lanczos_reg_kernel<8, 2, 16>), dim3(nq), dim3(512), lds, s, p, mmax,
+                               h->Gs.as<double>(), h->dq.as<double>(), h->lzsteps.as<int32_t>());
+        }
+        OEM_HIP_CHECK(hipGetLastError());
+        return OEM_OK;
+    }
+    const int mmax = std::min(p, 1024);
     int rc = h->lanczos.ensure((size_t)nq * (mmax + 1) * p * sizeof(double));
     if (rc) return rc;
     const size_t lds = (size_t)(p + 5 * mmax + 1 + kLzWaves + 4) * sizeof(double);

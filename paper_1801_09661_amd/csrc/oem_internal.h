@@ -115,7 +115,7 @@ struct oem_gram_s {
     std::vector<int32_t> lz_host;      // Lanczos steps (negative: not converged)
     int64_t rows_seen = 0;
     // workspaces
-    oem::DevBuf partial, partial_n, lanczos, paths, lam, betaw, groupbuf, cvw, flag;
+    oem::DevBuf partial, partial_n, lanczos, paths, order, lam, betaw, groupbuf, cvw, flag;
 };
 
 namespace oem {
@@ -131,7 +131,8 @@ int launch_lanczos(oem_gram_s *g, hipStream_t s);
 int launch_lambda_grid(const double *cs_full, int p, const int32_t *gstart, const int32_t *gidx,
                        int ngroups, const double *w, const double *cg, const oem_penalty *d_pens,
                        int npen, int L, double ratio, double *lambda_out, hipStream_t s);
-int launch_paths(const PathDesc *d_desc, int npaths, int max_p, hipStream_t s);
+int launch_paths(const PathDesc *d_desc, const std::vector<int> &path_p, DevBuf &orderbuf,
+                 hipStream_t s);
 int launch_cv(const double *Gk, const double *bk, const double *yyk, const int64_t *nk,
               int K, int p, int npen, int L, const double *beta_folds, double *mse,
               double *cvm, double *cvsd, int32_t *i_min, int32_t *i_1se, int32_t *best,

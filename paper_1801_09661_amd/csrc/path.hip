@@ -9,84 +9,9 @@
 // independent, so paths of different problems and sizes share one launch.
 #include <algorithm>
 
-#include "oem_internal.h"
+#include "path_common.h"
 
 namespace oem {
-
-constexpr int kPathThreads = 256;
-constexpr int kPathWaves = kPathThreads / kWave;
-
-// ---------------------------------------------------------------- updates
-
-__device__ inline double sgn(double v) { return v > 0.0 ? 1.0 : (v < 0.0 ? -1.0 : 0.0); }
-__device__ inline double pos(double v) { return v > 0.0 ? v : 0.0; }
-
-// Scalar thresholding operators of Section 2.2 (lam_w = w_j * lambda).
-__device__ inline double update1(int kind, double u, double lam_w, double d, double alpha,
-                                 double gamma)
-{
-    const double au = fabs(u);
-    switch (kind) {
-    case OEM_LASSO:  // S(u, w lambda, d)
-        return sgn(u) * pos(au - lam_w) / d;
-    case OEM_ENET:
-        return sgn(u) * pos(au - lam_w * alpha) / (d + lam_w * (1.0 - alpha));
-    case OEM_MCP:    // M(u, w lambda, gamma, d)
-        if (au <= lam_w * gamma * d) return sgn(u) * gamma * pos(au - lam_w) / (gamma * d - 1.0);
-        return u / d;
-    case OEM_SCAD:   // C(u, w lambda, gamma, d)
-        if (au <= (d + 1.0) * lam_w) return sgn(u) * pos(au - lam_w) / d;
-        if (au <= lam_w * gamma * d)
-            return sgn(u) * ((gamma - 1.0) * au - lam_w * gamma) / ((gamma - 1.0) * d - 1.0);
-        return u / d;
-    default:
-        return 0.0;
-    }
-}
-
-// derivative of the penalty at |b| > 0 (for the stationarity check)
-__device__ inline double pen_deriv(int kind, double ab, double lw, double alpha, double gamma)
-{
-    switch (kind) {
-    case OEM_LASSO: return lw;
-    case OEM_ENET: return alpha * lw + (1.0 - alpha) * lw * ab;
-    case OEM_MCP: return pos(lw - ab / gamma);
-    case OEM_SCAD:
-        if (ab <= lw) return lw;
-        if (ab <= gamma * lw) return (gamma * lw - ab) / (gamma - 1.0);
-        return 0.0;
-    default: return 0.0;
-    }
-}
-
-__device__ inline double pen_value(int kind, double b, double lw, double alpha, double gamma)
-{
-    const double ab = fabs(b);
-    switch (kind) {
-    case OEM_LASSO: return lw * ab;
-    case OEM_ENET: return alpha * lw * ab + 0.5 * (1.0 - alpha) * lw * b * b;
-    case OEM_MCP: return ab <= gamma * lw ? lw * ab - b * b / (2.0 * gamma) : 0.5 * gamma * lw * lw;
-    case OEM_SCAD:
-        if (ab <= lw) return lw * ab;
-        if (ab <= gamma * lw) return -(ab * ab - 2.0 * gamma * lw * ab + lw * lw) / (2.0 * (gamma - 1.0));
-        return 0.5 * (gamma + 1.0) * lw * lw;
-    default: return 0.0;
-    }
-}
-
-// ---------------------------------------------------------------- reductions
-
-__device__ inline double wave_max(double v)
-{
-    for (int o = kWave / 2; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
-    return v;
-}
-
-__device__ inline double wave_sum(double v)
-{
-    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return v;
-}
 
 // ---------------------------------------------------------------- lambda grid
 
@@ -193,10 +118,11 @@ __device__ inline int rebuild_active(const PathLds &S, int p)
 }
 
 __global__ __launch_bounds__(kPathThreads) void path_kernel(const PathDesc *__restrict__ descs,
+                                                            const int *__restrict__ order,
                                                             int lds_g_max_p)
 {
     extern __shared__ double sm[];
-    const PathDesc P = descs[blockIdx.x];
+    const PathDesc P = descs[order[blockIdx.x]];
     const int p = P.p;
     const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
     PathLds S;
@@ -366,21 +292,54 @@ size_t path_lds_bytes(int p, bool g_in_lds)
     return doubles * sizeof(double);
 }
 
-int launch_paths(const PathDesc *d_desc, int npaths, int max_p, hipStream_t s)
+int launch_paths_reg(const PathDesc *d_desc, const int *d_order, int count, int pmax,
+                     hipStream_t s);
+
+// Paths go to the register kernel when p <= 128, otherwise to the general
+// kernel (G in LDS when it fits, else streamed from L2).
+int launch_paths(const PathDesc *d_desc, const std::vector<int> &path_p, DevBuf &orderbuf,
+                 hipStream_t s)
 {
+    const int npaths = (int)path_p.size();
     if (npaths == 0) return OEM_OK;
+    std::vector<int> small, mid, big;
+    int pmax_big = 0;
+    for (int i = 0; i < npaths; ++i) {
+        if (path_p[i] <= 64) small.push_back(i);
+        else if (path_p[i] <= 128) mid.push_back(i);
+        else {
+            big.push_back(i);
+            pmax_big = std::max(pmax_big, path_p[i]);
+        }
+    }
+    std::vector<int> order;
+    order.insert(order.end(), small.begin(), small.end());
+    order.insert(order.end(), mid.begin(), mid.end());
+    order.insert(order.end(), big.begin(), big.end());
+    int rc = orderbuf.ensure(order.size() * sizeof(int));
+    if (rc) return rc;
+    OEM_HIP_CHECK(hipMemcpyAsync(orderbuf.ptr, order.data(), order.size() * sizeof(int),
+                                 hipMemcpyHostToDevice, s));
+    OEM_HIP_CHECK(hipStreamSynchronize(s));
+    const int *d_order = orderbuf.as<int>();
+    rc = launch_paths_reg(d_desc, d_order, (int)small.size(), 64, s);
+    if (rc) return rc;
+    rc = launch_paths_reg(d_desc, d_order + small.size(), (int)mid.size(), 128, s);
+    if (rc) return rc;
+    if (big.empty()) return OEM_OK;
     // keep G in LDS when the largest path's matrix fits next to its vectors
     const size_t limit = 150 * 1024;
     int lds_g_max_p = 0;
-    size_t lds = path_lds_bytes(max_p, false);
-    if (path_lds_bytes(max_p, true) <= limit) {
-        lds_g_max_p = max_p;
-        lds = path_lds_bytes(max_p, true);
+    size_t lds = path_lds_bytes(pmax_big, false);
+    if (path_lds_bytes(pmax_big, true) <= limit) {
+        lds_g_max_p = pmax_big;
+        lds = path_lds_bytes(pmax_big, true);
     }
     if (lds > 64 * 1024)
         OEM_HIP_CHECK(hipFuncSetAttribute((const void *)path_kernel,
                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    hipLaunchKernelGGL(path_kernel, dim3(npaths), dim3(kPathThreads), lds, s, d_desc, lds_g_max_p);
+    hipLaunchKernelGGL(path_kernel, dim3((int)big.size()), dim3(kPathThreads), lds, s, d_desc,
+                       d_order + small.size() + mid.size(), lds_g_max_p);
     OEM_HIP_CHECK(hipGetLastError());
     return OEM_OK;
 }

@@ -1,0 +1,109 @@
+// Device helpers shared by the path kernels: the thresholding operators of
+// Section 2.2, penalty values and derivatives, wave reductions.
+#pragma once
+
+#include "oem_internal.h"
+
+namespace oem {
+
+constexpr int kPathThreads = 256;
+constexpr int kPathWaves = kPathThreads / kWave;
+
+// ---------------------------------------------------------------- updates
+
+__device__ inline double sgn(double v) { return v > 0.0 ? 1.0 : (v < 0.0 ? -1.0 : 0.0); }
+__device__ inline double pos(double v) { return v > 0.0 ? v : 0.0; }
+
+// Scalar thresholding operators of Section 2.2 (lam_w = w_j * lambda).
+__device__ inline double update1(int kind, double u, double lam_w, double d, double alpha,
+                                 double gamma)
+{
+    const double au = fabs(u);
+    switch (kind) {
+    case OEM_LASSO:  // S(u, w lambda, d)
+        return sgn(u) * pos(au - lam_w) / d;
+    case OEM_ENET:
+        return sgn(u) * pos(au - lam_w * alpha) / (d + lam_w * (1.0 - alpha));
+    case OEM_MCP:    // M(u, w lambda, gamma, d)
+        if (au <= lam_w * gamma * d) return sgn(u) * gamma * pos(au - lam_w) / (gamma * d - 1.0);
+        return u / d;
+    case OEM_SCAD:   // C(u, w lambda, gamma, d)
+        if (au <= (d + 1.0) * lam_w) return sgn(u) * pos(au - lam_w) / d;
+        if (au <= lam_w * gamma * d)
+            return sgn(u) * ((gamma - 1.0) * au - lam_w * gamma) / ((gamma - 1.0) * d - 1.0);
+        return u / d;
+    default:
+        return 0.0;
+    }
+}
+
+// derivative of the penalty at |b| > 0 (for the stationarity check)
+__device__ inline double pen_deriv(int kind, double ab, double lw, double alpha, double gamma)
+{
+    switch (kind) {
+    case OEM_LASSO: return lw;
+    case OEM_ENET: return alpha * lw + (1.0 - alpha) * lw * ab;
+    case OEM_MCP: return pos(lw - ab / gamma);
+    case OEM_SCAD:
+        if (ab <= lw) return lw;
+        if (ab <= gamma * lw) return (gamma * lw - ab) / (gamma - 1.0);
+        return 0.0;
+    default: return 0.0;
+    }
+}
+
+__device__ inline double pen_value(int kind, double b, double lw, double alpha, double gamma)
+{
+    const double ab = fabs(b);
+    switch (kind) {
+    case OEM_LASSO: return lw * ab;
+    case OEM_ENET: return alpha * lw * ab + 0.5 * (1.0 - alpha) * lw * b * b;
+    case OEM_MCP: return ab <= gamma * lw ? lw * ab - b * b / (2.0 * gamma) : 0.5 * gamma * lw * lw;
+    case OEM_SCAD:
+        if (ab <= lw) return lw * ab;
+        if (ab <= gamma * lw) return -(ab * ab - 2.0 * gamma * lw * ab + lw * lw) / (2.0 * (gamma - 1.0));
+        return 0.5 * (gamma + 1.0) * lw * lw;
+    default: return 0.0;
+    }
+}
+
+// ---------------------------------------------------------------- reductions
+
+// Cross-lane moves with DPP (a 64-bit value moves as two 32-bit halves).
+template <int CTRL> __device__ inline double dpp_mov(double v)
+{
+    int lo = __double2loint(v), hi = __double2hiint(v);
+    lo = __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xF, 0xF, false);
+    hi = __builtin_amdgcn_update_dpp(0, hi, CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ inline double readlane_d(double v, int l)
+{
+    int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+    int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+    return __hiloint2double(hi, lo);
+}
+
+// Wave-wide max / sum: butterfly inside each 16-lane row (quad_perm xor 1,
+// xor 2, row rotate 4, 8), then the four row results read out lane by lane.
+// The result is the same value in every lane.
+__device__ inline double wave_max(double v)
+{
+    v = fmax(v, dpp_mov<0xB1>(v));
+    v = fmax(v, dpp_mov<0x4E>(v));
+    v = fmax(v, dpp_mov<0x124>(v));
+    v = fmax(v, dpp_mov<0x128>(v));
+    return fmax(fmax(readlane_d(v, 0), readlane_d(v, 16)), fmax(readlane_d(v, 32), readlane_d(v, 48)));
+}
+
+__device__ inline double wave_sum(double v)
+{
+    v = v + dpp_mov<0xB1>(v);
+    v = v + dpp_mov<0x4E>(v);
+    v = v + dpp_mov<0x124>(v);
+    v = v + dpp_mov<0x128>(v);
+    return (readlane_d(v, 0) + readlane_d(v, 16)) + (readlane_d(v, 32) + readlane_d(v, 48));
+}
+
+} // namespace oem

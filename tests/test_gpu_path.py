@@ -173,3 +173,20 @@ def test_cv_equals_naive_refits():
         r = oem.fit(_cuda(Xt), _cuda(pr.y[f != k]), ["lasso"], nlambda=15, lambdas=lam, tol=TOL)
         _assert_paths(res["beta_folds"].cpu().numpy()[k], r["beta"].cpu().numpy(), tol=1e-9,
                       what=f"naive fold {k}")
+
+
+@pytest.mark.parametrize("p,rho,corr", [(1, 0.0, "ar1"), (5, 0.3, "ar1"), (64, -0.6, "ar1"),
+                                        (100, 0.5, "ar1"), (128, 0.25, "cs"), (129, -0.4, "ar1"),
+                                        (300, 0.3, "ar1")])
+def test_d_matches_jacobi(p, rho, corr):
+    """d = lambda_1(Gs)(1 + 1e-10) from Lanczos agrees with the oracle's Jacobi."""
+    oem = _oem()
+    n = 4000 + 20 * p
+    print(f"case: d p={p} rho={rho} {corr}", flush=True)
+    X = workloads.draw_rows(n, p, rho, np.float32, workloads.subseed(300, p), correlation=corr)
+    y = workloads.response(X, np.ones(p) / p, 1.0, workloads.subseed(301, p))
+    res = oem.fit(_cuda(X), _cuda(y), ["lasso"], nlambda=1)
+    G, b, yy, nn = oracle.gram_train(X, y, -1)
+    st = oracle.prepare(G, b, yy, nn)
+    d_ref = oracle.oem_d(st["Gs"])
+    assert abs(res["d"].item() - d_ref) <= 1e-12 * d_ref
