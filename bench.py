@@ -9,7 +9,8 @@ penalties lasso, elastic net (alpha 0.5), MCP (gamma 3), SCAD (gamma 3.7);
 A step is: reset the statistics, one streaming Gram pass over the 400 MB of X
 (already resident in HBM), standardisation, d, lambda grids and the four
 warm-started paths.  value = lambda-path fits per second of whole steps
-(4 fits per step).  Prints one JSON line.
+(4 fits per step) in the chosen (mixed: split-BF16 Gram) form; the plain FP64
+form is timed the same way and reported beside it.  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -39,7 +40,7 @@ def parse():
     ap.add_argument("--n", type=int, default=1_000_000)
     ap.add_argument("--p", type=int, default=100)
     ap.add_argument("--nlambda", type=int, default=100)
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "split_bf16", "bf16"])
+    ap.add_argument("--precision", default="split_bf16", choices=["fp64", "split_bf16", "bf16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-rows", type=int, default=100_000)
     ap.add_argument("--profile-steps", type=int, default=0,
@@ -71,6 +72,61 @@ def cpu_baseline(pr, nlambda, sample_rows):
                 seconds_per_step=t_full)
 
 
+def run_form(oem, torch, X, y, precision, steps, warm, nlambda):
+    """Time `steps` whole steps of one precision form; then phase split."""
+    import numpy as np
+    n, p = X.shape
+    g = oem.Gram(p, 1, precision, X.dtype)
+    stream = torch.cuda.current_stream()
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+
+    def step(record=None):
+        oem.oem_gram_reset(g.h)
+        if record is not None:
+            record[0].record(stream)
+        g.add(X, y)
+        if record is not None:
+            record[1].record(stream)
+        res = g.fit_path(PENALTIES, nlambda=nlambda, lambda_min_ratio=1e-3, tol=1e-10,
+                         maxit=100000, sync=False)
+        if record is not None:
+            record[2].record(stream)
+        return res
+
+    for _ in range(warm):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        res = step()
+    torch.cuda.synchronize()
+    t_steps = time.perf_counter() - t0
+
+    gram_ms, fit_ms = [], []
+    for _ in range(3):
+        rec = [ev(), ev(), ev()]
+        res = step(rec)
+        torch.cuda.synchronize()
+        gram_ms.append(rec[0].elapsed_time(rec[1]))
+        fit_ms.append(rec[1].elapsed_time(rec[2]))
+    # Gram pass alone, back to back: average launch duration of the pass
+    reps = 20
+    a, b = ev(), ev()
+    a.record(stream)
+    for _ in range(reps):
+        g.add(X, y)
+    b.record(stream)
+    torch.cuda.synchronize()
+    gram_only_ms = a.elapsed_time(b) / reps
+    iters = res["iters"].cpu().numpy()
+    beta = res["beta"].cpu().numpy()
+    g.close()
+    return dict(t_steps=t_steps, ms_per_step=1e3 * t_steps / steps,
+                fits_per_s=len(PENALTIES) * steps / t_steps, gram_ms=float(np.mean(gram_ms)),
+                fit_ms=float(np.mean(fit_ms)), gram_only_ms=gram_only_ms,
+                updates=int(np.abs(iters).sum()), beta=beta)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -84,102 +140,68 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     oem.load_library()
-    t_gen = time.perf_counter()
     pr = workloads.tall_multi(n=args.n, p=args.p)
-    t_gen = time.perf_counter() - t_gen
     X = torch.from_numpy(pr.X).cuda()
     y = torch.from_numpy(pr.y).cuda()
     n, p = X.shape
     torch.cuda.synchronize()
 
-    g = oem.Gram(p, 1, args.precision, X.dtype)
-    stream = torch.cuda.current_stream()
-    ev = lambda: torch.cuda.Event(enable_timing=True)
-
-    def step(record=None):
-        oem.oem_gram_reset(g.h)
-        if record is not None:
-            record[0].record(stream)
-        g.add(X, y)
-        if record is not None:
-            record[1].record(stream)
-        res = g.fit_path(PENALTIES, nlambda=args.nlambda, lambda_min_ratio=1e-3, tol=1e-10,
-                         maxit=100000, sync=False)
-        if record is not None:
-            record[2].record(stream)
-        return res
-
     steps = args.profile_steps or args.steps
     warm = 0 if args.profile_steps else args.warmup
-    for _ in range(warm):
-        step()
-    torch.cuda.synchronize()
+    forms = [args.precision] if args.profile_steps else [args.precision, "fp64"]
+    if args.precision == "fp64" and not args.profile_steps:
+        forms = ["fp64"]
+    runs = {f: run_form(oem, torch, X, y, f, steps, warm, args.nlambda) for f in forms}
+    main_run = runs[args.precision]
 
-    # timed region: exactly `steps` whole steps
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        res = step()
-    torch.cuda.synchronize()
-    t_steps = time.perf_counter() - t0
-    ms_per_step = 1e3 * t_steps / steps
-    fits_per_s = len(PENALTIES) / (t_steps / steps)
-
-    # phase split with events on the launch stream (separate, untimed above)
-    gram_ms, fit_ms = [], []
-    for _ in range(max(3, min(steps, 5))):
-        rec = [ev(), ev(), ev()]
-        res = step(rec)
-        torch.cuda.synchronize()
-        gram_ms.append(rec[0].elapsed_time(rec[1]))
-        fit_ms.append(rec[1].elapsed_time(rec[2]))
-    gram_ms = float(np.mean(gram_ms))
-    fit_ms = float(np.mean(fit_ms))
-    iters = res["iters"].cpu().numpy()
-    total_iters = int(np.abs(iters).sum())
-    x_bytes = n * p * X.element_size()
-    gram_gbs = x_bytes / (gram_ms * 1e-3) / 1e9
-    path_flops = 2.0 * p * p * total_iters
-    path_tflops = path_flops / (fit_ms * 1e-3) / 1e12
-
-    if gram_ms >= fit_ms:
-        roof = dict(bound="hbm", kernel="gram_f64_kernel+gram_reduce_kernel", achieved=gram_gbs,
-                    peak=HBM_PEAK_GBS, unit="GB/s", frac=gram_gbs / HBM_PEAK_GBS, traffic=None,
-                    algorithmic=f"{x_bytes} B of X per launch")
-    else:
-        roof = dict(bound="alu", kernel="path_kernel (+derive, lambda grid)", achieved=path_tflops,
-                    peak=FP64_PEAK_TFLOPS, unit="TFLOP/s", frac=path_tflops / FP64_PEAK_TFLOPS,
-                    traffic=None,
-                    algorithmic=f"2 p^2 flops x {total_iters} OEM updates per launch")
-
+    x_bytes = n * p * X.element_size() + n * 8   # X and y, read once
+    gram_gbs = x_bytes / (main_run["gram_only_ms"] * 1e-3) / 1e9
+    path_flops = 2.0 * p * p * main_run["updates"]
+    path_tflops = path_flops / (main_run["fit_ms"] * 1e-3) / 1e12
+    gram_roof = dict(bound="hbm", kernel="gram pass (gram kernel + fixed-order reduction)",
+                     achieved=gram_gbs, peak=HBM_PEAK_GBS, unit="GB/s", frac=gram_gbs / HBM_PEAK_GBS,
+                     traffic=None, algorithmic=f"{x_bytes} B of X and y per launch")
+    path_roof = dict(bound="alu", kernel="path kernel (+ combine, Lanczos d, lambda grid)",
+                     achieved=path_tflops, peak=FP64_PEAK_TFLOPS, unit="TFLOP/s",
+                     frac=path_tflops / FP64_PEAK_TFLOPS, traffic=None,
+                     algorithmic=f"2 p^2 flops x {main_run['updates']} OEM updates per launch")
+    dominant = gram_roof if main_run["gram_ms"] >= main_run["fit_ms"] else path_roof
     out = {
         "metric": METRIC,
-        "value": fits_per_s,
+        "value": main_run["fits_per_s"],
         "unit": "fits/s",
         "n_gpus": 1,
         "steps": steps,
         "warmup": warm,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": main_run["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else args.precision,
+        "dtype": {"fp64": "f64", "split_bf16": "split-bf16 Gram (f32 acc, f64 reduce) + f64 paths",
+                  "bf16": "bf16 Gram (f32 acc, f64 reduce) + f64 paths"}[args.precision],
         "data": "synthetic",
         "config": {"workload": "tall_multi: n=1e6 p=100 AR(1) rho=0.5 FP32 X, lasso+enet+MCP+SCAD, "
-                               "100 lambdas each, tol 1e-10", "n": n, "p": p,
-                   "penalties": 4, "nlambda": args.nlambda, "precision": args.precision,
-                   "parallelism": "single GPU"},
-        "gram_ms": gram_ms,
+                               "100 lambdas each, tol 1e-10", "n": n, "p": p, "penalties": 4,
+                   "nlambda": args.nlambda, "precision": args.precision},
+        "gram_ms_in_step": main_run["gram_ms"],
+        "fit_ms_in_step": main_run["fit_ms"],
         "gram_gbps": gram_gbs,
-        "fit_ms": fit_ms,
-        "oem_updates": total_iters,
-        "x_gbps_end_to_end": x_bytes / (t_steps / steps) / 1e9,
-        "roofline": roof,
+        "oem_updates": main_run["updates"],
+        "roofline": dominant,
+        "gram_roofline": gram_roof,
     }
+    if "fp64" in runs and args.precision != "fp64":
+        f64 = runs["fp64"]
+        out["fp64_form"] = dict(fits_per_s=f64["fits_per_s"], ms_per_step=f64["ms_per_step"],
+                                gram_gbps=x_bytes / (f64["gram_only_ms"] * 1e-3) / 1e9,
+                                gram_ms_in_step=f64["gram_ms"], fit_ms_in_step=f64["fit_ms"])
+        out["mixed_vs_fp64_fits"] = main_run["fits_per_s"] / f64["fits_per_s"]
+        bm, bf = main_run["beta"], f64["beta"]
+        scale = np.maximum(np.abs(bf).max(axis=2), 1e-300)
+        out["mixed_coef_err_vs_fp64_form"] = float((np.abs(bm - bf).max(axis=2) / scale)[:, 1:].max())
     if not args.no_cpu_baseline and not args.profile_steps:
         out["cpu_baseline"] = cpu_baseline(pr, args.nlambda, min(args.cpu_sample_rows, n))
     print(json.dumps(out))
-    g.close()
 
 
 if __name__ == "__main__":

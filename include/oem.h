@@ -127,9 +127,12 @@ int oem_gram_reset(oem_handle g, void *stream);
  *     yy_k += sum y_i^2,                   n_k += |{i in fold k}|.
  * row_offset: global index of row 0 (the fold hash uses global indices, so
  * successive blocks of one data set keep their folds).  foldid: NULL (use
- * the hash) or a device array of n fold ids < nfolds.  n = 0 is a no-op.
- * X and y are not referenced after the work completes.  Errors: OEM_E_INVAL
- * (NULL X or y with n > 0, ldx < p, n < 0), OEM_E_HIP. */
+ * the hash) or a device array of n fold ids; rows whose id is >= nfolds are
+ * skipped.  n = 0 is a no-op; one call takes at most 2^31 - 1 rows (pass
+ * larger data sets as successive blocks).  X and y are not referenced after
+ * the work completes.  The BF16 forms take FP32 X only.  Errors: OEM_E_INVAL
+ * (NULL X or y with n > 0, ldx < p, n < 0 or too large, FP64 X with a BF16
+ * form), OEM_E_HIP. */
 int oem_gram(oem_handle g, const void *X, int64_t n, int64_t ldx, const double *y,
              int64_t row_offset, const uint8_t *foldid, void *stream);
 

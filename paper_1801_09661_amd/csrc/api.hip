@@ -327,7 +327,7 @@ void oem_gram_free(oem_handle h)
     if (!h) return;
     (void)hipDeviceSynchronize();
     for (DevBuf *b : {&h->Gk, &h->bk, &h->yyk, &h->nk, &h->Gs, &h->Gs32, &h->cs, &h->sc, &h->yyn,
-                      &h->dq, &h->ntrain, &h->lzsteps, &h->partial, &h->partial_n, &h->lanczos,
+                      &h->dq, &h->ntrain, &h->lzsteps, &h->partial, &h->partial_n, &h->rowlist, &h->redtmp, &h->lanczos,
                       &h->paths, &h->order, &h->lam, &h->betaw, &h->groupbuf, &h->cvw, &h->flag})
         b->release();
     delete h;
@@ -351,7 +351,7 @@ int oem_gram(oem_handle h, const void *X, int64_t n, int64_t ldx, const double *
              int64_t row_offset, const uint8_t *foldid, void *stream)
 {
     if (!h) return fail(OEM_E_INVAL, "handle is NULL");
-    if (n < 0) return fail(OEM_E_INVAL, "n must be >= 0");
+    if (n < 0 || n > INT32_MAX) return fail(OEM_E_INVAL, "n must be in [0, 2^31 - 1]");
     if (n == 0) return OEM_OK;
     if (!X || !y) return fail(OEM_E_INVAL, "X and y must not be NULL");
     if (ldx < h->p) return fail(OEM_E_INVAL, "ldx must be >= p");

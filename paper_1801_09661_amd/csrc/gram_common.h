@@ -1,0 +1,98 @@
+// Pieces shared by the Gram kernels: block numbering, row lists per
+// (fold, split), and the fixed-order two-stage reduction of partial sums.
+#pragma once
+
+#include <algorithm>
+
+#include "oem_internal.h"
+
+namespace oem {
+
+// Logical block index: consecutive logical ids land on the same XCD under
+// round-robin dispatch of hardware block ids over the 8 XCDs, so blocks that
+// read the same rows share that XCD's L2.
+__device__ inline int xcd_logical(int bid, int nb)
+{
+    const int nx = 8;
+    int per = (nb + nx - 1) / nx;
+    int full = (nb % nx == 0) ? nx : nb % nx;
+    int x = bid % nx, local = bid / nx;
+    if (x < full) return x * per + local;
+    return full * per + (x - full) * (per - 1) + local;
+}
+
+// Row-major numbering of the upper triangle of T x T tiles.
+__host__ __device__ inline int tile_pair_index(int ti, int tj, int T)
+{
+    return ti * T - (ti * (ti - 1)) / 2 + (tj - ti);
+}
+
+__device__ inline void tile_pair_decode(int tp, int T, int &ti, int &tj)
+{
+    int t = tp;
+    for (ti = 0; ti < T; ++ti) {
+        const int cnt = T - ti;
+        if (t < cnt) {
+            tj = ti + t;
+            return;
+        }
+        t -= cnt;
+    }
+}
+
+// (I, J), I <= J, of super-block pair q in row-major upper-triangle order.
+__device__ inline void sb_pair_decode(int q, int nsb, int &I, int &J)
+{
+    int qq = q;
+    for (I = 0; I < nsb; ++I) {
+        const int cnt = nsb - I;
+        if (qq < cnt) {
+            J = I + qq;
+            return;
+        }
+        qq -= cnt;
+    }
+}
+
+// Rows a workgroup streams: with one fold, the contiguous rows of its split;
+// with several folds, the ordered list of its split's rows in its fold.
+struct RowSource {
+    const int32_t *list;     // K x (rows), segment (k, s) at off[k * S + s]
+    const int64_t *off;      // K * S
+    const int32_t *cnt;      // K * S
+};
+
+__device__ inline void rows_of(const GramGeom &g, const RowSource &rs, int64_t n, int k, int s,
+                               int64_t &first, int64_t &count, const int32_t *&list)
+{
+    if (g.K == 1) {
+        first = (int64_t)s * g.rows_per_split;
+        const int64_t last = min(n, first + g.rows_per_split);
+        count = last > first ? last - first : 0;
+        list = nullptr;
+    } else {
+        const size_t i = (size_t)k * g.nsplit + s;
+        first = 0;
+        count = rs.cnt[i];
+        list = rs.list + rs.off[i];
+    }
+}
+
+__device__ inline int64_t row_at(int64_t first, const int32_t *list, int64_t i)
+{
+    return list ? (int64_t)list[i] : first + i;
+}
+
+// ---- host-side launchers (gram_common.hip) ----
+// Build per-(fold, split) ordered row lists for rows 0..n-1.
+int build_row_lists(oem_gram_s *h, const GramGeom &g, int64_t n, int64_t row_offset,
+                    const uint8_t *foldid, RowSource &rs, hipStream_t s);
+// out[k][e] (+)= sum over s (in order) of src[k][s][e], FP32 or FP64 source,
+// in two fixed-order stages; `accumulate` adds into out.
+int reduce_splits_f32(const float *src, int K, int S, size_t E, double *tmp, double *out,
+                      hipStream_t s);
+int reduce_splits_f64(const double *src, int K, int S, size_t E, double *tmp, double *out,
+                      hipStream_t s);
+size_t reduce_tmp_doubles(int K, int S, size_t E);
+
+} // namespace oem

@@ -115,7 +115,7 @@ struct oem_gram_s {
     std::vector<int32_t> lz_host;      // Lanczos steps (negative: not converged)
     int64_t rows_seen = 0;
     // workspaces
-    oem::DevBuf partial, partial_n, lanczos, paths, order, lam, betaw, groupbuf, cvw, flag;
+    oem::DevBuf partial, partial_n, rowlist, redtmp, lanczos, paths, order, lam, betaw, groupbuf, cvw, flag;
 };
 
 namespace oem {
@@ -126,6 +126,8 @@ int launch_fill_i64(int64_t *p, size_t n, int64_t v, hipStream_t s);
 int launch_scale_f64(double *p, size_t n, double v, hipStream_t s);
 int launch_gram(oem_gram_s *g, const void *X, int64_t n, int64_t ldx, const double *y,
                 int64_t row_offset, const uint8_t *foldid, hipStream_t s);
+int launch_gram_bf16(oem_gram_s *g, const void *X, int64_t n, int64_t ldx, const double *y,
+                     int64_t row_offset, const uint8_t *foldid, hipStream_t s);
 int launch_combine(oem_gram_s *g, int standardize, hipStream_t s);
 int launch_lanczos(oem_gram_s *g, hipStream_t s);
 int launch_lambda_grid(const double *cs_full, int p, const int32_t *gstart, const int32_t *gidx,

@@ -15,12 +15,12 @@ def _oem():
     return oem
 
 
-def _gram(X, y, K=1, seed=0, foldid=None, blocks=None, dtype=None):
+def _gram(X, y, K=1, seed=0, foldid=None, blocks=None, precision="fp64"):
     oem = _oem()
     Xd = torch.from_numpy(np.ascontiguousarray(X)).cuda()
     yd = torch.from_numpy(y).cuda()
     fd = None if foldid is None else torch.from_numpy(foldid).cuda()
-    with oem.Gram(X.shape[1], K, "fp64", Xd.dtype, seed) as g:
+    with oem.Gram(X.shape[1], K, precision, Xd.dtype, seed) as g:
         if blocks is None:
             g.add(Xd, yd, foldid=fd)
         else:
@@ -122,3 +122,44 @@ def test_deterministic_repeat():
     b = _gram(X, y, 3, 5)
     for u, v in zip(a, b):
         assert np.array_equal(u, v)
+
+
+# ---------------------------------------------------------------- BF16 forms
+# Integer X in [-8, 8] is exact in BF16 (hi = x, lo = 0) and every partial
+# sum here stays far below 2^24, so the mixed forms must also be bit-exact.
+
+@pytest.mark.parametrize("precision", ["split_bf16", "bf16"])
+@pytest.mark.parametrize("p,K", [(1, 1), (20, 1), (32, 1), (33, 1), (100, 1), (128, 1), (129, 1),
+                                 (300, 1), (50, 10), (161, 4)])
+def test_integer_gram_bit_exact_bf16(precision, p, K):
+    n = 5003
+    print(f"case: integer gram {precision} n={n} p={p} K={K}", flush=True)
+    X = workloads.integer_rows(n, p)
+    y = workloads.integer_response(n)
+    G, b, yy, nk = _gram(X, y, K, 17, precision=precision)
+    Go, bo, yyo, nko = oracle.gram_folds(X, y, K, 17)
+    assert np.array_equal(nk, nko)
+    assert np.array_equal(G, Go) and np.array_equal(b, bo) and np.array_equal(yy, yyo)
+
+
+@pytest.mark.parametrize("precision,bound", [("split_bf16", 2e-6), ("bf16", 2e-2)])
+@pytest.mark.parametrize("n,p,rho", [(200_000, 100, 0.5), (60_000, 257, 0.3)])
+def test_random_gram_bf16_error(precision, bound, n, p, rho):
+    """Entry error relative to sum_i |x_i||x_j|: split-BF16 carries ~2^-16 per
+    product plus FP32 accumulation within a row split; single BF16 ~2^-8.
+    The diagonal, X^T y and y^T y are FP64 in both forms."""
+    print(f"case: random gram {precision} n={n} p={p}", flush=True)
+    X = workloads.draw_rows(n, p, rho, np.float32, workloads.subseed(81, p))
+    y = workloads.response(X, np.ones(p) / p, 1.0, workloads.subseed(82, p))
+    G, b, yy, nk = _gram(X, y, precision=precision)
+    Go, bo, yyo, _ = oracle.gram_folds(X, y, 1)
+    A = np.abs(X.astype(np.float64))
+    scale = A.T @ A
+    rel = np.abs(G[0] - Go[0]) / scale
+    print(f"  max entry error / sum|x_i x_j| = {rel.max():.3e}")
+    assert rel.max() <= bound
+    gamma_n = 2 * n * 2.0 ** -53
+    assert np.all(np.abs(np.diag(G[0]) - np.diag(Go[0])) <= gamma_n * np.diag(scale))
+    assert np.all(np.abs(b[0] - bo[0]) <= gamma_n * (A.T @ np.abs(y)))
+    assert abs(yy[0] - yyo[0]) <= gamma_n * yyo[0]
+    assert np.array_equal(G[0], G[0].T)

@@ -190,3 +190,24 @@ def test_d_matches_jacobi(p, rho, corr):
     st = oracle.prepare(G, b, yy, nn)
     d_ref = oracle.oem_d(st["Gs"])
     assert abs(res["d"].item() - d_ref) <= 1e-12 * d_ref
+
+
+@pytest.mark.parametrize("precision", ["split_bf16"])
+def test_mixed_gram_paths_within_1e6(precision):
+    """Paths on the split-BF16 Gram match the FP64 oracle to 1e-6 relative."""
+    oem = _oem()
+    print(f"case: mixed gram paths {precision}", flush=True)
+    pr = workloads.tall_multi(n=200_000, p=100, seed_tag=220)
+    pens = [dict(kind="lasso"), dict(kind="enet", alpha=0.5), dict(kind="mcp", gamma=3.0),
+            dict(kind="scad", gamma=3.7)]
+    ref = oracle.fit(pr.X, pr.y, pens, nlambda=30, tol=TOL)
+    res = oem.fit(_cuda(pr.X), _cuda(pr.y), pens, precision=precision, nlambda=30, tol=TOL,
+                  lambdas=ref["lambda"])
+    b = res["beta"].cpu().numpy()
+    worst = 0.0
+    for q in range(4):
+        for l in range(1, 30):
+            r = ref["beta"][q, l]
+            worst = max(worst, np.abs(b[q, l] - r).max() / np.abs(r).max())
+    print(f"  worst coefficient error {worst:.3e}")
+    assert worst <= 1e-6
