@@ -45,7 +45,42 @@ def parse():
     ap.add_argument("--cpu-sample-rows", type=int, default=100_000)
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="run only this many steps (for profilers) and skip the baseline")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="after the steps, copy X once with a plain device copy (traffic calibration)")
     return ap.parse_args()
+
+
+# HBM traffic per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE passes, kept
+# in profiles/ with the hash of the kernel sources they were taken on; a
+# changed source makes the stored figures stale and traffic is reported null.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_tall_multi.txt")
+TRAFFIC_SOURCES = {"gram": ["gram_bf16.hip", "gram_common.hip", "gram_common.h"],
+                   "fit": ["derive.hip", "path.hip", "path_reg.hip", "path_common.h"]}
+
+
+def sources_hash(phase):
+    import hashlib
+    h = hashlib.sha256()
+    for name in TRAFFIC_SOURCES[phase]:
+        with open(os.path.join(ROOT, "paper_1801_09661_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic():
+    """{phase: bytes per launch} from the traffic summary; a phase whose
+    kernel sources changed since the counters were taken is left out."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return {}
+    vals, digest = {}, {}
+    with open(TRAFFIC_FILE) as f:
+        for line in f:
+            parts = line.split()
+            if len(parts) == 3 and parts[0] == "sources_sha256":
+                digest[parts[1]] = parts[2]
+            elif len(parts) == 3 and parts[0] == "traffic_bytes":
+                vals[parts[1]] = float(parts[2])
+    return {k: v for k, v in vals.items() if k in TRAFFIC_SOURCES and digest.get(k) == sources_hash(k)}
 
 
 def cpu_baseline(pr, nlambda, sample_rows):
@@ -154,16 +189,22 @@ def main():
     runs = {f: run_form(oem, torch, X, y, f, steps, warm, args.nlambda) for f in forms}
     main_run = runs[args.precision]
 
+    if args.calibrate_copy:
+        Z = torch.empty_like(X)
+        Z.copy_(X)
+        torch.cuda.synchronize()
+        del Z
+    traffic = stored_traffic() if args.precision == "split_bf16" else {}
     x_bytes = n * p * X.element_size() + n * 8   # X and y, read once
     gram_gbs = x_bytes / (main_run["gram_only_ms"] * 1e-3) / 1e9
     path_flops = 2.0 * p * p * main_run["updates"]
     path_tflops = path_flops / (main_run["fit_ms"] * 1e-3) / 1e12
     gram_roof = dict(bound="hbm", kernel="gram pass (gram kernel + fixed-order reduction)",
                      achieved=gram_gbs, peak=HBM_PEAK_GBS, unit="GB/s", frac=gram_gbs / HBM_PEAK_GBS,
-                     traffic=None, algorithmic=f"{x_bytes} B of X and y per launch")
+                     traffic=traffic.get("gram"), algorithmic=f"{x_bytes} B of X and y per launch")
     path_roof = dict(bound="alu", kernel="path kernel (+ combine, Lanczos d, lambda grid)",
                      achieved=path_tflops, peak=FP64_PEAK_TFLOPS, unit="TFLOP/s",
-                     frac=path_tflops / FP64_PEAK_TFLOPS, traffic=None,
+                     frac=path_tflops / FP64_PEAK_TFLOPS, traffic=traffic.get("fit"),
                      algorithmic=f"2 p^2 flops x {main_run['updates']} OEM updates per launch")
     dominant = gram_roof if main_run["gram_ms"] >= main_run["fit_ms"] else path_roof
     out = {

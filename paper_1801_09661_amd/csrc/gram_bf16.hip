@@ -12,13 +12,15 @@
 // A workgroup owns one (fold, row split, super-block pair) of 32x32 tiles
 // (super-blocks of up to 4 tiles = 128 columns) and streams its rows in
 // chunks of 64:
-//   load   thread (lane column l, row group rg) loads columns l, l+32, l+64,
-//          l+96 of 8 rows (coalesced 128-byte row segments); the next
-//          chunk's loads are issued before the current chunk's MFMAs;
+//   load   thread (q, rg) loads columns 4 q .. 4 q + 3 of 8 rows (16-byte
+//          loads when rows are aligned; a wave covers two 512-byte row
+//          segments per load); the next chunk's loads are issued before the
+//          current chunk's MFMAs, and rows past the end of the split are
+//          read as copies of its last row and cleared before staging;
 //   stage  the thread splits its values and writes each column's 8 rows as
-//          one 16-byte LDS store (consecutive lanes, consecutive columns:
-//          no bank conflicts), so the panel is column-major in LDS and one
-//          16-byte read is an MFMA operand (8 consecutive rows of a column);
+//          one 16-byte LDS store into a column-major, slot-swizzled panel,
+//          so one 16-byte read is an MFMA operand (8 consecutive rows of a
+//          column) and neither access has bank conflicts;
 //   mma    the waves form 2 pair groups x 2 k-groups: a pair group covers half
 //          of the tile pairs, a k-group every other 16-row k-step, so each
 //          wave reads a tile's operands once per k-step for several pairs;
@@ -33,14 +35,24 @@ namespace oem {
 
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float f32x16_t __attribute__((ext_vector_type(16)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
 
 constexpr int kBThreads = 256;
-constexpr int kBWaves = kBThreads / kWave;
 constexpr int kBTile = 32;                 // MFMA output tile
 constexpr int kBMaxW = 4;                  // tiles per super-block side
 constexpr int kBPanel = kBTile * kBMaxW;   // 128 columns per panel
 constexpr int kBRows = 64;                 // rows per chunk: 4 MFMA k-steps of 16
-constexpr int kBPitch = kBRows + 8;        // bf16 per staged column (144 bytes)
+
+// A staged panel is column-major: column c holds the chunk's 64 rows as
+// eight 16-byte slots of 8 rows, slot s stored at position s ^ bswz(c).  The
+// swizzle makes both access patterns conflict-free: a store covers columns
+// 4 l + j of eight consecutive threads l (bits 2..4 of c vary), an operand
+// read covers eight consecutive columns (bits 0..2 vary), and bswz is a
+// bijection on both bit ranges.
+__device__ inline int bswz(int c)
+{
+    return (c & 7) ^ ((c >> 3) & 3);
+}
 
 // Diagonal super-block: the 10 pairs (a, b), a <= b < 4, in two groups of 5
 // that together need few operand tiles: group 0 = (0,0) (0,1) (0,2) (0,3)
@@ -54,8 +66,34 @@ __host__ __device__ constexpr int dg_b(int grp, int t)
     return grp == 0 ? (t < 4 ? t : 3) : (t < 3 ? t + 1 : t - 1);
 }
 
+// Thread (q, rg) of a panel load: columns col .. col + 3 (col = base + 4 q)
+// of the 8 rows `row`.  Columns at or past p are read from a valid column
+// instead; they only feed tile entries that are discarded.
+template <bool VEC>
+__device__ inline void load_block(float (&x)[8][4], const float *__restrict__ X, int64_t ldx, int p,
+                                  int col, const int64_t (&row)[8])
+{
+    if constexpr (VEC) {
+        const int cv = (col + 3 < p) ? col : 0;          // p is a multiple of 4 here
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const f32x4_t v = *reinterpret_cast<const f32x4_t *>(X + row[e] * ldx + cv);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) x[e][j] = v[j];
+        }
+    } else {
+        int cj[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) cj[j] = min(col + j, p - 1);
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) x[e][j] = X[row[e] * ldx + cj[j]];
+    }
+}
+
 template <bool SPLIT>
-__device__ inline void stage_cols(const float (&x)[8][4], __bf16 *hi, __bf16 *lo, int l, int rg)
+__device__ inline void stage_block(const float (&x)[8][4], __bf16 *hi, __bf16 *lo, int q, int rg)
 {
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
@@ -67,9 +105,10 @@ __device__ inline void stage_cols(const float (&x)[8][4], __bf16 *hi, __bf16 *lo
             h[e] = hb;
             if (SPLIT) lw[e] = (__bf16)(v - (float)hb);
         }
-        const int c = l + 32 * j;
-        *reinterpret_cast<bf16x8_t *>(hi + c * kBPitch + 8 * rg) = h;
-        if (SPLIT) *reinterpret_cast<bf16x8_t *>(lo + c * kBPitch + 8 * rg) = lw;
+        const int c = 4 * q + j;
+        const int off = c * kBRows + 8 * (rg ^ bswz(c));
+        *reinterpret_cast<bf16x8_t *>(hi + off) = h;
+        if (SPLIT) *reinterpret_cast<bf16x8_t *>(lo + off) = lw;
     }
 }
 
@@ -85,17 +124,20 @@ __device__ inline f32x16_t mfma3(f32x16_t acc, const bf16x8_t &ah, const bf16x8_
     return acc;
 }
 
-template <bool SPLIT, bool DIAG>
+// SPLIT: split-BF16 (else single BF16).  DIAG: the launch over diagonal
+// super-blocks (which also accumulates the FP64 diagonal, X^T y, y^T y, n).
+// LIST: rows come from per-(fold, split) row lists (else the contiguous rows
+// of the split).  VEC: X rows are 16-byte aligned and p % 4 == 0.
+template <bool SPLIT, bool DIAG, bool LIST, bool VEC>
 __global__ __launch_bounds__(kBThreads) void gram_bf16_kernel(
     const float *__restrict__ X, int64_t n, int64_t ldx, const double *__restrict__ y, GramGeom g,
     RowSource rs, float *__restrict__ partial, double *__restrict__ pvec, double *__restrict__ pscal)
 {
     constexpr int NSLOT = DIAG ? 5 : 8;
-    constexpr bool diag = DIAG;
     extern __shared__ char smem_raw[];
     const int lane = threadIdx.x % kWave;
     const int wave = threadIdx.x / kWave;
-    const int lc = threadIdx.x % 32, rg = threadIdx.x / 32;
+    const int q4 = threadIdx.x % 32, rg = threadIdx.x / 32;
 
     // diagonal launch: blocks (k, s, I); off-diagonal launch: (k, s, I < J)
     const int nq = DIAG ? g.nsb : g.npsb - g.nsb;
@@ -119,11 +161,11 @@ __global__ __launch_bounds__(kBThreads) void gram_bf16_kernel(
     const int Wi = min(g.W, g.T - I * g.W);
     const int Wj = min(g.W, g.T - J * g.W);
 
-    const int panel_elems = kBPanel * kBPitch;
+    const int panel_elems = kBPanel * kBRows;
     __bf16 *hiA = reinterpret_cast<__bf16 *>(smem_raw);
     __bf16 *loA = hiA + panel_elems;
-    __bf16 *hiB = diag ? hiA : loA + panel_elems;
-    __bf16 *loB = diag ? loA : hiB + panel_elems;
+    __bf16 *hiB = DIAG ? hiA : loA + panel_elems;
+    __bf16 *loB = DIAG ? loA : hiB + panel_elems;
 
     // waves 2 pg, 2 pg + 1 form pair group pg and split the k-steps in two
     const int pg = wave / 2;
@@ -139,31 +181,54 @@ __global__ __launch_bounds__(kBThreads) void gram_bf16_kernel(
     const int32_t *list;
     rows_of(g, rs, n, k, s, first, count, list);
     const int nchunks = (int)((count + kBRows - 1) / kBRows);
-    const int colA = I * g.W * kBTile + lc, colB = J * g.W * kBTile + lc;
-    const bool want_yy = first_block && (lc == 0);
+    const int colA = I * g.W * kBTile + 4 * q4, colB = J * g.W * kBTile + 4 * q4;
     double sd[4] = {0.0, 0.0, 0.0, 0.0}, sxy[4] = {0.0, 0.0, 0.0, 0.0}, syy = 0.0;
 
     float xa[8][4], xb[8][4];
     double yv[8];
+    int32_t nidx[8];      // row list entries of the next chunk (LIST)
+    auto load_index = [&](int c) {
+        if constexpr (LIST) {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int64_t i = min((int64_t)c * kBRows + 8 * rg + e, count - 1);
+                nidx[e] = list[i];
+            }
+        }
+    };
     auto load_chunk = [&](int c) {
+        int64_t row[8];
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
-            const int64_t i = (int64_t)c * kBRows + 8 * rg + e;
-            const bool ok = i < count;
-            const int64_t row = ok ? row_at(first, list, i) : 0;
-            const float *xr = X + row * ldx;
+            if constexpr (LIST) row[e] = nidx[e];
+            else row[e] = first + min((int64_t)c * kBRows + 8 * rg + e, count - 1);
+        }
+        load_block<VEC>(xa, X, ldx, g.p, colA, row);
+        if (!DIAG) load_block<VEC>(xb, X, ldx, g.p, colB, row);
+        if (DIAG) {
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                xa[e][j] = (ok && colA + 32 * j < g.p) ? xr[colA + 32 * j] : 0.0f;
-                if (!diag) xb[e][j] = (ok && colB + 32 * j < g.p) ? xr[colB + 32 * j] : 0.0f;
+            for (int e = 0; e < 8; ++e) yv[e] = y[row[e]];
+        }
+    };
+    // rows past the end of the split were read as copies of its last row
+    auto clear_tail = [&](int c) {
+        const int64_t r0 = (int64_t)c * kBRows + 8 * rg;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            if (r0 + e >= count) {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    xa[e][j] = 0.0f;
+                    if (!DIAG) xb[e][j] = 0.0f;
+                }
+                if (DIAG) yv[e] = 0.0;
             }
-            if (diag) yv[e] = ok ? y[row] : 0.0;
         }
     };
     auto stage_chunk = [&]() {
-        stage_cols<SPLIT>(xa, hiA, loA, lc, rg);
-        if (!diag) stage_cols<SPLIT>(xb, hiB, loB, lc, rg);
-        if (diag) {
+        stage_block<SPLIT>(xa, hiA, loA, q4, rg);
+        if (!DIAG) stage_block<SPLIT>(xb, hiB, loB, q4, rg);
+        if (DIAG) {
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
 #pragma unroll
@@ -172,16 +237,19 @@ __global__ __launch_bounds__(kBThreads) void gram_bf16_kernel(
                     sd[j] += xd * xd;
                     sxy[j] += xd * yv[e];
                 }
-                if (want_yy) syy += yv[e] * yv[e];
+                syy += yv[e] * yv[e];
             }
         }
     };
     auto operand = [&](const __bf16 *panel, int tile, int ks) -> bf16x8_t {
-        return *reinterpret_cast<const bf16x8_t *>(panel + (tile * kBTile + (lane % 32)) * kBPitch +
-                                                   ks * 16 + 8 * (lane / 32));
+        const int c = tile * kBTile + (lane % 32);
+        const int slot = 2 * ks + lane / 32;
+        return *reinterpret_cast<const bf16x8_t *>(panel + c * kBRows + 8 * (slot ^ bswz(c)));
     };
     auto mma_chunk = [&]() {
-        for (int ks = ks0; ks < kBRows / 16; ks += 2) {
+#pragma unroll
+        for (int kh = 0; kh < kBRows / 32; ++kh) {
+            const int ks = 2 * kh + ks0;
             if (DIAG) {
                 // group 0 uses tiles 0..3, group 1 tiles 1..3
                 bf16x8_t h[kBMaxW], l[kBMaxW];
@@ -229,33 +297,37 @@ __global__ __launch_bounds__(kBThreads) void gram_bf16_kernel(
         }
     };
 
-    if (nchunks > 0) load_chunk(0);
+    if (nchunks > 0) {
+        load_index(0);
+        load_chunk(0);
+        load_index(1);
+    }
     for (int c = 0; c < nchunks; ++c) {
+        if ((int64_t)(c + 1) * kBRows > count) clear_tail(c);
         stage_chunk();
         __syncthreads();
-        if (c + 1 < nchunks) load_chunk(c + 1);   // in flight during the MFMAs
+        if (c + 1 < nchunks) {
+            load_chunk(c + 1);   // in flight during the MFMAs
+            load_index(c + 2);
+        }
         mma_chunk();
         __syncthreads();
     }
 
-    // Sum the waves' accumulators of each tile pair in wave order and write
-    // the FP32 partial.  v_mfma_f32_32x32x16_bf16 leaves
+    // Sum the two k-groups' accumulators of each tile pair (in wave order)
+    // and write the FP32 partial.  v_mfma_f32_32x32x16_bf16 leaves
     // D[8 (r / 4) + 4 (lane / 32) + r % 4][lane % 32] in element r.
-    float *red = reinterpret_cast<float *>(smem_raw);   // kBWaves x 1024 floats
+    float *red = reinterpret_cast<float *>(smem_raw);   // 2 x 1024 floats
     const size_t part_id = (size_t)k * g.nsplit + s;
     auto put = [&](const f32x16_t &v, int slot) {
 #pragma unroll
         for (int r = 0; r < 16; ++r)
             red[slot * 1024 + (8 * (r / 4) + 4 * (lane / 32) + (r % 4)) * kBTile + (lane % 32)] = v[r];
     };
-    auto emit = [&](int ti, int tj, int nw) {
+    auto emit = [&](int ti, int tj) {
         __syncthreads();
         float *dst = partial + (part_id * g.ntp + tile_pair_index(ti, tj, g.T)) * (kBTile * kBTile);
-        for (int e = threadIdx.x; e < 1024; e += kBThreads) {
-            float v = red[e];
-            for (int w = 1; w < nw; ++w) v += red[w * 1024 + e];
-            dst[e] = v;
-        }
+        for (int e = threadIdx.x; e < 1024; e += kBThreads) dst[e] = red[e] + red[1024 + e];
         __syncthreads();
     };
 #pragma unroll
@@ -266,21 +338,21 @@ __global__ __launch_bounds__(kBThreads) void gram_bf16_kernel(
             const int b = DIAG ? dg_b(grp, t) : t % 4;
             if (DIAG ? (b < Wi) : (a < Wi && b < Wj)) {
                 if (pg == grp) put(acc[t], wave % 2);
-                emit(I * g.W + a, J * g.W + b, 2);
+                emit(I * g.W + a, J * g.W + b);
             }
         }
     }
 
     // FP64 diagonal, X^T y, y^T y: the 8 row groups of a column are combined
-    // in order; pvec = [split][diag p | xy p], pscal = [split][yy, n]
-    if (diag) {
+    // in order; pvec = [part][diag p | xy p], pscal = [part][yy, n]
+    if (DIAG) {
         double *vred = reinterpret_cast<double *>(smem_raw);
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            vred[rg * kBPanel + lc + 32 * j] = sd[j];
-            vred[8 * kBPanel + rg * kBPanel + lc + 32 * j] = sxy[j];
+            vred[rg * kBPanel + 4 * q4 + j] = sd[j];
+            vred[8 * kBPanel + rg * kBPanel + 4 * q4 + j] = sxy[j];
         }
-        if (lc == 0) vred[16 * kBPanel + rg] = syy;
+        if (q4 == 0) vred[16 * kBPanel + rg] = syy;
         __syncthreads();
         if (threadIdx.x < kBPanel) {
             const int col = I * g.W * kBTile + threadIdx.x;
@@ -303,17 +375,16 @@ __global__ __launch_bounds__(kBThreads) void gram_bf16_kernel(
     }
 }
 
-// One launch for the whole cross-split reduction: thread e of fold k sums
-// the splits of entry e (tiles, then diagonal and X^T y, then y^T y and n)
-// in split order and adds the result into the running statistics; upper
-// tile entries are mirrored so G stays exactly symmetric.
-__global__ void gram_bf16_reduce_kernel(GramGeom g, const float *__restrict__ partial,
-                                        const double *__restrict__ pvec,
-                                        const double *__restrict__ pscal, double *__restrict__ Gk,
-                                        double *__restrict__ bk, double *__restrict__ yyk,
-                                        int64_t *__restrict__ nk)
+// Add the split-reduced statistics into the running sums: off-diagonal tile
+// entries (upper triangle, mirrored so G stays exactly symmetric), then the
+// FP64 diagonal and X^T y, then y^T y and n.
+__global__ void gram_bf16_scatter_kernel(GramGeom g, const double *__restrict__ tiles,
+                                         const double *__restrict__ vec,
+                                         const double *__restrict__ scal, double *__restrict__ Gk,
+                                         double *__restrict__ bk, double *__restrict__ yyk,
+                                         int64_t *__restrict__ nk)
 {
-    const int p = g.p, S = g.nsplit;
+    const int p = g.p;
     const size_t tile = kBTile * kBTile;
     const size_t Et = (size_t)g.ntp * tile;
     const size_t per_k = Et + 2 * (size_t)p + 1;
@@ -321,6 +392,7 @@ __global__ void gram_bf16_reduce_kernel(GramGeom g, const float *__restrict__ pa
     if (idx >= (size_t)g.K * per_k) return;
     const int k = (int)(idx / per_k);
     const size_t e = idx % per_k;
+    double *G = Gk + (size_t)k * p * p;
     if (e < Et) {
         const int te = (int)(e % tile);
         const int tp = (int)(e / tile);
@@ -330,28 +402,17 @@ __global__ void gram_bf16_reduce_kernel(GramGeom g, const float *__restrict__ pa
         if (ti == tj && ei >= ej) return;         // diagonal from FP64; lower half mirrored
         const int i = ti * kBTile + ei, j = tj * kBTile + ej;
         if (i >= p || j >= p) return;
-        const float *src = partial + (size_t)k * S * Et + e;
-        double sum = 0.0;
-        for (int sp = 0; sp < S; ++sp) sum += (double)src[(size_t)sp * Et];
-        double *G = Gk + (size_t)k * p * p;
-        G[(size_t)i * p + j] += sum;
-        G[(size_t)j * p + i] += sum;
+        const double v = tiles[(size_t)k * Et + e];
+        G[(size_t)i * p + j] += v;
+        G[(size_t)j * p + i] += v;
     } else if (e < Et + 2 * (size_t)p) {
         const size_t v = e - Et;
-        const double *src = pvec + (size_t)k * S * 2 * p + v;
-        double sum = 0.0;
-        for (int sp = 0; sp < S; ++sp) sum += src[(size_t)sp * 2 * p];
-        if (v < (size_t)p) Gk[(size_t)k * p * p + v * p + v] += sum;
+        const double sum = vec[(size_t)k * 2 * p + v];
+        if (v < (size_t)p) G[v * p + v] += sum;
         else bk[(size_t)k * p + (v - p)] += sum;
     } else {
-        const double *src = pscal + (size_t)k * S * 2;
-        double yy = 0.0, cnt = 0.0;
-        for (int sp = 0; sp < S; ++sp) {
-            yy += src[(size_t)sp * 2];
-            cnt += src[(size_t)sp * 2 + 1];
-        }
-        yyk[k] += yy;
-        nk[k] += (int64_t)cnt;
+        yyk[k] += scal[(size_t)k * 2];
+        nk[k] += (int64_t)scal[(size_t)k * 2 + 1];
     }
 }
 
@@ -379,14 +440,30 @@ static GramGeom plan_bf16(int p, int K, int64_t n)
     return g;
 }
 
-static size_t bf16_lds_bytes(const GramGeom &g, bool diag)
+static size_t bf16_lds_bytes(bool diag)
 {
-    (void)g;
     const int npanels = diag ? 2 : 4;
-    const size_t panels = (size_t)npanels * kBPanel * kBPitch * sizeof(__bf16);
-    const size_t red = std::max((size_t)kBWaves * 1024 * sizeof(float),
-                                (size_t)(16 * kBPanel + 8) * sizeof(double));
+    const size_t panels = (size_t)npanels * kBPanel * kBRows * sizeof(__bf16);
+    const size_t red = std::max((size_t)2 * 1024 * sizeof(float), (size_t)(16 * kBPanel + 8) * sizeof(double));
     return std::max(panels, red);
+}
+
+template <bool SPLIT, bool DIAG>
+static int launch_bf16_t(const GramGeom &g, bool list, bool vec, unsigned blocks, const float *X,
+                         int64_t n, int64_t ldx, const double *y, const RowSource &rs, float *part,
+                         double *pvec, double *pscal, hipStream_t s)
+{
+    const void *kern;
+    if (list) kern = vec ? (const void *)gram_bf16_kernel<SPLIT, DIAG, true, true>
+                         : (const void *)gram_bf16_kernel<SPLIT, DIAG, true, false>;
+    else kern = vec ? (const void *)gram_bf16_kernel<SPLIT, DIAG, false, true>
+                    : (const void *)gram_bf16_kernel<SPLIT, DIAG, false, false>;
+    const size_t lds = bf16_lds_bytes(DIAG);
+    OEM_HIP_CHECK(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    void *args[] = {(void *)&X, (void *)&n, (void *)&ldx, (void *)&y, (void *)&g, (void *)&rs,
+                    (void *)&part, (void *)&pvec, (void *)&pscal};
+    OEM_HIP_CHECK(hipLaunchKernel(kern, dim3(blocks), dim3(kBThreads), args, lds, s));
+    return OEM_OK;
 }
 
 int launch_gram_bf16(oem_gram_s *h, const void *Xv, int64_t n, int64_t ldx, const double *y,
@@ -407,27 +484,35 @@ int launch_gram_bf16(oem_gram_s *h, const void *Xv, int64_t n, int64_t ldx, cons
     float *part = h->partial.as<float>();
     double *pvec = reinterpret_cast<double *>(part + parts * Et);
     double *pscal = pvec + parts * 2 * g.p;
+    const size_t nred = reduce_tmp_doubles(g.K, g.nsplit, Et) + K * (Et + 2 * (size_t)g.p + 2) + 8;
+    rc = h->redtmp.ensure(nred * sizeof(double));
+    if (rc) return rc;
+
     const bool split = (h->prec == OEM_SPLIT_BF16);
-    {
-        const size_t lds = bf16_lds_bytes(g, true);
-        auto kern = split ? gram_bf16_kernel<true, true> : gram_bf16_kernel<false, true>;
-        OEM_HIP_CHECK(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        hipLaunchKernelGGL(kern, dim3(g.K * g.nsplit * g.nsb), dim3(kBThreads), lds, s, X, n, ldx, y, g, rs,
-                           part, pvec, pscal);
-        OEM_HIP_CHECK(hipGetLastError());
-    }
+    const bool list = g.K > 1;
+    const bool vec = ((reinterpret_cast<uintptr_t>(X) & 15) == 0) && (ldx % 4 == 0) && (g.p % 4 == 0);
+    const unsigned nd = (unsigned)(g.K * g.nsplit * g.nsb);
+    rc = split ? launch_bf16_t<true, true>(g, list, vec, nd, X, n, ldx, y, rs, part, pvec, pscal, s)
+               : launch_bf16_t<false, true>(g, list, vec, nd, X, n, ldx, y, rs, part, pvec, pscal, s);
+    if (rc) return rc;
     if (g.npsb > g.nsb) {
-        const size_t lds = bf16_lds_bytes(g, false);
-        auto kern = split ? gram_bf16_kernel<true, false> : gram_bf16_kernel<false, false>;
-        OEM_HIP_CHECK(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        hipLaunchKernelGGL(kern, dim3(g.K * g.nsplit * (g.npsb - g.nsb)), dim3(kBThreads), lds, s, X, n, ldx, y,
-                           g, rs, part, pvec, pscal);
-        OEM_HIP_CHECK(hipGetLastError());
+        const unsigned no = (unsigned)(g.K * g.nsplit * (g.npsb - g.nsb));
+        rc = split ? launch_bf16_t<true, false>(g, list, vec, no, X, n, ldx, y, rs, part, pvec, pscal, s)
+                   : launch_bf16_t<false, false>(g, list, vec, no, X, n, ldx, y, rs, part, pvec, pscal, s);
+        if (rc) return rc;
     }
+    double *tmp = h->redtmp.as<double>();
+    double *out_tiles = tmp + reduce_tmp_doubles(g.K, g.nsplit, Et);
+    double *out_vec = out_tiles + K * Et;
+    double *out_scal = out_vec + K * 2 * g.p;
+    rc = reduce_splits_f32(part, g.K, g.nsplit, Et, tmp, out_tiles, s);
+    rc = rc ? rc : reduce_splits_f64(pvec, g.K, g.nsplit, 2 * (size_t)g.p, tmp, out_vec, s);
+    rc = rc ? rc : reduce_splits_f64(pscal, g.K, g.nsplit, 2, tmp, out_scal, s);
+    if (rc) return rc;
     const size_t total = K * (Et + 2 * (size_t)g.p + 1);
-    hipLaunchKernelGGL(gram_bf16_reduce_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, g,
-                       part, pvec, pscal, h->Gk.as<double>(), h->bk.as<double>(), h->yyk.as<double>(),
-                       h->nk.as<int64_t>());
+    hipLaunchKernelGGL(gram_bf16_scatter_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, g,
+                       out_tiles, out_vec, out_scal, h->Gk.as<double>(), h->bk.as<double>(),
+                       h->yyk.as<double>(), h->nk.as<int64_t>());
     OEM_HIP_CHECK(hipGetLastError());
     return OEM_OK;
 }
