@@ -442,7 +442,7 @@ int oem_fit_path(oem_handle h, int32_t fold, const oem_penalty *pen, int32_t npe
                                   obj ? obj + (size_t)i * L : nullptr));
     rc = upload_descs(h, descs, s);
     if (rc) return rc;
-    rc = launch_paths(h->paths.as<PathDesc>(), std::vector<int>(npen, h->p), h->order, s);
+    rc = launch_paths(h->paths.as<PathDesc>(), descs, h->order, s);
     if (rc) return rc;
     if (lambda)
         OEM_HIP_CHECK(hipMemcpyAsync(lambda, h->lam.ptr, nl * sizeof(double), hipMemcpyDeviceToDevice, s));
@@ -507,7 +507,7 @@ int oem_cv(oem_handle h, const oem_penalty *pen, int32_t npen, const oem_path_op
         }
     rc = upload_descs(h, descs, s);
     if (rc) return rc;
-    rc = launch_paths(h->paths.as<PathDesc>(), std::vector<int>(descs.size(), p), h->order, s);
+    rc = launch_paths(h->paths.as<PathDesc>(), descs, h->order, s);
     if (rc) return rc;
     rc = launch_cv(h->Gk.as<double>(), h->bk.as<double>(), h->yyk.as<double>(), h->nk.as<int64_t>(),
                    K, p, npen, L, bf, mse, cvm, cvsd_w, i_min, i_1se, best, s);

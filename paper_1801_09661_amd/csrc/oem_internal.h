@@ -133,7 +133,7 @@ int launch_lanczos(oem_gram_s *g, hipStream_t s);
 int launch_lambda_grid(const double *cs_full, int p, const int32_t *gstart, const int32_t *gidx,
                        int ngroups, const double *w, const double *cg, const oem_penalty *d_pens,
                        int npen, int L, double ratio, double *lambda_out, hipStream_t s);
-int launch_paths(const PathDesc *d_desc, const std::vector<int> &path_p, DevBuf &orderbuf,
+int launch_paths(const PathDesc *d_desc, const std::vector<PathDesc> &host, DevBuf &orderbuf,
                  hipStream_t s);
 int launch_cv(const double *Gk, const double *bk, const double *yyk, const int64_t *nk,
               int K, int p, int npen, int L, const double *beta_folds, double *mse,

@@ -294,37 +294,49 @@ size_t path_lds_bytes(int p, bool g_in_lds)
 
 int launch_paths_reg(const PathDesc *d_desc, const int *d_order, int count, int pmax,
                      hipStream_t s);
+int launch_paths_blk(const PathDesc *d_desc, const int *d_order, int count, int pmax,
+                     hipStream_t s);
 
-// Paths go to the register kernel when p <= 128, otherwise to the general
-// kernel (G in LDS when it fits, else streamed from L2).
-int launch_paths(const PathDesc *d_desc, const std::vector<int> &path_p, DevBuf &orderbuf,
+// Separable-penalty paths with p <= 128 go to the block kernel, group-lasso
+// paths with p <= 128 to the register kernel, the rest to the general kernel
+// (G in LDS when it fits, else streamed from L2).
+int launch_paths(const PathDesc *d_desc, const std::vector<PathDesc> &host, DevBuf &orderbuf,
                  hipStream_t s)
 {
-    const int npaths = (int)path_p.size();
+    const int npaths = (int)host.size();
     if (npaths == 0) return OEM_OK;
-    std::vector<int> small, mid, big;
+    std::vector<int> sep32, sep64, sep128, grp64, grp128, big;
     int pmax_big = 0;
     for (int i = 0; i < npaths; ++i) {
-        if (path_p[i] <= 64) small.push_back(i);
-        else if (path_p[i] <= 128) mid.push_back(i);
+        const int p = host[i].p;
+        const bool grp = host[i].kind == OEM_GRP_LASSO;
+        if (p <= 128 && !grp) (p <= 32 ? sep32 : p <= 64 ? sep64 : sep128).push_back(i);
+        else if (p <= 128) (p <= 64 ? grp64 : grp128).push_back(i);
         else {
             big.push_back(i);
-            pmax_big = std::max(pmax_big, path_p[i]);
+            pmax_big = std::max(pmax_big, p);
         }
     }
     std::vector<int> order;
-    order.insert(order.end(), small.begin(), small.end());
-    order.insert(order.end(), mid.begin(), mid.end());
-    order.insert(order.end(), big.begin(), big.end());
+    for (const auto *v : {&sep32, &sep64, &sep128, &grp64, &grp128, &big})
+        order.insert(order.end(), v->begin(), v->end());
     int rc = orderbuf.ensure(order.size() * sizeof(int));
     if (rc) return rc;
     OEM_HIP_CHECK(hipMemcpyAsync(orderbuf.ptr, order.data(), order.size() * sizeof(int),
                                  hipMemcpyHostToDevice, s));
     OEM_HIP_CHECK(hipStreamSynchronize(s));
     const int *d_order = orderbuf.as<int>();
-    rc = launch_paths_reg(d_desc, d_order, (int)small.size(), 64, s);
-    if (rc) return rc;
-    rc = launch_paths_reg(d_desc, d_order + small.size(), (int)mid.size(), 128, s);
+    size_t off = 0;
+    rc = launch_paths_blk(d_desc, d_order + off, (int)sep32.size(), 32, s);
+    off += sep32.size();
+    rc = rc ? rc : launch_paths_blk(d_desc, d_order + off, (int)sep64.size(), 64, s);
+    off += sep64.size();
+    rc = rc ? rc : launch_paths_blk(d_desc, d_order + off, (int)sep128.size(), 128, s);
+    off += sep128.size();
+    rc = rc ? rc : launch_paths_reg(d_desc, d_order + off, (int)grp64.size(), 64, s);
+    off += grp64.size();
+    rc = rc ? rc : launch_paths_reg(d_desc, d_order + off, (int)grp128.size(), 128, s);
+    off += grp128.size();
     if (rc) return rc;
     if (big.empty()) return OEM_OK;
     // keep G in LDS when the largest path's matrix fits next to its vectors
@@ -339,7 +351,7 @@ int launch_paths(const PathDesc *d_desc, const std::vector<int> &path_p, DevBuf 
         OEM_HIP_CHECK(hipFuncSetAttribute((const void *)path_kernel,
                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     hipLaunchKernelGGL(path_kernel, dim3((int)big.size()), dim3(kPathThreads), lds, s, d_desc,
-                       d_order + small.size() + mid.size(), lds_g_max_p);
+                       d_order + off, lds_g_max_p);
     OEM_HIP_CHECK(hipGetLastError());
     return OEM_OK;
 }

@@ -37,6 +37,54 @@ __device__ inline double update1(int kind, double u, double lam_w, double d, dou
     }
 }
 
+// The same updates with the divisors of Section 2.2 replaced by reciprocals
+// fixed for one (coordinate, lambda): the iteration then needs no division.
+struct Upd {
+    double thr;    // soft-threshold level: w lambda (w lambda alpha for the elastic net)
+    double s1;     // scale of the soft-thresholded value
+    double t1;     // SCAD: end of the soft region, (d + 1) w lambda
+    double t2;     // MCP / SCAD: start of the unpenalised region, w lambda gamma d
+    double c2;     // SCAD: w lambda gamma
+    double s2;     // SCAD: 1 / ((gamma - 1) d - 1)
+    double inv_d;  // 1 / d
+};
+
+__device__ inline Upd make_upd(int kind, double lam_w, double d, double alpha, double gamma)
+{
+    Upd q;
+    q.inv_d = 1.0 / d;
+    q.thr = lam_w;
+    q.s1 = q.inv_d;
+    q.t1 = q.t2 = INFINITY;
+    q.c2 = 0.0;
+    q.s2 = 0.0;
+    if (kind == OEM_ENET) {
+        q.thr = lam_w * alpha;
+        q.s1 = 1.0 / (d + lam_w * (1.0 - alpha));
+    } else if (kind == OEM_MCP) {
+        q.s1 = gamma / (gamma * d - 1.0);
+        q.t1 = q.t2 = lam_w * gamma * d;
+    } else if (kind == OEM_SCAD) {
+        q.t1 = (d + 1.0) * lam_w;
+        q.t2 = lam_w * gamma * d;
+        q.c2 = lam_w * gamma;
+        q.s2 = 1.0 / ((gamma - 1.0) * d - 1.0);
+    }
+    return q;
+}
+
+// MCP and SCAD share the form: soft region up to t1, a linear middle piece
+// up to t2 (SCAD only; empty for MCP since t1 = t2), u / d beyond.
+__device__ inline double update_fast(int kind, double u, const Upd &q, double gamma)
+{
+    const double au = fabs(u);
+    const double soft = copysign(pos(au - q.thr) * q.s1, u);
+    if (kind == OEM_LASSO || kind == OEM_ENET) return soft;
+    if (au <= q.t1) return soft;
+    if (au <= q.t2) return copysign(((gamma - 1.0) * au - q.c2) * q.s2, u);
+    return u * q.inv_d;
+}
+
 // derivative of the penalty at |b| > 0 (for the stationarity check)
 __device__ inline double pen_deriv(int kind, double ab, double lw, double alpha, double gamma)
 {
@@ -104,6 +152,31 @@ __device__ inline double wave_sum(double v)
     v = v + dpp_mov<0x124>(v);
     v = v + dpp_mov<0x128>(v);
     return (readlane_d(v, 0) + readlane_d(v, 16)) + (readlane_d(v, 32) + readlane_d(v, 48));
+}
+
+// max for values that are not NaN (no quieting of signalling NaNs needed)
+__device__ inline double nmax(double a, double b) { return a > b ? a : b; }
+
+template <int CTRL> __device__ inline double dpp_get(double v)
+{
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, true);
+    return __hiloint2double(hi, lo);
+}
+
+// Max over lanes 0 .. N-1, valid in lane 0; the other lanes of those rows
+// must hold values not above the max (e.g. zero).  Butterfly inside each
+// 16-lane row: quad_perm xor 1, xor 2, half-row mirror, row mirror; the rows
+// are then joined through lanes 16, 32 and 48.
+template <int N> __device__ inline double lanes_max(double v)
+{
+    if (N > 1) v = nmax(v, dpp_get<0xB1>(v));
+    if (N > 2) v = nmax(v, dpp_get<0x4E>(v));
+    if (N > 4) v = nmax(v, dpp_get<0x141>(v));
+    if (N > 8) v = nmax(v, dpp_get<0x140>(v));
+    if (N > 16) v = nmax(v, readlane_d(v, 16));
+    if (N > 32) v = nmax(v, nmax(readlane_d(v, 32), readlane_d(v, 48)));
+    return v;
 }
 
 } // namespace oem

@@ -221,6 +221,190 @@ __global__ __launch_bounds__(64 * NW) void path_reg_kernel(const PathDesc *__res
     }
 }
 
+// ---------------------------------------------------------------------------
+// Separable penalties (lasso, elastic net, MCP, SCAD) for p <= 128: one
+// barrier per OEM update.
+//
+// NW waves; wave w owns the column block B_w = [CB w, CB (w + 1)) and lane l
+// holds G[l + 64 r][CB w + c] (r < R, c < CB).  Wave w also owns the
+// coordinates of B_w: lane l < CB keeps beta_{CB w + l} in a register.  One
+// update:
+//   1. every wave reads the NW partial sums of (G beta)_i for its own rows
+//      (written before the last barrier), forms u_i and the new beta_i;
+//   2. it broadcasts its new beta block lane by lane (readlane) and forms its
+//      partial sums of G beta for all rows, the next update's input;
+//   3. it writes those partials and its max |delta beta|, max |beta| into the
+//      other half of a double buffer, and the workgroup meets at one barrier;
+//   4. every wave reads the NW per-wave maxima and applies the stopping
+//      rule, all waves taking the same decision.
+// The FP64 vector rate bounds step 2 (R CB fused multiply-adds and 2 CB lane
+// reads per wave); fewer waves shorten the barrier, so p <= 32 runs on one
+// wave, p <= 64 on two and p <= 128 on four.
+// After the stopping rule holds, the partials already hold G beta for the
+// accepted beta, which gives the stationarity check and the objective.
+template <int NW, int R, int CB>
+__global__ __launch_bounds__(64 * NW) void path_blk_kernel(const PathDesc *__restrict__ descs,
+                                                           const int *__restrict__ order)
+{
+    static_assert(NW * CB <= 64 * R, "each owned coordinate must be a row held by the lanes");
+    __shared__ double part[2][NW][64 * R];
+    __shared__ double dm[2][NW][2];
+    __shared__ double fin[4][NW];
+
+    const PathDesc P = descs[order[blockIdx.x]];
+    const int p = P.p;
+    const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+
+    double Gr[R][CB];
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int c = 0; c < CB; ++c) {
+            const int i = lane + 64 * r, j = CB * wave + c;
+            Gr[r][c] = (i < p && j < p) ? P.G[(size_t)i * p + j] : 0.0;
+        }
+
+    const int row = CB * wave + lane;              // coordinate owned by this lane
+    const bool mine = (lane < CB) && (row < p);
+    const double ct = mine ? P.c[row] : 0.0;
+    const double st = mine ? P.s[row] : 1.0;
+    const double wt = (mine && P.w) ? P.w[row] : 1.0;
+    const double d = *P.d;
+    const double yyn = *P.yyn;
+    double bt = 0.0;
+
+    // partial sums of G beta over this wave's columns, into part[buf]; NA
+    // interleaved accumulators per row keep the FP64 add chains short
+    auto symv = [&](int buf) {
+        constexpr int NA = CB < 8 ? CB : 8;
+        double acc[R][NA];
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int a = 0; a < NA; ++a) acc[r][a] = 0.0;
+        const int blo = __double2loint(bt), bhi = __double2hiint(bt);
+#pragma unroll
+        for (int c = 0; c < CB; ++c) {
+            const double bj = __hiloint2double(__builtin_amdgcn_readlane(bhi, c),
+                                               __builtin_amdgcn_readlane(blo, c));
+#pragma unroll
+            for (int r = 0; r < R; ++r) acc[r][c % NA] += Gr[r][c] * bj;
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+#pragma unroll
+            for (int h = NA / 2; h > 0; h /= 2)
+#pragma unroll
+                for (int a = 0; a < h; ++a) acc[r][a] += acc[r][a + h];
+            part[buf][wave][lane + 64 * r] = acc[r][0];
+        }
+    };
+    // (G beta)_row from the NW partials, summed pairwise
+    auto gsum = [&](int buf) -> double {
+        if (lane >= CB) return 0.0;
+        double v[NW];
+#pragma unroll
+        for (int w = 0; w < NW; ++w) v[w] = part[buf][w][row];
+#pragma unroll
+        for (int h = NW / 2; h > 0; h /= 2)
+#pragma unroll
+            for (int w = 0; w < h; ++w) v[w] += v[w + h];
+        return v[0];
+    };
+
+    int cur = 0;
+    symv(cur);
+    __syncthreads();
+
+    for (int l = 0; l < P.L; ++l) {
+        const double lam = P.lambda[l];
+        const double lw = wt * lam;
+        const Upd q = make_upd(P.kind, lw, d, P.alpha, P.gamma);
+        int it = 0;
+        bool conv = false;
+        do {
+            const double gb = gsum(cur);
+            const double u = ct + (d * bt - gb);
+            double dl = 0.0, mx = 0.0;
+            if (mine) {
+                const double bn = update_fast(P.kind, u, q, P.gamma);
+                dl = fabs(bn - bt);
+                mx = fabs(bn);
+                bt = bn;
+            }
+            ++it;
+            dl = lanes_max<CB>(dl);
+            mx = lanes_max<CB>(mx);
+            const int nxt = cur ^ 1;
+            symv(nxt);
+            if (lane == 0) {
+                dm[nxt][wave][0] = dl;
+                dm[nxt][wave][1] = mx;
+            }
+            __syncthreads();
+            cur = nxt;
+            double DL[NW], MX[NW];
+#pragma unroll
+            for (int w = 0; w < NW; ++w) {
+                DL[w] = dm[cur][w][0];
+                MX[w] = dm[cur][w][1];
+            }
+#pragma unroll
+            for (int h = NW / 2; h > 0; h /= 2)
+#pragma unroll
+                for (int w = 0; w < h; ++w) {
+                    DL[w] = nmax(DL[w], DL[w + h]);
+                    MX[w] = nmax(MX[w], MX[w + h]);
+                }
+            conv = DL[0] <= P.tol * MX[0];
+        } while (!conv && it < P.maxit);
+
+        // stationarity and objective at the accepted beta (part[cur] = G beta)
+        const double gbt = gsum(cur);
+        double kv = 0.0, penv = 0.0, quad = 0.0, lin = 0.0;
+        if (mine) {
+            const double g = gbt - ct;
+            if (bt == 0.0)
+                kv = pos(fabs(g) - (P.kind == OEM_ENET ? P.alpha * lw : lw));
+            else
+                kv = fabs(g + sgn(bt) * pen_deriv(P.kind, fabs(bt), lw, P.alpha, P.gamma));
+            penv = pen_value(P.kind, bt, lw, P.alpha, P.gamma);
+            quad = bt * gbt;
+            lin = ct * bt;
+        }
+        kv = wave_max(kv);
+        penv = wave_sum(penv);
+        quad = wave_sum(quad);
+        lin = wave_sum(lin);
+        if (lane == 0) {
+            fin[0][wave] = kv;
+            fin[1][wave] = penv;
+            fin[2][wave] = quad;
+            fin[3][wave] = lin;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            kv = fin[0][0];
+            penv = fin[1][0];
+            quad = fin[2][0];
+            lin = fin[3][0];
+            for (int w = 1; w < NW; ++w) {
+                kv = fmax(kv, fin[0][w]);
+                penv += fin[1][w];
+                quad += fin[2][w];
+                lin += fin[3][w];
+            }
+            if (P.kkt) P.kkt[l] = kv;
+            if (P.obj) P.obj[l] = 0.5 * quad - lin + 0.5 * yyn + penv;
+            if (P.iters) P.iters[l] = conv ? it : -it;
+        }
+        if (mine) {
+            P.beta[(size_t)l * p + row] = bt / st;
+            if (P.beta_std) P.beta_std[(size_t)l * p + row] = bt;
+        }
+    }
+}
+
 // Path launch plan for the register kernel: paths with p <= 64 and
 // 64 < p <= 128 go to two instantiations.
 int launch_paths_reg(const PathDesc *d_desc, const int *d_order, int count, int pmax,
@@ -236,6 +420,36 @@ int launch_paths_reg(const PathDesc *d_desc, const int *d_order, int count, int 
     } else {
         return fail(OEM_E_INVAL, "register path kernel needs p <= 128");
     }
+    OEM_HIP_CHECK(hipGetLastError());
+    return OEM_OK;
+}
+
+#ifndef PBLK32_NW
+#define PBLK32_NW 1
+#endif
+#ifndef PBLK64_NW
+#define PBLK64_NW 2
+#endif
+#ifndef PBLK128_NW
+#define PBLK128_NW 4
+#endif
+// Separable-penalty paths: p <= 32, <= 64 and <= 128 go to three
+// instantiations of the block kernel (wave counts measured best at each size).
+int launch_paths_blk(const PathDesc *d_desc, const int *d_order, int count, int pmax,
+                     hipStream_t s)
+{
+    if (count == 0) return OEM_OK;
+    if (pmax <= 32)
+        hipLaunchKernelGGL((path_blk_kernel<PBLK32_NW, 1, 32 / PBLK32_NW>), dim3(count), dim3(64 * PBLK32_NW),
+                           0, s, d_desc, d_order);
+    else if (pmax <= 64)
+        hipLaunchKernelGGL((path_blk_kernel<PBLK64_NW, 1, 64 / PBLK64_NW>), dim3(count), dim3(64 * PBLK64_NW),
+                           0, s, d_desc, d_order);
+    else if (pmax <= 128)
+        hipLaunchKernelGGL((path_blk_kernel<PBLK128_NW, 2, 128 / PBLK128_NW>), dim3(count),
+                           dim3(64 * PBLK128_NW), 0, s, d_desc, d_order);
+    else
+        return fail(OEM_E_INVAL, "block path kernel needs p <= 128");
     OEM_HIP_CHECK(hipGetLastError());
     return OEM_OK;
 }
