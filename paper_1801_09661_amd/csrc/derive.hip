@@ -220,6 +220,302 @@ __device__ inline double start_component(int i)
     return (double)(z >> 11) * (1.0 / 9007199254740992.0) + 0.5;  // in [0.5, 1.5)
 }
 
+// Reciprocal of a nonzero double: hardware estimate refined by two Newton
+// steps (relative error at the rounding level), cheaper than a division in
+// the long dependent chains below.
+__device__ inline double rcp_fast(double q)
+{
+    double r = __builtin_amdgcn_rcp(q);
+    r = fma(r, fma(-q, r, 1.0), r);
+    r = fma(r, fma(-q, r, 1.0), r);
+    return r;
+}
+
+__device__ inline int sturm_below_fast(const double *a, const double *b, int m, double x)
+{
+    int cnt = 0;
+    double q = 1.0;
+    for (int i = 0; i < m; ++i) {
+        const double bb = (i > 0) ? b[i - 1] * b[i - 1] : 0.0;
+        q = (a[i] - x) - (i > 0 ? bb * rcp_fast(q) : 0.0);
+        if (q == 0.0) q = -1e-300;
+        if (q < 0.0) ++cnt;
+    }
+    return cnt;
+}
+
+// tri_top with the fast Sturm count and a known lower bound `floor` for the
+// top eigenvalue (the previous top Ritz value: Ritz values only grow).
+__device__ inline void tri_top_fast(const double *a, const double *b, int m, double floor,
+                                    double *lo_out, double *hi_out)
+{
+    const int lane = threadIdx.x % kWave;
+    double lo = -INFINITY, hi = -INFINITY;
+    for (int i = 0; i < m; ++i) {
+        double r = fabs(i > 0 ? b[i - 1] : 0.0) + fabs(i < m - 1 ? b[i] : 0.0);
+        lo = fmax(lo, a[i]);
+        hi = fmax(hi, a[i] + r);
+    }
+    lo = fmax(lo, floor);
+    hi = hi + fabs(hi) * 1e-15 + 1e-300;
+    lo = lo - fabs(lo) * 1e-15 - 1e-300;
+    for (int round = 0; round < 24; ++round) {
+        if (hi - lo <= 2e-16 * fmax(fabs(lo), fabs(hi))) break;
+        const double x = lo + (hi - lo) * (double)(lane + 1) / (double)(kWave + 1);
+        const int below = sturm_below_fast(a, b, m, x);
+        const uint64_t above = __ballot(below == m);
+        double nlo = lo, nhi = hi;
+        if (above) {
+            const int f = __ffsll((long long)above) - 1;
+            nhi = lo + (hi - lo) * (double)(f + 1) / (double)(kWave + 1);
+            if (f > 0) nlo = lo + (hi - lo) * (double)f / (double)(kWave + 1);
+        } else {
+            nlo = lo + (hi - lo) * (double)kWave / (double)(kWave + 1);
+        }
+        lo = nlo;
+        hi = nhi;
+    }
+    *lo_out = lo;
+    *hi_out = hi;
+}
+
+constexpr int kLzWideWaves = 16;
+constexpr int kLzWideThreads = 64 * kLzWideWaves;
+
+__device__ inline double wide_block_sum(double v, double *red)
+{
+    v = wave_sum(v);
+    const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+    __syncthreads();
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < kLzWideWaves; ++w) t += red[w];
+    return t;
+}
+
+// Lanczos for 128 < p <= 512 R: the same recurrence, reorthogonalisation and
+// stopping rule as lanczos_kernel, laid out for memory-level parallelism.
+// Wave w covers rows 64 (w % 8) + lane + 512 r and one half of the columns
+// (or of the basis vectors, in the reorthogonalisation); each lane keeps 8
+// (4 when R = 4) row-segment loads in flight per row, with the broadcast
+// operand taken by lane reads from a register that holds 64 consecutive
+// entries.  The top Ritz
+// value is tested at m = 8, 16, 24, 32, 40 and then every max(8, m / 4)
+// steps.
+template <int R>
+__global__ __launch_bounds__(kLzWideThreads) void lanczos_wide_kernel(int p, int mmax,
+                                                                      const double *__restrict__ Gs_all,
+                                                                      double *__restrict__ V_all,
+                                                                      double *__restrict__ d_out,
+                                                                      int32_t *__restrict__ steps_out)
+{
+    constexpr int PR = 512 * R;
+    extern __shared__ double sm[];
+    double *v = sm;                 // PR: current basis vector
+    double *w = v + PR;             // PR
+    double *part = w + PR;          // 2 PR: partial sums of the two halves
+    double *coef = part + 2 * PR;   // mmax + 1
+    double *al = coef + mmax + 1;   // mmax
+    double *be = al + mmax;         // mmax
+    double *tx = be + mmax;         // mmax
+    double *tw = tx + mmax;         // mmax
+    double *red = tw + mmax;        // kLzWideWaves
+    __shared__ int s_flag;
+    __shared__ double s_theta;
+
+    const int q = blockIdx.x;
+    const double *G = Gs_all + (size_t)q * p * p;
+    double *V = V_all + (size_t)q * (mmax + 1) * p;
+    const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+    const int half = wave / 8;
+    int row[R];
+    bool mine[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        row[r] = 64 * (wave % 8) + lane + 512 * r;
+        mine[r] = row[r] < p;
+    }
+
+    // v0 = pseudo-random positive start vector, normalised
+    double ss = 0.0;
+    for (int i = threadIdx.x; i < PR; i += kLzWideThreads) {
+        const double x = i < p ? start_component(i) : 0.0;
+        w[i] = x;
+        ss += x * x;
+    }
+    const double nrm0 = sqrt(wide_block_sum(ss, red));
+    for (int i = threadIdx.x; i < PR; i += kLzWideThreads) {
+        v[i] = w[i] / nrm0;
+        if (i < p) V[i] = v[i];
+    }
+    __syncthreads();
+
+    // out[rows] = sum over the columns c in [c0, c1) of M[c][rows] * x_c, x
+    // in LDS; M row-major with row length p (M = G or the basis V)
+    auto colsum = [&](const double *M, const double *x, int c0, int c1, double (&out)[R]) {
+        constexpr int U = R >= 4 ? 4 : 8;   // loads in flight per lane and row
+        double acc[R][4];
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int a = 0; a < 4; ++a) acc[r][a] = 0.0;
+        int rc[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) rc[r] = mine[r] ? row[r] : 0;
+        for (int cb = c0; cb < c1; cb += 64) {
+            const double xv = (cb + lane < c1) ? x[cb + lane] : 0.0;
+            const int xlo = __double2loint(xv), xhi = __double2hiint(xv);
+            const int m = min(64, c1 - cb);
+            for (int e0 = 0; e0 < m; e0 += U) {
+                double gv[U][R], xs[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int e = e0 + u;
+                    const int c = min(cb + e, c1 - 1);      // past the end: x = 0
+                    xs[u] = __hiloint2double(__builtin_amdgcn_readlane(xhi, e),
+                                             __builtin_amdgcn_readlane(xlo, e));
+#pragma unroll
+                    for (int r = 0; r < R; ++r) gv[u][r] = M[(size_t)c * p + rc[r]];
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+#pragma unroll
+                    for (int r = 0; r < R; ++r) acc[r][u % 4] += gv[u][r] * xs[u];
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) out[r] = (acc[r][0] + acc[r][1]) + (acc[r][2] + acc[r][3]);
+    };
+
+    double gnorm = 0.0, theta = 0.0, floor = -INFINITY;
+    int m = 0, next_test = 8;
+    if (threadIdx.x == 0) s_flag = 0;
+    for (int j = 0; j < mmax; ++j) {
+        // w = G v_j: two column halves, summed in order
+        {
+            const int ch = (p + 1) / 2;
+            double o[R];
+            colsum(G, v, half * ch, min(p, (half + 1) * ch), o);
+#pragma unroll
+            for (int r = 0; r < R; ++r) part[half * PR + row[r]] = o[r];
+        }
+        __syncthreads();
+        double pa = 0.0, pb = 0.0;
+        for (int i = threadIdx.x; i < PR; i += kLzWideThreads) {
+            const double x = i < p ? part[i] + part[PR + i] : 0.0;
+            w[i] = x;
+            pa += x * v[i];
+            pb += x * x;
+        }
+        const double a = wide_block_sum(pa, red);
+        double before = wide_block_sum(pb, red);
+        if (threadIdx.x == 0) al[j] = a;
+        gnorm = fmax(gnorm, fabs(a));
+        // full reorthogonalisation against v_0..v_j (classical Gram-Schmidt,
+        // repeated once when it removed most of w)
+        for (int pass = 0; pass < 2; ++pass) {
+            // coef[mm] = <v_mm, w>: wave w takes mm = w, w + 16, ...; lanes run over rows
+            for (int mm0 = wave; mm0 <= j; mm0 += 2 * kLzWideWaves) {
+                const int mm1 = mm0 + kLzWideWaves;
+                const double *v0 = V + (size_t)mm0 * p;
+                const double *v1 = V + (size_t)min(mm1, j) * p;
+                double t0 = 0.0, t1 = 0.0;
+                for (int i = lane; i < p; i += kWave) {
+                    t0 += v0[i] * w[i];
+                    t1 += v1[i] * w[i];
+                }
+                t0 = wave_sum(t0);
+                t1 = wave_sum(t1);
+                if (lane == 0) {
+                    coef[mm0] = t0;
+                    if (mm1 <= j) coef[mm1] = t1;
+                }
+            }
+            __syncthreads();
+            // w -= V^T coef over v_0..v_j: two halves of the basis, summed in order
+            {
+                const int mh = (j + 2) / 2;
+                double o[R];
+                colsum(V, coef, half * mh, min(j + 1, (half + 1) * mh), o);
+#pragma unroll
+                for (int r = 0; r < R; ++r) part[half * PR + row[r]] = o[r];
+            }
+            __syncthreads();
+            double pc = 0.0;
+            for (int i = threadIdx.x; i < PR; i += kLzWideThreads) {
+                const double x = i < p ? w[i] - (part[i] + part[PR + i]) : 0.0;
+                w[i] = x;
+                pc += x * x;
+            }
+            const double after = wide_block_sum(pc, red);
+            if (after > 0.5 * before) {
+                before = after;
+                break;   // little cancellation: one pass suffices
+            }
+            before = after;
+        }
+        const double b = sqrt(before);
+        if (threadIdx.x == 0) be[j] = b;
+        m = j + 1;
+        const bool invariant = (b <= 1e-14 * fmax(gnorm, 1e-300)) || (m == p);
+        const bool test_now = invariant || (m == next_test) || (m == mmax);
+        __syncthreads();
+        if (test_now) {
+            next_test = m + max(8, m / 4);
+            if (threadIdx.x < kWave) {
+                double lo, hi;
+                tri_top_fast(al, be, m, floor, &lo, &hi);
+                if (threadIdx.x == 0) {
+                    const double th = 0.5 * (lo + hi);
+                    const double shift = hi + (hi - lo) + 1e-13 * fabs(hi) + 1e-300;
+                    const double res = invariant ? 0.0 : tri_residual(al, be, m, shift, b, tx, tw);
+                    s_theta = th;
+                    s_flag = invariant || (res <= 1e-12 * fabs(th));
+                }
+            }
+            __syncthreads();
+            theta = s_theta;
+            floor = theta * (1.0 - 1e-14);
+            if (s_flag) break;
+        }
+        for (int i = threadIdx.x; i < PR; i += kLzWideThreads) {
+            const double x = w[i] / b;
+            v[i] = x;
+            if (i < p) V[(size_t)(j + 1) * p + i] = x;
+        }
+        __syncthreads();
+    }
+    // not settled within mmax steps: Gershgorin bound, as in lanczos_kernel
+    double dval = theta * (1.0 + 1e-10);
+    const bool ok = s_flag != 0;
+    if (!ok) {
+        double gm = 0.0;
+        for (int i = threadIdx.x; i < p; i += kLzWideThreads) {
+            double rr = 0.0;
+            for (int c = 0; c < p; ++c) rr += fabs(G[(size_t)c * p + i]);
+            gm = fmax(gm, rr);
+        }
+        gm = wave_max(gm);
+        __syncthreads();
+        if (lane == 0) red[wave] = gm;
+        __syncthreads();
+        gm = red[0];
+        for (int ww = 1; ww < kLzWideWaves; ++ww) gm = fmax(gm, red[ww]);
+        dval = fmax(dval, gm);
+    }
+    if (threadIdx.x == 0) {
+        d_out[q] = dval;
+        if (steps_out) steps_out[q] = ok ? m : -m;
+    }
+}
+
+size_t lanczos_wide_lds_bytes(int R, int mmax)
+{
+    return ((size_t)4 * 512 * R + 5 * (size_t)mmax + 1 + kLzWideWaves) * sizeof(double);
+}
+
 // One workgroup per problem.  V: (mmax + 1) x p workspace per problem.
 // LDS: v (p), w (p), alpha/beta/coef (mmax each), tridiagonal scratch.
 __global__ __launch_bounds__(kLzThreads) void lanczos_kernel(int p, int mmax,
@@ -532,6 +828,21 @@ int launch_lanczos(oem_gram_s *h, hipStream_t s)
     const int mmax = std::min(p, 1024);
     int rc = h->lanczos.ensure((size_t)nq * (mmax + 1) * p * sizeof(double));
     if (rc) return rc;
+    if (p <= 2048) {
+        const int R = p <= 512 ? 1 : (p <= 1024 ? 2 : 4);
+        const void *kern = R == 1 ? (const void *)lanczos_wide_kernel<1>
+                         : R == 2 ? (const void *)lanczos_wide_kernel<2> : (const void *)lanczos_wide_kernel<4>;
+        const size_t lw = lanczos_wide_lds_bytes(R, mmax);
+        OEM_HIP_CHECK(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lw));
+        const double *Gs = h->Gs.as<double>();
+        double *Vw = h->lanczos.as<double>();
+        double *dq = h->dq.as<double>();
+        int32_t *st = h->lzsteps.as<int32_t>();
+        int pa = p, ma = mmax;
+        void *args[] = {(void *)&pa, (void *)&ma, (void *)&Gs, (void *)&Vw, (void *)&dq, (void *)&st};
+        OEM_HIP_CHECK(hipLaunchKernel(kern, dim3(nq), dim3(kLzWideThreads), args, lw, s));
+        return OEM_OK;
+    }
     const size_t lds = (size_t)(p + 5 * mmax + 1 + kLzWaves + 4) * sizeof(double);
     hipLaunchKernelGGL(lanczos_kernel, dim3(nq), dim3(kLzThreads), lds, s, p, mmax,
                        h->Gs.as<double>(), h->lanczos.as<double>(), h->dq.as<double>(),

@@ -296,29 +296,35 @@ int launch_paths_reg(const PathDesc *d_desc, const int *d_order, int count, int 
                      hipStream_t s);
 int launch_paths_blk(const PathDesc *d_desc, const int *d_order, int count, int pmax,
                      hipStream_t s);
+int launch_paths_stream(const PathDesc *d_desc, const int *d_order, int count, int pmax,
+                        hipStream_t s);
 
 // Separable-penalty paths with p <= 128 go to the block kernel, group-lasso
-// paths with p <= 128 to the register kernel, the rest to the general kernel
-// (G in LDS when it fits, else streamed from L2).
+// paths with p <= 128 to the register kernel, paths with 128 < p <= 2048 to
+// the streaming kernel, and larger ones to the general kernel (G streamed
+// from L2 over the active columns).
 int launch_paths(const PathDesc *d_desc, const std::vector<PathDesc> &host, DevBuf &orderbuf,
                  hipStream_t s)
 {
     const int npaths = (int)host.size();
     if (npaths == 0) return OEM_OK;
-    std::vector<int> sep32, sep64, sep128, grp64, grp128, big;
-    int pmax_big = 0;
+    std::vector<int> sep32, sep64, sep128, grp64, grp128, mid, big;
+    int pmax_mid = 0, pmax_big = 0;
     for (int i = 0; i < npaths; ++i) {
         const int p = host[i].p;
         const bool grp = host[i].kind == OEM_GRP_LASSO;
         if (p <= 128 && !grp) (p <= 32 ? sep32 : p <= 64 ? sep64 : sep128).push_back(i);
         else if (p <= 128) (p <= 64 ? grp64 : grp128).push_back(i);
-        else {
+        else if (p <= 2048) {
+            mid.push_back(i);
+            pmax_mid = std::max(pmax_mid, p);
+        } else {
             big.push_back(i);
             pmax_big = std::max(pmax_big, p);
         }
     }
     std::vector<int> order;
-    for (const auto *v : {&sep32, &sep64, &sep128, &grp64, &grp128, &big})
+    for (const auto *v : {&sep32, &sep64, &sep128, &grp64, &grp128, &mid, &big})
         order.insert(order.end(), v->begin(), v->end());
     int rc = orderbuf.ensure(order.size() * sizeof(int));
     if (rc) return rc;
@@ -337,6 +343,8 @@ int launch_paths(const PathDesc *d_desc, const std::vector<PathDesc> &host, DevB
     off += grp64.size();
     rc = rc ? rc : launch_paths_reg(d_desc, d_order + off, (int)grp128.size(), 128, s);
     off += grp128.size();
+    rc = rc ? rc : launch_paths_stream(d_desc, d_order + off, (int)mid.size(), pmax_mid, s);
+    off += mid.size();
     if (rc) return rc;
     if (big.empty()) return OEM_OK;
     // keep G in LDS when the largest path's matrix fits next to its vectors

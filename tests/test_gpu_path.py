@@ -70,10 +70,11 @@ def test_small_lasso_workload_parity():
     assert np.allclose(res["obj"].cpu().numpy(), ref["obj"], rtol=1e-12)
 
 
-@pytest.mark.parametrize("p", [1, 2, 30, 64, 65, 150])
+@pytest.mark.parametrize("p", [1, 2, 30, 32, 33, 64, 65, 128, 150, 513])
 def test_four_penalties_parity(p):
-    print(f"case: tall_multi scaled n=20000 p={p}", flush=True)
-    pr = workloads.tall_multi(n=20_000, p=p, seed_tag=200 + p)
+    n = 20_000 if p <= 200 else 12_000
+    print(f"case: tall_multi scaled n={n} p={p}", flush=True)
+    pr = workloads.tall_multi(n=n, p=p, seed_tag=200 + p)
     pens = [dict(kind="lasso"), dict(kind="enet", alpha=0.5), dict(kind="mcp", gamma=3.0),
             dict(kind="scad", gamma=3.7)]
     res, ref = _fit_both(pr, pens, 30)
@@ -89,6 +90,17 @@ def test_group_lasso_parity_noncontiguous_groups():
     groups = rng.permutation(pr.groups).astype(np.int32)
     res, ref = _fit_both(pr, ["grp_lasso"], 25, groups=groups)
     _assert_paths(res["beta"].cpu().numpy(), ref["beta"], what="grp")
+
+
+def test_group_lasso_parity_large_p_noncontiguous():
+    """p = 300 (streaming kernel), shuffled group ids of size 10."""
+    print("case: group lasso p=300, shuffled group ids", flush=True)
+    pr = workloads.cv_grouped(n=15_000, p=300, group_size=10, active_groups=4, seed_tag=217)
+    rng = np.random.default_rng(1)
+    groups = rng.permutation(pr.groups).astype(np.int32)
+    res, ref = _fit_both(pr, ["grp_lasso", "lasso"], 20, groups=groups)
+    _assert_paths(res["beta"].cpu().numpy(), ref["beta"], what="grp p=300")
+    assert np.all(res["kkt"].cpu().numpy() <= 1e-8)
 
 
 def test_weights_and_unstandardized():
@@ -160,6 +172,23 @@ def test_cv_parity_grouped_workload_scaled():
         ref["cvm"][res["best"].item()].min() - ref["cvm"][ref["best"]].min()) <= 1e-9
 
 
+def test_cv_parity_grouped_large_p():
+    """CV with p = 200 (streaming kernel for every fold): K=3, three penalties."""
+    oem = _oem()
+    K, seed = 3, 777
+    print("case: cv_grouped scaled n=12000 p=200 K=3", flush=True)
+    pr = workloads.cv_grouped(n=12_000, p=200, group_size=10, active_groups=3, seed_tag=218)
+    pens = ["grp_lasso", "lasso", dict(kind="mcp", gamma=3.0)]
+    res = oem.cv(_cuda(pr.X), _cuda(pr.y), K, seed, pens, nlambda=12, tol=TOL, groups=pr.groups)
+    torch.cuda.synchronize()
+    ref = oracle.cv(pr.X, pr.y, K, seed, pens, groups=pr.groups, nlambda=12, tol=TOL)
+    _assert_paths(res["beta"].cpu().numpy(), ref["full"]["beta"], what="cv full p=200")
+    bf = res["beta_folds"].cpu().numpy()
+    for k in range(K):
+        _assert_paths(bf[k], ref["folds"][k]["beta"], what=f"cv fold {k} p=200")
+    assert np.allclose(res["cvm"].cpu().numpy(), ref["cvm"], rtol=1e-9, atol=0)
+
+
 def test_cv_equals_naive_refits():
     """oem_cv on fold statistics == separate fits on the physically split rows."""
     oem = _oem()
@@ -177,11 +206,11 @@ def test_cv_equals_naive_refits():
 
 @pytest.mark.parametrize("p,rho,corr", [(1, 0.0, "ar1"), (5, 0.3, "ar1"), (64, -0.6, "ar1"),
                                         (100, 0.5, "ar1"), (128, 0.25, "cs"), (129, -0.4, "ar1"),
-                                        (300, 0.3, "ar1")])
+                                        (300, 0.3, "ar1"), (520, 0.3, "ar1"), (1100, 0.2, "cs")])
 def test_d_matches_jacobi(p, rho, corr):
     """d = lambda_1(Gs)(1 + 1e-10) from Lanczos agrees with the oracle's Jacobi."""
     oem = _oem()
-    n = 4000 + 20 * p
+    n = 4000 + 20 * p if p <= 600 else 3 * p
     print(f"case: d p={p} rho={rho} {corr}", flush=True)
     X = workloads.draw_rows(n, p, rho, np.float32, workloads.subseed(300, p), correlation=corr)
     y = workloads.response(X, np.ones(p) / p, 1.0, workloads.subseed(301, p))
