@@ -191,6 +191,67 @@ int oem_cv(oem_handle g, const oem_penalty *pen, int32_t npen, const oem_path_op
            double *beta_full, double *beta_folds, double *lambda, double *cvm, double *cvsd,
            int32_t *i_min, int32_t *i_1se, int32_t *best, int32_t *iters, void *stream);
 
+/* Time the Gram pass of this handle's shape on the rows (X, n, ldx, y) (as
+ * oem_gram: device pointers, row-major) for several workgroup counts, keep
+ * the fastest for every later pass of the same (precision, folds, p rounded
+ * up to 32, floor(log2 n)) shape in this process, then clear the handle's
+ * sums as oem_gram_reset does.  Waits for `stream`.
+ * Errors: as oem_gram. */
+int oem_gram_autotune(oem_handle g, const void *X, int64_t n, int64_t ldx, const double *y,
+                      void *stream);
+
+/* ------------------------------------------------------------------ batches
+ * Many independent tall problems of uneven p fitted together (the same
+ * penalties and path options for all).  Each problem is the full-data fit of
+ * oem_fit_path: Gram pass, standardisation, d, lambda grid, warm-started
+ * paths.  All problems' d are found by one Lanczos launch per kernel class
+ * and all (problem, penalty) paths by one path launch per kernel class, so
+ * the launch count does not grow with the number of problems. */
+typedef struct {
+    int32_t p;            /* columns, 1..4096 */
+    int64_t n;            /* rows, 1..2^31-1 */
+    int64_t ldx;          /* row stride of X, >= p */
+    const void *X;        /* device, n x ldx row-major, element type x_dtype */
+    const double *y;      /* device, n */
+    double *beta;         /* device output, npen x L x p (original scale) */
+    double *lambda;       /* device output, npen x L, or NULL */
+    int32_t *iters;       /* device output, npen x L, or NULL */
+    double *kkt;          /* device output, npen x L, or NULL */
+    double *obj;          /* device output, npen x L, or NULL */
+} oem_problem;
+
+typedef struct oem_batch_s *oem_batch;
+
+/* Plan a batch: copies the nprob problem records (their X, y and output
+ * pointers must stay valid while the batch is used), creates every device
+ * buffer, tunes the Gram pass of each problem shape with n p >= 2^22
+ * (oem_gram_autotune), and runs the batch once on the null stream.
+ * Restrictions: opts->standardize = 1 (then d >= 1, so MCP gamma > 1 and
+ * SCAD gamma > 2 are valid for every problem), no group penalties and no
+ * explicit lambda (opts->groups, opts->lambda NULL).
+ * Errors: OEM_E_INVAL (bad problem record or option, nprob < 1),
+ * OEM_E_NOMEM, OEM_E_HIP. */
+int oem_batch_create(const oem_problem *probs, int32_t nprob, int32_t precision, int32_t x_dtype,
+                     const oem_penalty *pen, int32_t npen, const oem_path_opts *opts,
+                     oem_batch *out);
+
+/* Enqueue the whole batch on `stream`: per problem a Gram pass from zero
+ * sums and the standardisation, then the batched Lanczos, lambda-grid and
+ * path launches.  Kernels and device-to-device copies only: no allocation
+ * and no host wait, so the sequence may be captured into a hipGraph. */
+int oem_batch_run(oem_batch b, void *stream);
+
+/* The work of oem_batch_run captured into a hipGraph on the first call (on
+ * `stream`) and replayed with hipGraphLaunch on every call. */
+int oem_batch_run_graph(oem_batch b, void *stream);
+
+/* Wait for `stream`; OEM_NOT_CONVERGED if some lambda of some problem reached
+ * maxit in the last run, else OEM_OK. */
+int oem_batch_status(oem_batch b, void *stream);
+
+/* Release the batch's device buffers and graph (waits for the device). */
+void oem_batch_free(oem_batch b);
+
 /* Message for the calling thread's last non-OK return ("" if none). */
 const char *oem_last_error(void);
 

@@ -30,7 +30,9 @@ PENALTY_KIND = {"lasso": OEM_LASSO, "enet": OEM_ENET, "elastic_net": OEM_ENET, "
 PRECISION = {"fp64": OEM_FP64, "split_bf16": OEM_SPLIT_BF16, "bf16": OEM_BF16}
 
 EXPORTED = ["oem_gram_create", "oem_gram_free", "oem_gram_reset", "oem_gram", "oem_gram_import",
-            "oem_gram_export", "oem_fit_path", "oem_cv", "oem_last_error", "oem_version"]
+            "oem_gram_export", "oem_fit_path", "oem_cv", "oem_gram_autotune", "oem_batch_create",
+            "oem_batch_run", "oem_batch_run_graph", "oem_batch_status", "oem_batch_free",
+            "oem_last_error", "oem_version"]
 
 
 class OemError(RuntimeError):
@@ -50,6 +52,12 @@ class oem_path_opts(C.Structure):
                 ("standardize", C.c_int32), ("groups", C.POINTER(C.c_int32)),
                 ("w", C.POINTER(C.c_double)), ("cg", C.POINTER(C.c_double)),
                 ("sync", C.c_int32)]
+
+
+class oem_problem(C.Structure):
+    _fields_ = [("p", C.c_int32), ("n", C.c_int64), ("ldx", C.c_int64), ("X", C.c_void_p),
+                ("y", C.c_void_p), ("beta", C.c_void_p), ("lambda_", C.c_void_p),
+                ("iters", C.c_void_p), ("kkt", C.c_void_p), ("obj", C.c_void_p)]
 
 
 _lib = None
@@ -84,6 +92,17 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     L.oem_cv.restype = C.c_int
     L.oem_cv.argtypes = [vp, C.POINTER(oem_penalty), C.c_int32, C.POINTER(oem_path_opts), vp, vp,
                          vp, vp, vp, vp, vp, vp, vp, vp]
+    L.oem_gram_autotune.restype = C.c_int
+    L.oem_gram_autotune.argtypes = [vp, vp, C.c_int64, C.c_int64, vp, vp]
+    L.oem_batch_create.restype = C.c_int
+    L.oem_batch_create.argtypes = [C.POINTER(oem_problem), C.c_int32, C.c_int32, C.c_int32,
+                                   C.POINTER(oem_penalty), C.c_int32, C.POINTER(oem_path_opts),
+                                   C.POINTER(C.c_void_p)]
+    for name in ("oem_batch_run", "oem_batch_run_graph", "oem_batch_status"):
+        getattr(L, name).restype = C.c_int
+        getattr(L, name).argtypes = [vp, vp]
+    L.oem_batch_free.restype = None
+    L.oem_batch_free.argtypes = [vp]
     L.oem_last_error.restype = C.c_char_p
     L.oem_last_error.argtypes = []
     L.oem_version.restype = C.c_char_p
@@ -311,3 +330,70 @@ def cv(X, y, nfolds: int, fold_seed: int, penalties, precision: str = "fp64", fo
     with Gram(X.shape[1], nfolds, precision, X.dtype, fold_seed) as g:
         g.add(X, y, foldid=foldid)
         return g.cv(penalties, **kw)
+
+
+def oem_gram_autotune(h, X, y, stream=None) -> None:
+    """Tune the Gram pass of this handle's shape on (X, y); clears the sums."""
+    n, p = X.shape
+    _check(load_library().oem_gram_autotune(h, _ptr(X), n, X.stride(0), _ptr(y), _stream(stream)))
+
+
+class Batch:
+    """Many independent problems of uneven p fitted together (oem_batch_*).
+
+    ``problems`` is a list of (X, y) cuda tensors (X row-major, FP32 or FP64
+    for all).  Outputs are cuda tensors per problem, refreshed by run()."""
+
+    def __init__(self, problems, penalties, precision: str = "fp64", nlambda: int = 100,
+                 lambda_min_ratio: float = 1e-3, tol: float = 1e-10, maxit: int = 100000):
+        torch = _torch()
+        pens = _penalties(penalties)
+        self.npen, self.nlambda = len(pens), nlambda
+        self.pen_arr = (oem_penalty * len(pens))(*[q.c() for q in pens])
+        self.opts = _Opts(nlambda, lambda_min_ratio, None, tol, maxit, True, None, None, None, False)
+        f64 = dict(dtype=torch.float64, device="cuda")
+        self.inputs = [(X, y) for X, y in problems]          # keep the device memory alive
+        xd = OEM_X_F64 if problems[0][0].dtype == torch.float64 else OEM_X_F32
+        self.out = []
+        recs = []
+        for X, y in problems:
+            n, p = X.shape
+            o = dict(beta=torch.zeros((self.npen, nlambda, p), **f64),
+                     lambda_=torch.zeros((self.npen, nlambda), **f64),
+                     iters=torch.zeros((self.npen, nlambda), dtype=torch.int32, device="cuda"),
+                     kkt=torch.zeros((self.npen, nlambda), **f64),
+                     obj=torch.zeros((self.npen, nlambda), **f64))
+            self.out.append(o)
+            recs.append(oem_problem(p, n, X.stride(0), X.data_ptr(), y.data_ptr(), o["beta"].data_ptr(),
+                                    o["lambda_"].data_ptr(), o["iters"].data_ptr(), o["kkt"].data_ptr(),
+                                    o["obj"].data_ptr()))
+        self.recs = (oem_problem * len(recs))(*recs)
+        h = C.c_void_p()
+        _check(load_library().oem_batch_create(self.recs, len(recs), PRECISION[precision], xd,
+                                               self.pen_arr, self.npen, C.byref(self.opts.c),
+                                               C.byref(h)))
+        self.h = h
+
+    def run(self, graph: bool = False, stream=None) -> None:
+        f = load_library().oem_batch_run_graph if graph else load_library().oem_batch_run
+        _check(f(self.h, _stream(stream)))
+
+    def status(self, stream=None) -> int:
+        return _check(load_library().oem_batch_status(self.h, _stream(stream)))
+
+    def close(self):
+        if getattr(self, "h", None):
+            load_library().oem_batch_free(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -7,6 +7,7 @@
 #include <cstring>
 #include <numeric>
 
+#include "gram_common.h"
 #include "oem_internal.h"
 
 namespace oem {
@@ -267,6 +268,20 @@ static int finish_sync(const int32_t *d_iters, size_t count, hipStream_t s)
 
 } // namespace oem
 
+struct oem_batch_s {
+    std::vector<oem_problem> probs;
+    std::vector<oem_gram_s *> hs;
+    int32_t prec = OEM_FP64, xdt = OEM_X_F32, npen = 0;
+    std::vector<oem_penalty> pens;
+    oem_path_opts opts{};
+    oem::DevBuf descs, order, jobs, iters_own;
+    std::vector<oem::LzLaunch> lz;
+    oem::PathPlan plan;
+    std::vector<int32_t *> iters_of;   // per problem: where its iteration counts go
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
 using namespace oem;
 
 extern "C" {
@@ -515,6 +530,230 @@ int oem_cv(oem_handle h, const oem_penalty *pen, int32_t npen, const oem_path_op
     if (lambda)
         OEM_HIP_CHECK(hipMemcpyAsync(lambda, h->lam.ptr, nl * sizeof(double), hipMemcpyDeviceToDevice, s));
     if (opts->sync) return finish_sync(it, (size_t)(K + 1) * nl, s);
+    return OEM_OK;
+}
+
+int oem_gram_autotune(oem_handle h, const void *X, int64_t n, int64_t ldx, const double *y,
+                      void *stream)
+{
+    if (!h) return fail(OEM_E_INVAL, "handle is NULL");
+    if (n < 1 || n > INT32_MAX) return fail(OEM_E_INVAL, "n must be in [1, 2^31 - 1]");
+    if (!X || !y) return fail(OEM_E_INVAL, "X and y must not be NULL");
+    if (ldx < h->p) return fail(OEM_E_INVAL, "ldx must be >= p");
+    hipStream_t s = as_stream(stream);
+    const int cand[] = {256, 512, 1024, 2048};
+    hipEvent_t e0, e1;
+    OEM_HIP_CHECK(hipEventCreate(&e0));
+    OEM_HIP_CHECK(hipEventCreate(&e1));
+    int best = kGramDefaultTarget;
+    float best_ms = INFINITY;
+    int rc = OEM_OK;
+    for (int c : cand) {
+        gram_set_target(h->prec, h->K, h->p, n, c);
+        rc = launch_gram(h, X, n, ldx, y, 0, nullptr, s);   // sizes the buffers
+        if (rc) break;
+        if (hipEventRecord(e0, s) != hipSuccess) { rc = fail(OEM_E_HIP, "hipEventRecord failed"); break; }
+        for (int r = 0; r < 2 && !rc; ++r) rc = launch_gram(h, X, n, ldx, y, 0, nullptr, s);
+        if (rc) break;
+        float ms = 0.0f;
+        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+            rc = fail(OEM_E_HIP, "timing the Gram pass failed");
+            break;
+        }
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = c;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    gram_set_target(h->prec, h->K, h->p, n, best);
+    if (rc) return rc;
+    rc = oem_gram_reset(h, stream);
+    if (rc) return rc;
+    OEM_HIP_CHECK(hipStreamSynchronize(s));
+    return OEM_OK;
+}
+
+void oem_batch_free(oem_batch b)
+{
+    if (!b) return;
+    (void)hipDeviceSynchronize();
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    for (oem_gram_s *h : b->hs) oem_gram_free(h);
+    for (DevBuf *d : {&b->descs, &b->order, &b->jobs, &b->iters_own}) d->release();
+    delete b;
+}
+
+int oem_batch_run(oem_batch b, void *stream)
+{
+    if (!b) return fail(OEM_E_INVAL, "batch is NULL");
+    hipStream_t s = as_stream(stream);
+    const int L = b->opts.nlambda, npen = b->npen;
+    const size_t nl = (size_t)npen * L;
+    for (size_t i = 0; i < b->hs.size(); ++i) {
+        oem_gram_s *h = b->hs[i];
+        const oem_problem &pr = b->probs[i];
+        int rc = oem_gram_reset(h, stream);
+        rc = rc ? rc : launch_gram(h, pr.X, pr.n, pr.ldx, pr.y, 0, nullptr, s);
+        rc = rc ? rc : launch_combine(h, 1, s);
+        if (rc) return rc;
+    }
+    int rc = launch_lanczos_jobs(b->jobs.as<LzJob>(), b->lz, s);
+    if (rc) return rc;
+    for (oem_gram_s *h : b->hs) {
+        double *dl = h->lam.as<double>();
+        rc = launch_lambda_grid(h->cs.as<double>(), h->p, nullptr, nullptr, 0, nullptr, nullptr,
+                                reinterpret_cast<const oem_penalty *>(dl + nl), npen, L,
+                                b->opts.lambda_min_ratio, dl, s);
+        if (rc) return rc;
+    }
+    rc = launch_paths_planned(b->descs.as<PathDesc>(), b->order.as<int>(), b->plan, s);
+    if (rc) return rc;
+    for (size_t i = 0; i < b->hs.size(); ++i)
+        if (b->probs[i].lambda)
+            OEM_HIP_CHECK(hipMemcpyAsync(b->probs[i].lambda, b->hs[i]->lam.ptr, nl * sizeof(double),
+                                         hipMemcpyDeviceToDevice, s));
+    return OEM_OK;
+}
+
+int oem_batch_run_graph(oem_batch b, void *stream)
+{
+    if (!b) return fail(OEM_E_INVAL, "batch is NULL");
+    hipStream_t s = as_stream(stream);
+    if (!s) return fail(OEM_E_INVAL, "graph capture needs a stream other than the null stream");
+    if (!b->exec) {
+        OEM_HIP_CHECK(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
+        const int rc = oem_batch_run(b, stream);
+        hipGraph_t g = nullptr;
+        const hipError_t ec = hipStreamEndCapture(s, &g);
+        if (rc) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc;
+        }
+        if (ec != hipSuccess) return fail(OEM_E_HIP, std::string("graph capture failed: ") + hipGetErrorString(ec));
+        b->graph = g;
+        OEM_HIP_CHECK(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+    }
+    OEM_HIP_CHECK(hipGraphLaunch(b->exec, s));
+    return OEM_OK;
+}
+
+int oem_batch_status(oem_batch b, void *stream)
+{
+    if (!b) return fail(OEM_E_INVAL, "batch is NULL");
+    hipStream_t s = as_stream(stream);
+    OEM_HIP_CHECK(hipStreamSynchronize(s));
+    const size_t nl = (size_t)b->npen * b->opts.nlambda;
+    std::vector<int32_t> it(nl);
+    for (int32_t *d : b->iters_of) {
+        OEM_HIP_CHECK(hipMemcpy(it.data(), d, nl * sizeof(int32_t), hipMemcpyDeviceToHost));
+        for (int32_t v : it)
+            if (v < 0) {
+                set_error("some lambda of some problem reached maxit before the convergence test held");
+                return OEM_NOT_CONVERGED;
+            }
+    }
+    return OEM_OK;
+}
+
+int oem_batch_create(const oem_problem *probs, int32_t nprob, int32_t precision, int32_t x_dtype,
+                     const oem_penalty *pen, int32_t npen, const oem_path_opts *opts, oem_batch *out)
+{
+    if (!out) return fail(OEM_E_INVAL, "out is NULL");
+    *out = nullptr;
+    if (!probs || nprob < 1) return fail(OEM_E_INVAL, "need at least one problem");
+    if (!pen || npen < 1) return fail(OEM_E_INVAL, "need at least one penalty");
+    int rc = check_opts(opts);
+    if (rc) return rc;
+    if (!opts->standardize) return fail(OEM_E_INVAL, "batched fits need standardize = 1");
+    if (opts->groups || opts->lambda || opts->w || opts->cg)
+        return fail(OEM_E_INVAL, "batched fits take no groups, weights or explicit lambda");
+    for (int i = 0; i < npen; ++i) {
+        if (pen[i].kind == OEM_GRP_LASSO) return fail(OEM_E_INVAL, "batched fits take no group penalty");
+        rc = check_penalty(pen[i], 1.0);   // standardised: d >= 1
+        if (rc) return rc;
+    }
+    for (int i = 0; i < nprob; ++i) {
+        const oem_problem &q = probs[i];
+        if (q.p < 1 || q.p > 4096 || q.n < 1 || q.n > INT32_MAX || q.ldx < q.p || !q.X || !q.y || !q.beta)
+            return fail(OEM_E_INVAL, "problem " + std::to_string(i) + ": bad p, n, ldx or pointer");
+    }
+    oem_batch_s *b = new oem_batch_s();
+    b->probs.assign(probs, probs + nprob);
+    b->prec = precision;
+    b->xdt = x_dtype;
+    b->npen = npen;
+    b->pens.assign(pen, pen + npen);
+    b->opts = *opts;
+    b->opts.sync = 0;
+    const int L = opts->nlambda;
+    const size_t nl = (size_t)npen * L;
+    hipStream_t s = nullptr;
+    auto bail = [&](int code) {
+        oem_batch_free(b);
+        return code;
+    };
+    // handles, tuning, buffers sized by one pass each
+    size_t own_iters = 0;
+    for (int i = 0; i < nprob; ++i)
+        if (!probs[i].iters) own_iters += nl;
+    rc = b->iters_own.ensure(std::max<size_t>(own_iters, 1) * sizeof(int32_t));
+    if (rc) return bail(rc);
+    size_t own_off = 0;
+    std::vector<LzJob> jobs;
+    std::vector<PathDesc> descs;
+    for (int i = 0; i < nprob; ++i) {
+        const oem_problem &q = b->probs[i];
+        oem_gram_s *h = nullptr;
+        rc = oem_gram_create(q.p, 1, precision, x_dtype, 0, &h);
+        if (rc) return bail(rc);
+        b->hs.push_back(h);
+        if ((double)q.n * q.p >= 4194304.0) {
+            rc = oem_gram_autotune(h, q.X, q.n, q.ldx, q.y, nullptr);
+            if (rc) return bail(rc);
+        }
+        rc = launch_gram(h, q.X, q.n, q.ldx, q.y, 0, nullptr, s);
+        if (rc) return bail(rc);
+        const size_t ws = lanczos_workspace_doubles(q.p);
+        if (ws) {
+            rc = h->lanczos.ensure(ws * sizeof(double));
+            if (rc) return bail(rc);
+        }
+        rc = h->lam.ensure(nl * sizeof(double) + npen * sizeof(oem_penalty) + 64);
+        if (rc) return bail(rc);
+        if (hipMemcpy(h->lam.as<double>() + nl, pen, npen * sizeof(oem_penalty), hipMemcpyHostToDevice) != hipSuccess)
+            return bail(fail(OEM_E_HIP, "copying the penalties failed"));
+        jobs.push_back(LzJob{h->Gs.as<double>(), ws ? h->lanczos.as<double>() : nullptr, h->dq.as<double>(),
+                             h->lzsteps.as<int32_t>(), q.p, lanczos_mmax(q.p)});
+        int32_t *it = q.iters ? q.iters : b->iters_own.as<int32_t>() + own_off;
+        if (!q.iters) own_off += nl;
+        b->iters_of.push_back(it);
+        GroupPlan gp;
+        for (int k = 0; k < npen; ++k)
+            descs.push_back(make_desc(h, 0, pen[k], &b->opts, gp, h->lam.as<double>() + (size_t)k * L,
+                                      q.beta + (size_t)k * L * q.p, it + (size_t)k * L,
+                                      q.kkt ? q.kkt + (size_t)k * L : nullptr,
+                                      q.obj ? q.obj + (size_t)k * L : nullptr));
+    }
+    lanczos_job_plan(jobs, b->lz);
+    plan_paths(descs, b->plan);
+    rc = b->jobs.ensure(jobs.size() * sizeof(LzJob));
+    rc = rc ? rc : b->descs.ensure(descs.size() * sizeof(PathDesc));
+    rc = rc ? rc : b->order.ensure(b->plan.order.size() * sizeof(int));
+    if (rc) return bail(rc);
+    if (hipMemcpy(b->jobs.ptr, jobs.data(), jobs.size() * sizeof(LzJob), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(b->descs.ptr, descs.data(), descs.size() * sizeof(PathDesc), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(b->order.ptr, b->plan.order.data(), b->plan.order.size() * sizeof(int),
+                  hipMemcpyHostToDevice) != hipSuccess)
+        return bail(fail(OEM_E_HIP, "uploading the batch tables failed"));
+    // one full run: every buffer reaches its size, so later runs allocate nothing
+    rc = oem_batch_run(b, nullptr);
+    if (rc) return bail(rc);
+    if (hipDeviceSynchronize() != hipSuccess) return bail(fail(OEM_E_HIP, "the first batch run failed"));
+    *out = b;
     return OEM_OK;
 }
 

@@ -110,6 +110,24 @@ int launch_combine(oem_gram_s *h, int standardize, hipStream_t s)
 constexpr int kLzThreads = 256;
 constexpr int kLzWaves = kLzThreads / kWave;
 
+// The problem a Lanczos workgroup works on: from a job table (batched
+// launches over problems of different p) or from strided arrays (the K + 1
+// problems of one handle).
+__device__ inline LzJob lz_job(const LzJob *jobs, int p, int mmax, const double *Gs_all,
+                               double *V_all, double *d_out, int32_t *steps_out)
+{
+    if (jobs) return jobs[blockIdx.x];
+    const int q = blockIdx.x;
+    LzJob J;
+    J.G = Gs_all + (size_t)q * p * p;
+    J.V = V_all ? V_all + (size_t)q * (mmax + 1) * p : nullptr;
+    J.d = d_out + q;
+    J.steps = steps_out ? steps_out + q : nullptr;
+    J.p = p;
+    J.mmax = mmax;
+    return J;
+}
+
 __device__ inline double block_sum(double v, double *red)
 {
     for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
@@ -305,13 +323,16 @@ __device__ inline double wide_block_sum(double v, double *red)
 // value is tested at m = 8, 16, 24, 32, 40 and then every max(8, m / 4)
 // steps.
 template <int R>
-__global__ __launch_bounds__(kLzWideThreads) void lanczos_wide_kernel(int p, int mmax,
+__global__ __launch_bounds__(kLzWideThreads) void lanczos_wide_kernel(int p_all, int mmax_all,
                                                                       const double *__restrict__ Gs_all,
                                                                       double *__restrict__ V_all,
                                                                       double *__restrict__ d_out,
-                                                                      int32_t *__restrict__ steps_out)
+                                                                      int32_t *__restrict__ steps_out,
+                                                                      const LzJob *__restrict__ jobs)
 {
     constexpr int PR = 512 * R;
+    const LzJob J = lz_job(jobs, p_all, mmax_all, Gs_all, V_all, d_out, steps_out);
+    const int p = J.p, mmax = J.mmax;
     extern __shared__ double sm[];
     double *v = sm;                 // PR: current basis vector
     double *w = v + PR;             // PR
@@ -325,9 +346,8 @@ __global__ __launch_bounds__(kLzWideThreads) void lanczos_wide_kernel(int p, int
     __shared__ int s_flag;
     __shared__ double s_theta;
 
-    const int q = blockIdx.x;
-    const double *G = Gs_all + (size_t)q * p * p;
-    double *V = V_all + (size_t)q * (mmax + 1) * p;
+    const double *G = J.G;
+    double *V = J.V;
     const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
     const int half = wave / 8;
     int row[R];
@@ -506,8 +526,8 @@ __global__ __launch_bounds__(kLzWideThreads) void lanczos_wide_kernel(int p, int
         dval = fmax(dval, gm);
     }
     if (threadIdx.x == 0) {
-        d_out[q] = dval;
-        if (steps_out) steps_out[q] = ok ? m : -m;
+        *J.d = dval;
+        if (J.steps) *J.steps = ok ? m : -m;
     }
 }
 
@@ -518,16 +538,18 @@ size_t lanczos_wide_lds_bytes(int R, int mmax)
 
 // One workgroup per problem.  V: (mmax + 1) x p workspace per problem.
 // LDS: v (p), w (p), alpha/beta/coef (mmax each), tridiagonal scratch.
-__global__ __launch_bounds__(kLzThreads) void lanczos_kernel(int p, int mmax,
+__global__ __launch_bounds__(kLzThreads) void lanczos_kernel(int p_all, int mmax_all,
                                                              const double *__restrict__ Gs_all,
                                                              double *__restrict__ V_all,
                                                              double *__restrict__ d_out,
-                                                             int32_t *__restrict__ steps_out)
+                                                             int32_t *__restrict__ steps_out,
+                                                             const LzJob *__restrict__ jobs)
 {
     extern __shared__ double sm[];
-    const int q = blockIdx.x;
-    const double *G = Gs_all + (size_t)q * p * p;
-    double *V = V_all + (size_t)q * (mmax + 1) * p;
+    const LzJob J = lz_job(jobs, p_all, mmax_all, Gs_all, V_all, d_out, steps_out);
+    const int p = J.p, mmax = J.mmax;
+    const double *G = J.G;
+    double *V = J.V;
     double *w = sm;                 // p
     double *al = w + p;             // mmax
     double *be = al + mmax;         // mmax
@@ -647,8 +669,8 @@ __global__ __launch_bounds__(kLzThreads) void lanczos_kernel(int p, int mmax,
         dval = fmax(dval, gm);
     }
     if (threadIdx.x == 0) {
-        d_out[q] = dval;
-        if (steps_out) steps_out[q] = s_flag ? m : -m;
+        *J.d = dval;
+        if (J.steps) *J.steps = s_flag ? m : -m;
     }
 }
 
@@ -656,15 +678,17 @@ __global__ __launch_bounds__(kLzThreads) void lanczos_kernel(int p, int mmax,
 // (wave w, lane l) holds G[l + 64 r][NW c + w]), the Krylov basis V in LDS.
 // Same recurrence, reorthogonalisation and stopping rule as lanczos_kernel.
 template <int NW, int R, int CPW>
-__global__ __launch_bounds__(64 * NW) void lanczos_reg_kernel(int p, int mmax,
+__global__ __launch_bounds__(64 * NW) void lanczos_reg_kernel(int p_all, int mmax_all,
                                                               const double *__restrict__ Gs_all,
                                                               double *__restrict__ d_out,
-                                                              int32_t *__restrict__ steps_out)
+                                                              int32_t *__restrict__ steps_out,
+                                                              const LzJob *__restrict__ jobs)
 {
     constexpr int NT = 64 * NW;
     extern __shared__ double sm[];
-    const int q = blockIdx.x;
-    const double *G = Gs_all + (size_t)q * p * p;
+    const LzJob J = lz_job(jobs, p_all, mmax_all, Gs_all, nullptr, d_out, steps_out);
+    const int p = J.p, mmax = J.mmax;
+    const double *G = J.G;
     const int t = threadIdx.x, lane = t % kWave, wave = t / kWave;
     const int ldv = p + 1;                    // padded row pitch of V
     double *V = sm;                           // (mmax + 1) x ldv
@@ -796,58 +820,105 @@ __global__ __launch_bounds__(64 * NW) void lanczos_reg_kernel(int p, int mmax,
         dval = fmax(dval, gm);
     }
     if (t == 0) {
-        d_out[q] = dval;
-        if (steps_out) steps_out[q] = settled ? m : -m;
+        *J.d = dval;
+        if (J.steps) *J.steps = settled ? m : -m;
     }
+}
+
+// Lanczos kernel class of a problem size: 0, 1 register kernels (p <= 64,
+// <= 128), 2..4 wide kernels (p <= 512, 1024, 2048), 5 general kernel.
+static int lz_class(int p)
+{
+    if (p <= 64) return 0;
+    if (p <= 128) return 1;
+    if (p <= 512) return 2;
+    if (p <= 1024) return 3;
+    if (p <= 2048) return 4;
+    return 5;
+}
+
+int lanczos_mmax(int p) { return p <= 128 ? p : std::min(p, 1024); }
+
+size_t lanczos_workspace_doubles(int p)
+{
+    return p <= 128 ? 0 : (size_t)(lanczos_mmax(p) + 1) * p;
+}
+
+// One launch of `count` problems of one class: strided arrays (jobs == NULL)
+// or rows of a job table; pmax bounds the p of every problem in the launch.
+static int launch_lz_class(int cls, int count, int pmax, int p_all, const double *Gs_all,
+                           double *V_all, double *d_out, int32_t *steps_out, const LzJob *jobs,
+                           hipStream_t s)
+{
+    if (count == 0) return OEM_OK;
+    const int mmax = lanczos_mmax(pmax);
+    const int p_arg = p_all, m_arg = lanczos_mmax(p_all);
+    const void *kern = nullptr;
+    int threads = 0;
+    size_t lds = 0;
+    if (cls <= 1) {
+        const int NW = cls == 0 ? 4 : 8, R = cls == 0 ? 1 : 2;
+        lds = ((size_t)(mmax + 1) * (pmax + 1) + pmax + NW * 64 * R + 5 * mmax + 1 + NW) * sizeof(double);
+        kern = cls == 0 ? (const void *)lanczos_reg_kernel<4, 1, 16> : (const void *)lanczos_reg_kernel<8, 2, 16>;
+        threads = 64 * NW;
+        OEM_HIP_CHECK(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        void *args[] = {(void *)&p_arg, (void *)&m_arg, (void *)&Gs_all, (void *)&d_out, (void *)&steps_out,
+                        (void *)&jobs};
+        OEM_HIP_CHECK(hipLaunchKernel(kern, dim3(count), dim3(threads), args, lds, s));
+        return OEM_OK;
+    }
+    if (cls <= 4) {
+        const int R = cls == 2 ? 1 : (cls == 3 ? 2 : 4);
+        kern = R == 1 ? (const void *)lanczos_wide_kernel<1>
+             : R == 2 ? (const void *)lanczos_wide_kernel<2> : (const void *)lanczos_wide_kernel<4>;
+        lds = lanczos_wide_lds_bytes(R, mmax);
+        threads = kLzWideThreads;
+    } else {
+        kern = (const void *)lanczos_kernel;
+        lds = (size_t)(pmax + 5 * mmax + 1 + kLzWaves + 4) * sizeof(double);
+        threads = kLzThreads;
+    }
+    OEM_HIP_CHECK(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    void *args[] = {(void *)&p_arg, (void *)&m_arg, (void *)&Gs_all, (void *)&V_all, (void *)&d_out,
+                    (void *)&steps_out, (void *)&jobs};
+    OEM_HIP_CHECK(hipLaunchKernel(kern, dim3(count), dim3(threads), args, lds, s));
+    return OEM_OK;
 }
 
 int launch_lanczos(oem_gram_s *h, hipStream_t s)
 {
     const int p = h->p, nq = (h->K == 1) ? 1 : h->K + 1;
-    if (p <= 128) {
-        const int mmax = p;
-        const int NW = p <= 64 ? 4 : 8, R = p <= 64 ? 1 : 2;
-        const size_t lds = ((size_t)(mmax + 1) * (p + 1) + p + NW * 64 * R + 5 * mmax + 1 + NW) *
-                           sizeof(double);
-        if (p <= 64) {
-            if (lds > 64 * 1024)
-                OEM_HIP_CHECK(hipFuncSetAttribute((const void *)lanczos_reg_kernel<4, 1, 16>,
-                                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-            hipLaunchKernelGGL((lanczos_reg_kernel<4, 1, 16>), dim3(nq), dim3(256), lds, s, p, mmax,
-                               h->Gs.as<double>(), h->dq.as<double>(), h->lzsteps.as<int32_t>());
-        } else {
-            if (lds > 64 * 1024)
-                OEM_HIP_CHECK(hipFuncSetAttribute((const void *)lanczos_reg_kernel<8, 2, 16>,
-                                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-            hipLaunchKernelGGL((lanczos_reg_kernel<8, 2, 16>), dim3(nq), dim3(512), lds, s, p, mmax,
-                               h->Gs.as<double>(), h->dq.as<double>(), h->lzsteps.as<int32_t>());
-        }
-        OEM_HIP_CHECK(hipGetLastError());
-        return OEM_OK;
+    const size_t ws = lanczos_workspace_doubles(p);
+    if (ws) {
+        int rc = h->lanczos.ensure((size_t)nq * ws * sizeof(double));
+        if (rc) return rc;
     }
-    const int mmax = std::min(p, 1024);
-    int rc = h->lanczos.ensure((size_t)nq * (mmax + 1) * p * sizeof(double));
-    if (rc) return rc;
-    if (p <= 2048) {
-        const int R = p <= 512 ? 1 : (p <= 1024 ? 2 : 4);
-        const void *kern = R == 1 ? (const void *)lanczos_wide_kernel<1>
-                         : R == 2 ? (const void *)lanczos_wide_kernel<2> : (const void *)lanczos_wide_kernel<4>;
-        const size_t lw = lanczos_wide_lds_bytes(R, mmax);
-        OEM_HIP_CHECK(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lw));
-        const double *Gs = h->Gs.as<double>();
-        double *Vw = h->lanczos.as<double>();
-        double *dq = h->dq.as<double>();
-        int32_t *st = h->lzsteps.as<int32_t>();
-        int pa = p, ma = mmax;
-        void *args[] = {(void *)&pa, (void *)&ma, (void *)&Gs, (void *)&Vw, (void *)&dq, (void *)&st};
-        OEM_HIP_CHECK(hipLaunchKernel(kern, dim3(nq), dim3(kLzWideThreads), args, lw, s));
-        return OEM_OK;
+    return launch_lz_class(lz_class(p), nq, p, p, h->Gs.as<double>(), ws ? h->lanczos.as<double>() : nullptr,
+                           h->dq.as<double>(), h->lzsteps.as<int32_t>(), nullptr, s);
+}
+
+void lanczos_job_plan(std::vector<LzJob> &jobs, std::vector<LzLaunch> &launches)
+{
+    std::stable_sort(jobs.begin(), jobs.end(),
+                     [](const LzJob &a, const LzJob &b) { return lz_class(a.p) < lz_class(b.p); });
+    launches.clear();
+    for (size_t i = 0; i < jobs.size();) {
+        const int c = lz_class(jobs[i].p);
+        size_t j = i;
+        int pmax = 0;
+        while (j < jobs.size() && lz_class(jobs[j].p) == c) pmax = std::max(pmax, jobs[j++].p);
+        launches.push_back(LzLaunch{c, (int)i, (int)(j - i), pmax});
+        i = j;
     }
-    const size_t lds = (size_t)(p + 5 * mmax + 1 + kLzWaves + 4) * sizeof(double);
-    hipLaunchKernelGGL(lanczos_kernel, dim3(nq), dim3(kLzThreads), lds, s, p, mmax,
-                       h->Gs.as<double>(), h->lanczos.as<double>(), h->dq.as<double>(),
-                       h->lzsteps.as<int32_t>());
-    OEM_HIP_CHECK(hipGetLastError());
+}
+
+int launch_lanczos_jobs(const LzJob *d_jobs, const std::vector<LzLaunch> &launches, hipStream_t s)
+{
+    for (const LzLaunch &L : launches) {
+        int rc = launch_lz_class(L.cls, L.count, L.pmax, 0, nullptr, nullptr, nullptr, nullptr,
+                                 d_jobs + L.first, s);
+        if (rc) return rc;
+    }
     return OEM_OK;
 }
 

@@ -270,7 +270,7 @@ int launch_fill_i64(int64_t *p, size_t n, int64_t v, hipStream_t s)
     return OEM_OK;
 }
 
-static GramGeom plan_f64(int p, int K, int64_t n)
+static GramGeom plan_f64(int prec, int p, int K, int64_t n)
 {
     GramGeom g{};
     g.p = p;
@@ -283,7 +283,7 @@ static GramGeom plan_f64(int p, int K, int64_t n)
     g.ntp = g.T * (g.T + 1) / 2;
     g.K = K;
     g.rk = kRows;
-    const int64_t target = 512;
+    const int64_t target = gram_target(prec, K, p, n);
     int64_t ns = std::max<int64_t>(1, (target + (int64_t)K * g.npsb - 1) / ((int64_t)K * g.npsb));
     int64_t rps = (n + ns - 1) / ns;
     const int64_t quantum = (K == 1) ? kRows : 4096;
@@ -311,7 +311,7 @@ int launch_gram(oem_gram_s *h, const void *X, int64_t n, int64_t ldx, const doub
                 int64_t row_offset, const uint8_t *foldid, hipStream_t s)
 {
     if (h->prec != OEM_FP64) return launch_gram_bf16(h, X, n, ldx, y, row_offset, foldid, s);
-    const GramGeom g = plan_f64(h->p, h->K, n);
+    const GramGeom g = plan_f64(h->prec, h->p, h->K, n);
     RowSource rs;
     int rc = build_row_lists(h, g, n, row_offset, foldid, rs, s);
     if (rc) return rc;

@@ -416,7 +416,7 @@ __global__ void gram_bf16_scatter_kernel(GramGeom g, const double *__restrict__ 
     }
 }
 
-static GramGeom plan_bf16(int p, int K, int64_t n)
+static GramGeom plan_bf16(int prec, int p, int K, int64_t n)
 {
     GramGeom g{};
     g.p = p;
@@ -430,7 +430,7 @@ static GramGeom plan_bf16(int p, int K, int64_t n)
     g.K = K;
     g.rk = kBRows;
     // about two workgroups per CU; with folds, splits are whole 4096-row blocks
-    const int64_t target = 512;
+    const int64_t target = gram_target(prec, K, p, n);
     int64_t ns = std::max<int64_t>(1, (target + (int64_t)K * g.npsb - 1) / ((int64_t)K * g.npsb));
     int64_t rps = (n + ns - 1) / ns;
     const int64_t quantum = (K == 1) ? kBRows : 4096;
@@ -471,7 +471,7 @@ int launch_gram_bf16(oem_gram_s *h, const void *Xv, int64_t n, int64_t ldx, cons
 {
     if (h->xdt != OEM_X_F32) return fail(OEM_E_INVAL, "the BF16 Gram forms take FP32 X");
     const float *X = static_cast<const float *>(Xv);
-    const GramGeom g = plan_bf16(h->p, h->K, n);
+    const GramGeom g = plan_bf16(h->prec, h->p, h->K, n);
     RowSource rs;
     int rc = build_row_lists(h, g, n, row_offset, foldid, rs, s);
     if (rc) return rc;

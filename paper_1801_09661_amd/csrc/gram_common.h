@@ -84,6 +84,11 @@ __device__ inline int64_t row_at(int64_t first, const int32_t *list, int64_t i)
 }
 
 // ---- host-side launchers (gram_common.hip) ----
+// Target number of workgroups of a Gram pass (about two per CU by default;
+// oem_gram_autotune may pick another for a shape).
+constexpr int kGramDefaultTarget = 512;
+int gram_target(int prec, int K, int p, int64_t n);
+void gram_set_target(int prec, int K, int p, int64_t n, int target);
 // Build per-(fold, split) ordered row lists for rows 0..n-1.
 int build_row_lists(oem_gram_s *h, const GramGeom &g, int64_t n, int64_t row_offset,
                     const uint8_t *foldid, RowSource &rs, hipStream_t s);

@@ -7,7 +7,37 @@
 // and a split (a whole number of blocks) owns a contiguous piece of it.
 #include "gram_common.h"
 
+#include <map>
+#include <mutex>
+#include <tuple>
+
 namespace oem {
+
+// ---------------------------------------------------------------- tuning
+// Workgroup-count targets of the Gram pass chosen by oem_gram_autotune,
+// keyed by (precision, folds > 1, p rounded up to 32, floor(log2 n)).
+static std::mutex g_tune_mu;
+static std::map<std::tuple<int, int, int, int>, int> g_tune;
+
+static std::tuple<int, int, int, int> tune_key(int prec, int K, int p, int64_t n)
+{
+    int lg = 0;
+    while (lg < 62 && (int64_t(1) << (lg + 1)) <= n) ++lg;
+    return std::make_tuple(prec, K > 1 ? 1 : 0, (p + 31) / 32, lg);
+}
+
+int gram_target(int prec, int K, int p, int64_t n)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(tune_key(prec, K, p, n));
+    return it == g_tune.end() ? kGramDefaultTarget : it->second;
+}
+
+void gram_set_target(int prec, int K, int p, int64_t n, int target)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[tune_key(prec, K, p, n)] = target;
+}
 
 constexpr int kListBlock = 4096;
 constexpr int kListThreads = 256;

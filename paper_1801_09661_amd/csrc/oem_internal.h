@@ -89,6 +89,20 @@ struct PathDesc {
     int32_t prec;
 };
 
+// ------------------------------------------------------------------ Lanczos jobs
+// One problem of a batched Lanczos launch (d = lambda_1 (1 + 1e-10) of G).
+struct LzJob {
+    const double *G;     // p x p
+    double *V;           // (mmax + 1) x p workspace for p > 128, else unused
+    double *d;           // output
+    int32_t *steps;      // output or null
+    int p;
+    int mmax;
+};
+struct LzLaunch {
+    int cls, first, count, pmax;
+};
+
 // ------------------------------------------------------------------ handle
 struct DevBuf {
     void *ptr = nullptr;
@@ -130,11 +144,28 @@ int launch_gram_bf16(oem_gram_s *g, const void *X, int64_t n, int64_t ldx, const
                      int64_t row_offset, const uint8_t *foldid, hipStream_t s);
 int launch_combine(oem_gram_s *g, int standardize, hipStream_t s);
 int launch_lanczos(oem_gram_s *g, hipStream_t s);
+int lanczos_mmax(int p);
+size_t lanczos_workspace_doubles(int p);
+// sort jobs by kernel class and cut them into launches
+void lanczos_job_plan(std::vector<LzJob> &jobs, std::vector<LzLaunch> &launches);
+int launch_lanczos_jobs(const LzJob *d_jobs, const std::vector<LzLaunch> &launches, hipStream_t s);
 int launch_lambda_grid(const double *cs_full, int p, const int32_t *gstart, const int32_t *gidx,
                        int ngroups, const double *w, const double *cg, const oem_penalty *d_pens,
                        int npen, int L, double ratio, double *lambda_out, hipStream_t s);
 int launch_paths(const PathDesc *d_desc, const std::vector<PathDesc> &host, DevBuf &orderbuf,
                  hipStream_t s);
+// The same split into a plan (host: order table grouped by kernel class) and
+// launches that enqueue kernels only (no allocation, no host wait).
+struct PathLaunch {
+    int cls, first, count, pmax;
+};
+struct PathPlan {
+    std::vector<int> order;
+    std::vector<PathLaunch> launches;
+};
+void plan_paths(const std::vector<PathDesc> &host, PathPlan &plan);
+int launch_paths_planned(const PathDesc *d_desc, const int *d_order, const PathPlan &plan,
+                         hipStream_t s);
 int launch_cv(const double *Gk, const double *bk, const double *yyk, const int64_t *nk,
               int K, int p, int npen, int L, const double *beta_folds, double *mse,
               double *cvm, double *cvsd, int32_t *i_min, int32_t *i_1se, int32_t *best,

@@ -299,69 +299,82 @@ int launch_paths_blk(const PathDesc *d_desc, const int *d_order, int count, int 
 int launch_paths_stream(const PathDesc *d_desc, const int *d_order, int count, int pmax,
                         hipStream_t s);
 
-// Separable-penalty paths with p <= 128 go to the block kernel, group-lasso
-// paths with p <= 128 to the register kernel, paths with 128 < p <= 2048 to
-// the streaming kernel, and larger ones to the general kernel (G streamed
-// from L2 over the active columns).
+// Path kernel class: 0..2 block kernel (separable penalties, p <= 32, 64,
+// 128), 3, 4 register kernel (group lasso, p <= 64, 128), 5 streaming kernel
+// (128 < p <= 2048), 6 general kernel (larger p).
+static int path_class(const PathDesc &d)
+{
+    const bool grp = d.kind == OEM_GRP_LASSO;
+    if (d.p <= 128 && !grp) return d.p <= 32 ? 0 : (d.p <= 64 ? 1 : 2);
+    if (d.p <= 128) return d.p <= 64 ? 3 : 4;
+    return d.p <= 2048 ? 5 : 6;
+}
+
+void plan_paths(const std::vector<PathDesc> &host, PathPlan &plan)
+{
+    plan.order.clear();
+    plan.launches.clear();
+    for (int c = 0; c < 7; ++c) {
+        const int first = (int)plan.order.size();
+        int pmax = 0;
+        for (int i = 0; i < (int)host.size(); ++i)
+            if (path_class(host[i]) == c) {
+                plan.order.push_back(i);
+                pmax = std::max(pmax, host[i].p);
+            }
+        const int count = (int)plan.order.size() - first;
+        if (count) plan.launches.push_back(PathLaunch{c, first, count, pmax});
+    }
+}
+
+int launch_paths_planned(const PathDesc *d_desc, const int *d_order, const PathPlan &plan,
+                         hipStream_t s)
+{
+    for (const PathLaunch &L : plan.launches) {
+        const int *ord = d_order + L.first;
+        int rc = OEM_OK;
+        switch (L.cls) {
+        case 0: rc = launch_paths_blk(d_desc, ord, L.count, 32, s); break;
+        case 1: rc = launch_paths_blk(d_desc, ord, L.count, 64, s); break;
+        case 2: rc = launch_paths_blk(d_desc, ord, L.count, 128, s); break;
+        case 3: rc = launch_paths_reg(d_desc, ord, L.count, 64, s); break;
+        case 4: rc = launch_paths_reg(d_desc, ord, L.count, 128, s); break;
+        case 5: rc = launch_paths_stream(d_desc, ord, L.count, L.pmax, s); break;
+        default: {
+            // keep G in LDS when the largest path's matrix fits next to its vectors
+            const size_t limit = 150 * 1024;
+            int lds_g_max_p = 0;
+            size_t lds = path_lds_bytes(L.pmax, false);
+            if (path_lds_bytes(L.pmax, true) <= limit) {
+                lds_g_max_p = L.pmax;
+                lds = path_lds_bytes(L.pmax, true);
+            }
+            OEM_HIP_CHECK(hipFuncSetAttribute((const void *)path_kernel,
+                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+            hipLaunchKernelGGL(path_kernel, dim3(L.count), dim3(kPathThreads), lds, s, d_desc, ord,
+                               lds_g_max_p);
+            OEM_HIP_CHECK(hipGetLastError());
+        }
+        }
+        if (rc) return rc;
+    }
+    return OEM_OK;
+}
+
+// One set of launches for paths of any p: the order table groups the paths
+// by kernel class.
 int launch_paths(const PathDesc *d_desc, const std::vector<PathDesc> &host, DevBuf &orderbuf,
                  hipStream_t s)
 {
-    const int npaths = (int)host.size();
-    if (npaths == 0) return OEM_OK;
-    std::vector<int> sep32, sep64, sep128, grp64, grp128, mid, big;
-    int pmax_mid = 0, pmax_big = 0;
-    for (int i = 0; i < npaths; ++i) {
-        const int p = host[i].p;
-        const bool grp = host[i].kind == OEM_GRP_LASSO;
-        if (p <= 128 && !grp) (p <= 32 ? sep32 : p <= 64 ? sep64 : sep128).push_back(i);
-        else if (p <= 128) (p <= 64 ? grp64 : grp128).push_back(i);
-        else if (p <= 2048) {
-            mid.push_back(i);
-            pmax_mid = std::max(pmax_mid, p);
-        } else {
-            big.push_back(i);
-            pmax_big = std::max(pmax_big, p);
-        }
-    }
-    std::vector<int> order;
-    for (const auto *v : {&sep32, &sep64, &sep128, &grp64, &grp128, &mid, &big})
-        order.insert(order.end(), v->begin(), v->end());
-    int rc = orderbuf.ensure(order.size() * sizeof(int));
+    if (host.empty()) return OEM_OK;
+    PathPlan plan;
+    plan_paths(host, plan);
+    int rc = orderbuf.ensure(plan.order.size() * sizeof(int));
     if (rc) return rc;
-    OEM_HIP_CHECK(hipMemcpyAsync(orderbuf.ptr, order.data(), order.size() * sizeof(int),
+    OEM_HIP_CHECK(hipMemcpyAsync(orderbuf.ptr, plan.order.data(), plan.order.size() * sizeof(int),
                                  hipMemcpyHostToDevice, s));
     OEM_HIP_CHECK(hipStreamSynchronize(s));
-    const int *d_order = orderbuf.as<int>();
-    size_t off = 0;
-    rc = launch_paths_blk(d_desc, d_order + off, (int)sep32.size(), 32, s);
-    off += sep32.size();
-    rc = rc ? rc : launch_paths_blk(d_desc, d_order + off, (int)sep64.size(), 64, s);
-    off += sep64.size();
-    rc = rc ? rc : launch_paths_blk(d_desc, d_order + off, (int)sep128.size(), 128, s);
-    off += sep128.size();
-    rc = rc ? rc : launch_paths_reg(d_desc, d_order + off, (int)grp64.size(), 64, s);
-    off += grp64.size();
-    rc = rc ? rc : launch_paths_reg(d_desc, d_order + off, (int)grp128.size(), 128, s);
-    off += grp128.size();
-    rc = rc ? rc : launch_paths_stream(d_desc, d_order + off, (int)mid.size(), pmax_mid, s);
-    off += mid.size();
-    if (rc) return rc;
-    if (big.empty()) return OEM_OK;
-    // keep G in LDS when the largest path's matrix fits next to its vectors
-    const size_t limit = 150 * 1024;
-    int lds_g_max_p = 0;
-    size_t lds = path_lds_bytes(pmax_big, false);
-    if (path_lds_bytes(pmax_big, true) <= limit) {
-        lds_g_max_p = pmax_big;
-        lds = path_lds_bytes(pmax_big, true);
-    }
-    if (lds > 64 * 1024)
-        OEM_HIP_CHECK(hipFuncSetAttribute((const void *)path_kernel,
-                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    hipLaunchKernelGGL(path_kernel, dim3((int)big.size()), dim3(kPathThreads), lds, s, d_desc,
-                       d_order + off, lds_g_max_p);
-    OEM_HIP_CHECK(hipGetLastError());
-    return OEM_OK;
+    return launch_paths_planned(d_desc, orderbuf.as<int>(), plan, s);
 }
 
 int launch_lambda_grid(const double *cs_full, int p, const int32_t *gstart, const int32_t *gidx,

@@ -53,6 +53,17 @@ def test_invalid_arguments_rejected_without_gpu(lib):
                             None) == oem.OEM_E_INVAL
     assert lib.oem_cv(None, None, 0, None, None, None, None, None, None, None, None, None, None,
                       None) == oem.OEM_E_INVAL
+    b = ctypes.c_void_p()
+    pen = (oem.oem_penalty * 1)(oem.oem_penalty(oem.OEM_LASSO, 0.0, 0.0, 0.0))
+    opts = oem.oem_path_opts(10, 1e-3, None, 1e-10, 100, 1, None, None, None, 0)
+    assert lib.oem_batch_create(None, 0, 0, 0, pen, 1, ctypes.byref(opts), ctypes.byref(b)) == oem.OEM_E_INVAL
+    recs = (oem.oem_problem * 1)(oem.oem_problem(0, 10, 10, None, None, None, None, None, None, None))
+    assert lib.oem_batch_create(recs, 1, 0, 0, pen, 1, ctypes.byref(opts), ctypes.byref(b)) == oem.OEM_E_INVAL
+    assert b"bad p" in lib.oem_last_error()
+    opts.standardize = 0
+    assert lib.oem_batch_create(recs, 1, 0, 0, pen, 1, ctypes.byref(opts), ctypes.byref(b)) == oem.OEM_E_INVAL
+    assert lib.oem_batch_run(None, None) == oem.OEM_E_INVAL
+    assert lib.oem_gram_autotune(None, None, 0, 0, None, None) == oem.OEM_E_INVAL
 
 
 def test_no_cpu_fallback_without_gpu():
