@@ -252,6 +252,70 @@ int oem_batch_status(oem_batch b, void *stream);
 /* Release the batch's device buffers and graph (waits for the device). */
 void oem_batch_free(oem_batch b);
 
+/* ------------------------------------------------------------------ serving
+ * A request loop that keeps a number of fit and cross-validation requests
+ * of differing n and p in flight at once.  Each of `nslots` worker threads
+ * owns a stream and its device buffers; a request is admitted when a slot is
+ * free and the device bytes of the requests in flight plus its own stay
+ * within `device_bytes` (a request larger than the budget runs alone), in
+ * arrival order.  A request is: copy of X, y to the device (when they are
+ * host memory), Gram pass (with fold statistics for CV), and the full-data
+ * path of oem_fit_path or the cross validation of oem_cv, outputs copied to
+ * the caller's host arrays.  Requests in flight overlap on the device; each
+ * result is the one the request gives alone (same kernels, same inputs). */
+typedef struct {
+    int64_t id;                /* caller's tag, returned in the completion */
+    int32_t p;                 /* columns, 1..4096 */
+    int64_t n;                 /* rows, 1..2^31-1 */
+    int64_t ldx;               /* row stride of X, >= p */
+    const float *X;            /* FP32 rows: host (pinned: asynchronous copy) or device */
+    const double *y;           /* n responses: host or device */
+    int32_t nfolds;            /* 1: fit on all rows; 2..64: K-fold cross validation */
+    uint64_t fold_seed;        /* fold hash seed (cross validation) */
+    oem_penalty pen;           /* one penalty */
+    const int32_t *groups;     /* host, p group ids (group lasso), else NULL */
+    double *beta;              /* host output, L x p: full-data path, original scale */
+    double *lambda;            /* host output, L, or NULL */
+    double *cvm;               /* host output, L (cross validation), or NULL */
+    int32_t *i_min;            /* host output, 1 (cross validation), or NULL */
+    double t_arrival;          /* arrival time on the oem_server_now clock; < 0: submit time */
+} oem_request;
+
+typedef struct {
+    int64_t id;
+    int32_t status;            /* OEM_OK, OEM_NOT_CONVERGED or a negative error code */
+    int32_t slot;              /* worker that ran it */
+    double t_arrival, t_admit, t_done;   /* seconds on the oem_server_now clock */
+    int64_t bytes;             /* device bytes it was admitted with */
+} oem_completion;
+
+typedef struct oem_server_s *oem_server;
+
+/* Start the workers.  opts: the path options of every request (lambda,
+ * groups, w, cg must be NULL; a request's groups come with the request).
+ * Errors: OEM_E_INVAL (nslots not in 1..16, device_bytes < 1, bad opts). */
+int oem_server_create(int32_t nslots, int64_t device_bytes, int32_t precision,
+                      const oem_path_opts *opts, oem_server *out);
+
+/* Queue a request (copied; its host arrays must stay valid until its
+ * completion is returned).  Thread-safe.  Errors: OEM_E_INVAL (bad shape,
+ * pointer or fold count). */
+int oem_server_submit(oem_server s, const oem_request *req);
+
+/* Move up to `max` completions into out (host array), their number into
+ * *count; with wait != 0, block until at least one is available or nothing
+ * is queued or running. */
+int oem_server_poll(oem_server s, oem_completion *out, int32_t max, int32_t *count, int32_t wait);
+
+/* Block until every submitted request has completed. */
+int oem_server_drain(oem_server s);
+
+/* Seconds on the server's monotonic clock. */
+double oem_server_now(void);
+
+/* Stop the workers after the queued requests and release everything. */
+void oem_server_free(oem_server s);
+
 /* Message for the calling thread's last non-OK return ("" if none). */
 const char *oem_last_error(void);
 

@@ -32,7 +32,8 @@ PRECISION = {"fp64": OEM_FP64, "split_bf16": OEM_SPLIT_BF16, "bf16": OEM_BF16}
 EXPORTED = ["oem_gram_create", "oem_gram_free", "oem_gram_reset", "oem_gram", "oem_gram_import",
             "oem_gram_export", "oem_fit_path", "oem_cv", "oem_gram_autotune", "oem_batch_create",
             "oem_batch_run", "oem_batch_run_graph", "oem_batch_status", "oem_batch_free",
-            "oem_last_error", "oem_version"]
+            "oem_server_create", "oem_server_submit", "oem_server_poll", "oem_server_drain",
+            "oem_server_now", "oem_server_free", "oem_last_error", "oem_version"]
 
 
 class OemError(RuntimeError):
@@ -58,6 +59,20 @@ class oem_problem(C.Structure):
     _fields_ = [("p", C.c_int32), ("n", C.c_int64), ("ldx", C.c_int64), ("X", C.c_void_p),
                 ("y", C.c_void_p), ("beta", C.c_void_p), ("lambda_", C.c_void_p),
                 ("iters", C.c_void_p), ("kkt", C.c_void_p), ("obj", C.c_void_p)]
+
+
+class oem_request(C.Structure):
+    _fields_ = [("id", C.c_int64), ("p", C.c_int32), ("n", C.c_int64), ("ldx", C.c_int64),
+                ("X", C.c_void_p), ("y", C.c_void_p), ("nfolds", C.c_int32), ("fold_seed", C.c_uint64),
+                ("pen", oem_penalty), ("groups", C.c_void_p), ("beta", C.c_void_p),
+                ("lambda_", C.c_void_p), ("cvm", C.c_void_p), ("i_min", C.c_void_p),
+                ("t_arrival", C.c_double)]
+
+
+class oem_completion(C.Structure):
+    _fields_ = [("id", C.c_int64), ("status", C.c_int32), ("slot", C.c_int32),
+                ("t_arrival", C.c_double), ("t_admit", C.c_double), ("t_done", C.c_double),
+                ("bytes", C.c_int64)]
 
 
 _lib = None
@@ -103,6 +118,20 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         getattr(L, name).argtypes = [vp, vp]
     L.oem_batch_free.restype = None
     L.oem_batch_free.argtypes = [vp]
+    L.oem_server_create.restype = C.c_int
+    L.oem_server_create.argtypes = [C.c_int32, C.c_int64, C.c_int32, C.POINTER(oem_path_opts),
+                                    C.POINTER(C.c_void_p)]
+    L.oem_server_submit.restype = C.c_int
+    L.oem_server_submit.argtypes = [vp, C.POINTER(oem_request)]
+    L.oem_server_poll.restype = C.c_int
+    L.oem_server_poll.argtypes = [vp, C.POINTER(oem_completion), C.c_int32, C.POINTER(C.c_int32),
+                                  C.c_int32]
+    L.oem_server_drain.restype = C.c_int
+    L.oem_server_drain.argtypes = [vp]
+    L.oem_server_now.restype = C.c_double
+    L.oem_server_now.argtypes = []
+    L.oem_server_free.restype = None
+    L.oem_server_free.argtypes = [vp]
     L.oem_last_error.restype = C.c_char_p
     L.oem_last_error.argtypes = []
     L.oem_version.restype = C.c_char_p
@@ -384,6 +413,86 @@ class Batch:
     def close(self):
         if getattr(self, "h", None):
             load_library().oem_batch_free(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Request loop (oem_server_*): submit fit / CV requests, collect completions.
+
+    A request's X (FP32) and y may be pinned host tensors (pin_memory=True)
+    or cuda tensors; its outputs are host arrays returned with the
+    completion.  The caller keeps the inputs alive until then (the server
+    keeps a reference)."""
+
+    def __init__(self, nslots: int = 4, device_bytes: int = 64 << 30, precision: str = "fp64",
+                 nlambda: int = 100, lambda_min_ratio: float = 1e-3, tol: float = 1e-10,
+                 maxit: int = 100000):
+        self.nlambda = nlambda
+        self.opts = _Opts(nlambda, lambda_min_ratio, None, tol, maxit, True, None, None, None, False)
+        h = C.c_void_p()
+        _check(load_library().oem_server_create(nslots, int(device_bytes), PRECISION[precision],
+                                                C.byref(self.opts.c), C.byref(h)))
+        self.h = h
+        self.live = {}
+        self.results = {}
+
+    @staticmethod
+    def now() -> float:
+        return load_library().oem_server_now()
+
+    def submit(self, rid: int, X, y, penalty, nfolds: int = 1, fold_seed: int = 0, groups=None,
+               t_arrival: float = -1.0) -> None:
+        pen = _penalties([penalty])[0].c()
+        n, p = X.shape
+        L = self.nlambda
+        out = dict(beta=np.zeros((L, p)), lambda_=np.zeros(L), cvm=np.zeros(L),
+                   i_min=np.zeros(1, dtype=np.int32))
+        g = None if groups is None else np.ascontiguousarray(groups, dtype=np.int32)
+        dp = lambda a: a.ctypes.data
+        req = oem_request(int(rid), p, n, X.stride(0), X.data_ptr(), y.data_ptr(), int(nfolds),
+                          int(fold_seed), pen, None if g is None else dp(g), dp(out["beta"]),
+                          dp(out["lambda_"]), dp(out["cvm"]), dp(out["i_min"]), float(t_arrival))
+        self.live[int(rid)] = (X, y, g, out, req)
+        _check(load_library().oem_server_submit(self.h, C.byref(req)))
+
+    def poll(self, wait: bool = True, max_n: int = 256) -> list:
+        buf = (oem_completion * max_n)()
+        cnt = C.c_int32(0)
+        _check(load_library().oem_server_poll(self.h, buf, max_n, C.byref(cnt), 1 if wait else 0))
+        res = []
+        for i in range(cnt.value):
+            c = buf[i]
+            X, y, g, out, req = self.live.pop(int(c.id))
+            rec = dict(id=int(c.id), status=int(c.status), slot=int(c.slot), t_arrival=c.t_arrival,
+                       t_admit=c.t_admit, t_done=c.t_done, bytes=int(c.bytes), **out)
+            self.results[int(c.id)] = rec
+            res.append(rec)
+        return res
+
+    def drain(self) -> list:
+        _check(load_library().oem_server_drain(self.h))
+        out = []
+        while True:
+            got = self.poll(wait=False)
+            if not got:
+                return out
+            out.extend(got)
+
+    def close(self):
+        if getattr(self, "h", None):
+            load_library().oem_server_free(self.h)
             self.h = None
 
     def __enter__(self):

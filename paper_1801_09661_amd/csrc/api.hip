@@ -266,6 +266,32 @@ static int finish_sync(const int32_t *d_iters, size_t count, hipStream_t s)
     return OEM_OK;
 }
 
+// Give a handle new dimensions (buffers only grow) and clear its sums.
+int handle_reconfigure(oem_gram_s *h, int32_t p, int32_t K, int32_t prec, int32_t xdt, uint64_t seed,
+                       hipStream_t s)
+{
+    h->p = p;
+    h->K = K;
+    h->prec = prec;
+    h->xdt = xdt;
+    h->seed = seed;
+    const size_t pp = (size_t)p * p, nq = (K == 1) ? 1 : (size_t)K + 1;
+    int rc = OEM_OK;
+    rc = rc ? rc : h->Gk.ensure((size_t)K * pp * sizeof(double));
+    rc = rc ? rc : h->bk.ensure((size_t)K * p * sizeof(double));
+    rc = rc ? rc : h->yyk.ensure((size_t)K * sizeof(double));
+    rc = rc ? rc : h->nk.ensure((size_t)K * sizeof(int64_t));
+    rc = rc ? rc : h->Gs.ensure(nq * pp * sizeof(double));
+    rc = rc ? rc : h->cs.ensure(nq * p * sizeof(double));
+    rc = rc ? rc : h->sc.ensure(nq * p * sizeof(double));
+    rc = rc ? rc : h->yyn.ensure(nq * sizeof(double));
+    rc = rc ? rc : h->dq.ensure(nq * sizeof(double));
+    rc = rc ? rc : h->ntrain.ensure(nq * sizeof(int64_t));
+    rc = rc ? rc : h->lzsteps.ensure(nq * sizeof(int32_t));
+    if (rc) return rc;
+    return oem_gram_reset(h, s);
+}
+
 } // namespace oem
 
 struct oem_batch_s {
@@ -301,33 +327,11 @@ int oem_gram_create(int32_t p, int32_t nfolds, int32_t precision, int32_t x_dtyp
         return fail(OEM_E_INVAL, "unknown precision");
     if (x_dtype != OEM_X_F32 && x_dtype != OEM_X_F64) return fail(OEM_E_INVAL, "unknown x_dtype");
     oem_gram_s *h = new oem_gram_s();
-    h->p = p;
-    h->K = nfolds;
-    h->prec = precision;
-    h->xdt = x_dtype;
-    h->seed = fold_seed;
     if (hipGetDevice(&h->device) != hipSuccess) {
         delete h;
         return fail(OEM_E_HIP, "hipGetDevice failed");
     }
-    const size_t pp = (size_t)p * p, K = nfolds, nq = (nfolds == 1) ? 1 : nfolds + 1;
-    int rc = OEM_OK;
-    rc = rc ? rc : h->Gk.ensure(K * pp * sizeof(double));
-    rc = rc ? rc : h->bk.ensure(K * p * sizeof(double));
-    rc = rc ? rc : h->yyk.ensure(K * sizeof(double));
-    rc = rc ? rc : h->nk.ensure(K * sizeof(int64_t));
-    rc = rc ? rc : h->Gs.ensure(nq * pp * sizeof(double));
-    rc = rc ? rc : h->cs.ensure(nq * p * sizeof(double));
-    rc = rc ? rc : h->sc.ensure(nq * p * sizeof(double));
-    rc = rc ? rc : h->yyn.ensure(nq * sizeof(double));
-    rc = rc ? rc : h->dq.ensure(nq * sizeof(double));
-    rc = rc ? rc : h->ntrain.ensure(nq * sizeof(int64_t));
-    rc = rc ? rc : h->lzsteps.ensure(nq * sizeof(int32_t));
-    if (rc) {
-        oem_gram_free(h);
-        return rc;
-    }
-    rc = oem_gram_reset(h, nullptr);
+    int rc = handle_reconfigure(h, p, nfolds, precision, x_dtype, fold_seed, nullptr);
     if (rc == OEM_OK) rc = (hipStreamSynchronize(nullptr) == hipSuccess) ? OEM_OK : OEM_E_HIP;
     if (rc) {
         oem_gram_free(h);

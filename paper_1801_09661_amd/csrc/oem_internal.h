@@ -135,6 +135,8 @@ struct oem_gram_s {
 namespace oem {
 
 // ------------------------------------------------------------------ launchers
+int handle_reconfigure(oem_gram_s *h, int32_t p, int32_t K, int32_t prec, int32_t xdt, uint64_t seed,
+                       hipStream_t s);
 int launch_fill_f64(double *p, size_t n, double v, hipStream_t s);
 int launch_fill_i64(int64_t *p, size_t n, int64_t v, hipStream_t s);
 int launch_scale_f64(double *p, size_t n, double v, hipStream_t s);

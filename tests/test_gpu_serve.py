@@ -1,0 +1,124 @@
+"""GPU tests of the request loop (oem_server_*): results alone and in the mix
+are identical, admission respects the device-byte budget, results match the
+oracle.
+
+In the mix, several requests run at once on different streams, but each
+one runs the same kernels on the same inputs as when it runs alone, so the
+outputs must be bit-identical."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+def _oem():
+    import paper_1801_09661_amd as oem
+    return oem
+
+
+def _requests():
+    """(id, problem, penalty, nfolds, groups, host?) of differing n and p."""
+    specs = [(12, 6000, "lasso", 1), (50, 20000, dict(kind="mcp", gamma=3.0), 1),
+             (130, 15000, "lasso", 3), (40, 12000, "grp_lasso", 1),
+             (260, 9000, dict(kind="scad", gamma=3.7), 1), (24, 30000, dict(kind="mcp", gamma=3.0), 4),
+             (90, 8000, "grp_lasso", 3), (8, 5000, "lasso", 1)]
+    out = []
+    for i, (p, n, pen, K) in enumerate(specs):
+        req = workloads.Request(i, 0.0, n, p, 0.3 + 0.05 * (i % 4), "lasso", K, 0)
+        pr = workloads.serving_problem(req)
+        groups = (np.arange(p) // 5).astype(np.int32) if (isinstance(pen, str) and pen == "grp_lasso") else None
+        out.append((i, pr, pen, K, groups, i % 2 == 0))
+    return out
+
+
+def _submit_all(srv, reqs, seed=321):
+    keep = []
+    for rid, pr, pen, K, groups, host in reqs:
+        X = torch.from_numpy(pr.X)
+        y = torch.from_numpy(pr.y)
+        if host:
+            X, y = X.pin_memory(), y.pin_memory()
+        else:
+            X, y = X.cuda(), y.cuda()
+        keep.append((X, y))
+        srv.submit(rid, X, y, pen, nfolds=K, fold_seed=seed + rid, groups=groups)
+    return keep
+
+
+def test_server_same_alone_and_in_mix():
+    oem = _oem()
+    reqs = _requests()
+    print(f"case: {len(reqs)} requests, 4 slots vs alone", flush=True)
+    with oem.Server(nslots=4, device_bytes=8 << 30, nlambda=20, tol=TOL) as srv:
+        keep = _submit_all(srv, reqs)
+        mix = {r["id"]: r for r in srv.drain()}
+        torch.cuda.synchronize()
+    assert sorted(mix) == [r[0] for r in reqs]
+    assert all(r["status"] == oem.OEM_OK for r in mix.values())
+    # several requests were in flight together
+    iv = sorted((r["t_admit"], r["t_done"]) for r in mix.values())
+    assert any(iv[k + 1][0] < iv[k][1] for k in range(len(iv) - 1))
+    alone = {}
+    with oem.Server(nslots=1, device_bytes=8 << 30, nlambda=20, tol=TOL) as srv:
+        for req in reqs:
+            keep2 = _submit_all(srv, [req])
+            for r in srv.drain():
+                alone[r["id"]] = r
+            del keep2
+    for rid in mix:
+        for key in ("beta", "lambda_", "cvm", "i_min"):
+            assert np.array_equal(mix[rid][key], alone[rid][key]), f"request {rid} {key}"
+    # fits against the oracle
+    for rid, pr, pen, K, groups, host in reqs:
+        if K != 1 or rid not in (0, 1, 3):
+            continue
+        ref = oracle.fit(pr.X, pr.y, [pen], groups=groups, nlambda=20, tol=TOL)
+        b = mix[rid]["beta"]
+        for l in range(20):
+            r = ref["beta"][0, l]
+            s = np.abs(r).max()
+            if s == 0.0:
+                assert np.all(b[l] == 0.0)
+            else:
+                assert np.abs(b[l] - r).max() <= TOL * s, f"request {rid} lambda {l}"
+    # one CV request against the oracle's held-out error
+    rid, pr, pen, K, groups, host = reqs[2]
+    ref = oracle.cv(pr.X, pr.y, K, 321 + rid, [pen], groups=groups, nlambda=20, tol=TOL)
+    assert np.allclose(mix[rid]["cvm"], ref["cvm"][0], rtol=1e-9, atol=0)
+
+
+def test_server_admission_by_bytes():
+    oem = _oem()
+    reqs = _requests()[:6]
+    with oem.Server(nslots=4, device_bytes=8 << 30, nlambda=10, tol=1e-8) as srv:
+        keep = _submit_all(srv, reqs)
+        first = srv.drain()
+    big = max(r["bytes"] for r in first)
+    budget = int(1.2 * big)
+    print(f"case: budget {budget} bytes, largest request {big}", flush=True)
+    with oem.Server(nslots=4, device_bytes=budget, nlambda=10, tol=1e-8) as srv:
+        keep = _submit_all(srv, reqs)
+        done = srv.drain()
+    assert len(done) == len(reqs) and all(r["status"] == oem.OEM_OK for r in done)
+    # at every admission, the bytes in flight stayed within the budget
+    for r in done:
+        t = r["t_admit"]
+        live = sum(q["bytes"] for q in done if q["t_admit"] <= t < q["t_done"])
+        assert live <= budget or live == r["bytes"]
+
+
+def test_server_rejects_bad_request():
+    oem = _oem()
+    with oem.Server(nslots=1, nlambda=5) as srv:
+        X = torch.zeros((10, 3), dtype=torch.float32).cuda()
+        y = torch.zeros(10, dtype=torch.float64).cuda()
+        with pytest.raises(oem.OemError):
+            srv.submit(1, X, y, "lasso", nfolds=0)
+        with pytest.raises(oem.OemError):
+            srv.submit(2, X, y, "grp_lasso")          # no groups
