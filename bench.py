@@ -45,6 +45,11 @@ def parse():
     ap.add_argument("--cpu-sample-rows", type=int, default=100_000)
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="run only this many steps (for profilers) and skip the baseline")
+    ap.add_argument("--serve", action="store_true",
+                    help="serving workload instead: Poisson arrivals of fit / CV requests")
+    ap.add_argument("--requests", type=int, default=2000)
+    ap.add_argument("--rate", type=float, default=50.0)
+    ap.add_argument("--slots", type=int, default=8)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="after the steps, copy X once with a plain device copy (traffic calibration)")
     return ap.parse_args()
@@ -162,12 +167,97 @@ def run_form(oem, torch, X, y, precision, steps, warm, nlambda):
                 updates=int(np.abs(iters).sum()), beta=beta)
 
 
+def serve_main(args):
+    """Serving workload: requests with Poisson arrivals at `rate`/s, p
+    log-uniform in [10, 1000], n log-uniform in [1e4, 1e6] (n >= 10 p),
+    AR(1) rows in pinned host memory, penalty uniform over lasso / MCP / SCAD
+    / group lasso (groups of 5), 20% with 5-fold CV, 100 lambdas, split-BF16
+    Gram.  Latency runs from arrival to the result in host memory.  Prints
+    one JSON line."""
+    import numpy as np
+    import torch
+    from concurrent.futures import ThreadPoolExecutor
+    import paper_1801_09661_amd as oem
+    import workloads
+    import oracle
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    oem.load_library()
+    reqs = workloads.serving_requests(count=args.requests, rate_per_s=args.rate)
+    nmax, pmax = max(r.n for r in reqs), max(r.p for r in reqs)
+    t0 = time.perf_counter()
+    pool = {}
+    for bk in sorted({workloads.serving_bucket(r.rho) for r in reqs}):
+        pool[bk] = torch.from_numpy(workloads.serving_pool(nmax, pmax, bk)).pin_memory()
+    views = [pool[workloads.serving_bucket(r.rho)][:r.n, :r.p] for r in reqs]
+    offs = np.concatenate([[0], np.cumsum([r.n for r in reqs])])
+    yall = torch.empty(int(offs[-1]), dtype=torch.float64).pin_memory()
+
+    def make_y(i):
+        y, _ = workloads.serving_response(reqs[i], views[i].numpy())
+        yall[int(offs[i]):int(offs[i + 1])] = torch.from_numpy(y)
+
+    with ThreadPoolExecutor(16) as ex:
+        list(ex.map(make_y, range(len(reqs))))
+    t_setup = time.perf_counter() - t0
+    L = 100
+    kinds = {"lasso": "lasso", "mcp": dict(kind="mcp", gamma=3.0), "scad": dict(kind="scad", gamma=3.7),
+             "grp_lasso": "grp_lasso"}
+    srv = oem.Server(nslots=args.slots, device_bytes=200 << 30, precision="split_bf16", nlambda=L, tol=1e-10)
+    start = srv.now() + 0.5
+    done = []
+    for r, X in zip(reqs, views):
+        while srv.now() < start + r.arrival_s:
+            done.extend(srv.poll(wait=False))
+            time.sleep(0.0005)
+        groups = (np.arange(r.p) // 5).astype(np.int32) if r.penalty == "grp_lasso" else None
+        srv.submit(r.index, X, yall[int(offs[r.index]):int(offs[r.index + 1])], kinds[r.penalty],
+                   nfolds=r.nfolds, fold_seed=r.fold_seed, groups=groups, t_arrival=start + r.arrival_s)
+    done.extend(srv.drain())
+    srv.close()
+    lat = np.array([d["t_done"] - d["t_arrival"] for d in done])
+    dev = np.array([d["t_done"] - d["t_admit"] for d in done])
+    span = max(d["t_done"] for d in done) - start
+    xbytes = sum(r.n * r.p * 4 for r in reqs)
+    # accuracy on a sample of small plain fits against the FP64 oracle on the
+    # lambdas the request used (untimed)
+    res = {d["id"]: d for d in done}
+    sample = [r for r in reqs if r.nfolds == 1 and r.p <= 120 and r.n <= 60000][:8]
+    worst = 0.0
+    for r in sample:
+        X = np.ascontiguousarray(views[r.index].numpy())
+        y = yall[int(offs[r.index]):int(offs[r.index + 1])].numpy()
+        groups = (np.arange(r.p) // 5).astype(np.int32) if r.penalty == "grp_lasso" else None
+        ref = oracle.fit(X, y, [kinds[r.penalty]], groups=groups, lambdas=res[r.index]["lambda_"][None, :],
+                         tol=1e-10)
+        for l in range(1, L):
+            sc = np.abs(ref["beta"][0, l]).max()
+            if sc > 0:
+                worst = max(worst, float(np.abs(res[r.index]["beta"][l] - ref["beta"][0, l]).max() / sc))
+    out = {
+        "metric": "serve p50/p99 latency (arrival to result in host memory)",
+        "value": len(done) / span, "unit": "requests/s", "n_gpus": 1, "higher_is_better": True,
+        "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
+        "device_p50_ms": float(np.percentile(dev, 50) * 1e3), "device_p99_ms": float(np.percentile(dev, 99) * 1e3),
+        "x_gb_per_s": xbytes / span / 1e9, "requests": len(done),
+        "not_ok": int(sum(d["status"] != 0 for d in done)), "setup_s": t_setup,
+        "coef_err_vs_fp64_oracle_sample": worst, "sample": len(sample),
+        "dtype": "split-bf16 Gram (f32 acc, f64 reduce) + f64 paths", "data": "synthetic",
+        "config": {"workload": f"serving: {args.requests} requests, Poisson {args.rate}/s, p in [10,1000], "
+                               "n in [1e4,1e6], AR(1) rho~U(0,0.8) (8 levels), lasso/MCP/SCAD/group lasso, "
+                               "20% 5-fold CV, 100 lambdas", "slots": args.slots},
+    }
+    print(json.dumps(out))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
+    if args.serve:
+        return serve_main(args)
     import numpy as np
     import torch
     import paper_1801_09661_amd as oem

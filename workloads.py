@@ -218,6 +218,29 @@ def serving_problem(req: Request, seed_tag: int = 5) -> Problem:
                    meta=dict(workload="serving", index=req.index, n=req.n, p=req.p))
 
 
+# The serving benchmark cannot draw ~185 MB of fresh rows per request at 50
+# requests/s, so requests take the first n rows and p columns of one of 8
+# pre-drawn matrices, one per AR(1) correlation level (rho quantised to the
+# centres 0.05, 0.15, ..., 0.75); each request keeps its own coefficients and
+# noise.
+def serving_bucket(rho: float) -> int:
+    return min(7, int(rho / 0.1))
+
+
+def serving_pool(n: int, p: int, bucket: int, seed_tag: int = 5) -> np.ndarray:
+    return draw_rows(n, p, 0.05 + 0.1 * bucket, np.float32, subseed(seed_tag, 900 + bucket))
+
+
+def serving_response(req: Request, X: np.ndarray, seed_tag: int = 5):
+    """(y, beta) of request `req` on rows X (n x p, any row stride)."""
+    k = int(math.ceil(0.05 * req.p))
+    b = sparse_beta(req.p, k, subseed(seed_tag, 10 + req.index, 1))
+    supp = np.flatnonzero(b)
+    g = _rng(subseed(seed_tag, 10 + req.index, 2))
+    y = X[:, supp].astype(np.float64) @ b[supp] + g.standard_normal(X.shape[0])
+    return y, b
+
+
 def integer_rows(n: int, p: int, lo: int = -8, hi: int = 8, seed_tag: int = 6,
                  dtype=np.float32) -> np.ndarray:
     """Integer-valued X: every Gram product and partial sum is exact in FP32/BF16/FP64."""
