@@ -1,28 +1,31 @@
 // Streaming Gram pass (Section 3: per-fold X_k^T X_k and X_k^T y_k in one
 // pass over the rows) for gfx950.
 //
-// FP64 form: the augmented matrix [X y] is staged through LDS in 64-row
-// chunks and multiplied on the FP64 matrix cores (v_mfma_f64_16x16x4f64); FP32
-// X is kept FP32 in LDS and widened (exactly) when an operand is read, y is
-// kept FP64.  The upper triangle of [X y]^T [X y] holds X^T X, X^T y
-// (column p) and y^T y (corner), so one contraction gives every statistic.
+// FP64 form: X is staged through LDS in 64-row chunks (FP32 X stays FP32 in
+// LDS and is widened, exactly, when an operand is read) and X^T X is formed on
+// the FP64 matrix cores (v_mfma_f64_16x16x4f64).  X^T y and y^T y are
+// accumulated in FP64 on the vector units from the loaded values, by the
+// workgroups of the diagonal super-blocks.
 //
 // Work decomposition: the upper triangle of 16x16 tiles is cut into
 // super-blocks of W x W tiles; a workgroup owns one (fold, row split,
-// super-block pair) and streams that split's rows of its fold (a
-// precomputed ordered row list), so every row is fetched once per
-// super-block pair.  Each thread loads an 8-row x 4-column block per chunk,
-// and the next chunk's loads are issued before the current chunk's MFMAs.
-// Workgroups sharing a row split are numbered so that round-robin dispatch
-// places them on one XCD, where they share that XCD's L2.  Partial tiles are
-// summed over splits in a fixed order (deterministic, no floating-point
-// atomics).
+// super-block pair) and streams that split's rows (contiguous rows with one
+// fold, an ordered row list per (fold, split) with several), so every row is
+// fetched once per super-block pair.  Thread (q, rg) loads columns
+// 4q .. 4q + 3 of 8 rows (16-byte loads when rows are aligned) and the next
+// chunk's loads are issued before the current chunk's MFMAs; rows past the
+// end of the split are read as copies of its last row and cleared before
+// staging.  Workgroups sharing a row split are numbered so that round-robin
+// dispatch places them on one XCD, where they share that XCD's L2.  Partial
+// tiles are summed over splits in a fixed order (deterministic, no
+// floating-point atomics).
 #include "gram_common.h"
 
 namespace oem {
 
 typedef double d4_t __attribute__((ext_vector_type(4)));
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
+typedef double f64x2_t __attribute__((ext_vector_type(2)));
 
 constexpr int kGramThreads = 256;
 constexpr int kGramWaves = kGramThreads / kWave;
@@ -31,66 +34,80 @@ constexpr int kPanelCols = 16 * kMaxW;                     // 128
 constexpr int kRows = 64;                                  // rows per chunk (16 MFMA k-steps)
 constexpr int kMaxSlots = (kMaxW * kMaxW + kGramWaves - 1) / kGramWaves;  // tile pairs per wave
 
-// LDS row pitch (elements) of a staged panel: 128 + 4 keeps 16-byte rows
-// aligned and shifts successive rows across banks.
-constexpr int kPitch = kPanelCols + 4;
+// LDS row pitch (elements) of a staged row-major panel: 16-byte aligned rows,
+// successive rows shifted across banks.
+template <typename XT> constexpr int panel_pitch() { return sizeof(XT) == 4 ? kPanelCols + 4 : kPanelCols + 2; }
 
-// Thread (c4, rg) loads rows 8 rg .. 8 rg + 7, columns 4 c4 .. 4 c4 + 3 of a
-// panel and stores them row-major into LDS (elements of the input type).
+// Thread (q, rg): columns col .. col + 3 of the 8 rows `row`.  Columns at or
+// past p read a valid column instead (they only feed discarded tile entries).
 template <typename XT, bool VEC>
-__device__ inline void load_rows(XT (&b)[8][4], const XT *__restrict__ X, int64_t ldx, int p, int col,
-                                 const int64_t *rows, const bool *ok)
+__device__ inline void load_block64(XT (&x)[8][4], const XT *__restrict__ X, int64_t ldx, int p, int col,
+                                    const int64_t (&row)[8])
 {
+    if constexpr (VEC) {
+        const int cv = (col + 3 < p) ? col : 0;          // p % 4 == 0 here
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-        if constexpr (VEC) {
-            if (ok[e] && col + 3 < p) {
-                const f32x4_t v = *reinterpret_cast<const f32x4_t *>(X + rows[e] * ldx + col);
-                b[e][0] = v[0];
-                b[e][1] = v[1];
-                b[e][2] = v[2];
-                b[e][3] = v[3];
-                continue;
+        for (int e = 0; e < 8; ++e) {
+            const XT *src = X + row[e] * ldx + cv;
+            if constexpr (sizeof(XT) == 4) {
+                const f32x4_t v = *reinterpret_cast<const f32x4_t *>(src);
+#pragma unroll
+                for (int j = 0; j < 4; ++j) x[e][j] = v[j];
+            } else {
+                const f64x2_t v0 = *reinterpret_cast<const f64x2_t *>(src);
+                const f64x2_t v1 = *reinterpret_cast<const f64x2_t *>(src + 2);
+                x[e][0] = v0[0];
+                x[e][1] = v0[1];
+                x[e][2] = v1[0];
+                x[e][3] = v1[1];
             }
         }
+    } else {
+        int cj[4];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) b[e][j] = (ok[e] && col + j < p) ? X[rows[e] * ldx + col + j] : XT(0);
+        for (int j = 0; j < 4; ++j) cj[j] = min(col + j, p - 1);
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) x[e][j] = X[row[e] * ldx + cj[j]];
     }
 }
 
 template <typename XT>
-__device__ inline void store_rows(const XT (&b)[8][4], XT *panel, int c4, int rg)
+__device__ inline void store_block64(const XT (&x)[8][4], XT *panel, int q, int rg)
 {
+    constexpr int PP = panel_pitch<XT>();
 #pragma unroll
     for (int e = 0; e < 8; ++e)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) panel[(8 * rg + e) * kPitch + 4 * c4 + j] = b[e][j];
+        for (int j = 0; j < 4; ++j) panel[(8 * rg + e) * PP + 4 * q + j] = x[e][j];
 }
 
-template <typename XT, bool VEC>
+template <typename XT, bool LIST, bool VEC>
 __global__ __launch_bounds__(kGramThreads) void gram_f64_kernel(
     const XT *__restrict__ X, int64_t n, int64_t ldx, const double *__restrict__ y, GramGeom g,
-    RowSource rs, double *__restrict__ partial, double *__restrict__ pscal)
+    RowSource rs, double *__restrict__ partial, double *__restrict__ pvec, double *__restrict__ pscal)
 {
+    constexpr int PP = panel_pitch<XT>();
     extern __shared__ double smem[];
     const int lane = threadIdx.x % kWave;
     const int wave = threadIdx.x / kWave;
-    const int c4 = threadIdx.x % 32, rg = threadIdx.x / 32;
+    const int q4 = threadIdx.x % 32, rg = threadIdx.x / 32;
 
     const int L = xcd_logical(blockIdx.x, gridDim.x);
-    const int q = L % g.npsb;
+    const int qq = L % g.npsb;
     const int rest = L / g.npsb;
     const int s = rest % g.nsplit;
     const int k = rest / g.nsplit;
     int I = 0, J = 0;
-    sb_pair_decode(q, g.nsb, I, J);
+    sb_pair_decode(qq, g.nsb, I, J);
     const int Wi = min(g.W, g.T - I * g.W);
     const int Wj = min(g.W, g.T - J * g.W);
     const bool diag = (I == J);
+    const bool first_block = (qq == 0);
 
-    double *ylds = smem;                                   // kRows
-    XT *A = reinterpret_cast<XT *>(smem + kRows);          // kRows x kPitch
-    XT *B = diag ? A : A + kRows * kPitch;
+    XT *A = reinterpret_cast<XT *>(smem);
+    XT *B = diag ? A : A + kRows * PP;
 
     const int npairs = diag ? Wi * (Wi + 1) / 2 : Wi * Wj;
     int ta[kMaxSlots], tb[kMaxSlots];
@@ -124,53 +141,86 @@ __global__ __launch_bounds__(kGramThreads) void gram_f64_kernel(
     const int32_t *list;
     rows_of(g, rs, n, k, s, first, count, list);
     const int nchunks = (int)((count + kRows - 1) / kRows);
-    const int baseA = I * g.W * 16, baseB = J * g.W * 16;
+    const int colA = I * g.W * 16 + 4 * q4, colB = J * g.W * 16 + 4 * q4;
+    double sxy[4] = {0.0, 0.0, 0.0, 0.0}, syy = 0.0;
 
-    XT ba[8][4], bb[8][4];
-    double yv = 0.0;
+    XT xa[8][4], xb[8][4];
+    double yv[8];
+    int32_t nidx[8];
+    auto load_index = [&](int c) {
+        if constexpr (LIST) {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) nidx[e] = list[min((int64_t)c * kRows + 8 * rg + e, count - 1)];
+        }
+    };
     auto load_chunk = [&](int c) {
-        int64_t rows[8];
-        bool ok[8];
+        int64_t row[8];
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
-            const int64_t i = (int64_t)c * kRows + 8 * rg + e;
-            ok[e] = i < count;
-            rows[e] = ok[e] ? row_at(first, list, i) : 0;
+            if constexpr (LIST) row[e] = nidx[e];
+            else row[e] = first + min((int64_t)c * kRows + 8 * rg + e, count - 1);
         }
-        load_rows<XT, VEC>(ba, X, ldx, g.p, baseA + 4 * c4, rows, ok);
-        if (!diag) load_rows<XT, VEC>(bb, X, ldx, g.p, baseB + 4 * c4, rows, ok);
-        if (threadIdx.x < kRows) {
-            const int64_t i = (int64_t)c * kRows + threadIdx.x;
-            yv = (i < count) ? y[row_at(first, list, i)] : 0.0;
+        load_block64<XT, VEC>(xa, X, ldx, g.p, colA, row);
+        if (!diag) load_block64<XT, VEC>(xb, X, ldx, g.p, colB, row);
+        if (diag) {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) yv[e] = y[row[e]];
         }
     };
-    // operand of augmented column `col` (global index) at chunk row r
-    auto aug = [&](const XT *panel, int base, int r, int cl) -> double {
-        const int col = base + cl;
-        if (col < g.p) return (double)panel[r * kPitch + cl];
-        return (col == g.p) ? ylds[r] : 0.0;
+    auto clear_tail = [&](int c) {
+        const int64_t r0 = (int64_t)c * kRows + 8 * rg;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            if (r0 + e >= count) {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    xa[e][j] = XT(0);
+                    xb[e][j] = XT(0);
+                }
+                yv[e] = 0.0;
+            }
+        }
+    };
+    auto stage_chunk = [&]() {
+        store_block64<XT>(xa, A, q4, rg);
+        if (!diag) store_block64<XT>(xb, B, q4, rg);
+        if (diag) {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) sxy[j] += (double)xa[e][j] * yv[e];
+                syy += yv[e] * yv[e];
+            }
+        }
     };
     auto mma_chunk = [&]() {
+#pragma unroll 4
         for (int kk = 0; kk < kRows / 4; ++kk) {
             const int r = 4 * kk + lane / 16;
 #pragma unroll
             for (int t = 0; t < kMaxSlots; ++t) {
                 if (t < nslots) {
-                    const double a = aug(A, baseA, r, ta[t] * 16 + (lane % 16));
-                    const double b = aug(B, baseB, r, tb[t] * 16 + (lane % 16));
+                    const double a = (double)A[r * PP + ta[t] * 16 + (lane % 16)];
+                    const double b = (double)B[r * PP + tb[t] * 16 + (lane % 16)];
                     acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[t], 0, 0, 0);
                 }
             }
         }
     };
 
-    if (nchunks > 0) load_chunk(0);
+    if (nchunks > 0) {
+        load_index(0);
+        load_chunk(0);
+        load_index(1);
+    }
     for (int c = 0; c < nchunks; ++c) {
-        store_rows(ba, A, c4, rg);
-        if (!diag) store_rows(bb, B, c4, rg);
-        if (threadIdx.x < kRows) ylds[threadIdx.x] = yv;
+        if ((int64_t)(c + 1) * kRows > count) clear_tail(c);
+        stage_chunk();
         __syncthreads();
-        if (c + 1 < nchunks) load_chunk(c + 1);   // in flight during the MFMAs
+        if (c + 1 < nchunks) {
+            load_chunk(c + 1);   // in flight during the MFMAs
+            load_index(c + 2);
+        }
         mma_chunk();
         __syncthreads();
     }
@@ -186,39 +236,60 @@ __global__ __launch_bounds__(kGramThreads) void gram_f64_kernel(
             for (int r = 0; r < 4; ++r) dst[(4 * r + lane / 16) * 16 + (lane % 16)] = acc[t][r];
         }
     }
-    if (q == 0 && threadIdx.x == 0) pscal[part_id] = (double)count;
+    // X^T y and y^T y: the 8 row groups of a column combined in order
+    if (diag) {
+        double *vred = smem;   // 8 x kPanelCols + 8
+#pragma unroll
+        for (int j = 0; j < 4; ++j) vred[rg * kPanelCols + 4 * q4 + j] = sxy[j];
+        if (q4 == 0) vred[8 * kPanelCols + rg] = syy;
+        __syncthreads();
+        if (threadIdx.x < kPanelCols) {
+            const int col = I * g.W * 16 + threadIdx.x;
+            double b = 0.0;
+            for (int r = 0; r < 8; ++r) b += vred[r * kPanelCols + threadIdx.x];
+            if (col < g.p) pvec[part_id * g.p + col] = b;
+        }
+        if (first_block && threadIdx.x == 0) {
+            double t = 0.0;
+            for (int r = 0; r < 8; ++r) t += vred[8 * kPanelCols + r];
+            pscal[part_id * 2] = t;
+            pscal[part_id * 2 + 1] = (double)count;
+        }
+    }
 }
 
-// Add the reduced tiles of [X y]^T [X y] into G, X^T y and y^T y; the upper
-// triangle is mirrored so G stays exactly symmetric.
+// Add the reduced tiles into G (upper triangle mirrored, so G stays exactly
+// symmetric), X^T y into b, y^T y and n.
 __global__ void gram_f64_scatter_kernel(GramGeom g, const double *__restrict__ tiles,
-                                        const double *__restrict__ cnt, double *__restrict__ Gk,
-                                        double *__restrict__ bk, double *__restrict__ yyk,
-                                        int64_t *__restrict__ nk)
+                                        const double *__restrict__ vec, const double *__restrict__ scal,
+                                        double *__restrict__ Gk, double *__restrict__ bk,
+                                        double *__restrict__ yyk, int64_t *__restrict__ nk)
 {
-    const size_t per_k = (size_t)g.ntp * 256;
-    const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx < (size_t)g.K) nk[idx] += (int64_t)cnt[idx];
-    if (idx >= (size_t)g.K * per_k) return;
-    const int e = (int)(idx % 256);
-    const int tp = (int)((idx / 256) % g.ntp);
-    const int k = (int)(idx / per_k);
-    int ti, tj;
-    tile_pair_decode(tp, g.T, ti, tj);
-    const int ei = e / 16, ej = e % 16;
-    if (ti == tj && ei > ej) return;
-    const int i = ti * 16 + ei, j = tj * 16 + ej;
-    if (i > g.p || j > g.p) return;
-    const double sum = tiles[idx];
     const int p = g.p;
-    if (j < p) {
+    const size_t Et = (size_t)g.ntp * 256;
+    const size_t per_k = Et + p + 1;
+    const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (size_t)g.K * per_k) return;
+    const int k = (int)(idx / per_k);
+    const size_t e = idx % per_k;
+    if (e < Et) {
+        const int te = (int)(e % 256);
+        const int tp = (int)(e / 256);
+        int ti, tj;
+        tile_pair_decode(tp, g.T, ti, tj);
+        const int ei = te / 16, ej = te % 16;
+        if (ti == tj && ei > ej) return;
+        const int i = ti * 16 + ei, j = tj * 16 + ej;
+        if (i >= p || j >= p) return;
+        const double v = tiles[(size_t)k * Et + e];
         double *G = Gk + (size_t)k * p * p;
-        G[(size_t)i * p + j] += sum;
-        if (i != j) G[(size_t)j * p + i] += sum;
-    } else if (i < p) {
-        bk[(size_t)k * p + i] += sum;
+        G[(size_t)i * p + j] += v;
+        if (i != j) G[(size_t)j * p + i] += v;
+    } else if (e < Et + p) {
+        bk[(size_t)k * p + (e - Et)] += vec[(size_t)k * p + (e - Et)];
     } else {
-        yyk[k] += sum;
+        yyk[k] += scal[(size_t)k * 2];
+        nk[k] += (int64_t)scal[(size_t)k * 2 + 1];
     }
 }
 
@@ -274,9 +345,9 @@ static GramGeom plan_f64(int prec, int p, int K, int64_t n)
 {
     GramGeom g{};
     g.p = p;
-    g.pa = p + 1;
+    g.pa = p;
     g.tile = 16;
-    g.T = (g.pa + 15) / 16;
+    g.T = (p + 15) / 16;
     g.W = std::min(g.T, kMaxW);
     g.nsb = (g.T + g.W - 1) / g.W;
     g.npsb = g.nsb * (g.nsb + 1) / 2;
@@ -293,17 +364,22 @@ static GramGeom plan_f64(int prec, int p, int K, int64_t n)
     return g;
 }
 
-template <typename XT, bool VEC>
-static int launch_f64_t(const GramGeom &g, const XT *X, int64_t n, int64_t ldx, const double *y,
-                        const RowSource &rs, double *part, double *pscal, hipStream_t s)
+template <typename XT>
+static int launch_f64_t(const GramGeom &g, bool list, bool vec, const XT *X, int64_t n, int64_t ldx,
+                        const double *y, const RowSource &rs, double *part, double *pvec, double *pscal,
+                        hipStream_t s)
 {
     const int npanels = (g.nsb == 1) ? 1 : 2;
-    const size_t lds = kRows * sizeof(double) + (size_t)npanels * kRows * kPitch * sizeof(XT);
-    const int blocks = g.K * g.nsplit * g.npsb;
-    auto kern = gram_f64_kernel<XT, VEC>;
-    OEM_HIP_CHECK(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    hipLaunchKernelGGL(kern, dim3(blocks), dim3(kGramThreads), lds, s, X, n, ldx, y, g, rs, part, pscal);
-    OEM_HIP_CHECK(hipGetLastError());
+    const size_t lds = std::max((size_t)npanels * kRows * panel_pitch<XT>() * sizeof(XT),
+                                (size_t)(8 * kPanelCols + 8) * sizeof(double));
+    const void *kern;
+    if (list) kern = vec ? (const void *)gram_f64_kernel<XT, true, true> : (const void *)gram_f64_kernel<XT, true, false>;
+    else kern = vec ? (const void *)gram_f64_kernel<XT, false, true> : (const void *)gram_f64_kernel<XT, false, false>;
+    const unsigned blocks = (unsigned)(g.K * g.nsplit * g.npsb);
+    OEM_HIP_CHECK(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    void *args[] = {(void *)&X, (void *)&n, (void *)&ldx, (void *)&y, (void *)&g, (void *)&rs,
+                    (void *)&part, (void *)&pvec, (void *)&pscal};
+    OEM_HIP_CHECK(hipLaunchKernel(kern, dim3(blocks), dim3(kGramThreads), args, lds, s));
     return OEM_OK;
 }
 
@@ -316,33 +392,39 @@ int launch_gram(oem_gram_s *h, const void *X, int64_t n, int64_t ldx, const doub
     int rc = build_row_lists(h, g, n, row_offset, foldid, rs, s);
     if (rc) return rc;
     const size_t K = g.K, S = g.nsplit;
-    const size_t E = (size_t)g.ntp * 256;
-    rc = h->partial.ensure((K * S * E + K * S + 8) * sizeof(double));
+    const size_t Et = (size_t)g.ntp * 256;
+    const size_t parts = K * S;
+    rc = h->partial.ensure((parts * (Et + g.p + 2) + 8) * sizeof(double));
     if (rc) return rc;
     double *part = h->partial.as<double>();
-    double *pscal = part + K * S * E;
-    const size_t red = reduce_tmp_doubles(g.K, g.nsplit, E) + K * (E + 1) + 8;
+    double *pvec = part + parts * Et;
+    double *pscal = pvec + parts * g.p;
+    const size_t red = reduce_tmp_doubles(g.K, g.nsplit, Et) + K * (Et + g.p + 2) + 8;
     rc = h->redtmp.ensure(red * sizeof(double));
     if (rc) return rc;
+    const bool list = g.K > 1;
     if (h->xdt == OEM_X_F32) {
         const float *Xf = static_cast<const float *>(X);
-        const bool vec = ((reinterpret_cast<uintptr_t>(Xf) & 15) == 0) && (ldx % 4 == 0);
-        rc = vec ? launch_f64_t<float, true>(g, Xf, n, ldx, y, rs, part, pscal, s)
-                 : launch_f64_t<float, false>(g, Xf, n, ldx, y, rs, part, pscal, s);
+        const bool vec = ((reinterpret_cast<uintptr_t>(Xf) & 15) == 0) && (ldx % 4 == 0) && (g.p % 4 == 0);
+        rc = launch_f64_t<float>(g, list, vec, Xf, n, ldx, y, rs, part, pvec, pscal, s);
     } else {
-        rc = launch_f64_t<double, false>(g, static_cast<const double *>(X), n, ldx, y, rs, part, pscal, s);
+        const double *Xd = static_cast<const double *>(X);
+        const bool vec = ((reinterpret_cast<uintptr_t>(Xd) & 15) == 0) && (ldx % 4 == 0) && (g.p % 4 == 0);
+        rc = launch_f64_t<double>(g, list, vec, Xd, n, ldx, y, rs, part, pvec, pscal, s);
     }
     if (rc) return rc;
     double *tmp = h->redtmp.as<double>();
-    double *out_tiles = tmp + reduce_tmp_doubles(g.K, g.nsplit, E);
-    double *out_cnt = out_tiles + K * E;
-    rc = reduce_splits_f64(part, g.K, g.nsplit, E, tmp, out_tiles, s);
-    rc = rc ? rc : reduce_splits_f64(pscal, g.K, g.nsplit, 1, tmp, out_cnt, s);
+    double *out_tiles = tmp + reduce_tmp_doubles(g.K, g.nsplit, Et);
+    double *out_vec = out_tiles + K * Et;
+    double *out_scal = out_vec + K * g.p;
+    rc = reduce_splits_f64(part, g.K, g.nsplit, Et, tmp, out_tiles, s);
+    rc = rc ? rc : reduce_splits_f64(pvec, g.K, g.nsplit, (size_t)g.p, tmp, out_vec, s);
+    rc = rc ? rc : reduce_splits_f64(pscal, g.K, g.nsplit, 2, tmp, out_scal, s);
     if (rc) return rc;
-    const size_t total = K * E;
+    const size_t total = K * (Et + g.p + 1);
     hipLaunchKernelGGL(gram_f64_scatter_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, g,
-                       out_tiles, out_cnt, h->Gk.as<double>(), h->bk.as<double>(), h->yyk.as<double>(),
-                       h->nk.as<int64_t>());
+                       out_tiles, out_vec, out_scal, h->Gk.as<double>(), h->bk.as<double>(),
+                       h->yyk.as<double>(), h->nk.as<int64_t>());
     OEM_HIP_CHECK(hipGetLastError());
     return OEM_OK;
 }
