@@ -346,8 +346,8 @@ __global__ __launch_bounds__(kLzWideThreads) void lanczos_wide_kernel(int p_all,
     __shared__ int s_flag;
     __shared__ double s_theta;
 
-    const double *G = J.G;
-    double *V = J.V;
+    const auto G = gmem(J.G);
+    const auto V = gmem(J.V);
     const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
     const int half = wave / 8;
     int row[R];
@@ -374,7 +374,7 @@ __global__ __launch_bounds__(kLzWideThreads) void lanczos_wide_kernel(int p_all,
 
     // out[rows] = sum over the columns c in [c0, c1) of M[c][rows] * x_c, x
     // in LDS; M row-major with row length p (M = G or the basis V)
-    auto colsum = [&](const double *M, const double *x, int c0, int c1, double (&out)[R]) {
+    auto colsum = [&](auto M, const double *x, int c0, int c1, double (&out)[R]) {
         constexpr int U = R >= 4 ? 4 : 8;   // loads in flight per lane and row
         double acc[R][4];
 #pragma unroll
@@ -439,8 +439,8 @@ __global__ __launch_bounds__(kLzWideThreads) void lanczos_wide_kernel(int p_all,
             // coef[mm] = <v_mm, w>: wave w takes mm = w, w + 16, ...; lanes run over rows
             for (int mm0 = wave; mm0 <= j; mm0 += 2 * kLzWideWaves) {
                 const int mm1 = mm0 + kLzWideWaves;
-                const double *v0 = V + (size_t)mm0 * p;
-                const double *v1 = V + (size_t)min(mm1, j) * p;
+                const auto v0 = V + (size_t)mm0 * p;
+                const auto v1 = V + (size_t)min(mm1, j) * p;
                 double t0 = 0.0, t1 = 0.0;
                 for (int i = lane; i < p; i += kWave) {
                     t0 += v0[i] * w[i];
@@ -548,8 +548,8 @@ __global__ __launch_bounds__(kLzThreads) void lanczos_kernel(int p_all, int mmax
     extern __shared__ double sm[];
     const LzJob J = lz_job(jobs, p_all, mmax_all, Gs_all, V_all, d_out, steps_out);
     const int p = J.p, mmax = J.mmax;
-    const double *G = J.G;
-    double *V = J.V;
+    const auto G = gmem(J.G);
+    const auto V = gmem(J.V);
     double *w = sm;                 // p
     double *al = w + p;             // mmax
     double *be = al + mmax;         // mmax
@@ -575,7 +575,7 @@ __global__ __launch_bounds__(kLzThreads) void lanczos_kernel(int p_all, int mmax
     int m = 0;
     double theta = 0.0;
     for (int j = 0; j < mmax; ++j) {
-        const double *vj = V + (size_t)j * p;
+        const auto vj = V + (size_t)j * p;
         // w = G v_j (G symmetric: column reads are coalesced across threads)
         for (int i = threadIdx.x; i < p; i += kLzThreads) {
             double acc = 0.0;
@@ -596,7 +596,7 @@ __global__ __launch_bounds__(kLzThreads) void lanczos_kernel(int p_all, int mmax
         for (int pass = 0; pass < 2; ++pass) {
             const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
             for (int mm = wave; mm <= j; mm += kLzWaves) {
-                const double *vm = V + (size_t)mm * p;
+                const auto vm = V + (size_t)mm * p;
                 double t = 0.0;
                 for (int i = lane; i < p; i += kWave) t += vm[i] * w[i];
                 for (int o = kWave / 2; o > 0; o >>= 1) t += __shfl_xor(t, o);
@@ -626,7 +626,7 @@ __global__ __launch_bounds__(kLzThreads) void lanczos_kernel(int p_all, int mmax
         __syncthreads();
         const bool test_now = invariant || (m % 8 == 0) || (m == mmax);
         if (!test_now) {
-            double *vn = V + (size_t)(j + 1) * p;
+            const auto vn = V + (size_t)(j + 1) * p;
             for (int i = threadIdx.x; i < p; i += kLzThreads) vn[i] = w[i] / b;
             __syncthreads();
             continue;
@@ -645,7 +645,7 @@ __global__ __launch_bounds__(kLzThreads) void lanczos_kernel(int p_all, int mmax
         __syncthreads();
         theta = s_theta;
         if (s_flag) break;
-        double *vn = V + (size_t)(j + 1) * p;
+        const auto vn = V + (size_t)(j + 1) * p;
         for (int i = threadIdx.x; i < p; i += kLzThreads) vn[i] = w[i] / b;
         __syncthreads();
     }
@@ -688,7 +688,7 @@ __global__ __launch_bounds__(64 * NW) void lanczos_reg_kernel(int p_all, int mma
     extern __shared__ double sm[];
     const LzJob J = lz_job(jobs, p_all, mmax_all, Gs_all, nullptr, d_out, steps_out);
     const int p = J.p, mmax = J.mmax;
-    const double *G = J.G;
+    const auto G = gmem(J.G);
     const int t = threadIdx.x, lane = t % kWave, wave = t / kWave;
     const int ldv = p + 1;                    // padded row pitch of V
     double *V = sm;                           // (mmax + 1) x ldv

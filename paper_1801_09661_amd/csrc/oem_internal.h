@@ -25,6 +25,17 @@ int fail(int code, const std::string &msg);
                                               hipGetErrorString(e_));              \
     } while (0)
 
+// ------------------------------------------------------------------ memory
+// A pointer read from memory (a descriptor field) is generic to the
+// compiler, so accesses through it become flat instructions, which also
+// count against the LDS wait counter: every LDS wait then waits for the
+// outstanding global loads as well.  gmem() marks such a pointer as global
+// memory.
+template <typename T> __device__ inline __attribute__((address_space(1))) T *gmem(T *p)
+{
+    return (__attribute__((address_space(1))) T *)p;
+}
+
 // ------------------------------------------------------------------ fold hash
 // SplitMix64 (Steele, Lea & Flood 2014): the (i+1)-th output from state seed
 // is mix64(seed + (i+1) * 0x9E3779B97F4A7C15).  The fold is the high word

@@ -123,6 +123,19 @@ __global__ __launch_bounds__(kPathThreads) void path_kernel(const PathDesc *__re
 {
     extern __shared__ double sm[];
     const PathDesc P = descs[order[blockIdx.x]];
+    const auto G_g = gmem(P.G);
+    const auto lambda_g = gmem(P.lambda);
+    const auto beta_g = gmem(P.beta);
+    const auto beta_std_g = gmem(P.beta_std);
+    const auto kkt_g = gmem(P.kkt);
+    const auto obj_g = gmem(P.obj);
+    const auto iters_g = gmem(P.iters);
+    const auto c_g = gmem(P.c);
+    const auto s_g = gmem(P.s);
+    const auto w_g = gmem(P.w);
+    const auto gstart_g = gmem(P.gstart);
+    const auto gidx_g = gmem(P.gidx);
+    const auto cg_g = gmem(P.cg);
     const int p = P.p;
     const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
     PathLds S;
@@ -133,10 +146,10 @@ __global__ __launch_bounds__(kPathThreads) void path_kernel(const PathDesc *__re
     S.iscan = S.act + p + 1;                       // kPathWaves
     double *after_ints = sm + 2 * p + 4 * kPathWaves + 2 + (p + 1 + kPathWaves + 1) / 2 + 1;
     const bool g_in_lds = p <= lds_g_max_p;
-    const double *G = P.G;
+    const double *G = P.G;   // G may move to LDS below: generic pointer
     if (g_in_lds) {
         S.Gl = after_ints;
-        for (size_t e = threadIdx.x; e < (size_t)p * p; e += kPathThreads) S.Gl[e] = P.G[e];
+        for (size_t e = threadIdx.x; e < (size_t)p * p; e += kPathThreads) S.Gl[e] = G_g[e];
         G = S.Gl;
     }
     const double d = *P.d;
@@ -147,7 +160,7 @@ __global__ __launch_bounds__(kPathThreads) void path_kernel(const PathDesc *__re
     int nact = 0;
 
     for (int l = 0; l < P.L; ++l) {
-        const double lam = P.lambda[l];
+        const double lam = lambda_g[l];
         int it = 0;
         bool conv = false;
         while (it < P.maxit) {
@@ -158,13 +171,13 @@ __global__ __launch_bounds__(kPathThreads) void path_kernel(const PathDesc *__re
             if (grp) {
                 for (int gi = threadIdx.x; gi < P.ngroups; gi += kPathThreads) {
                     double ss = 0.0;
-                    const int t0 = P.gstart[gi], t1 = P.gstart[gi + 1];
-                    for (int t = t0; t < t1; ++t) ss += S.u[P.gidx[t]] * S.u[P.gidx[t]];
+                    const int t0 = gstart_g[gi], t1 = gstart_g[gi + 1];
+                    for (int t = t0; t < t1; ++t) ss += S.u[gidx_g[t]] * S.u[gidx_g[t]];
                     const double nrm = sqrt(ss);
-                    const double lam_c = P.cg[gi] * lam;
+                    const double lam_c = cg_g[gi] * lam;
                     const double f = nrm > 0.0 ? 1.0 - lam_c / nrm : 0.0;
                     for (int t = t0; t < t1; ++t) {
-                        const int j = P.gidx[t];
+                        const int j = gidx_g[t];
                         const double bn = f > 0.0 ? (S.u[j] / d) * f : 0.0;
                         dl = fmax(dl, fabs(bn - S.beta[j]));
                         mx = fmax(mx, fabs(bn));
@@ -173,7 +186,7 @@ __global__ __launch_bounds__(kPathThreads) void path_kernel(const PathDesc *__re
                 }
             } else {
                 for (int i = threadIdx.x; i < p; i += kPathThreads) {
-                    const double lw = (P.w ? P.w[i] : 1.0) * lam;
+                    const double lw = (w_g ? w_g[i] : 1.0) * lam;
                     const double bn = update1(P.kind, S.u[i], lw, d, P.alpha, P.gamma);
                     dl = fmax(dl, fabs(bn - S.beta[i]));
                     mx = fmax(mx, fabs(bn));
@@ -208,11 +221,11 @@ __global__ __launch_bounds__(kPathThreads) void path_kernel(const PathDesc *__re
                 const int j = S.act[a];
                 acc += G[(size_t)j * p + i] * S.beta[j];
             }
-            S.u[i] = acc - P.c[i];   // gradient
+            S.u[i] = acc - c_g[i];   // gradient
             quad += S.beta[i] * acc;
-            lin += P.c[i] * S.beta[i];
+            lin += c_g[i] * S.beta[i];
             if (!grp) {
-                const double lw = (P.w ? P.w[i] : 1.0) * lam;
+                const double lw = (w_g ? w_g[i] : 1.0) * lam;
                 const double b = S.beta[i];
                 double v;
                 if (b == 0.0) {
@@ -227,11 +240,11 @@ __global__ __launch_bounds__(kPathThreads) void path_kernel(const PathDesc *__re
         __syncthreads();
         if (grp) {
             for (int gi = threadIdx.x; gi < P.ngroups; gi += kPathThreads) {
-                const double lc = lam * P.cg[gi];
+                const double lc = lam * cg_g[gi];
                 double bn = 0.0, gn = 0.0;
-                const int t0 = P.gstart[gi], t1 = P.gstart[gi + 1];
+                const int t0 = gstart_g[gi], t1 = gstart_g[gi + 1];
                 for (int t = t0; t < t1; ++t) {
-                    const int j = P.gidx[t];
+                    const int j = gidx_g[t];
                     bn += S.beta[j] * S.beta[j];
                     gn += S.u[j] * S.u[j];
                 }
@@ -241,7 +254,7 @@ __global__ __launch_bounds__(kPathThreads) void path_kernel(const PathDesc *__re
                 if (bn > 0.0) {
                     double ss = 0.0;
                     for (int t = t0; t < t1; ++t) {
-                        const int j = P.gidx[t];
+                        const int j = gidx_g[t];
                         const double r = S.u[j] + lc * S.beta[j] / bn;
                         ss += r * r;
                     }
@@ -273,13 +286,13 @@ __global__ __launch_bounds__(kPathThreads) void path_kernel(const PathDesc *__re
                 l2 += S.red[2 * kPathWaves + wv];
                 p2 += S.red[3 * kPathWaves + wv];
             }
-            if (P.kkt) P.kkt[l] = k2;
-            if (P.obj) P.obj[l] = 0.5 * q2 - l2 + 0.5 * yyn + p2;
-            if (P.iters) P.iters[l] = conv ? it : -it;
+            if (kkt_g) kkt_g[l] = k2;
+            if (obj_g) obj_g[l] = 0.5 * q2 - l2 + 0.5 * yyn + p2;
+            if (iters_g) iters_g[l] = conv ? it : -it;
         }
         for (int i = threadIdx.x; i < p; i += kPathThreads) {
-            P.beta[(size_t)l * p + i] = S.beta[i] / P.s[i];
-            if (P.beta_std) P.beta_std[(size_t)l * p + i] = S.beta[i];
+            beta_g[(size_t)l * p + i] = S.beta[i] / s_g[i];
+            if (beta_std_g) beta_std_g[(size_t)l * p + i] = S.beta[i];
         }
         __syncthreads();
     }

@@ -29,6 +29,19 @@ __global__ __launch_bounds__(64 * NW) void path_reg_kernel(const PathDesc *__res
     __shared__ double cg_s[PMAX];
 
     const PathDesc P = descs[order[blockIdx.x]];
+    const auto G_g = gmem(P.G);
+    const auto lambda_g = gmem(P.lambda);
+    const auto beta_g = gmem(P.beta);
+    const auto beta_std_g = gmem(P.beta_std);
+    const auto kkt_g = gmem(P.kkt);
+    const auto obj_g = gmem(P.obj);
+    const auto iters_g = gmem(P.iters);
+    const auto c_g = gmem(P.c);
+    const auto s_g = gmem(P.s);
+    const auto w_g = gmem(P.w);
+    const auto gstart_g = gmem(P.gstart);
+    const auto gidx_g = gmem(P.gidx);
+    const auto cg_g = gmem(P.cg);
     const int p = P.p;
     const int t = threadIdx.x;
     const int lane = t % kWave, wave = t / kWave;
@@ -39,21 +52,21 @@ __global__ __launch_bounds__(64 * NW) void path_reg_kernel(const PathDesc *__res
 #pragma unroll
         for (int c = 0; c < CPW; ++c) {
             const int i = lane + 64 * r, j = NW * c + wave;
-            Gr[r][c] = (i < p && j < p) ? P.G[(size_t)i * p + j] : 0.0;
+            Gr[r][c] = (i < p && j < p) ? G_g[(size_t)i * p + j] : 0.0;
         }
     for (int e = t; e < NW * CPW; e += NT) beta_s[e] = 0.0;
 
     const bool mine = t < p;
-    const double ct = mine ? P.c[t] : 0.0;
-    const double st = mine ? P.s[t] : 1.0;
-    const double wt = (mine && P.w) ? P.w[t] : 1.0;
+    const double ct = mine ? c_g[t] : 0.0;
+    const double st = mine ? s_g[t] : 1.0;
+    const double wt = (mine && w_g) ? w_g[t] : 1.0;
     const double d = *P.d;
     const double yyn = *P.yyn;
     const bool grp = (P.kind == OEM_GRP_LASSO);
     if (grp) {
-        for (int e = t; e <= P.ngroups; e += NT) gstart_s[e] = P.gstart[e];
-        for (int e = t; e < p; e += NT) gidx_s[e] = P.gidx[e];
-        for (int e = t; e < P.ngroups; e += NT) cg_s[e] = P.cg[e];
+        for (int e = t; e <= P.ngroups; e += NT) gstart_s[e] = gstart_g[e];
+        for (int e = t; e < p; e += NT) gidx_s[e] = gidx_g[e];
+        for (int e = t; e < P.ngroups; e += NT) cg_s[e] = cg_g[e];
     }
     double bt = 0.0;
     __syncthreads();
@@ -98,7 +111,7 @@ __global__ __launch_bounds__(64 * NW) void path_reg_kernel(const PathDesc *__res
     };
 
     for (int l = 0; l < P.L; ++l) {
-        const double lam = P.lambda[l];
+        const double lam = lambda_g[l];
         int it = 0;
         bool conv = false;
         while (it < P.maxit) {
@@ -209,13 +222,13 @@ __global__ __launch_bounds__(64 * NW) void path_reg_kernel(const PathDesc *__res
             lin += red[3][w];
         }
         if (t == 0) {
-            if (P.kkt) P.kkt[l] = kv;
-            if (P.obj) P.obj[l] = 0.5 * quad - lin + 0.5 * yyn + penv;
-            if (P.iters) P.iters[l] = conv ? it : -it;
+            if (kkt_g) kkt_g[l] = kv;
+            if (obj_g) obj_g[l] = 0.5 * quad - lin + 0.5 * yyn + penv;
+            if (iters_g) iters_g[l] = conv ? it : -it;
         }
         if (mine) {
-            P.beta[(size_t)l * p + t] = bt / st;
-            if (P.beta_std) P.beta_std[(size_t)l * p + t] = bt;
+            beta_g[(size_t)l * p + t] = bt / st;
+            if (beta_std_g) beta_std_g[(size_t)l * p + t] = bt;
         }
         __syncthreads();
     }
@@ -252,6 +265,19 @@ __global__ __launch_bounds__(64 * NW) void path_blk_kernel(const PathDesc *__res
     __shared__ double fin[4][NW];
 
     const PathDesc P = descs[order[blockIdx.x]];
+    const auto G_g = gmem(P.G);
+    const auto lambda_g = gmem(P.lambda);
+    const auto beta_g = gmem(P.beta);
+    const auto beta_std_g = gmem(P.beta_std);
+    const auto kkt_g = gmem(P.kkt);
+    const auto obj_g = gmem(P.obj);
+    const auto iters_g = gmem(P.iters);
+    const auto c_g = gmem(P.c);
+    const auto s_g = gmem(P.s);
+    const auto w_g = gmem(P.w);
+    const auto gstart_g = gmem(P.gstart);
+    const auto gidx_g = gmem(P.gidx);
+    const auto cg_g = gmem(P.cg);
     const int p = P.p;
     const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
 
@@ -261,14 +287,14 @@ __global__ __launch_bounds__(64 * NW) void path_blk_kernel(const PathDesc *__res
 #pragma unroll
         for (int c = 0; c < CB; ++c) {
             const int i = lane + 64 * r, j = CB * wave + c;
-            Gr[r][c] = (i < p && j < p) ? P.G[(size_t)i * p + j] : 0.0;
+            Gr[r][c] = (i < p && j < p) ? G_g[(size_t)i * p + j] : 0.0;
         }
 
     const int row = CB * wave + lane;              // coordinate owned by this lane
     const bool mine = (lane < CB) && (row < p);
-    const double ct = mine ? P.c[row] : 0.0;
-    const double st = mine ? P.s[row] : 1.0;
-    const double wt = (mine && P.w) ? P.w[row] : 1.0;
+    const double ct = mine ? c_g[row] : 0.0;
+    const double st = mine ? s_g[row] : 1.0;
+    const double wt = (mine && w_g) ? w_g[row] : 1.0;
     const double d = *P.d;
     const double yyn = *P.yyn;
     double bt = 0.0;
@@ -317,7 +343,7 @@ __global__ __launch_bounds__(64 * NW) void path_blk_kernel(const PathDesc *__res
     __syncthreads();
 
     for (int l = 0; l < P.L; ++l) {
-        const double lam = P.lambda[l];
+        const double lam = lambda_g[l];
         const double lw = wt * lam;
         const Upd q = make_upd(P.kind, lw, d, P.alpha, P.gamma);
         int it = 0;
@@ -394,13 +420,13 @@ __global__ __launch_bounds__(64 * NW) void path_blk_kernel(const PathDesc *__res
                 quad += fin[2][w];
                 lin += fin[3][w];
             }
-            if (P.kkt) P.kkt[l] = kv;
-            if (P.obj) P.obj[l] = 0.5 * quad - lin + 0.5 * yyn + penv;
-            if (P.iters) P.iters[l] = conv ? it : -it;
+            if (kkt_g) kkt_g[l] = kv;
+            if (obj_g) obj_g[l] = 0.5 * quad - lin + 0.5 * yyn + penv;
+            if (iters_g) iters_g[l] = conv ? it : -it;
         }
         if (mine) {
-            P.beta[(size_t)l * p + row] = bt / st;
-            if (P.beta_std) P.beta_std[(size_t)l * p + row] = bt;
+            beta_g[(size_t)l * p + row] = bt / st;
+            if (beta_std_g) beta_std_g[(size_t)l * p + row] = bt;
         }
     }
 }

@@ -61,6 +61,19 @@ __global__ __launch_bounds__(kStreamThreads) void path_stream_kernel(const PathD
 
     const PathDesc P = descs[order[blockIdx.x]];
     const int p = P.p;
+    const auto Gg = gmem(P.G);
+    const auto gstart = gmem(P.gstart);
+    const auto gidx = gmem(P.gidx);
+    const auto cgw = gmem(P.cg);
+    const auto lambda_g = gmem(P.lambda);
+    const auto beta_g = gmem(P.beta);
+    const auto beta_std_g = gmem(P.beta_std);
+    const auto kkt_g = gmem(P.kkt);
+    const auto obj_g = gmem(P.obj);
+    const auto iters_g = gmem(P.iters);
+    const auto c_g = gmem(P.c);
+    const auto s_g = gmem(P.s);
+    const auto w_g = gmem(P.w);
     const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
     const bool grp = (P.kind == OEM_GRP_LASSO);
     const double d = *P.d;
@@ -74,14 +87,14 @@ __global__ __launch_bounds__(kStreamThreads) void path_stream_kernel(const PathD
     for (int r = 0; r < R; ++r) {
         row[r] = 64 * wave + lane + 512 * r;
         mine[r] = row[r] < p;
-        ct[r] = mine[r] ? P.c[row[r]] : 0.0;
-        st[r] = mine[r] ? P.s[row[r]] : 1.0;
-        wt[r] = (mine[r] && P.w) ? P.w[row[r]] : 1.0;
+        ct[r] = mine[r] ? c_g[row[r]] : 0.0;
+        st[r] = mine[r] ? s_g[row[r]] : 1.0;
+        wt[r] = (mine[r] && w_g) ? w_g[row[r]] : 1.0;
         bt[r] = 0.0;
     }
     if (grp) {
         for (int g = threadIdx.x; g < P.ngroups; g += kStreamThreads)
-            for (int q = P.gstart[g]; q < P.gstart[g + 1]; ++q) S.gof[P.gidx[q]] = g;
+            for (int q = gstart[g]; q < gstart[g + 1]; ++q) S.gof[gidx[q]] = g;
     }
 
     // publish this wave's nonzero coefficients into list buffer `buf`
@@ -141,7 +154,7 @@ __global__ __launch_bounds__(kStreamThreads) void path_stream_kernel(const PathD
                     bj[u] = (e0 + u < m) ? __hiloint2double(__builtin_amdgcn_readlane(bhi, e),
                                                             __builtin_amdgcn_readlane(blo, e))
                                          : 0.0;
-                    const double *gcol = P.G + (size_t)j * p;
+                    const auto gcol = Gg + (size_t)j * p;
 #pragma unroll
                     for (int r = 0; r < R; ++r) gv[u][r] = gcol[rc[r]];
                 }
@@ -162,7 +175,7 @@ __global__ __launch_bounds__(kStreamThreads) void path_stream_kernel(const PathD
     matvec(cur, gb);
 
     for (int l = 0; l < P.L; ++l) {
-        const double lam = P.lambda[l];
+        const double lam = lambda_g[l];
         Upd q[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) q[r] = make_upd(P.kind, wt[r] * lam, d, P.alpha, P.gamma);
@@ -183,12 +196,12 @@ __global__ __launch_bounds__(kStreamThreads) void path_stream_kernel(const PathD
                     if (!mine[r]) continue;
                     const int g = S.gof[row[r]];
                     double ss = 0.0;
-                    for (int qq = P.gstart[g]; qq < P.gstart[g + 1]; ++qq) {
-                        const double v = S.us[P.gidx[qq]];
+                    for (int qq = gstart[g]; qq < gstart[g + 1]; ++qq) {
+                        const double v = S.us[gidx[qq]];
                         ss += v * v;
                     }
                     const double nrm = sqrt(ss);
-                    const double f = nrm > 0.0 ? 1.0 - P.cg[g] * lam / nrm : 0.0;
+                    const double f = nrm > 0.0 ? 1.0 - cgw[g] * lam / nrm : 0.0;
                     const double bn = f > 0.0 ? (u[r] * inv_d) * f : 0.0;
                     dl = nmax(dl, fabs(bn - bt[r]));
                     mx = nmax(mx, fabs(bn));
@@ -260,12 +273,12 @@ __global__ __launch_bounds__(kStreamThreads) void path_stream_kernel(const PathD
             for (int r = 0; r < R; ++r) {
                 if (!mine[r]) continue;
                 const int g = S.gof[row[r]];
-                const int q0 = P.gstart[g], q1 = P.gstart[g + 1];
-                if (P.gidx[q0] != row[r]) continue;
-                const double lc = lam * P.cg[g];
+                const int q0 = gstart[g], q1 = gstart[g + 1];
+                if (gidx[q0] != row[r]) continue;
+                const double lc = lam * cgw[g];
                 double bn = 0.0, gn = 0.0;
                 for (int qq = q0; qq < q1; ++qq) {
-                    const int j = P.gidx[qq];
+                    const int j = gidx[qq];
                     bn += bs[j] * bs[j];
                     gn += S.us[j] * S.us[j];
                 }
@@ -275,7 +288,7 @@ __global__ __launch_bounds__(kStreamThreads) void path_stream_kernel(const PathD
                 if (bn > 0.0) {
                     double ss = 0.0;
                     for (int qq = q0; qq < q1; ++qq) {
-                        const int j = P.gidx[qq];
+                        const int j = gidx[qq];
                         const double rr = S.us[j] + lc * bs[j] / bn;
                         ss += rr * rr;
                     }
@@ -309,15 +322,15 @@ __global__ __launch_bounds__(kStreamThreads) void path_stream_kernel(const PathD
                 quad += S.fin[2 * NW + w];
                 lin += S.fin[3 * NW + w];
             }
-            if (P.kkt) P.kkt[l] = kv;
-            if (P.obj) P.obj[l] = 0.5 * quad - lin + 0.5 * yyn + penv;
-            if (P.iters) P.iters[l] = conv ? it : -it;
+            if (kkt_g) kkt_g[l] = kv;
+            if (obj_g) obj_g[l] = 0.5 * quad - lin + 0.5 * yyn + penv;
+            if (iters_g) iters_g[l] = conv ? it : -it;
         }
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             if (!mine[r]) continue;
-            P.beta[(size_t)l * p + row[r]] = bt[r] / st[r];
-            if (P.beta_std) P.beta_std[(size_t)l * p + row[r]] = bt[r];
+            beta_g[(size_t)l * p + row[r]] = bt[r] / st[r];
+            if (beta_std_g) beta_std_g[(size_t)l * p + row[r]] = bt[r];
         }
         if (grp) {
             // the staged beta overwrote list buffers: publish the current
