@@ -676,7 +676,8 @@ __global__ __launch_bounds__(kLzThreads) void lanczos_kernel(int p_all, int mmax
 
 // Lanczos for p <= 128: G spread over the registers of 64 NW threads (thread
 // (wave w, lane l) holds G[l + 64 r][NW c + w]), the Krylov basis V in LDS.
-// Same recurrence, reorthogonalisation and stopping rule as lanczos_kernel.
+// Same recurrence, reorthogonalisation and stopping rule as lanczos_kernel;
+// the top Ritz value is tested on the schedule of lanczos_wide_kernel.
 template <int NW, int R, int CPW>
 __global__ __launch_bounds__(64 * NW) void lanczos_reg_kernel(int p_all, int mmax_all,
                                                               const double *__restrict__ Gs_all,
@@ -699,7 +700,7 @@ __global__ __launch_bounds__(64 * NW) void lanczos_reg_kernel(int p_all, int mma
     double *coef = be + mmax;                 // mmax + 1
     double *tx = coef + mmax + 1;             // mmax
     double *tw = tx + mmax;                   // mmax
-    double *red = tw + mmax;                  // NW
+    double *red = tw + mmax;                  // 2 NW
     __shared__ int s_flag;
     __shared__ double s_theta;
 
@@ -722,6 +723,23 @@ __global__ __launch_bounds__(64 * NW) void lanczos_reg_kernel(int p_all, int mma
         for (int w = 0; w < NW; ++w) a += red[w];
         return a;
     };
+    // two sums with one pair of barriers (red holds 2 NW values)
+    auto bsum2 = [&](double u, double v, double &su, double &sv) {
+        u = wave_sum(u);
+        v = wave_sum(v);
+        __syncthreads();
+        if (lane == 0) {
+            red[wave] = u;
+            red[NW + wave] = v;
+        }
+        __syncthreads();
+        su = 0.0;
+        sv = 0.0;
+        for (int w = 0; w < NW; ++w) {
+            su += red[w];
+            sv += red[NW + w];
+        }
+    };
 
     // start vector
     double v0 = mine ? start_component(t) : 0.0;
@@ -729,7 +747,8 @@ __global__ __launch_bounds__(64 * NW) void lanczos_reg_kernel(int p_all, int mma
     if (mine) V[t] = v0 / nrm0;
     __syncthreads();
 
-    double gnorm = 0.0, theta = 0.0;
+    double gnorm = 0.0, theta = 0.0, floor = -INFINITY;
+    int next_test = 8;
     int m = 0;
     for (int j = 0; j < mmax; ++j) {
         const double *vj = V + (size_t)j * ldv;
@@ -750,31 +769,42 @@ __global__ __launch_bounds__(64 * NW) void lanczos_reg_kernel(int p_all, int mma
         double wt = 0.0;
         if (mine)
             for (int w = 0; w < NW; ++w) wt += part[w * 64 * R + t];
-        const double a = bsum(mine ? wt * vj[t] : 0.0);
+        double a, before;
+        bsum2(mine ? wt * vj[t] : 0.0, wt * wt, a, before);
         if (t == 0) al[j] = a;
         gnorm = fmax(gnorm, fabs(a));
         // full reorthogonalisation against v_0..v_j, repeated once when it
-        // removed most of w
-        double before = bsum(wt * wt);
+        // removed most of w; each dot is split over the 4 lanes of a quad
         for (int pass = 0; pass < 2; ++pass) {
             if (mine) ws[t] = wt;
             __syncthreads();
-            for (int mm = t; mm <= j; mm += NT) {
+            for (int mm = t / 4; mm <= j; mm += NT / 4) {
+                // one quad per vector: the 4 lanes of a quad always share mm
                 const double *vm = V + (size_t)mm * ldv;
                 double c0 = 0.0, c1 = 0.0;
-                int i = 0;
-                for (; i + 1 < p; i += 2) {
+                int i = t % 4;
+                for (; i + 4 < p; i += 8) {
                     c0 += vm[i] * ws[i];
-                    c1 += vm[i + 1] * ws[i + 1];
+                    c1 += vm[i + 4] * ws[i + 4];
                 }
                 if (i < p) c0 += vm[i] * ws[i];
-                coef[mm] = c0 + c1;
+                double c = c0 + c1;
+                c += dpp_mov<0xB1>(c);
+                c += dpp_mov<0x4E>(c);
+                if (t % 4 == 0) coef[mm] = c;
             }
             __syncthreads();
             if (mine) {
-                double tv = wt;
-                for (int mm = 0; mm <= j; ++mm) tv -= coef[mm] * V[(size_t)mm * ldv + t];
-                wt = tv;
+                double t0 = 0.0, t1 = 0.0, t2 = 0.0, t3 = 0.0;
+                int mm = 0;
+                for (; mm + 3 <= j; mm += 4) {
+                    t0 += coef[mm] * V[(size_t)mm * ldv + t];
+                    t1 += coef[mm + 1] * V[(size_t)(mm + 1) * ldv + t];
+                    t2 += coef[mm + 2] * V[(size_t)(mm + 2) * ldv + t];
+                    t3 += coef[mm + 3] * V[(size_t)(mm + 3) * ldv + t];
+                }
+                for (; mm <= j; ++mm) t0 += coef[mm] * V[(size_t)mm * ldv + t];
+                wt -= (t0 + t1) + (t2 + t3);
             }
             const double after = bsum(wt * wt);
             if (after > 0.5 * before) break;
@@ -784,12 +814,13 @@ __global__ __launch_bounds__(64 * NW) void lanczos_reg_kernel(int p_all, int mma
         if (t == 0) be[j] = b;
         m = j + 1;
         const bool invariant = (b <= 1e-14 * fmax(gnorm, 1e-300)) || (m == p);
-        const bool test_now = invariant || (m % 8 == 0) || (m == mmax);
+        const bool test_now = invariant || (m == next_test) || (m == mmax);
         if (test_now) {
+            next_test = m + max(8, m / 4);
             __syncthreads();
             if (t < kWave) {
                 double lo, hi;
-                tri_top(al, be, m, &lo, &hi);
+                tri_top_fast(al, be, m, floor, &lo, &hi);
                 if (t == 0) {
                     const double th = 0.5 * (lo + hi);
                     const double shift = hi + (hi - lo) + 1e-13 * fabs(hi) + 1e-300;
@@ -800,6 +831,7 @@ __global__ __launch_bounds__(64 * NW) void lanczos_reg_kernel(int p_all, int mma
             }
             __syncthreads();
             theta = s_theta;
+            floor = theta * (1.0 - 1e-14);
             if (s_flag) break;
         }
         if (mine) V[(size_t)(j + 1) * ldv + t] = wt / b;
@@ -858,7 +890,7 @@ static int launch_lz_class(int cls, int count, int pmax, int p_all, const double
     size_t lds = 0;
     if (cls <= 1) {
         const int NW = cls == 0 ? 4 : 8, R = cls == 0 ? 1 : 2;
-        lds = ((size_t)(mmax + 1) * (pmax + 1) + pmax + NW * 64 * R + 5 * mmax + 1 + NW) * sizeof(double);
+        lds = ((size_t)(mmax + 1) * (pmax + 1) + pmax + NW * 64 * R + 5 * mmax + 1 + 2 * NW) * sizeof(double);
         kern = cls == 0 ? (const void *)lanczos_reg_kernel<4, 1, 16> : (const void *)lanczos_reg_kernel<8, 2, 16>;
         threads = 64 * NW;
         OEM_HIP_CHECK(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
