@@ -20,6 +20,12 @@
 //      in every wave.
 // When the stopping rule holds, step 3 has already formed G beta for the
 // accepted beta, which gives the stationarity check and the objective.
+//
+// One CU draws only some tens of GB/s from L2, so the columns of the active
+// set are also kept in LDS: after a lambda whose support changed, the first
+// nonzero coordinates (as many columns as fit) get cache slots and their
+// columns are loaded once; step 3 then reads those columns from LDS and only
+// the rest from L2.
 #include "path_common.h"
 
 namespace oem {
@@ -35,18 +41,37 @@ struct StreamLds {
     double *fin;    // [4][NW]
     double *us;     // [NW * SEG] u or gradient (group penalties)
     int *gof;       // [NW * SEG] group of each coordinate
+    double *cache;  // [C][p] cached columns of G
+    double *cb;     // [2][64] beta of the cached coordinates
+    int *cj;        // [64] coordinate of each cache slot
+    int *wcnt;      // [NW] per-wave counts (cache refill)
 };
 
-size_t path_stream_lds_bytes(int R)
+constexpr int kCacheMax = 64;            // cached columns at most (one lane-read chunk)
+constexpr size_t kStreamLdsLimit = 160 * 1024;
+
+size_t path_stream_lds_bytes(int R, int p, int cols)
 {
     const size_t seg = 64 * (size_t)R, nw = kStreamWaves;
     return 2 * nw * seg * (sizeof(int) + sizeof(double)) + 2 * nw * sizeof(int) + 2 * nw * 2 * sizeof(double) +
-           4 * nw * sizeof(double) + nw * seg * (sizeof(double) + sizeof(int)) + 64;
+           4 * nw * sizeof(double) + nw * seg * (sizeof(double) + sizeof(int)) +
+           (size_t)cols * p * sizeof(double) + 2 * kCacheMax * sizeof(double) + kCacheMax * sizeof(int) +
+           nw * sizeof(int) + 64;
+}
+
+// Columns of G that fit in LDS next to the kernel's other arrays.
+int path_stream_cache_cols(int R, int pmax)
+{
+    const size_t base = path_stream_lds_bytes(R, pmax, 0);
+    if (base >= kStreamLdsLimit) return 0;
+    const size_t c = (kStreamLdsLimit - base) / ((size_t)pmax * sizeof(double));
+    return (int)std::min<size_t>(c, kCacheMax);
 }
 
 template <int R>
 __global__ __launch_bounds__(kStreamThreads) void path_stream_kernel(const PathDesc *__restrict__ descs,
-                                                                     const int *__restrict__ order)
+                                                                     const int *__restrict__ order,
+                                                                     int cache_cols)
 {
     constexpr int NW = kStreamWaves, SEG = 64 * R;
     extern __shared__ double smem_d[];
@@ -58,6 +83,10 @@ __global__ __launch_bounds__(kStreamThreads) void path_stream_kernel(const PathD
     S.lj = reinterpret_cast<int *>(S.us + NW * SEG);        // 2 NW SEG
     S.lcnt = S.lj + 2 * NW * SEG;                           // 2 NW
     S.gof = S.lcnt + 2 * NW;                                // NW SEG
+    S.cj = S.gof + NW * SEG;                                // kCacheMax
+    S.wcnt = S.cj + kCacheMax;                              // NW
+    S.cb = reinterpret_cast<double *>(S.wcnt + NW + (NW % 2));  // 2 kCacheMax (8-byte aligned)
+    S.cache = S.cb + 2 * kCacheMax;                         // cache_cols x p
 
     const PathDesc P = descs[order[blockIdx.x]];
     const int p = P.p;
@@ -92,17 +121,25 @@ __global__ __launch_bounds__(kStreamThreads) void path_stream_kernel(const PathD
         wt[r] = (mine[r] && w_g) ? w_g[row[r]] : 1.0;
         bt[r] = 0.0;
     }
+    int myslot[R];        // cache slot of this lane's coordinate, -1 if not cached
+#pragma unroll
+    for (int r = 0; r < R; ++r) myslot[r] = -1;
+    int ncached = 0;      // slots in use (uniform)
+    bool moved = false;   // some coordinate of this lane changed between zero and nonzero
     if (grp) {
         for (int g = threadIdx.x; g < P.ngroups; g += kStreamThreads)
             for (int q = gstart[g]; q < gstart[g + 1]; ++q) S.gof[gidx[q]] = g;
     }
 
-    // publish this wave's nonzero coefficients into list buffer `buf`
+    // publish this wave's nonzero coefficients into list buffer `buf`: cached
+    // coordinates write their value (zero included) to their slot, the other
+    // nonzero ones go to the wave's list segment
     auto publish = [&](int buf) {
         int base = 0;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            const bool nz = mine[r] && bt[r] != 0.0;
+            if (myslot[r] >= 0) S.cb[buf * kCacheMax + myslot[r]] = bt[r];
+            const bool nz = mine[r] && bt[r] != 0.0 && myslot[r] < 0;
             const uint64_t ball = __ballot(nz);
             if (nz) {
                 const int k = base + __popcll(ball & ((1ull << lane) - 1ull));
@@ -119,7 +156,7 @@ __global__ __launch_bounds__(kStreamThreads) void path_stream_kernel(const PathD
     // issued before their products, so each lane keeps 2 U R row-segment
     // loads in flight.  Entries past the end read as (column 0, value 0).
     auto matvec = [&](int buf, double (&gb)[R]) {
-        constexpr int U = R == 1 ? 16 : (R == 2 ? 8 : 4);
+        constexpr int U = R == 1 ? 16 : (R == 2 ? 4 : 2);
         int pref[NW + 1];
         pref[0] = 0;
 #pragma unroll
@@ -134,6 +171,29 @@ __global__ __launch_bounds__(kStreamThreads) void path_stream_kernel(const PathD
         int rc[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) rc[r] = mine[r] ? row[r] : 0;
+        // cached columns from LDS (slots past ncached read as value 0)
+        if (ncached > 0) {
+            const double cv = lane < ncached ? S.cb[buf * kCacheMax + lane] : 0.0;
+            const int clo = __double2loint(cv), chi = __double2hiint(cv);
+            constexpr int UC = R == 1 ? 8 : 4;
+            for (int e0 = 0; e0 < ncached; e0 += UC) {
+                double gv[UC][R], bj[UC];
+#pragma unroll
+                for (int u = 0; u < UC; ++u) {
+                    const int e = min(e0 + u, 63);
+                    const int sl = min(e0 + u, ncached - 1);
+                    bj[u] = (e0 + u < ncached) ? __hiloint2double(__builtin_amdgcn_readlane(chi, e),
+                                                                  __builtin_amdgcn_readlane(clo, e))
+                                               : 0.0;
+#pragma unroll
+                    for (int r = 0; r < R; ++r) gv[u][r] = S.cache[(size_t)sl * p + rc[r]];
+                }
+#pragma unroll
+                for (int u = 0; u < UC; ++u)
+#pragma unroll
+                    for (int r = 0; r < R; ++r) acc[r][u % 4] += gv[u][r] * bj[u];
+            }
+        }
         for (int cb = 0; cb < total; cb += 64) {
             const int idx = cb + lane;
             int sg = 0;
@@ -203,6 +263,7 @@ __global__ __launch_bounds__(kStreamThreads) void path_stream_kernel(const PathD
                     const double nrm = sqrt(ss);
                     const double f = nrm > 0.0 ? 1.0 - cgw[g] * lam / nrm : 0.0;
                     const double bn = f > 0.0 ? (u[r] * inv_d) * f : 0.0;
+                    moved |= (bn == 0.0) != (bt[r] == 0.0);
                     dl = nmax(dl, fabs(bn - bt[r]));
                     mx = nmax(mx, fabs(bn));
                     bt[r] = bn;
@@ -212,6 +273,7 @@ __global__ __launch_bounds__(kStreamThreads) void path_stream_kernel(const PathD
                 for (int r = 0; r < R; ++r) {
                     if (!mine[r]) continue;
                     const double bn = update_fast(P.kind, u[r], q[r], P.gamma);
+                    moved |= (bn == 0.0) != (bt[r] == 0.0);
                     dl = nmax(dl, fabs(bn - bt[r]));
                     mx = nmax(mx, fabs(bn));
                     bt[r] = bn;
@@ -304,13 +366,18 @@ __global__ __launch_bounds__(kStreamThreads) void path_stream_kernel(const PathD
         penv = wave_sum(penv);
         quad = wave_sum(quad);
         lin = wave_sum(lin);
+        const bool wmoved = __ballot(moved) != 0;
         if (lane == 0) {
             S.fin[0 * NW + wave] = kv;
             S.fin[1 * NW + wave] = penv;
             S.fin[2 * NW + wave] = quad;
             S.fin[3 * NW + wave] = lin;
+            S.wcnt[wave] = wmoved ? 1 : 0;
         }
         __syncthreads();
+        bool refill = false;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) refill |= S.wcnt[w] != 0;
         if (threadIdx.x == 0) {
             kv = S.fin[0];
             penv = S.fin[NW];
@@ -339,6 +406,43 @@ __global__ __launch_bounds__(kStreamThreads) void path_stream_kernel(const PathD
             publish(cur);
             __syncthreads();
         }
+        // the support changed during this lambda: give the cache slots to the
+        // first nonzero coordinates (wave order, then r, then lane) and load
+        // their columns; the G beta carried into the next lambda is unchanged
+        if (refill && cache_cols > 0) {
+            __syncthreads();                       // flags in S.wcnt are read
+            int wc = 0;
+            uint64_t ball[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                ball[r] = __ballot(mine[r] && bt[r] != 0.0);
+                wc += __popcll(ball[r]);
+            }
+            if (lane == 0) S.wcnt[wave] = wc;
+            __syncthreads();
+            int off = 0, total = 0;
+            for (int w = 0; w < NW; ++w) {
+                off += (w < wave) ? S.wcnt[w] : 0;
+                total += S.wcnt[w];
+            }
+            int pos = off;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const bool nz = (ball[r] >> lane) & 1ull;
+                const int at = pos + __popcll(ball[r] & ((1ull << lane) - 1ull));
+                myslot[r] = (nz && at < cache_cols) ? at : -1;
+                if (myslot[r] >= 0) S.cj[at] = row[r];
+                pos += __popcll(ball[r]);
+            }
+            ncached = min(total, cache_cols);
+            __syncthreads();
+            for (int e = threadIdx.x; e < ncached * p; e += kStreamThreads) {
+                const int sl = e / p, i = e - sl * p;
+                S.cache[(size_t)sl * p + i] = Gg[(size_t)S.cj[sl] * p + i];
+            }
+            __syncthreads();
+        }
+        moved = false;
     }
 }
 
@@ -360,9 +464,10 @@ int launch_paths_stream(const PathDesc *d_desc, const int *d_order, int count, i
     } else {
         return fail(OEM_E_INVAL, "streaming path kernel needs p <= 2048");
     }
-    const size_t lds = path_stream_lds_bytes(R);
+    int cols = path_stream_cache_cols(R, pmax);
+    const size_t lds = path_stream_lds_bytes(R, pmax, cols);
     OEM_HIP_CHECK(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    void *args[] = {(void *)&d_desc, (void *)&d_order};
+    void *args[] = {(void *)&d_desc, (void *)&d_order, (void *)&cols};
     OEM_HIP_CHECK(hipLaunchKernel(kern, dim3(count), dim3(kStreamThreads), args, lds, s));
     return OEM_OK;
 }
