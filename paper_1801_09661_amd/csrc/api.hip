@@ -545,7 +545,7 @@ int oem_gram_autotune(oem_handle h, const void *X, int64_t n, int64_t ldx, const
     if (!X || !y) return fail(OEM_E_INVAL, "X and y must not be NULL");
     if (ldx < h->p) return fail(OEM_E_INVAL, "ldx must be >= p");
     hipStream_t s = as_stream(stream);
-    const int cand[] = {256, 512, 1024, 2048};
+    const int cand[] = {256, 512, 1024, 2048, 4096, 8192};
     hipEvent_t e0, e1;
     OEM_HIP_CHECK(hipEventCreate(&e0));
     OEM_HIP_CHECK(hipEventCreate(&e1));

@@ -12,7 +12,7 @@
 // super-block pair) and streams that split's rows (contiguous rows with one
 // fold, an ordered row list per (fold, split) with several), so every row is
 // fetched once per super-block pair.  Thread (q, rg) loads columns
-// 4q .. 4q + 3 of 8 rows (16-byte loads when rows are aligned) and the next
+// 4q .. 4q + 3 of 8 rows (16-byte loads whatever the row pitch) and the next
 // chunk's loads are issued before the current chunk's MFMAs; rows past the
 // end of the split are read as copies of its last row and cleared before
 // staging.  Workgroups sharing a row split are numbered so that round-robin
@@ -44,8 +44,12 @@ template <typename XT, bool VEC>
 __device__ inline void load_block64(XT (&x)[8][4], const XT *__restrict__ X, int64_t ldx, int p, int col,
                                     const int64_t (&row)[8])
 {
-    if constexpr (VEC) {
-        const int cv = (col + 3 < p) ? col : 0;          // p % 4 == 0 here
+    // 16-byte loads need only element alignment on gfx950; a group past p
+    // loads columns 0..3 instead, and the one group that straddles p loads
+    // its columns one by one, clamped to p - 1.
+    const bool vec = VEC && (col + 3 < p || col >= p);
+    if (vec) {
+        const int cv = (col + 3 < p) ? col : 0;
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
             const XT *src = X + row[e] * ldx + cv;
@@ -405,11 +409,11 @@ int launch_gram(oem_gram_s *h, const void *X, int64_t n, int64_t ldx, const doub
     const bool list = g.K > 1;
     if (h->xdt == OEM_X_F32) {
         const float *Xf = static_cast<const float *>(X);
-        const bool vec = ((reinterpret_cast<uintptr_t>(Xf) & 15) == 0) && (ldx % 4 == 0) && (g.p % 4 == 0);
+        const bool vec = (reinterpret_cast<uintptr_t>(Xf) & 3) == 0;
         rc = launch_f64_t<float>(g, list, vec, Xf, n, ldx, y, rs, part, pvec, pscal, s);
     } else {
         const double *Xd = static_cast<const double *>(X);
-        const bool vec = ((reinterpret_cast<uintptr_t>(Xd) & 15) == 0) && (ldx % 4 == 0) && (g.p % 4 == 0);
+        const bool vec = (reinterpret_cast<uintptr_t>(Xd) & 7) == 0;
         rc = launch_f64_t<double>(g, list, vec, Xd, n, ldx, y, rs, part, pvec, pscal, s);
     }
     if (rc) return rc;

@@ -13,7 +13,7 @@
 // (super-blocks of up to 4 tiles = 128 columns) and streams its rows in
 // chunks of 64:
 //   load   thread (q, rg) loads columns 4 q .. 4 q + 3 of 8 rows (16-byte
-//          loads when rows are aligned; a wave covers two 512-byte row
+//          loads whatever the row pitch; a wave covers two 512-byte row
 //          segments per load); the next chunk's loads are issued before the
 //          current chunk's MFMAs, and rows past the end of the split are
 //          read as copies of its last row and cleared before staging;
@@ -73,8 +73,12 @@ template <bool VEC>
 __device__ inline void load_block(float (&x)[8][4], const float *__restrict__ X, int64_t ldx, int p,
                                   int col, const int64_t (&row)[8])
 {
-    if constexpr (VEC) {
-        const int cv = (col + 3 < p) ? col : 0;          // p is a multiple of 4 here
+    // 16-byte loads need only 4-byte alignment on gfx950; a group past p
+    // loads columns 0..3 instead, and the one group that straddles p (p % 4
+    // != 0) loads its columns one by one, clamped to p - 1.
+    const bool vec = VEC && (col + 3 < p || col >= p);
+    if (vec) {
+        const int cv = (col + 3 < p) ? col : 0;
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
             const f32x4_t v = *reinterpret_cast<const f32x4_t *>(X + row[e] * ldx + cv);
@@ -127,7 +131,7 @@ __device__ inline f32x16_t mfma3(f32x16_t acc, const bf16x8_t &ah, const bf16x8_
 // SPLIT: split-BF16 (else single BF16).  DIAG: the launch over diagonal
 // super-blocks (which also accumulates the FP64 diagonal, X^T y, y^T y, n).
 // LIST: rows come from per-(fold, split) row lists (else the contiguous rows
-// of the split).  VEC: X rows are 16-byte aligned and p % 4 == 0.
+// of the split).  VEC: 16-byte loads (X 4-byte aligned).
 template <bool SPLIT, bool DIAG, bool LIST, bool VEC>
 __global__ __launch_bounds__(kBThreads) void gram_bf16_kernel(
     const float *__restrict__ X, int64_t n, int64_t ldx, const double *__restrict__ y, GramGeom g,
@@ -490,7 +494,7 @@ int launch_gram_bf16(oem_gram_s *h, const void *Xv, int64_t n, int64_t ldx, cons
 
     const bool split = (h->prec == OEM_SPLIT_BF16);
     const bool list = g.K > 1;
-    const bool vec = ((reinterpret_cast<uintptr_t>(X) & 15) == 0) && (ldx % 4 == 0) && (g.p % 4 == 0);
+    const bool vec = (reinterpret_cast<uintptr_t>(X) & 3) == 0;
     const unsigned nd = (unsigned)(g.K * g.nsplit * g.nsb);
     rc = split ? launch_bf16_t<true, true>(g, list, vec, nd, X, n, ldx, y, rs, part, pvec, pscal, s)
                : launch_bf16_t<false, true>(g, list, vec, nd, X, n, ldx, y, rs, part, pvec, pscal, s);
