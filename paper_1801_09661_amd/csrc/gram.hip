@@ -262,20 +262,29 @@ __global__ __launch_bounds__(kGramThreads) void gram_f64_kernel(
     }
 }
 
-// Add the reduced tiles into G (upper triangle mirrored, so G stays exactly
-// symmetric), X^T y into b, y^T y and n.
-__global__ void gram_f64_scatter_kernel(GramGeom g, const double *__restrict__ tiles,
-                                        const double *__restrict__ vec, const double *__restrict__ scal,
-                                        double *__restrict__ Gk, double *__restrict__ bk,
-                                        double *__restrict__ yyk, int64_t *__restrict__ nk)
+// Finish the pass: sum each statistic over the row splits (fixed order) and
+// add it into the running sums: upper-triangle tile entries mirrored into the
+// lower triangle (G stays exactly symmetric), then X^T y, then y^T y and n.
+// Grid (statistic blocks of 64, folds).
+__global__ __launch_bounds__(kFinishThreads) void gram_f64_finish_kernel(
+    GramGeom g, const double *__restrict__ tiles, const double *__restrict__ vec,
+    const double *__restrict__ scal, double *__restrict__ Gk, double *__restrict__ bk,
+    double *__restrict__ yyk, int64_t *__restrict__ nk)
 {
-    const int p = g.p;
+    __shared__ double red[kFinishThreads];
+    const int p = g.p, S = g.nsplit, k = blockIdx.y;
     const size_t Et = (size_t)g.ntp * 256;
-    const size_t per_k = Et + p + 1;
-    const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= (size_t)g.K * per_k) return;
-    const int k = (int)(idx / per_k);
-    const size_t e = idx % per_k;
+    const size_t per_k = Et + p + 2;
+    const size_t e = (size_t)blockIdx.x * kWave + threadIdx.x % kWave;
+    double v = 0.0;
+    if (e < Et)
+        v = split_sum(tiles + (size_t)k * S * Et + e, Et, S);
+    else if (e < Et + p)
+        v = split_sum(vec + (size_t)k * S * p + (e - Et), (size_t)p, S);
+    else if (e < per_k)
+        v = split_sum(scal + (size_t)k * S * 2 + (e - Et - p), 2, S);
+    v = finish_combine(v, red);
+    if (threadIdx.x >= kWave || e >= per_k) return;
     if (e < Et) {
         const int te = (int)(e % 256);
         const int tp = (int)(e / 256);
@@ -285,15 +294,15 @@ __global__ void gram_f64_scatter_kernel(GramGeom g, const double *__restrict__ t
         if (ti == tj && ei > ej) return;
         const int i = ti * 16 + ei, j = tj * 16 + ej;
         if (i >= p || j >= p) return;
-        const double v = tiles[(size_t)k * Et + e];
         double *G = Gk + (size_t)k * p * p;
         G[(size_t)i * p + j] += v;
         if (i != j) G[(size_t)j * p + i] += v;
     } else if (e < Et + p) {
-        bk[(size_t)k * p + (e - Et)] += vec[(size_t)k * p + (e - Et)];
+        bk[(size_t)k * p + (e - Et)] += v;
+    } else if (e == Et + p) {
+        yyk[k] += v;
     } else {
-        yyk[k] += scal[(size_t)k * 2];
-        nk[k] += (int64_t)scal[(size_t)k * 2 + 1];
+        nk[k] += (int64_t)v;
     }
 }
 
@@ -403,9 +412,6 @@ int launch_gram(oem_gram_s *h, const void *X, int64_t n, int64_t ldx, const doub
     double *part = h->partial.as<double>();
     double *pvec = part + parts * Et;
     double *pscal = pvec + parts * g.p;
-    const size_t red = reduce_tmp_doubles(g.K, g.nsplit, Et) + K * (Et + g.p + 2) + 8;
-    rc = h->redtmp.ensure(red * sizeof(double));
-    if (rc) return rc;
     const bool list = g.K > 1;
     if (h->xdt == OEM_X_F32) {
         const float *Xf = static_cast<const float *>(X);
@@ -417,18 +423,10 @@ int launch_gram(oem_gram_s *h, const void *X, int64_t n, int64_t ldx, const doub
         rc = launch_f64_t<double>(g, list, vec, Xd, n, ldx, y, rs, part, pvec, pscal, s);
     }
     if (rc) return rc;
-    double *tmp = h->redtmp.as<double>();
-    double *out_tiles = tmp + reduce_tmp_doubles(g.K, g.nsplit, Et);
-    double *out_vec = out_tiles + K * Et;
-    double *out_scal = out_vec + K * g.p;
-    rc = reduce_splits_f64(part, g.K, g.nsplit, Et, tmp, out_tiles, s);
-    rc = rc ? rc : reduce_splits_f64(pvec, g.K, g.nsplit, (size_t)g.p, tmp, out_vec, s);
-    rc = rc ? rc : reduce_splits_f64(pscal, g.K, g.nsplit, 2, tmp, out_scal, s);
-    if (rc) return rc;
-    const size_t total = K * (Et + g.p + 1);
-    hipLaunchKernelGGL(gram_f64_scatter_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, g,
-                       out_tiles, out_vec, out_scal, h->Gk.as<double>(), h->bk.as<double>(),
-                       h->yyk.as<double>(), h->nk.as<int64_t>());
+    const size_t per_k = Et + g.p + 2;
+    const dim3 fgrid((unsigned)((per_k + kWave - 1) / kWave), (unsigned)K);
+    hipLaunchKernelGGL(gram_f64_finish_kernel, fgrid, dim3(kFinishThreads), 0, s, g, part, pvec, pscal,
+                       h->Gk.as<double>(), h->bk.as<double>(), h->yyk.as<double>(), h->nk.as<int64_t>());
     OEM_HIP_CHECK(hipGetLastError());
     return OEM_OK;
 }

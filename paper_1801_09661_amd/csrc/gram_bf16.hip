@@ -379,23 +379,30 @@ __global__ __launch_bounds__(kBThreads) void gram_bf16_kernel(
     }
 }
 
-// Add the split-reduced statistics into the running sums: off-diagonal tile
-// entries (upper triangle, mirrored so G stays exactly symmetric), then the
-// FP64 diagonal and X^T y, then y^T y and n.
-__global__ void gram_bf16_scatter_kernel(GramGeom g, const double *__restrict__ tiles,
-                                         const double *__restrict__ vec,
-                                         const double *__restrict__ scal, double *__restrict__ Gk,
-                                         double *__restrict__ bk, double *__restrict__ yyk,
-                                         int64_t *__restrict__ nk)
+// Finish the pass: sum each statistic over the row splits (fixed order) and
+// add it into the running sums: off-diagonal tile entries (upper triangle,
+// mirrored so G stays exactly symmetric), then the FP64 diagonal and X^T y,
+// then y^T y and n.  Grid (statistic blocks of 64, folds).
+__global__ __launch_bounds__(kFinishThreads) void gram_bf16_finish_kernel(
+    GramGeom g, const float *__restrict__ tiles, const double *__restrict__ vec,
+    const double *__restrict__ scal, double *__restrict__ Gk, double *__restrict__ bk,
+    double *__restrict__ yyk, int64_t *__restrict__ nk)
 {
-    const int p = g.p;
+    __shared__ double red[kFinishThreads];
+    const int p = g.p, S = g.nsplit, k = blockIdx.y;
     const size_t tile = kBTile * kBTile;
     const size_t Et = (size_t)g.ntp * tile;
-    const size_t per_k = Et + 2 * (size_t)p + 1;
-    const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= (size_t)g.K * per_k) return;
-    const int k = (int)(idx / per_k);
-    const size_t e = idx % per_k;
+    const size_t per_k = Et + 2 * (size_t)p + 2;
+    const size_t e = (size_t)blockIdx.x * kWave + threadIdx.x % kWave;
+    double v = 0.0;
+    if (e < Et)
+        v = split_sum(tiles + (size_t)k * S * Et + e, Et, S);
+    else if (e < Et + 2 * (size_t)p)
+        v = split_sum(vec + (size_t)k * S * 2 * p + (e - Et), 2 * (size_t)p, S);
+    else if (e < per_k)
+        v = split_sum(scal + (size_t)k * S * 2 + (e - Et - 2 * p), 2, S);
+    v = finish_combine(v, red);
+    if (threadIdx.x >= kWave || e >= per_k) return;
     double *G = Gk + (size_t)k * p * p;
     if (e < Et) {
         const int te = (int)(e % tile);
@@ -406,17 +413,16 @@ __global__ void gram_bf16_scatter_kernel(GramGeom g, const double *__restrict__ 
         if (ti == tj && ei >= ej) return;         // diagonal from FP64; lower half mirrored
         const int i = ti * kBTile + ei, j = tj * kBTile + ej;
         if (i >= p || j >= p) return;
-        const double v = tiles[(size_t)k * Et + e];
         G[(size_t)i * p + j] += v;
         G[(size_t)j * p + i] += v;
     } else if (e < Et + 2 * (size_t)p) {
-        const size_t v = e - Et;
-        const double sum = vec[(size_t)k * 2 * p + v];
-        if (v < (size_t)p) G[v * p + v] += sum;
-        else bk[(size_t)k * p + (v - p)] += sum;
+        const size_t c = e - Et;
+        if (c < (size_t)p) G[c * p + c] += v;
+        else bk[(size_t)k * p + (c - p)] += v;
+    } else if (e == Et + 2 * (size_t)p) {
+        yyk[k] += v;
     } else {
-        yyk[k] += scal[(size_t)k * 2];
-        nk[k] += (int64_t)scal[(size_t)k * 2 + 1];
+        nk[k] += (int64_t)v;
     }
 }
 
@@ -488,9 +494,6 @@ int launch_gram_bf16(oem_gram_s *h, const void *Xv, int64_t n, int64_t ldx, cons
     float *part = h->partial.as<float>();
     double *pvec = reinterpret_cast<double *>(part + parts * Et);
     double *pscal = pvec + parts * 2 * g.p;
-    const size_t nred = reduce_tmp_doubles(g.K, g.nsplit, Et) + K * (Et + 2 * (size_t)g.p + 2) + 8;
-    rc = h->redtmp.ensure(nred * sizeof(double));
-    if (rc) return rc;
 
     const bool split = (h->prec == OEM_SPLIT_BF16);
     const bool list = g.K > 1;
@@ -505,18 +508,10 @@ int launch_gram_bf16(oem_gram_s *h, const void *Xv, int64_t n, int64_t ldx, cons
                    : launch_bf16_t<false, false>(g, list, vec, no, X, n, ldx, y, rs, part, pvec, pscal, s);
         if (rc) return rc;
     }
-    double *tmp = h->redtmp.as<double>();
-    double *out_tiles = tmp + reduce_tmp_doubles(g.K, g.nsplit, Et);
-    double *out_vec = out_tiles + K * Et;
-    double *out_scal = out_vec + K * 2 * g.p;
-    rc = reduce_splits_f32(part, g.K, g.nsplit, Et, tmp, out_tiles, s);
-    rc = rc ? rc : reduce_splits_f64(pvec, g.K, g.nsplit, 2 * (size_t)g.p, tmp, out_vec, s);
-    rc = rc ? rc : reduce_splits_f64(pscal, g.K, g.nsplit, 2, tmp, out_scal, s);
-    if (rc) return rc;
-    const size_t total = K * (Et + 2 * (size_t)g.p + 1);
-    hipLaunchKernelGGL(gram_bf16_scatter_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, g,
-                       out_tiles, out_vec, out_scal, h->Gk.as<double>(), h->bk.as<double>(),
-                       h->yyk.as<double>(), h->nk.as<int64_t>());
+    const size_t per_k = Et + 2 * (size_t)g.p + 2;
+    const dim3 fgrid((unsigned)((per_k + kWave - 1) / kWave), (unsigned)K);
+    hipLaunchKernelGGL(gram_bf16_finish_kernel, fgrid, dim3(kFinishThreads), 0, s, g, part, pvec, pscal,
+                       h->Gk.as<double>(), h->bk.as<double>(), h->yyk.as<double>(), h->nk.as<int64_t>());
     OEM_HIP_CHECK(hipGetLastError());
     return OEM_OK;
 }

@@ -92,12 +92,40 @@ void gram_set_target(int prec, int K, int p, int64_t n, int target);
 // Build per-(fold, split) ordered row lists for rows 0..n-1.
 int build_row_lists(oem_gram_s *h, const GramGeom &g, int64_t n, int64_t row_offset,
                     const uint8_t *foldid, RowSource &rs, hipStream_t s);
-// out[k][e] (+)= sum over s (in order) of src[k][s][e], FP32 or FP64 source,
-// in two fixed-order stages; `accumulate` adds into out.
-int reduce_splits_f32(const float *src, int K, int S, size_t E, double *tmp, double *out,
-                      hipStream_t s);
-int reduce_splits_f64(const double *src, int K, int S, size_t E, double *tmp, double *out,
-                      hipStream_t s);
-size_t reduce_tmp_doubles(int K, int S, size_t E);
+
+// ---- split sums (device) ----
+// Workgroups of kFinishThreads threads finish a Gram pass: each owns 64
+// consecutive statistics of one fold; thread group h (threadIdx.x / 64) sums
+// the splits s = h, h + 4, h + 8, ... of one statistic with four interleaved
+// accumulators, and finish_combine adds the four groups' sums.  Every step has
+// a fixed order, so the result is deterministic.
+constexpr int kFinishThreads = 256;
+
+template <typename T>
+__device__ inline double split_sum(const T *__restrict__ base, size_t stride, int S)
+{
+    const int h = threadIdx.x / kWave;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int s = h;
+    for (; s + 12 < S; s += 16) {
+        a0 += (double)base[(size_t)s * stride];
+        a1 += (double)base[(size_t)(s + 4) * stride];
+        a2 += (double)base[(size_t)(s + 8) * stride];
+        a3 += (double)base[(size_t)(s + 12) * stride];
+    }
+    for (; s < S; s += 4) a0 += (double)base[(size_t)s * stride];
+    return (a0 + a1) + (a2 + a3);
+}
+
+// Sum of the four thread groups' values for lane `threadIdx.x % 64`, valid in
+// group 0 (the others return 0).
+__device__ inline double finish_combine(double v, double *red)
+{
+    const int lane = threadIdx.x % kWave, h = threadIdx.x / kWave;
+    red[h * kWave + lane] = v;
+    __syncthreads();
+    if (h != 0) return 0.0;
+    return (red[lane] + red[kWave + lane]) + (red[2 * kWave + lane] + red[3 * kWave + lane]);
+}
 
 } // namespace oem

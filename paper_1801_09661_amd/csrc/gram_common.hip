@@ -194,62 +194,4 @@ int build_row_lists(oem_gram_s *h, const GramGeom &g, int64_t n, int64_t row_off
     return OEM_OK;
 }
 
-// ---------------------------------------------------------------- reduction
-
-constexpr int kRedChunk = 16;   // splits summed per thread in the first stage
-
-template <typename T>
-__global__ void reduce_stage1_kernel(const T *__restrict__ src, int S, size_t E, int NC,
-                                     double *__restrict__ tmp)
-{
-    const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int c = blockIdx.y, k = blockIdx.z;
-    if (e >= E) return;
-    const T *p = src + (size_t)k * S * E + e;
-    const int s0 = c * kRedChunk, s1 = min(S, s0 + kRedChunk);
-    double acc = 0.0;
-    for (int s = s0; s < s1; ++s) acc += (double)p[(size_t)s * E];
-    tmp[((size_t)k * NC + c) * E + e] = acc;
-}
-
-__global__ void reduce_stage2_kernel(const double *__restrict__ tmp, int NC, size_t E,
-                                     double *__restrict__ out)
-{
-    const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int k = blockIdx.z;
-    if (e >= E) return;
-    double acc = 0.0;
-    for (int c = 0; c < NC; ++c) acc += tmp[((size_t)k * NC + c) * E + e];
-    out[(size_t)k * E + e] = acc;
-}
-
-size_t reduce_tmp_doubles(int K, int S, size_t E)
-{
-    const int NC = (S + kRedChunk - 1) / kRedChunk;
-    return (size_t)K * NC * E;
-}
-
-template <typename T>
-static int reduce_splits(const T *src, int K, int S, size_t E, double *tmp, double *out, hipStream_t s)
-{
-    if (E == 0) return OEM_OK;
-    const int NC = (S + kRedChunk - 1) / kRedChunk;
-    const unsigned gx = (unsigned)((E + 255) / 256);
-    hipLaunchKernelGGL(reduce_stage1_kernel<T>, dim3(gx, NC, K), dim3(256), 0, s, src, S, E, NC, tmp);
-    OEM_HIP_CHECK(hipGetLastError());
-    hipLaunchKernelGGL(reduce_stage2_kernel, dim3(gx, 1, K), dim3(256), 0, s, tmp, NC, E, out);
-    OEM_HIP_CHECK(hipGetLastError());
-    return OEM_OK;
-}
-
-int reduce_splits_f32(const float *src, int K, int S, size_t E, double *tmp, double *out, hipStream_t s)
-{
-    return reduce_splits<float>(src, K, S, E, tmp, out, s);
-}
-
-int reduce_splits_f64(const double *src, int K, int S, size_t E, double *tmp, double *out, hipStream_t s)
-{
-    return reduce_splits<double>(src, K, S, E, tmp, out, s);
-}
-
 } // namespace oem

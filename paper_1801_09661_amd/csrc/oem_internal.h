@@ -140,7 +140,7 @@ struct oem_gram_s {
     std::vector<int32_t> lz_host;      // Lanczos steps (negative: not converged)
     int64_t rows_seen = 0;
     // workspaces
-    oem::DevBuf partial, partial_n, rowlist, redtmp, lanczos, paths, order, lam, betaw, groupbuf, cvw, flag;
+    oem::DevBuf partial, partial_n, rowlist, lanczos, paths, order, lam, betaw, groupbuf, cvw, flag;
 };
 
 namespace oem {

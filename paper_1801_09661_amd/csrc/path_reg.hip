@@ -275,9 +275,6 @@ __global__ __launch_bounds__(64 * NW) void path_blk_kernel(const PathDesc *__res
     const auto c_g = gmem(P.c);
     const auto s_g = gmem(P.s);
     const auto w_g = gmem(P.w);
-    const auto gstart_g = gmem(P.gstart);
-    const auto gidx_g = gmem(P.gidx);
-    const auto cg_g = gmem(P.cg);
     const int p = P.p;
     const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
 
