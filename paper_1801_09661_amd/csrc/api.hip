@@ -224,6 +224,8 @@ static PathDesc make_desc(oem_gram_s *h, int q, const oem_penalty &pn, const oem
     d.lambda = lam;
     d.beta = beta;
     d.beta_std = nullptr;
+    d.lstart = nullptr;
+    d.bws = nullptr;
     d.iters = iters;
     d.kkt = kkt;
     d.obj = obj;
@@ -300,7 +302,7 @@ struct oem_batch_s {
     int32_t prec = OEM_FP64, xdt = OEM_X_F32, npen = 0;
     std::vector<oem_penalty> pens;
     oem_path_opts opts{};
-    oem::DevBuf descs, order, jobs, iters_own;
+    oem::DevBuf descs, order, jobs, iters_own, pathws;
     std::vector<oem::LzLaunch> lz;
     oem::PathPlan plan;
     std::vector<int32_t *> iters_of;   // per problem: where its iteration counts go
@@ -347,7 +349,7 @@ void oem_gram_free(oem_handle h)
     (void)hipDeviceSynchronize();
     for (DevBuf *b : {&h->Gk, &h->bk, &h->yyk, &h->nk, &h->Gs, &h->Gs32, &h->cs, &h->sc, &h->yyn,
                       &h->dq, &h->ntrain, &h->lzsteps, &h->partial, &h->partial_n, &h->rowlist, &h->lanczos,
-                      &h->paths, &h->order, &h->lam, &h->betaw, &h->groupbuf, &h->cvw, &h->flag})
+                      &h->paths, &h->order, &h->lam, &h->betaw, &h->groupbuf, &h->cvw, &h->flag, &h->pathws})
         b->release();
     delete h;
 }
@@ -459,6 +461,8 @@ int oem_fit_path(oem_handle h, int32_t fold, const oem_penalty *pen, int32_t npe
                                   beta + (size_t)i * L * h->p, it + (size_t)i * L,
                                   kkt ? kkt + (size_t)i * L : nullptr,
                                   obj ? obj + (size_t)i * L : nullptr));
+    rc = attach_path_handover(descs, h->pathws);
+    if (rc) return rc;
     rc = upload_descs(h, descs, s);
     if (rc) return rc;
     rc = launch_paths(h->paths.as<PathDesc>(), descs, h->order, s);
@@ -524,6 +528,8 @@ int oem_cv(oem_handle h, const oem_penalty *pen, int32_t npen, const oem_path_op
             descs.push_back(make_desc(h, q, pen[i], opts, gp, h->lam.as<double>() + (size_t)i * L, b,
                                       it + ((size_t)q * npen + i) * L, nullptr, nullptr));
         }
+    rc = attach_path_handover(descs, h->pathws);
+    if (rc) return rc;
     rc = upload_descs(h, descs, s);
     if (rc) return rc;
     rc = launch_paths(h->paths.as<PathDesc>(), descs, h->order, s);
@@ -587,7 +593,7 @@ void oem_batch_free(oem_batch b)
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
     for (oem_gram_s *h : b->hs) oem_gram_free(h);
-    for (DevBuf *d : {&b->descs, &b->order, &b->jobs, &b->iters_own}) d->release();
+    for (DevBuf *d : {&b->descs, &b->order, &b->jobs, &b->iters_own, &b->pathws}) d->release();
     delete b;
 }
 
@@ -743,6 +749,8 @@ int oem_batch_create(const oem_problem *probs, int32_t nprob, int32_t precision,
                                       q.obj ? q.obj + (size_t)k * L : nullptr));
     }
     lanczos_job_plan(jobs, b->lz);
+    rc = attach_path_handover(descs, b->pathws);
+    if (rc) return bail(rc);
     plan_paths(descs, b->plan);
     rc = b->jobs.ensure(jobs.size() * sizeof(LzJob));
     rc = rc ? rc : b->descs.ensure(descs.size() * sizeof(PathDesc));

@@ -98,6 +98,11 @@ struct PathDesc {
     double tol;
     int32_t maxit;
     int32_t prec;
+    // hand-over between the kernels of one path's launch chain: the first
+    // lambda index the next kernel computes, and the standardised
+    // coefficients of the lambda before it (p)
+    int32_t *lstart;
+    double *bws;
 };
 
 // ------------------------------------------------------------------ Lanczos jobs
@@ -140,7 +145,7 @@ struct oem_gram_s {
     std::vector<int32_t> lz_host;      // Lanczos steps (negative: not converged)
     int64_t rows_seen = 0;
     // workspaces
-    oem::DevBuf partial, partial_n, rowlist, lanczos, paths, order, lam, betaw, groupbuf, cvw, flag;
+    oem::DevBuf partial, partial_n, rowlist, lanczos, paths, order, lam, betaw, groupbuf, cvw, flag, pathws;
 };
 
 namespace oem {
@@ -169,14 +174,18 @@ int launch_paths(const PathDesc *d_desc, const std::vector<PathDesc> &host, DevB
                  hipStream_t s);
 // The same split into a plan (host: order table grouped by kernel class) and
 // launches that enqueue kernels only (no allocation, no host wait).
+// cls: path kernel; first: offset of its paths in the order table; chain:
+// the kernel continues the paths of an earlier launch from their hand-over
 struct PathLaunch {
-    int cls, first, count, pmax;
+    int cls, first, count, pmax, chain;
 };
 struct PathPlan {
     std::vector<int> order;
     std::vector<PathLaunch> launches;
 };
 void plan_paths(const std::vector<PathDesc> &host, PathPlan &plan);
+// hand-over buffers of the paths: lstart and bws of every descriptor point into buf
+int attach_path_handover(std::vector<PathDesc> &descs, DevBuf &buf);
 int launch_paths_planned(const PathDesc *d_desc, const int *d_order, const PathPlan &plan,
                          hipStream_t s);
 int launch_cv(const double *Gk, const double *bk, const double *yyk, const int64_t *nk,

@@ -8,6 +8,7 @@
 // otherwise it streams from L2.  Every (problem, fold, penalty) path is
 // independent, so paths of different problems and sizes share one launch.
 #include <algorithm>
+#include <cstdlib>
 
 #include "path_common.h"
 
@@ -305,39 +306,114 @@ size_t path_lds_bytes(int p, bool g_in_lds)
     return doubles * sizeof(double);
 }
 
-int launch_paths_reg(const PathDesc *d_desc, const int *d_order, int count, int pmax,
+int launch_paths_reg(const PathDesc *d_desc, const int *d_order, int count, int pmax, int chain,
                      hipStream_t s);
-int launch_paths_blk(const PathDesc *d_desc, const int *d_order, int count, int pmax,
+int launch_paths_blk(const PathDesc *d_desc, const int *d_order, int count, int pmax, int chain,
                      hipStream_t s);
-int launch_paths_stream(const PathDesc *d_desc, const int *d_order, int count, int pmax,
+int launch_paths_stream(const PathDesc *d_desc, const int *d_order, int count, int pmax, int chain,
                         hipStream_t s);
+int launch_paths_ws(const PathDesc *d_desc, const int *d_order, int count, int nw, int first, int pmax,
+                    hipStream_t s);
 
-// Path kernel class: 0..2 block kernel (separable penalties, p <= 32, 64,
-// 128), 3, 4 register kernel (group lasso, p <= 64, 128), 5 streaming kernel
-// (128 < p <= 2048), 6 general kernel (larger p).
-static int path_class(const PathDesc &d)
+// Path kernels: 0..2 block kernel (separable penalties, p <= 32, 64, 128),
+// 3, 4 register kernel (group lasso, p <= 64, 128), 5 streaming kernel
+// (128 < p <= 2048), 6 general kernel (larger p), 7, 8, 9 working-set kernel
+// on 1, 2, 4 waves.
+enum { kBlk32, kBlk64, kBlk128, kReg64, kReg128, kStream, kGeneral, kWs1, kWs2, kWs4 };
+
+// Launch slots in enqueue order: (kernel, continues an earlier launch).  A
+// path's launches are always enqueued in the order of its chain, and a
+// kernel reads the hand-over only in a slot marked as continuing.
+struct PathSlot {
+    int kernel, chain;
+};
+static const PathSlot kSlots[] = {
+    {kWs1, 0},    {kWs2, 0},     {kWs2, 1},    {kWs4, 1},    {kBlk32, 0},   {kBlk64, 0},
+    {kBlk128, 0}, {kReg64, 0},   {kReg128, 0}, {kStream, 0}, {kBlk64, 1},   {kBlk128, 1},
+    {kReg64, 1},  {kReg128, 1},  {kStream, 1}, {kGeneral, 0}};
+constexpr int kNumSlots = sizeof(kSlots) / sizeof(kSlots[0]);
+
+static int slot_index(int kernel, int chain)
+{
+    for (int i = 0; i < kNumSlots; ++i)
+        if (kSlots[i].kernel == kernel && kSlots[i].chain == chain) return i;
+    return -1;
+}
+
+// The working-set kernels can be switched off (OEM_PATH_WS=0) to run every
+// path on its kernel class alone.
+static bool ws_enabled()
+{
+    static const bool on = [] {
+        const char *e = getenv("OEM_PATH_WS");
+        return !(e && e[0] == '0');
+    }();
+    return on;
+}
+
+// Launch slots of one path, in order.  Separable penalties at p <= 32 run on
+// the block kernel alone; larger p start on a working-set kernel of 1 or 2
+// waves, continue on one of 2 or 4 waves when the working set outgrows it,
+// and end on the kernel of their class; p > 2048 runs on the general kernel.
+static int path_chain(const PathDesc &d, int *slots)
 {
     const bool grp = d.kind == OEM_GRP_LASSO;
-    if (d.p <= 128 && !grp) return d.p <= 32 ? 0 : (d.p <= 64 ? 1 : 2);
-    if (d.p <= 128) return d.p <= 64 ? 3 : 4;
-    return d.p <= 2048 ? 5 : 6;
+    const int cls = d.p > 2048 ? kGeneral
+                    : d.p > 128 ? kStream
+                    : grp       ? (d.p <= 64 ? kReg64 : kReg128)
+                                : (d.p <= 32 ? kBlk32 : (d.p <= 64 ? kBlk64 : kBlk128));
+    int n = 0;
+    if (cls == kGeneral || cls == kBlk32 || !ws_enabled()) {
+        slots[n++] = slot_index(cls, 0);
+        return n;
+    }
+    if (d.p <= 128) {
+        slots[n++] = slot_index(kWs1, 0);
+        if (d.p > 64) slots[n++] = slot_index(kWs2, 1);
+    } else {
+        slots[n++] = slot_index(kWs2, 0);
+        slots[n++] = slot_index(kWs4, 1);
+    }
+    slots[n++] = slot_index(cls, 1);
+    return n;
 }
 
 void plan_paths(const std::vector<PathDesc> &host, PathPlan &plan)
 {
     plan.order.clear();
     plan.launches.clear();
-    for (int c = 0; c < 7; ++c) {
+    std::vector<std::vector<int>> by_slot(kNumSlots);
+    for (int i = 0; i < (int)host.size(); ++i) {
+        int sl[4];
+        const int n = path_chain(host[i], sl);
+        for (int k = 0; k < n; ++k) by_slot[sl[k]].push_back(i);
+    }
+    for (int c = 0; c < kNumSlots; ++c) {
+        if (by_slot[c].empty()) continue;
         const int first = (int)plan.order.size();
         int pmax = 0;
-        for (int i = 0; i < (int)host.size(); ++i)
-            if (path_class(host[i]) == c) {
-                plan.order.push_back(i);
-                pmax = std::max(pmax, host[i].p);
-            }
-        const int count = (int)plan.order.size() - first;
-        if (count) plan.launches.push_back(PathLaunch{c, first, count, pmax});
+        for (int i : by_slot[c]) {
+            plan.order.push_back(i);
+            pmax = std::max(pmax, host[i].p);
+        }
+        plan.launches.push_back(PathLaunch{c, first, (int)by_slot[c].size(), pmax, kSlots[c].chain});
     }
+}
+
+int attach_path_handover(std::vector<PathDesc> &descs, DevBuf &buf)
+{
+    size_t bytes = 0;
+    for (const PathDesc &d : descs) bytes += sizeof(double) * (1 + (size_t)d.p);
+    int rc = buf.ensure(std::max<size_t>(bytes, 64));
+    if (rc) return rc;
+    char *base = buf.as<char>();
+    size_t off = 0;
+    for (PathDesc &d : descs) {
+        d.lstart = reinterpret_cast<int32_t *>(base + off);
+        d.bws = reinterpret_cast<double *>(base + off + sizeof(double));
+        off += sizeof(double) * (1 + (size_t)d.p);
+    }
+    return OEM_OK;
 }
 
 int launch_paths_planned(const PathDesc *d_desc, const int *d_order, const PathPlan &plan,
@@ -345,14 +421,18 @@ int launch_paths_planned(const PathDesc *d_desc, const int *d_order, const PathP
 {
     for (const PathLaunch &L : plan.launches) {
         const int *ord = d_order + L.first;
+        const int ch = L.chain;
         int rc = OEM_OK;
-        switch (L.cls) {
-        case 0: rc = launch_paths_blk(d_desc, ord, L.count, 32, s); break;
-        case 1: rc = launch_paths_blk(d_desc, ord, L.count, 64, s); break;
-        case 2: rc = launch_paths_blk(d_desc, ord, L.count, 128, s); break;
-        case 3: rc = launch_paths_reg(d_desc, ord, L.count, 64, s); break;
-        case 4: rc = launch_paths_reg(d_desc, ord, L.count, 128, s); break;
-        case 5: rc = launch_paths_stream(d_desc, ord, L.count, L.pmax, s); break;
+        switch (kSlots[L.cls].kernel) {
+        case kWs1: rc = launch_paths_ws(d_desc, ord, L.count, 1, !ch, L.pmax, s); break;
+        case kWs2: rc = launch_paths_ws(d_desc, ord, L.count, 2, !ch, L.pmax, s); break;
+        case kWs4: rc = launch_paths_ws(d_desc, ord, L.count, 4, !ch, L.pmax, s); break;
+        case kBlk32: rc = launch_paths_blk(d_desc, ord, L.count, 32, ch, s); break;
+        case kBlk64: rc = launch_paths_blk(d_desc, ord, L.count, 64, ch, s); break;
+        case kBlk128: rc = launch_paths_blk(d_desc, ord, L.count, 128, ch, s); break;
+        case kReg64: rc = launch_paths_reg(d_desc, ord, L.count, 64, ch, s); break;
+        case kReg128: rc = launch_paths_reg(d_desc, ord, L.count, 128, ch, s); break;
+        case kStream: rc = launch_paths_stream(d_desc, ord, L.count, L.pmax, ch, s); break;
         default: {
             // keep G in LDS when the largest path's matrix fits next to its vectors
             const size_t limit = 150 * 1024;

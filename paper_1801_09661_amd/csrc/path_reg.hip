@@ -16,7 +16,7 @@ namespace oem {
 
 template <int NW, int R, int CPW>
 __global__ __launch_bounds__(64 * NW) void path_reg_kernel(const PathDesc *__restrict__ descs,
-                                                           const int *__restrict__ order)
+                                                           const int *__restrict__ order, int chain)
 {
     constexpr int NT = 64 * NW;
     constexpr int PMAX = (64 * R < NW * CPW) ? 64 * R : NW * CPW;
@@ -45,6 +45,10 @@ __global__ __launch_bounds__(64 * NW) void path_reg_kernel(const PathDesc *__res
     const int p = P.p;
     const int t = threadIdx.x;
     const int lane = t % kWave, wave = t / kWave;
+    // a chained launch continues from the hand-over of the kernel before it
+    const int l0 = chain ? *P.lstart : 0;
+    if (l0 >= P.L) return;
+    const auto bws = gmem(P.bws);
 
     double Gr[R][CPW];
 #pragma unroll
@@ -54,7 +58,7 @@ __global__ __launch_bounds__(64 * NW) void path_reg_kernel(const PathDesc *__res
             const int i = lane + 64 * r, j = NW * c + wave;
             Gr[r][c] = (i < p && j < p) ? G_g[(size_t)i * p + j] : 0.0;
         }
-    for (int e = t; e < NW * CPW; e += NT) beta_s[e] = 0.0;
+    for (int e = t; e < NW * CPW; e += NT) beta_s[e] = (l0 > 0 && e < p) ? bws[e] : 0.0;
 
     const bool mine = t < p;
     const double ct = mine ? c_g[t] : 0.0;
@@ -68,7 +72,7 @@ __global__ __launch_bounds__(64 * NW) void path_reg_kernel(const PathDesc *__res
         for (int e = t; e < p; e += NT) gidx_s[e] = gidx_g[e];
         for (int e = t; e < P.ngroups; e += NT) cg_s[e] = cg_g[e];
     }
-    double bt = 0.0;
+    double bt = (l0 > 0 && mine) ? bws[t] : 0.0;
     __syncthreads();
 
     // partial sums of (G beta) for this thread's rows; returns row t's total
@@ -110,7 +114,7 @@ __global__ __launch_bounds__(64 * NW) void path_reg_kernel(const PathDesc *__res
         b = rb;
     };
 
-    for (int l = 0; l < P.L; ++l) {
+    for (int l = l0; l < P.L; ++l) {
         const double lam = lambda_g[l];
         int it = 0;
         bool conv = false;
@@ -257,7 +261,7 @@ __global__ __launch_bounds__(64 * NW) void path_reg_kernel(const PathDesc *__res
 // accepted beta, which gives the stationarity check and the objective.
 template <int NW, int R, int CB>
 __global__ __launch_bounds__(64 * NW) void path_blk_kernel(const PathDesc *__restrict__ descs,
-                                                           const int *__restrict__ order)
+                                                           const int *__restrict__ order, int chain)
 {
     static_assert(NW * CB <= 64 * R, "each owned coordinate must be a row held by the lanes");
     __shared__ double part[2][NW][64 * R];
@@ -277,6 +281,9 @@ __global__ __launch_bounds__(64 * NW) void path_blk_kernel(const PathDesc *__res
     const auto w_g = gmem(P.w);
     const int p = P.p;
     const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+    // a chained launch continues from the hand-over of the kernel before it
+    const int l0 = chain ? *P.lstart : 0;
+    if (l0 >= P.L) return;
 
     double Gr[R][CB];
 #pragma unroll
@@ -294,7 +301,7 @@ __global__ __launch_bounds__(64 * NW) void path_blk_kernel(const PathDesc *__res
     const double wt = (mine && w_g) ? w_g[row] : 1.0;
     const double d = *P.d;
     const double yyn = *P.yyn;
-    double bt = 0.0;
+    double bt = (l0 > 0 && mine) ? P.bws[row] : 0.0;
 
     // partial sums of G beta over this wave's columns, into part[buf]; NA
     // interleaved accumulators per row keep the FP64 add chains short
@@ -339,7 +346,7 @@ __global__ __launch_bounds__(64 * NW) void path_blk_kernel(const PathDesc *__res
     symv(cur);
     __syncthreads();
 
-    for (int l = 0; l < P.L; ++l) {
+    for (int l = l0; l < P.L; ++l) {
         const double lam = lambda_g[l];
         const double lw = wt * lam;
         const Upd q = make_upd(P.kind, lw, d, P.alpha, P.gamma);
@@ -430,16 +437,16 @@ __global__ __launch_bounds__(64 * NW) void path_blk_kernel(const PathDesc *__res
 
 // Path launch plan for the register kernel: paths with p <= 64 and
 // 64 < p <= 128 go to two instantiations.
-int launch_paths_reg(const PathDesc *d_desc, const int *d_order, int count, int pmax,
+int launch_paths_reg(const PathDesc *d_desc, const int *d_order, int count, int pmax, int chain,
                      hipStream_t s)
 {
     if (count == 0) return OEM_OK;
     if (pmax <= 64) {
         hipLaunchKernelGGL((path_reg_kernel<4, 1, 16>), dim3(count), dim3(256), 0, s, d_desc,
-                           d_order);
+                           d_order, chain);
     } else if (pmax <= 128) {
         hipLaunchKernelGGL((path_reg_kernel<8, 2, 16>), dim3(count), dim3(512), 0, s, d_desc,
-                           d_order);
+                           d_order, chain);
     } else {
         return fail(OEM_E_INVAL, "register path kernel needs p <= 128");
     }
@@ -458,19 +465,19 @@ int launch_paths_reg(const PathDesc *d_desc, const int *d_order, int count, int 
 #endif
 // Separable-penalty paths: p <= 32, <= 64 and <= 128 go to three
 // instantiations of the block kernel (wave counts measured best at each size).
-int launch_paths_blk(const PathDesc *d_desc, const int *d_order, int count, int pmax,
+int launch_paths_blk(const PathDesc *d_desc, const int *d_order, int count, int pmax, int chain,
                      hipStream_t s)
 {
     if (count == 0) return OEM_OK;
     if (pmax <= 32)
         hipLaunchKernelGGL((path_blk_kernel<PBLK32_NW, 1, 32 / PBLK32_NW>), dim3(count), dim3(64 * PBLK32_NW),
-                           0, s, d_desc, d_order);
+                           0, s, d_desc, d_order, chain);
     else if (pmax <= 64)
         hipLaunchKernelGGL((path_blk_kernel<PBLK64_NW, 1, 64 / PBLK64_NW>), dim3(count), dim3(64 * PBLK64_NW),
-                           0, s, d_desc, d_order);
+                           0, s, d_desc, d_order, chain);
     else if (pmax <= 128)
         hipLaunchKernelGGL((path_blk_kernel<PBLK128_NW, 2, 128 / PBLK128_NW>), dim3(count),
-                           dim3(64 * PBLK128_NW), 0, s, d_desc, d_order);
+                           dim3(64 * PBLK128_NW), 0, s, d_desc, d_order, chain);
     else
         return fail(OEM_E_INVAL, "block path kernel needs p <= 128");
     OEM_HIP_CHECK(hipGetLastError());

@@ -71,7 +71,7 @@ int path_stream_cache_cols(int R, int pmax)
 template <int R>
 __global__ __launch_bounds__(kStreamThreads) void path_stream_kernel(const PathDesc *__restrict__ descs,
                                                                      const int *__restrict__ order,
-                                                                     int cache_cols)
+                                                                     int cache_cols, int chain)
 {
     constexpr int NW = kStreamWaves, SEG = 64 * R;
     extern __shared__ double smem_d[];
@@ -90,6 +90,10 @@ __global__ __launch_bounds__(kStreamThreads) void path_stream_kernel(const PathD
 
     const PathDesc P = descs[order[blockIdx.x]];
     const int p = P.p;
+    // a chained launch continues from the hand-over of the kernel before it
+    const int l0 = chain ? *P.lstart : 0;
+    if (l0 >= P.L) return;
+    const auto bws = gmem(P.bws);
     const auto Gg = gmem(P.G);
     const auto gstart = gmem(P.gstart);
     const auto gidx = gmem(P.gidx);
@@ -119,13 +123,15 @@ __global__ __launch_bounds__(kStreamThreads) void path_stream_kernel(const PathD
         ct[r] = mine[r] ? c_g[row[r]] : 0.0;
         st[r] = mine[r] ? s_g[row[r]] : 1.0;
         wt[r] = (mine[r] && w_g) ? w_g[row[r]] : 1.0;
-        bt[r] = 0.0;
+        bt[r] = (l0 > 0 && mine[r]) ? bws[row[r]] : 0.0;
     }
     int myslot[R];        // cache slot of this lane's coordinate, -1 if not cached
 #pragma unroll
     for (int r = 0; r < R; ++r) myslot[r] = -1;
     int ncached = 0;      // slots in use (uniform)
-    bool moved = false;   // some coordinate of this lane changed between zero and nonzero
+    // some coordinate of this lane changed between zero and nonzero (a warm
+    // start counts as a change, so the cache is filled after its first lambda)
+    bool moved = l0 > 0;
     if (grp) {
         for (int g = threadIdx.x; g < P.ngroups; g += kStreamThreads)
             for (int q = gstart[g]; q < gstart[g + 1]; ++q) S.gof[gidx[q]] = g;
@@ -234,7 +240,7 @@ __global__ __launch_bounds__(kStreamThreads) void path_stream_kernel(const PathD
     double gb[R];
     matvec(cur, gb);
 
-    for (int l = 0; l < P.L; ++l) {
+    for (int l = l0; l < P.L; ++l) {
         const double lam = lambda_g[l];
         Upd q[R];
 #pragma unroll
@@ -446,7 +452,7 @@ __global__ __launch_bounds__(kStreamThreads) void path_stream_kernel(const PathD
     }
 }
 
-int launch_paths_stream(const PathDesc *d_desc, const int *d_order, int count, int pmax,
+int launch_paths_stream(const PathDesc *d_desc, const int *d_order, int count, int pmax, int chain,
                         hipStream_t s)
 {
     if (count == 0) return OEM_OK;
@@ -467,7 +473,7 @@ int launch_paths_stream(const PathDesc *d_desc, const int *d_order, int count, i
     int cols = path_stream_cache_cols(R, pmax);
     const size_t lds = path_stream_lds_bytes(R, pmax, cols);
     OEM_HIP_CHECK(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    void *args[] = {(void *)&d_desc, (void *)&d_order, (void *)&cols};
+    void *args[] = {(void *)&d_desc, (void *)&d_order, (void *)&cols, (void *)&chain};
     OEM_HIP_CHECK(hipLaunchKernel(kern, dim3(count), dim3(kStreamThreads), args, lds, s));
     return OEM_OK;
 }

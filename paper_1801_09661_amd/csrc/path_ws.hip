@@ -1,0 +1,583 @@
+// OEM path kernel on a working set of coordinates with exact screening of the
+// others (Section 2.1 iteration, Section 2.2 updates).
+//
+// Every update of Section 2.1 leaves a coordinate j at zero exactly when its
+// thresholding input is small: |u_j| <= w_j lambda (lasso, MCP, SCAD; times
+// alpha for the elastic net) or ||u_g|| <= c_g lambda for a group.  For a
+// coordinate that is zero, u_j = c_j - (G beta)_j, and between two iterates
+//     |u_j(beta) - u_j(beta')| <= r_j max_k |beta_k - beta'_k|,
+// r_j = sum_k |G_jk|  (for a group, sqrt(sum_{j in g} r_j^2) bounds the change
+// of ||u_g||).  So after an exact evaluation of u at a reference beta, a zero
+// coordinate with slack s_j = threshold - |u_j| stays zero in every update
+// whose input beta is within s_j / r_j of the reference (max norm).
+//
+// The kernel keeps a working set W of at most C = 32 NW coordinates (whole
+// groups for the group lasso): the nonzero coordinates and the zero ones
+// closest to their threshold (smallest s_j / r_j).  G restricted to W lives
+// in registers.  Wave w owns slots [32 w, 32 w + 32); lanes l and l + 32 both
+// own slot 32 w + l and hold its row of G_WW, split by columns: lane l the
+// first C / 2 columns, lane l + 32 the rest.  An update reads beta_W from LDS
+// as broadcast loads, forms the two half-row products, joins them with one
+// cross-half lane swap (both lanes then hold the same sum, and compute the
+// same update), and writes the new beta of the slot back to LDS; with more
+// than one wave that write is followed by the update's only barrier.  The
+// stopping rule needs max |beta| (one reduction); whether every change is
+// within tol times it, and whether any coordinate drifted past the screening
+// bound, are wave ballots.  The coordinates outside W are not touched while the drift
+// max_k |beta_k - beta_ref_k| stays below S = min over j outside W of
+// s_j / r_j.  At a check point - the start of the path, the end of every
+// lambda, and whenever the drift reaches S - the kernel forms G beta for all
+// p coordinates from the columns of the nonzero coordinates (read from
+// memory), which gives the exact u, the stationarity check and the objective,
+// and rebuilds W when a coordinate outside it needs to enter or the drift
+// reached S.  The iterates are those of the full update: the coordinates
+// outside W are exactly the ones the full update would leave at zero.
+//
+// When more than C coordinates need W, the kernel stops before that lambda:
+// *lstart receives the lambda index and bws the coefficients (standardised)
+// of the lambda before it, and the next kernel of the launch plan continues
+// from there with the same warm start.
+#include <cfloat>
+
+#include "path_common.h"
+
+namespace oem {
+
+constexpr int kWsCB = 32;   // slots per wave
+
+static __host__ __device__ inline int ws_pow2(int v)
+{
+    int s = 2;
+    while (s < v) s <<= 1;
+    return s;
+}
+
+size_t path_ws_lds_bytes(int NW, int pcap)
+{
+    const int C = NW * kWsCB, PSC = ws_pow2(pcap);
+    const size_t dbl = 2 * (size_t)C + 8 * (size_t)NW + 4 * (size_t)NW + 3 * (size_t)pcap + PSC + C;
+    const size_t ints = (size_t)PSC + 2 * (size_t)pcap + 2 * (size_t)C + 2 * (size_t)C + 16 + 2 * (size_t)NW;
+    return dbl * sizeof(double) + ints * sizeof(int) + 64;
+}
+
+template <int NW>
+__global__ __launch_bounds__(64 * NW) void path_ws_kernel(const PathDesc *__restrict__ descs,
+                                                          const int *__restrict__ order, int first,
+                                                          int pcap)
+{
+    constexpr int CB = kWsCB, C = NW * CB, HC = C / 2, NT = 64 * NW;
+    const PathDesc P = descs[order[blockIdx.x]];
+    const int p = P.p, L = P.L;
+    const bool grp = (P.kind == OEM_GRP_LASSO);
+    const int nkeys = grp ? P.ngroups : p;
+    const int PS = ws_pow2(nkeys), PSC = ws_pow2(pcap);
+
+    extern __shared__ double sm[];
+    double *bsl = sm;                         // [2][C] beta of each slot (double-buffered)
+    double *dm = bsl + 2 * C;                 // [2][NW][4] per-wave stopping-rule values
+    double *fin = dm + 8 * NW;                // [4][NW] per-wave check-point sums
+    double *bfull = fin + 4 * NW;             // [pcap] beta (zero outside W)
+    double *gfull = bfull + pcap;             // [pcap] G beta
+    double *r1 = gfull + pcap;                // [pcap] sum_k |G_jk|
+    double *key = r1 + pcap;                  // [PSC] s_j / r_j, -1 when j needs W
+    double *ab = key + PSC;                   // [C] values of the nonzero coordinates
+    int *kid = reinterpret_cast<int *>(ab + C);   // [PSC] coordinate (group) of each key
+    int *slot_of = kid + PSC;                 // [pcap] slot of each coordinate, -1 outside W
+    int *gof = slot_of + pcap;                // [pcap] group of each coordinate
+    int *ws = gof + pcap;                     // [C] coordinate of each slot, -1 when empty
+    int *aj = ws + C;                         // [C] indices of the nonzero coordinates
+    int *gl = aj + C;                         // [2 C] lane range of each slot's group in its wave
+    int *misc = gl + 2 * C;                   // [16 + 2 NW] counters and flags
+
+    const auto G = gmem(P.G);
+    const auto lambda_g = gmem(P.lambda);
+    const auto beta_g = gmem(P.beta);
+    const auto beta_std_g = gmem(P.beta_std);
+    const auto kkt_g = gmem(P.kkt);
+    const auto obj_g = gmem(P.obj);
+    const auto iters_g = gmem(P.iters);
+    const auto c_g = gmem(P.c);
+    const auto s_g = gmem(P.s);
+    const auto w_g = gmem(P.w);
+    const auto gstart = gmem(P.gstart);
+    const auto gidx = gmem(P.gidx);
+    const auto cgw = gmem(P.cg);
+    const auto bws = gmem(P.bws);
+    const int t = threadIdx.x, lane = t % kWave, wave = t / kWave;
+    const int half = lane / CB;               // which half of the slot's row this lane holds
+    const int os = CB * wave + lane % CB;     // slot owned by this lane (and by its partner lane)
+    const double d = *P.d;
+    const double yyn = *P.yyn;
+    const double inv_d = 1.0 / d;
+    const double thr_scale = (P.kind == OEM_ENET) ? P.alpha : 1.0;
+
+    int l0 = first ? 0 : *P.lstart;
+    if (l0 >= L) return;
+
+    // r_j (G is symmetric: column sums, coalesced), start coefficients, empty W
+    for (int j = t; j < p; j += NT) {
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        int k = 0;
+        for (; k + 4 <= p; k += 4) {
+            const double g0 = G[(size_t)k * p + j], g1 = G[(size_t)(k + 1) * p + j];
+            const double g2 = G[(size_t)(k + 2) * p + j], g3 = G[(size_t)(k + 3) * p + j];
+            a0 += fabs(g0);
+            a1 += fabs(g1);
+            a2 += fabs(g2);
+            a3 += fabs(g3);
+        }
+        for (; k < p; ++k) a0 += fabs(G[(size_t)k * p + j]);
+        r1[j] = (a0 + a1) + (a2 + a3);
+        bfull[j] = l0 > 0 ? bws[j] : 0.0;
+        slot_of[j] = -1;
+    }
+    for (int s = t; s < C; s += NT) {
+        ws[s] = -1;
+        gl[2 * s] = gl[2 * s + 1] = s % CB;
+    }
+    if (grp)
+        for (int g = t; g < P.ngroups; g += NT)
+            for (int q = gstart[g]; q < gstart[g + 1]; ++q) gof[gidx[q]] = g;
+    __syncthreads();
+
+    // per-slot state of the owning lanes (the same in both)
+    double Gr[HC];                // row W(os) of G_WW, columns [half HC, half HC + HC)
+#pragma unroll
+    for (int c = 0; c < HC; ++c) Gr[c] = 0.0;
+    int jc = -1;                  // coordinate of the owned slot
+    double bt = 0.0, bref = 0.0, ct = 0.0, wt = 1.0;
+    int gA = lane, gB = lane, gmaxw = 0;   // group lane range, largest group of the wave
+    double S = -1.0;              // drift allowed before the next check point
+    double Sthr = -1.0;           // S less a relative margin for rounding
+    Upd q{};
+    double lamc = 0.0;            // c_g lambda of the owned slot's group
+
+    // (G_WW beta_W) of the owned slot: beta_W from bsl[buf] by broadcast
+    // loads (each half reads its own column range), four accumulators, then
+    // the two halves joined.  The join adds the same two values in the same
+    // order in both lanes, so both get the same result.
+    auto symv = [&](int buf) -> double {
+        const double *bb = bsl + buf * C + half * HC;
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+#pragma unroll
+        for (int c = 0; c < HC; c += 4) {
+            const double2 v0 = *reinterpret_cast<const double2 *>(bb + c);
+            const double2 v1 = *reinterpret_cast<const double2 *>(bb + c + 2);
+            a0 += Gr[c] * v0.x;
+            a1 += Gr[c + 1] * v0.y;
+            a2 += Gr[c + 2] * v1.x;
+            a3 += Gr[c + 3] * v1.y;
+        }
+        const double sh = (a0 + a1) + (a2 + a3);
+        const int lo = __double2loint(sh), hi = __double2hiint(sh);
+        const auto pl = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+        const auto ph = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+        return __hiloint2double((int)ph[0], (int)pl[0]) + __hiloint2double((int)ph[1], (int)pl[1]);
+    };
+    // max over the 32 slots of the wave (lanes 0-31; lanes 32-63 hold the
+    // same values), the same in every lane
+    auto slot_max = [&](double v) -> double {
+        v = fmax(v, dpp_mov<0xB1>(v));
+        v = fmax(v, dpp_mov<0x4E>(v));
+        v = fmax(v, dpp_mov<0x124>(v));
+        v = fmax(v, dpp_mov<0x128>(v));
+        return fmax(readlane_d(v, 0), readlane_d(v, 16));
+    };
+    auto set_upd = [&](double lam) {
+        q = make_upd(P.kind, wt * lam, d, P.alpha, P.gamma);
+        lamc = (grp && jc >= 0) ? cgw[gof[jc]] * lam : 0.0;
+    };
+
+    // Check point at the current beta.  lam_end >= 0: the lambda whose
+    // iterations just ended (outputs, stationarity, objective for index
+    // l_end).  lam_next >= 0: the lambda the next updates use (screening
+    // keys).  from_slots: beta is in the owners' registers (else in bfull).
+    // force: rebuild W even when every needed coordinate is in it.
+    // Returns 1 when more than C coordinates need W (uniform).
+    auto checkpoint = [&](int l_end, double lam_end, double lam_next, bool from_slots, bool force,
+                          int it_end, bool conv_end) -> int {
+        if (from_slots) {
+            if (half == 0 && jc >= 0) bfull[jc] = bt;
+            __syncthreads();
+        }
+        // nonzero coordinates in ascending order
+        int nact = 0;
+        for (int base = 0; base < p; base += NT) {
+            const int j = base + t;
+            const bool nz = j < p && bfull[j] != 0.0;
+            const uint64_t ball = __ballot(nz);
+            if (lane == 0) misc[16 + wave] = __popcll(ball);
+            __syncthreads();
+            int before = 0, total = 0;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) {
+                const int cw = misc[16 + w];
+                before += (w < wave) ? cw : 0;
+                total += cw;
+            }
+            if (nz) {
+                const int k = nact + before + __popcll(ball & ((1ull << lane) - 1ull));
+                if (k < C) {
+                    aj[k] = j;
+                    ab[k] = bfull[j];
+                }
+            }
+            nact += total;
+            __syncthreads();
+        }
+        if (nact > C) return 1;
+        // G beta for every coordinate from the columns of the nonzero ones
+        for (int j = t; j < p; j += NT) {
+            double a[4] = {0.0, 0.0, 0.0, 0.0};
+            for (int e0 = 0; e0 < nact; e0 += 16) {
+                double gv[16], bv[16];
+#pragma unroll
+                for (int u = 0; u < 16; ++u) {
+                    const int e = min(e0 + u, nact - 1);
+                    bv[u] = (e0 + u < nact) ? ab[e] : 0.0;
+                    gv[u] = G[(size_t)aj[e] * p + j];
+                }
+#pragma unroll
+                for (int u = 0; u < 16; ++u) a[u % 4] += gv[u] * bv[u];
+            }
+            gfull[j] = (a[0] + a[1]) + (a[2] + a[3]);
+        }
+        __syncthreads();
+        // exact u, outputs of the finished lambda, screening keys of the next
+        const bool has_next = lam_next >= 0.0;
+        double kv = 0.0, penv = 0.0, quad = 0.0, lin = 0.0, smin = INFINITY;
+        int nneed = 0;
+        if (!grp) {
+            for (int j = t; j < p; j += NT) {
+                const double b = bfull[j], g = gfull[j], cj = c_g[j];
+                const double wj = w_g ? w_g[j] : 1.0;
+                if (lam_end >= 0.0) {
+                    const double lw = wj * lam_end;
+                    const double gr = g - cj;
+                    if (b == 0.0)
+                        kv = nmax(kv, pos(fabs(gr) - thr_scale * lw));
+                    else
+                        kv = nmax(kv, fabs(gr + sgn(b) * pen_deriv(P.kind, fabs(b), lw, P.alpha, P.gamma)));
+                    penv += pen_value(P.kind, b, lw, P.alpha, P.gamma);
+                    quad += b * g;
+                    lin += cj * b;
+                    beta_g[(size_t)l_end * p + j] = b / s_g[j];
+                    if (beta_std_g) beta_std_g[(size_t)l_end * p + j] = b;
+                    bws[j] = b;
+                }
+                if (has_next) {
+                    const double u = cj + (d * b - g);
+                    const double thr = wj * lam_next * thr_scale;
+                    const double sl = thr - fabs(u);
+                    const bool need = (b != 0.0) || !(sl > 1e-12 * thr);
+                    const double kj = need ? -1.0 : (r1[j] > 0.0 ? fmin(sl / r1[j], DBL_MAX) : DBL_MAX);
+                    key[j] = kj;
+                    kid[j] = j;
+                    nneed += need ? 1 : 0;
+                    if (slot_of[j] < 0) smin = fmin(smin, kj);
+                }
+            }
+        } else {
+            for (int g = t; g < P.ngroups; g += NT) {
+                const int q0 = gstart[g], q1 = gstart[g + 1];
+                double uu = 0.0, bb = 0.0, gg = 0.0, rr = 0.0;
+                bool nz = false;
+                for (int qq = q0; qq < q1; ++qq) {
+                    const int j = gidx[qq];
+                    const double b = bfull[j], gv = gfull[j], cj = c_g[j];
+                    const double u = cj + (d * b - gv);
+                    uu += u * u;
+                    bb += b * b;
+                    gg += (gv - cj) * (gv - cj);
+                    rr += r1[j] * r1[j];
+                    nz |= b != 0.0;
+                    if (lam_end >= 0.0) {
+                        quad += b * gv;
+                        lin += cj * b;
+                        beta_g[(size_t)l_end * p + j] = b / s_g[j];
+                        if (beta_std_g) beta_std_g[(size_t)l_end * p + j] = b;
+                        bws[j] = b;
+                    }
+                }
+                if (lam_end >= 0.0) {
+                    const double lc = lam_end * cgw[g];
+                    const double bn = sqrt(bb);
+                    double v;
+                    if (bn > 0.0) {
+                        double ss = 0.0;
+                        for (int qq = q0; qq < q1; ++qq) {
+                            const int j = gidx[qq];
+                            const double e = (gfull[j] - c_g[j]) + lc * bfull[j] / bn;
+                            ss += e * e;
+                        }
+                        v = sqrt(ss);
+                    } else {
+                        v = pos(sqrt(gg) - lc);
+                    }
+                    kv = nmax(kv, v);
+                    penv += lc * bn;
+                }
+                if (has_next) {
+                    const double thr = cgw[g] * lam_next;
+                    const double sl = thr - sqrt(uu);
+                    const bool need = nz || !(sl > 1e-12 * thr);
+                    const double kg = need ? -1.0 : (rr > 0.0 ? fmin(sl / sqrt(rr), DBL_MAX) : DBL_MAX);
+                    key[g] = kg;
+                    kid[g] = g;
+                    nneed += need ? (q1 - q0) : 0;
+                    if (slot_of[gidx[q0]] < 0) smin = fmin(smin, kg);
+                }
+            }
+        }
+        if (has_next)
+            for (int i = nkeys + t; i < PS; i += NT) {
+                key[i] = INFINITY;
+                kid[i] = -1;
+            }
+        // block reductions: max kv, sums penv quad lin, min smin, sum nneed
+        kv = wave_max(kv);
+        penv = wave_sum(penv);
+        quad = wave_sum(quad);
+        lin = wave_sum(lin);
+        smin = -wave_max(-smin);
+        const double nn = wave_sum((double)nneed);
+        if (lane == 0) {
+            fin[0 * NW + wave] = kv;
+            fin[1 * NW + wave] = penv;
+            fin[2 * NW + wave] = quad;
+            fin[3 * NW + wave] = lin;
+            dm[wave * 4 + 0] = smin;      // dm[0][*] is free between updates
+            dm[wave * 4 + 1] = nn;
+        }
+        __syncthreads();
+        double SM = dm[0], NN = dm[1];
+        for (int w = 1; w < NW; ++w) {
+            SM = fmin(SM, dm[w * 4]);
+            NN += dm[w * 4 + 1];
+        }
+        if (lam_end >= 0.0 && t == 0) {
+            double K = fin[0], Pn = fin[NW], Q = fin[2 * NW], Li = fin[3 * NW];
+            for (int w = 1; w < NW; ++w) {
+                K = fmax(K, fin[w]);
+                Pn += fin[NW + w];
+                Q += fin[2 * NW + w];
+                Li += fin[3 * NW + w];
+            }
+            if (kkt_g) kkt_g[l_end] = K;
+            if (obj_g) obj_g[l_end] = 0.5 * Q - Li + 0.5 * yyn + Pn;
+            if (iters_g) iters_g[l_end] = conv_end ? it_end : -it_end;
+        }
+        if (!has_next) return 0;
+        if (NN > (double)C) return 1;
+        if (!force && SM > 0.0) {       // every needed coordinate is in W
+            S = SM;
+            Sthr = S * (1.0 - 1e-9);
+            bref = bt;
+            __syncthreads();            // dm and fin are read before they are reused
+            return 0;
+        }
+        // rebuild W: sort the keys (bitonic, ascending), needed ones first
+        for (int k = 2; k <= PS; k <<= 1)
+            for (int jj = k >> 1; jj > 0; jj >>= 1) {
+                __syncthreads();
+                for (int i = t; i < PS; i += NT) {
+                    const int ixj = i ^ jj;
+                    if (ixj > i) {
+                        const bool up = (i & k) == 0;
+                        const double a = key[i], b = key[ixj];
+                        if ((a > b) == up) {
+                            key[i] = b;
+                            key[ixj] = a;
+                            const int ti = kid[i];
+                            kid[i] = kid[ixj];
+                            kid[ixj] = ti;
+                        }
+                    }
+                }
+            }
+        __syncthreads();
+        for (int s = t; s < C; s += NT)
+            if (ws[s] >= 0) slot_of[ws[s]] = -1;
+        __syncthreads();
+        if (!grp) {
+            for (int s = t; s < C; s += NT) ws[s] = (s < nkeys) ? kid[s] : -1;
+            if (t == 0) {
+                misc[0] = 0;
+                dm[2] = (PS > C) ? key[C] : INFINITY;
+            }
+        } else if (t == 0) {
+            // whole groups into waves, first fit, in key order; stop at the
+            // first group that does not fit (its key bounds the drift)
+            for (int s = 0; s < C; ++s) {
+                ws[s] = -1;
+                gl[2 * s] = gl[2 * s + 1] = s % CB;
+            }
+            int fill[NW];
+            for (int w = 0; w < NW; ++w) fill[w] = 0;
+            double Sn = INFINITY;
+            int ovf = 0;
+            for (int i = 0; i < nkeys; ++i) {
+                const int g = kid[i];
+                if (g < 0) break;   // padding: every group has been placed
+                const int q0 = gstart[g], sz = gstart[g + 1] - q0;
+                int w = 0;
+                while (w < NW && fill[w] + sz > CB) ++w;
+                if (w == NW) {
+                    if (key[i] < 0.0) ovf = 1;
+                    Sn = key[i];
+                    break;
+                }
+                for (int m = 0; m < sz; ++m) {
+                    const int s = CB * w + fill[w] + m;
+                    ws[s] = gidx[q0 + m];
+                    gl[2 * s] = fill[w];
+                    gl[2 * s + 1] = fill[w] + sz;
+                }
+                fill[w] += sz;
+            }
+            misc[0] = ovf;
+            dm[2] = Sn;
+        }
+        __syncthreads();
+        if (misc[0]) return 1;
+        S = dm[2];
+        Sthr = S * (1.0 - 1e-9);
+        for (int s = t; s < C; s += NT)
+            if (ws[s] >= 0) slot_of[ws[s]] = s;
+        // both lanes of a slot take its new coordinate; G_WW into registers
+        jc = ws[os];
+        bt = jc >= 0 ? bfull[jc] : 0.0;
+        bref = bt;
+        ct = jc >= 0 ? c_g[jc] : 0.0;
+        wt = (jc >= 0 && w_g) ? w_g[jc] : 1.0;
+        if (grp) {
+            gA = gl[2 * os];
+            gB = gl[2 * os + 1];
+            int m = 0;
+            for (int c = 0; c < CB; ++c) m = max(m, gl[2 * (CB * wave + c) + 1] - gl[2 * (CB * wave + c)]);
+            gmaxw = m;
+        }
+#pragma unroll
+        for (int c = 0; c < HC; ++c) {
+            const int jcol = ws[half * HC + c];
+            Gr[c] = (jcol >= 0 && jc >= 0) ? G[(size_t)jcol * p + jc] : 0.0;
+        }
+        set_upd(lam_next);
+        __syncthreads();
+        return 0;
+    };
+
+    int cur = 0;
+    if (checkpoint(-1, -1.0, lambda_g[l0], false, true, 0, false)) {
+        if (t == 0) *P.lstart = l0;
+        return;
+    }
+    bsl[cur * C + os] = bt;       // both lanes of a slot write the same value
+    __syncthreads();
+
+    for (int l = l0; l < L; ++l) {
+        const double lam = lambda_g[l];
+        set_upd(lam);
+        int it = 0;
+        bool conv = false;
+        do {
+            const double gb = symv(cur);
+            const double u = ct + (d * bt - gb);
+            double bn;
+            if (grp) {
+                // the slot's group lies in lanes [gA, gB) of the first half
+                double ss = 0.0;
+                for (int k = 0; k < gmaxw; ++k) {
+                    const int src = min(gA + k, 63);
+                    const double v = __shfl(u, src);
+                    if (gA + k < gB) ss += v * v;
+                }
+                const double nrm = sqrt(ss);
+                const double f = nrm > 0.0 ? 1.0 - lamc / nrm : 0.0;
+                bn = (jc >= 0 && f > 0.0) ? (u * inv_d) * f : 0.0;
+            } else {
+                bn = jc >= 0 ? update_fast(P.kind, u, q, P.gamma) : 0.0;
+            }
+            const double dl = fabs(bn - bt), mx = fabs(bn), dr = fabs(bn - bref);
+            bt = bn;
+            ++it;
+            const int nxt = cur ^ 1;
+            bsl[nxt * C + os] = bn;
+            bool drift;
+            if (NW == 1) {
+                // stop when every change is within tol max|beta| (a NaN
+                // change never is); drift when any coordinate moved S or more
+                const double lim = P.tol * slot_max(mx);
+                conv = __ballot(!(dl <= lim)) == 0;
+                drift = __ballot(!(dr < Sthr)) != 0;
+                __syncthreads();
+            } else {
+                const double DLw = slot_max(dl <= INFINITY ? dl : INFINITY);
+                const double MXw = slot_max(mx);
+                const bool dw = __ballot(!(dr < Sthr)) != 0;
+                if (lane == 0) {
+                    dm[(nxt * NW + wave) * 4 + 0] = DLw;
+                    dm[(nxt * NW + wave) * 4 + 1] = MXw;
+                    dm[(nxt * NW + wave) * 4 + 2] = dw ? 1.0 : 0.0;
+                }
+                __syncthreads();
+                double DL = dm[nxt * NW * 4], MX = dm[nxt * NW * 4 + 1], DF = dm[nxt * NW * 4 + 2];
+#pragma unroll
+                for (int w = 1; w < NW; ++w) {
+                    DL = fmax(DL, dm[(nxt * NW + w) * 4]);
+                    MX = fmax(MX, dm[(nxt * NW + w) * 4 + 1]);
+                    DF = fmax(DF, dm[(nxt * NW + w) * 4 + 2]);
+                }
+                conv = DL <= P.tol * MX;
+                drift = DF > 0.0;
+            }
+            cur = nxt;
+            if (!conv && it < P.maxit && drift) {
+                // the drift reached S: exact u again, and a new W
+                __syncthreads();   // dm[cur] is read before the check point reuses dm
+                if (checkpoint(-1, -1.0, lam, true, true, 0, false)) {
+                    if (t == 0) *P.lstart = l;
+                    return;
+                }
+                bsl[cur * C + os] = bt;
+                __syncthreads();
+            }
+        } while (!conv && it < P.maxit);
+        __syncthreads();           // dm[cur] is read before the check point reuses dm
+        const double lnext = (l + 1 < L) ? lambda_g[l + 1] : -1.0;
+        if (checkpoint(l, lam, lnext, true, false, it, conv)) {
+            if (t == 0) *P.lstart = l + 1;
+            return;
+        }
+        if (l + 1 < L) {
+            // W may have been rebuilt: beta of the (new) slots
+            bsl[cur * C + os] = bt;
+            __syncthreads();
+        }
+    }
+    if (t == 0) *P.lstart = L;
+}
+
+int launch_paths_ws(const PathDesc *d_desc, const int *d_order, int count, int nw, int first, int pmax,
+                    hipStream_t s)
+{
+    if (count == 0) return OEM_OK;
+    const void *kern;
+    if (nw == 1)
+        kern = (const void *)path_ws_kernel<1>;
+    else if (nw == 2)
+        kern = (const void *)path_ws_kernel<2>;
+    else if (nw == 4)
+        kern = (const void *)path_ws_kernel<4>;
+    else
+        return fail(OEM_E_INVAL, "working-set path kernel: 1, 2 or 4 waves");
+    if (pmax > 2048) return fail(OEM_E_INVAL, "working-set path kernel needs p <= 2048");
+    int pcap = pmax;
+    const size_t lds = path_ws_lds_bytes(nw, pcap);
+    OEM_HIP_CHECK(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    void *args[] = {(void *)&d_desc, (void *)&d_order, (void *)&first, (void *)&pcap};
+    OEM_HIP_CHECK(hipLaunchKernel(kern, dim3(count), dim3(64 * nw), args, lds, s));
+    return OEM_OK;
+}
+
+} // namespace oem

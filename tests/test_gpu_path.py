@@ -111,6 +111,50 @@ def test_weights_and_unstandardized():
     _assert_paths(res["beta"].cpu().numpy(), ref["beta"], what="weighted")
 
 
+def test_zero_column_unstandardized():
+    """A column of zeros (standardize=0): its coefficient stays zero and its
+    screening key is unbounded, which must neither stall nor shift the rest."""
+    print("case: zero column, standardize=0, p=70", flush=True)
+    pr = workloads.tall_multi(n=6000, p=70, seed_tag=219)
+    pr.X[:, 7] = 0.0
+    pr.X[:, 41] = 0.0
+    res, ref = _fit_both(pr, ["lasso", dict(kind="scad", gamma=3.7)], 25, standardize=False)
+    b = res["beta"].cpu().numpy()
+    assert np.all(b[:, :, 7] == 0.0) and np.all(b[:, :, 41] == 0.0)
+    _assert_paths(b, ref["beta"], what="zero column")
+
+
+@pytest.mark.parametrize("p,n", [(48, 400), (100, 600), (120, 300_000), (260, 2_000)])
+def test_active_set_outgrows_working_set(p, n):
+    """Short, wide-ish problems whose active sets outgrow 32, 64 and 128
+    coordinates part-way along the path, so every path is handed from one
+    kernel to the next at some lambda (mid-lambda and at lambda ends).
+    Parity over the whole path."""
+    print(f"case: working-set hand-over p={p} n={n}", flush=True)
+    pr = workloads.tall_multi(n=n, p=p, seed_tag=230 + p)
+    pens = [dict(kind="lasso"), dict(kind="enet", alpha=0.5), dict(kind="mcp", gamma=3.0),
+            dict(kind="scad", gamma=3.7)]
+    res, ref = _fit_both(pr, pens, 40, ratio=1e-4)
+    _assert_paths(res["beta"].cpu().numpy(), ref["beta"], what=f"hand-over p={p}")
+    it = res["iters"].cpu().numpy()
+    assert np.all(it > 0)
+    assert np.all(np.abs(it - ref["iters"]) <= 1)
+    assert np.all(res["kkt"].cpu().numpy() <= 1e-8)
+
+
+def test_group_active_set_outgrows_working_set():
+    """Group lasso whose active groups outgrow the working set (p=150,
+    groups of 7 and 3, n small)."""
+    print("case: group working-set hand-over p=150", flush=True)
+    pr = workloads.tall_multi(n=700, p=150, seed_tag=241)
+    groups = np.repeat(np.arange(30), [7, 3] * 15).astype(np.int32)
+    rng = np.random.default_rng(5)
+    groups = rng.permutation(groups)
+    res, ref = _fit_both(pr, ["grp_lasso"], 30, ratio=1e-4, groups=groups)
+    _assert_paths(res["beta"].cpu().numpy(), ref["beta"], what="grp hand-over")
+    assert np.all(res["kkt"].cpu().numpy() <= 1e-8)
+
+
 def test_explicit_lambda_and_lambda_zero():
     oem = _oem()
     pr = workloads.tall_multi(n=8000, p=10, seed_tag=212)
