@@ -52,10 +52,14 @@ static __host__ __device__ inline int ws_pow2(int v)
     return s;
 }
 
+// G stays in LDS for the one-wave kernel (p <= 128)
+constexpr int kWsLdsGMaxP = 128;
+
 size_t path_ws_lds_bytes(int NW, int pcap)
 {
     const int C = NW * kWsCB, PSC = ws_pow2(pcap);
-    const size_t dbl = 2 * (size_t)C + 8 * (size_t)NW + 4 * (size_t)NW + 3 * (size_t)pcap + PSC + C;
+    const size_t gl = NW == 1 ? (size_t)pcap * pcap : 0;
+    const size_t dbl = 2 * (size_t)C + 8 * (size_t)NW + 4 * (size_t)NW + 6 * (size_t)pcap + PSC + C + gl;
     const size_t ints = (size_t)PSC + 2 * (size_t)pcap + 2 * (size_t)C + 2 * (size_t)C + 16 + 2 * (size_t)NW;
     return dbl * sizeof(double) + ints * sizeof(int) + 64;
 }
@@ -78,10 +82,14 @@ __global__ __launch_bounds__(64 * NW) void path_ws_kernel(const PathDesc *__rest
     double *fin = dm + 8 * NW;                // [4][NW] per-wave check-point sums
     double *bfull = fin + 4 * NW;             // [pcap] beta (zero outside W)
     double *gfull = bfull + pcap;             // [pcap] G beta
-    double *r1 = gfull + pcap;                // [pcap] sum_k |G_jk|
+    double *r1 = gfull + pcap;                // [pcap] r_j = sum_k |G_jk| (group lasso), else 1 / r_j
     double *key = r1 + pcap;                  // [PSC] s_j / r_j, -1 when j needs W
     double *ab = key + PSC;                   // [C] values of the nonzero coordinates
-    int *kid = reinterpret_cast<int *>(ab + C);   // [PSC] coordinate (group) of each key
+    double *cl = ab + C;                      // [pcap] c
+    double *sl_ = cl + pcap;                  // [pcap] column scales
+    double *wl = sl_ + pcap;                  // [pcap] penalty weights
+    double *gls = wl + pcap;                  // [pcap pcap] G (one-wave kernel only)
+    int *kid = reinterpret_cast<int *>(gls + (NW == 1 ? pcap * pcap : 0));   // [PSC] coordinate (group) of each key
     int *slot_of = kid + PSC;                 // [pcap] slot of each coordinate, -1 outside W
     int *gof = slot_of + pcap;                // [pcap] group of each coordinate
     int *ws = gof + pcap;                     // [C] coordinate of each slot, -1 when empty
@@ -111,23 +119,53 @@ __global__ __launch_bounds__(64 * NW) void path_ws_kernel(const PathDesc *__rest
     const double inv_d = 1.0 / d;
     const double thr_scale = (P.kind == OEM_ENET) ? P.alpha : 1.0;
 
+    // Workgroup barrier.  A one-wave workgroup needs none: its LDS operations
+    // complete in order, so a wavefront-scope fence (which also keeps global
+    // stores from being waited for) is enough.
+    auto sync = [&]() {
+        if constexpr (NW == 1) {
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+        } else {
+            __syncthreads();
+        }
+    };
+    // G from LDS (one wave) or from memory
+    auto gat = [&](size_t idx) -> double {
+        if constexpr (NW == 1)
+            return gls[idx];
+        else
+            return G[idx];
+    };
+
     int l0 = first ? 0 : *P.lstart;
     if (l0 >= L) return;
 
+    for (int j = t; j < p; j += NT) {
+        cl[j] = c_g[j];
+        sl_[j] = s_g[j];
+        wl[j] = w_g ? w_g[j] : 1.0;
+    }
+    if constexpr (NW == 1) {
+        const int pp = p * p;
+        for (int e = t; e < pp; e += NT) gls[e] = G[e];
+        sync();
+    }
     // r_j (G is symmetric: column sums, coalesced), start coefficients, empty W
     for (int j = t; j < p; j += NT) {
         double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
         int k = 0;
         for (; k + 4 <= p; k += 4) {
-            const double g0 = G[(size_t)k * p + j], g1 = G[(size_t)(k + 1) * p + j];
-            const double g2 = G[(size_t)(k + 2) * p + j], g3 = G[(size_t)(k + 3) * p + j];
+            const double g0 = gat((size_t)k * p + j), g1 = gat((size_t)(k + 1) * p + j);
+            const double g2 = gat((size_t)(k + 2) * p + j), g3 = gat((size_t)(k + 3) * p + j);
             a0 += fabs(g0);
             a1 += fabs(g1);
             a2 += fabs(g2);
             a3 += fabs(g3);
         }
-        for (; k < p; ++k) a0 += fabs(G[(size_t)k * p + j]);
-        r1[j] = (a0 + a1) + (a2 + a3);
+        for (; k < p; ++k) a0 += fabs(gat((size_t)k * p + j));
+        const double rj = (a0 + a1) + (a2 + a3);
+        r1[j] = grp ? rj : 1.0 / rj;   // 1 / r_j (inf for a zero column) for separable penalties
         bfull[j] = l0 > 0 ? bws[j] : 0.0;
         slot_of[j] = -1;
     }
@@ -138,7 +176,7 @@ __global__ __launch_bounds__(64 * NW) void path_ws_kernel(const PathDesc *__rest
     if (grp)
         for (int g = t; g < P.ngroups; g += NT)
             for (int q = gstart[g]; q < gstart[g + 1]; ++q) gof[gidx[q]] = g;
-    __syncthreads();
+    sync();
 
     // per-slot state of the owning lanes (the same in both)
     double Gr[HC];                // row W(os) of G_WW, columns [half HC, half HC + HC)
@@ -198,7 +236,7 @@ __global__ __launch_bounds__(64 * NW) void path_ws_kernel(const PathDesc *__rest
                           int it_end, bool conv_end) -> int {
         if (from_slots) {
             if (half == 0 && jc >= 0) bfull[jc] = bt;
-            __syncthreads();
+            sync();
         }
         // nonzero coordinates in ascending order
         int nact = 0;
@@ -207,7 +245,7 @@ __global__ __launch_bounds__(64 * NW) void path_ws_kernel(const PathDesc *__rest
             const bool nz = j < p && bfull[j] != 0.0;
             const uint64_t ball = __ballot(nz);
             if (lane == 0) misc[16 + wave] = __popcll(ball);
-            __syncthreads();
+            sync();
             int before = 0, total = 0;
 #pragma unroll
             for (int w = 0; w < NW; ++w) {
@@ -223,34 +261,73 @@ __global__ __launch_bounds__(64 * NW) void path_ws_kernel(const PathDesc *__rest
                 }
             }
             nact += total;
-            __syncthreads();
+            sync();
         }
         if (nact > C) return 1;
         // G beta for every coordinate from the columns of the nonzero ones
-        for (int j = t; j < p; j += NT) {
-            double a[4] = {0.0, 0.0, 0.0, 0.0};
+        if constexpr (NW == 1) {
+            // at most two coordinates per lane: the indices and values of
+            // the nonzero coordinates are read once per chunk of 16
+            constexpr int JM = (kWsLdsGMaxP + NT - 1) / NT;
+            double acc[JM];
+#pragma unroll
+            for (int jj = 0; jj < JM; ++jj) acc[jj] = 0.0;
             for (int e0 = 0; e0 < nact; e0 += 16) {
-                double gv[16], bv[16];
+                int je[16];
+                double be[16];
 #pragma unroll
                 for (int u = 0; u < 16; ++u) {
                     const int e = min(e0 + u, nact - 1);
-                    bv[u] = (e0 + u < nact) ? ab[e] : 0.0;
-                    gv[u] = G[(size_t)aj[e] * p + j];
+                    be[u] = (e0 + u < nact) ? ab[e] : 0.0;
+                    je[u] = aj[e];
                 }
 #pragma unroll
-                for (int u = 0; u < 16; ++u) a[u % 4] += gv[u] * bv[u];
+                for (int jj = 0; jj < JM; ++jj) {
+                    if (jj * NT >= p) break;
+                    const int j = min(t + jj * NT, p - 1);
+                    double gv[16];
+#pragma unroll
+                    for (int u = 0; u < 16; ++u) gv[u] = gat((size_t)je[u] * p + j);
+                    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+#pragma unroll
+                    for (int u = 0; u < 16; u += 4) {
+                        a0 += gv[u] * be[u];
+                        a1 += gv[u + 1] * be[u + 1];
+                        a2 += gv[u + 2] * be[u + 2];
+                        a3 += gv[u + 3] * be[u + 3];
+                    }
+                    acc[jj] += (a0 + a1) + (a2 + a3);
+                }
             }
-            gfull[j] = (a[0] + a[1]) + (a[2] + a[3]);
+#pragma unroll
+            for (int jj = 0; jj < JM; ++jj)
+                if (t + jj * NT < p) gfull[t + jj * NT] = acc[jj];
+        } else {
+            for (int j = t; j < p; j += NT) {
+                double a[4] = {0.0, 0.0, 0.0, 0.0};
+                for (int e0 = 0; e0 < nact; e0 += 16) {
+                    double gv[16], bv[16];
+#pragma unroll
+                    for (int u = 0; u < 16; ++u) {
+                        const int e = min(e0 + u, nact - 1);
+                        bv[u] = (e0 + u < nact) ? ab[e] : 0.0;
+                        gv[u] = gat((size_t)aj[e] * p + j);
+                    }
+#pragma unroll
+                    for (int u = 0; u < 16; ++u) a[u % 4] += gv[u] * bv[u];
+                }
+                gfull[j] = (a[0] + a[1]) + (a[2] + a[3]);
+            }
         }
-        __syncthreads();
+        sync();
         // exact u, outputs of the finished lambda, screening keys of the next
         const bool has_next = lam_next >= 0.0;
         double kv = 0.0, penv = 0.0, quad = 0.0, lin = 0.0, smin = INFINITY;
         int nneed = 0;
         if (!grp) {
             for (int j = t; j < p; j += NT) {
-                const double b = bfull[j], g = gfull[j], cj = c_g[j];
-                const double wj = w_g ? w_g[j] : 1.0;
+                const double b = bfull[j], g = gfull[j], cj = cl[j];
+                const double wj = wl[j];
                 if (lam_end >= 0.0) {
                     const double lw = wj * lam_end;
                     const double gr = g - cj;
@@ -261,7 +338,7 @@ __global__ __launch_bounds__(64 * NW) void path_ws_kernel(const PathDesc *__rest
                     penv += pen_value(P.kind, b, lw, P.alpha, P.gamma);
                     quad += b * g;
                     lin += cj * b;
-                    beta_g[(size_t)l_end * p + j] = b / s_g[j];
+                    beta_g[(size_t)l_end * p + j] = b / sl_[j];
                     if (beta_std_g) beta_std_g[(size_t)l_end * p + j] = b;
                     bws[j] = b;
                 }
@@ -270,7 +347,7 @@ __global__ __launch_bounds__(64 * NW) void path_ws_kernel(const PathDesc *__rest
                     const double thr = wj * lam_next * thr_scale;
                     const double sl = thr - fabs(u);
                     const bool need = (b != 0.0) || !(sl > 1e-12 * thr);
-                    const double kj = need ? -1.0 : (r1[j] > 0.0 ? fmin(sl / r1[j], DBL_MAX) : DBL_MAX);
+                    const double kj = need ? -1.0 : fmin(sl * r1[j], DBL_MAX);
                     key[j] = kj;
                     kid[j] = j;
                     nneed += need ? 1 : 0;
@@ -284,7 +361,7 @@ __global__ __launch_bounds__(64 * NW) void path_ws_kernel(const PathDesc *__rest
                 bool nz = false;
                 for (int qq = q0; qq < q1; ++qq) {
                     const int j = gidx[qq];
-                    const double b = bfull[j], gv = gfull[j], cj = c_g[j];
+                    const double b = bfull[j], gv = gfull[j], cj = cl[j];
                     const double u = cj + (d * b - gv);
                     uu += u * u;
                     bb += b * b;
@@ -294,7 +371,7 @@ __global__ __launch_bounds__(64 * NW) void path_ws_kernel(const PathDesc *__rest
                     if (lam_end >= 0.0) {
                         quad += b * gv;
                         lin += cj * b;
-                        beta_g[(size_t)l_end * p + j] = b / s_g[j];
+                        beta_g[(size_t)l_end * p + j] = b / sl_[j];
                         if (beta_std_g) beta_std_g[(size_t)l_end * p + j] = b;
                         bws[j] = b;
                     }
@@ -307,7 +384,7 @@ __global__ __launch_bounds__(64 * NW) void path_ws_kernel(const PathDesc *__rest
                         double ss = 0.0;
                         for (int qq = q0; qq < q1; ++qq) {
                             const int j = gidx[qq];
-                            const double e = (gfull[j] - c_g[j]) + lc * bfull[j] / bn;
+                            const double e = (gfull[j] - cl[j]) + lc * bfull[j] / bn;
                             ss += e * e;
                         }
                         v = sqrt(ss);
@@ -349,7 +426,7 @@ __global__ __launch_bounds__(64 * NW) void path_ws_kernel(const PathDesc *__rest
             dm[wave * 4 + 0] = smin;      // dm[0][*] is free between updates
             dm[wave * 4 + 1] = nn;
         }
-        __syncthreads();
+        sync();
         double SM = dm[0], NN = dm[1];
         for (int w = 1; w < NW; ++w) {
             SM = fmin(SM, dm[w * 4]);
@@ -373,32 +450,70 @@ __global__ __launch_bounds__(64 * NW) void path_ws_kernel(const PathDesc *__rest
             S = SM;
             Sthr = S * (1.0 - 1e-9);
             bref = bt;
-            __syncthreads();            // dm and fin are read before they are reused
+            sync();            // dm and fin are read before they are reused
             return 0;
         }
-        // rebuild W: sort the keys (bitonic, ascending), needed ones first
-        for (int k = 2; k <= PS; k <<= 1)
-            for (int jj = k >> 1; jj > 0; jj >>= 1) {
-                __syncthreads();
-                for (int i = t; i < PS; i += NT) {
-                    const int ixj = i ^ jj;
-                    if (ixj > i) {
-                        const bool up = (i & k) == 0;
-                        const double a = key[i], b = key[ixj];
-                        if ((a > b) == up) {
-                            key[i] = b;
-                            key[ixj] = a;
-                            const int ti = kid[i];
-                            kid[i] = kid[ixj];
-                            kid[ixj] = ti;
-                        }
+        // rebuild W: order the keys ascending, needed ones first
+        if constexpr (NW == 1) {
+            // at most 128 keys (two per lane): the rank of each key among all
+            // of them (ties by position) is its place in the order
+            sync();
+            double mk[2];
+            int mi[2], rk[2] = {0, 0};
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                const int i = t + 64 * e;
+                mk[e] = i < PS ? key[i] : 0.0;
+                mi[e] = i < PS ? kid[i] : -1;
+            }
+            for (int j0 = 0; j0 < PS; j0 += 8) {
+                double kk[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) kk[u] = key[min(j0 + u, PS - 1)];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int j = j0 + u;
+                    const int jv = j < PS;
+#pragma unroll
+                    for (int e = 0; e < 2; ++e) {
+                        // bitwise, not short-circuit: no branches
+                        const int lt = kk[u] < mk[e], eq = kk[u] == mk[e], before = j < t + 64 * e;
+                        rk[e] += jv & (lt | (eq & before));
                     }
                 }
             }
-        __syncthreads();
+            sync();
+#pragma unroll
+            for (int e = 0; e < 2; ++e)
+                if (t + 64 * e < PS) {
+                    key[rk[e]] = mk[e];
+                    kid[rk[e]] = mi[e];
+                }
+        } else {
+            // bitonic sort
+            for (int k = 2; k <= PS; k <<= 1)
+                for (int jj = k >> 1; jj > 0; jj >>= 1) {
+                    sync();
+                    for (int i = t; i < PS; i += NT) {
+                        const int ixj = i ^ jj;
+                        if (ixj > i) {
+                            // compare-exchange with selects (stores are unconditional)
+                            const bool up = (i & k) == 0;
+                            const double a = key[i], b = key[ixj];
+                            const int ta = kid[i], tb = kid[ixj];
+                            const bool sw = (a > b) == up;
+                            key[i] = sw ? b : a;
+                            key[ixj] = sw ? a : b;
+                            kid[i] = sw ? tb : ta;
+                            kid[ixj] = sw ? ta : tb;
+                        }
+                    }
+                }
+        }
+        sync();
         for (int s = t; s < C; s += NT)
             if (ws[s] >= 0) slot_of[ws[s]] = -1;
-        __syncthreads();
+        sync();
         if (!grp) {
             for (int s = t; s < C; s += NT) ws[s] = (s < nkeys) ? kid[s] : -1;
             if (t == 0) {
@@ -438,7 +553,7 @@ __global__ __launch_bounds__(64 * NW) void path_ws_kernel(const PathDesc *__rest
             misc[0] = ovf;
             dm[2] = Sn;
         }
-        __syncthreads();
+        sync();
         if (misc[0]) return 1;
         S = dm[2];
         Sthr = S * (1.0 - 1e-9);
@@ -448,8 +563,8 @@ __global__ __launch_bounds__(64 * NW) void path_ws_kernel(const PathDesc *__rest
         jc = ws[os];
         bt = jc >= 0 ? bfull[jc] : 0.0;
         bref = bt;
-        ct = jc >= 0 ? c_g[jc] : 0.0;
-        wt = (jc >= 0 && w_g) ? w_g[jc] : 1.0;
+        ct = jc >= 0 ? cl[jc] : 0.0;
+        wt = jc >= 0 ? wl[jc] : 1.0;
         if (grp) {
             gA = gl[2 * os];
             gB = gl[2 * os + 1];
@@ -460,10 +575,10 @@ __global__ __launch_bounds__(64 * NW) void path_ws_kernel(const PathDesc *__rest
 #pragma unroll
         for (int c = 0; c < HC; ++c) {
             const int jcol = ws[half * HC + c];
-            Gr[c] = (jcol >= 0 && jc >= 0) ? G[(size_t)jcol * p + jc] : 0.0;
+            Gr[c] = (jcol >= 0 && jc >= 0) ? gat((size_t)jcol * p + jc) : 0.0;
         }
         set_upd(lam_next);
-        __syncthreads();
+        sync();
         return 0;
     };
 
@@ -473,15 +588,17 @@ __global__ __launch_bounds__(64 * NW) void path_ws_kernel(const PathDesc *__rest
         return;
     }
     bsl[cur * C + os] = bt;       // both lanes of a slot write the same value
-    __syncthreads();
+    sync();
+    double gb = symv(cur);
 
+    double lam_cur = lambda_g[l0];
     for (int l = l0; l < L; ++l) {
-        const double lam = lambda_g[l];
+        const double lam = lam_cur;
+        const double lnext = (l + 1 < L) ? lambda_g[l + 1] : -1.0;   // in flight during the updates
         set_upd(lam);
         int it = 0;
         bool conv = false;
         do {
-            const double gb = symv(cur);
             const double u = ct + (d * bt - gb);
             double bn;
             if (grp) {
@@ -505,12 +622,15 @@ __global__ __launch_bounds__(64 * NW) void path_ws_kernel(const PathDesc *__rest
             bsl[nxt * C + os] = bn;
             bool drift;
             if (NW == 1) {
+                sync();
+                // the next product does not depend on the stopping test, so
+                // its loads and products overlap the reduction below
+                gb = symv(nxt);
                 // stop when every change is within tol max|beta| (a NaN
                 // change never is); drift when any coordinate moved S or more
                 const double lim = P.tol * slot_max(mx);
                 conv = __ballot(!(dl <= lim)) == 0;
                 drift = __ballot(!(dr < Sthr)) != 0;
-                __syncthreads();
             } else {
                 const double DLw = slot_max(dl <= INFINITY ? dl : INFINITY);
                 const double MXw = slot_max(mx);
@@ -520,7 +640,7 @@ __global__ __launch_bounds__(64 * NW) void path_ws_kernel(const PathDesc *__rest
                     dm[(nxt * NW + wave) * 4 + 1] = MXw;
                     dm[(nxt * NW + wave) * 4 + 2] = dw ? 1.0 : 0.0;
                 }
-                __syncthreads();
+                sync();
                 double DL = dm[nxt * NW * 4], MX = dm[nxt * NW * 4 + 1], DF = dm[nxt * NW * 4 + 2];
 #pragma unroll
                 for (int w = 1; w < NW; ++w) {
@@ -530,21 +650,22 @@ __global__ __launch_bounds__(64 * NW) void path_ws_kernel(const PathDesc *__rest
                 }
                 conv = DL <= P.tol * MX;
                 drift = DF > 0.0;
+                gb = symv(nxt);
             }
             cur = nxt;
             if (!conv && it < P.maxit && drift) {
                 // the drift reached S: exact u again, and a new W
-                __syncthreads();   // dm[cur] is read before the check point reuses dm
+                sync();   // dm[cur] is read before the check point reuses dm
                 if (checkpoint(-1, -1.0, lam, true, true, 0, false)) {
                     if (t == 0) *P.lstart = l;
                     return;
                 }
                 bsl[cur * C + os] = bt;
-                __syncthreads();
+                sync();
+                gb = symv(cur);
             }
         } while (!conv && it < P.maxit);
-        __syncthreads();           // dm[cur] is read before the check point reuses dm
-        const double lnext = (l + 1 < L) ? lambda_g[l + 1] : -1.0;
+        sync();           // dm[cur] is read before the check point reuses dm
         if (checkpoint(l, lam, lnext, true, false, it, conv)) {
             if (t == 0) *P.lstart = l + 1;
             return;
@@ -552,8 +673,10 @@ __global__ __launch_bounds__(64 * NW) void path_ws_kernel(const PathDesc *__rest
         if (l + 1 < L) {
             // W may have been rebuilt: beta of the (new) slots
             bsl[cur * C + os] = bt;
-            __syncthreads();
+            sync();
+            gb = symv(cur);
         }
+        lam_cur = lnext;
     }
     if (t == 0) *P.lstart = L;
 }
@@ -572,6 +695,7 @@ int launch_paths_ws(const PathDesc *d_desc, const int *d_order, int count, int n
     else
         return fail(OEM_E_INVAL, "working-set path kernel: 1, 2 or 4 waves");
     if (pmax > 2048) return fail(OEM_E_INVAL, "working-set path kernel needs p <= 2048");
+    if (nw == 1 && pmax > kWsLdsGMaxP) return fail(OEM_E_INVAL, "one-wave working-set kernel needs p <= 128");
     int pcap = pmax;
     const size_t lds = path_ws_lds_bytes(nw, pcap);
     OEM_HIP_CHECK(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
