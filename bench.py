@@ -60,7 +60,8 @@ def parse():
 # changed source makes the stored figures stale and traffic is reported null.
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_tall_multi.txt")
 TRAFFIC_SOURCES = {"gram": ["gram_bf16.hip", "gram_common.hip", "gram_common.h"],
-                   "fit": ["derive.hip", "path.hip", "path_reg.hip", "path_common.h"]}
+                   "fit": ["derive.hip", "path.hip", "path_reg.hip", "path_stream.hip", "path_ws.hip",
+                           "path_common.h"]}
 
 
 def sources_hash(phase):

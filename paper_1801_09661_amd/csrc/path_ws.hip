@@ -454,32 +454,40 @@ __global__ __launch_bounds__(64 * NW) void path_ws_kernel(const PathDesc *__rest
             return 0;
         }
         // rebuild W: order the keys ascending, needed ones first
+        double s_out = INFINITY;   // one wave: smallest key left outside W
         if constexpr (NW == 1) {
-            // at most 128 keys (two per lane): the rank of each key among all
-            // of them (ties by position) is its place in the order
+            // At most 128 keys, two per lane.  Each key gets a 64-bit order
+            // code: its bit pattern (keys are -1 for needed coordinates, else
+            // positive, +inf for padding) with the low 8 bits replaced by its
+            // position, so codes are distinct and ordered as the keys up to
+            // 2^-44 relative.  A key's rank among the codes is its place.
             sync();
             double mk[2];
             int mi[2], rk[2] = {0, 0};
+            unsigned long long mc[2];
 #pragma unroll
             for (int e = 0; e < 2; ++e) {
                 const int i = t + 64 * e;
-                mk[e] = i < PS ? key[i] : 0.0;
+                mk[e] = i < PS ? key[i] : INFINITY;
                 mi[e] = i < PS ? kid[i] : -1;
+                const unsigned long long kb = (unsigned long long)__double_as_longlong(mk[e]);
+                mc[e] = mk[e] < 0.0 ? (unsigned long long)i : (((kb < 256ull ? 256ull : kb) & ~255ull) | (unsigned long long)i);
             }
-            for (int j0 = 0; j0 < PS; j0 += 8) {
-                double kk[8];
+            sync();
+            unsigned long long *code = reinterpret_cast<unsigned long long *>(key);
 #pragma unroll
-                for (int u = 0; u < 8; ++u) kk[u] = key[min(j0 + u, PS - 1)];
+            for (int e = 0; e < 2; ++e)
+                if (t + 64 * e < PS) code[t + 64 * e] = mc[e];
+            sync();
+            for (int j0 = 0; j0 < PS; j0 += 8) {
+                unsigned long long cc[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) cc[u] = code[min(j0 + u, PS - 1)];
 #pragma unroll
                 for (int u = 0; u < 8; ++u) {
-                    const int j = j0 + u;
-                    const int jv = j < PS;
+                    const int jv = j0 + u < PS;
 #pragma unroll
-                    for (int e = 0; e < 2; ++e) {
-                        // bitwise, not short-circuit: no branches
-                        const int lt = kk[u] < mk[e], eq = kk[u] == mk[e], before = j < t + 64 * e;
-                        rk[e] += jv & (lt | (eq & before));
-                    }
+                    for (int e = 0; e < 2; ++e) rk[e] += jv & (int)(cc[u] < mc[e]);
                 }
             }
             sync();
@@ -489,6 +497,13 @@ __global__ __launch_bounds__(64 * NW) void path_ws_kernel(const PathDesc *__rest
                     key[rk[e]] = mk[e];
                     kid[rk[e]] = mi[e];
                 }
+            // the drift bound: the smallest key ranked at C or later (exact,
+            // whatever the order codes did with near-equal keys)
+            double so = INFINITY;
+#pragma unroll
+            for (int e = 0; e < 2; ++e)
+                if (t + 64 * e < PS && rk[e] >= C) so = fmin(so, mk[e]);
+            s_out = -wave_max(-so);
         } else {
             // bitonic sort
             for (int k = 2; k <= PS; k <<= 1)
@@ -518,7 +533,7 @@ __global__ __launch_bounds__(64 * NW) void path_ws_kernel(const PathDesc *__rest
             for (int s = t; s < C; s += NT) ws[s] = (s < nkeys) ? kid[s] : -1;
             if (t == 0) {
                 misc[0] = 0;
-                dm[2] = (PS > C) ? key[C] : INFINITY;
+                dm[2] = (NW == 1) ? s_out : ((PS > C) ? key[C] : INFINITY);
             }
         } else if (t == 0) {
             // whole groups into waves, first fit, in key order; stop at the
