@@ -23,15 +23,16 @@
 // than one wave that write is followed by the update's only barrier.  The
 // stopping rule needs max |beta| (one reduction); whether every change is
 // within tol times it, and whether any coordinate drifted past the screening
-// bound, are wave ballots.  The coordinates outside W are not touched while the drift
-// max_k |beta_k - beta_ref_k| stays below S = min over j outside W of
-// s_j / r_j.  At a check point - the start of the path, the end of every
+// bound, are wave ballots.  The coordinates outside W are not touched while
+// the drift max_k |beta_k - beta_ref_k| stays below S = min over j outside W
+// of s_j / r_j.  At a check point - the start of the path, the end of every
 // lambda, and whenever the drift reaches S - the kernel forms G beta for all
-// p coordinates from the columns of the nonzero coordinates (read from
-// memory), which gives the exact u, the stationarity check and the objective,
-// and rebuilds W when a coordinate outside it needs to enter or the drift
-// reached S.  The iterates are those of the full update: the coordinates
-// outside W are exactly the ones the full update would leave at zero.
+// p coordinates from the columns of the nonzero coordinates (from LDS in the
+// one-wave kernel, else from memory), which gives the exact u, the
+// stationarity check, the objective and new keys, and rebuilds W when a
+// coordinate outside it needs to enter.  The iterates are those of the full
+// update: the coordinates outside W are exactly the ones the full update
+// would leave at zero.
 //
 // When more than C coordinates need W, the kernel stops before that lambda:
 // *lstart receives the lambda index and bws the coefficients (standardised)
@@ -230,9 +231,11 @@ __global__ __launch_bounds__(64 * NW) void path_ws_kernel(const PathDesc *__rest
     // iterations just ended (outputs, stationarity, objective for index
     // l_end).  lam_next >= 0: the lambda the next updates use (screening
     // keys).  from_slots: beta is in the owners' registers (else in bfull).
-    // force: rebuild W even when every needed coordinate is in it.
+    // keep: W is kept when every needed coordinate is in it and the drift
+    // it then allows (the smallest key outside it) exceeds keep; otherwise
+    // W is rebuilt (keep = inf always rebuilds).
     // Returns 1 when more than C coordinates need W (uniform).
-    auto checkpoint = [&](int l_end, double lam_end, double lam_next, bool from_slots, bool force,
+    auto checkpoint = [&](int l_end, double lam_end, double lam_next, bool from_slots, double keep,
                           int it_end, bool conv_end) -> int {
         if (from_slots) {
             if (half == 0 && jc >= 0) bfull[jc] = bt;
@@ -446,7 +449,7 @@ __global__ __launch_bounds__(64 * NW) void path_ws_kernel(const PathDesc *__rest
         }
         if (!has_next) return 0;
         if (NN > (double)C) return 1;
-        if (!force && SM > 0.0) {       // every needed coordinate is in W
+        if (SM > 0.0 && SM > keep) {    // every needed coordinate is in W
             S = SM;
             Sthr = S * (1.0 - 1e-9);
             bref = bt;
@@ -598,7 +601,7 @@ __global__ __launch_bounds__(64 * NW) void path_ws_kernel(const PathDesc *__rest
     };
 
     int cur = 0;
-    if (checkpoint(-1, -1.0, lambda_g[l0], false, true, 0, false)) {
+    if (checkpoint(-1, -1.0, lambda_g[l0], false, INFINITY, 0, false)) {
         if (t == 0) *P.lstart = l0;
         return;
     }
@@ -669,9 +672,12 @@ __global__ __launch_bounds__(64 * NW) void path_ws_kernel(const PathDesc *__rest
             }
             cur = nxt;
             if (!conv && it < P.maxit && drift) {
-                // the drift reached S: exact u again, and a new W
+                // the drift reached S: exact u again, new keys and bound; W
+                // is rebuilt only when a coordinate outside it needs to enter
+                // (rebuilding every time costs more than the extra check
+                // points it saves)
                 sync();   // dm[cur] is read before the check point reuses dm
-                if (checkpoint(-1, -1.0, lam, true, true, 0, false)) {
+                if (checkpoint(-1, -1.0, lam, true, 0.0, 0, false)) {
                     if (t == 0) *P.lstart = l;
                     return;
                 }
@@ -681,7 +687,7 @@ __global__ __launch_bounds__(64 * NW) void path_ws_kernel(const PathDesc *__rest
             }
         } while (!conv && it < P.maxit);
         sync();           // dm[cur] is read before the check point reuses dm
-        if (checkpoint(l, lam, lnext, true, false, it, conv)) {
+        if (checkpoint(l, lam, lnext, true, 0.0, it, conv)) {
             if (t == 0) *P.lstart = l + 1;
             return;
         }
