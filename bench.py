@@ -50,6 +50,8 @@ def parse():
     ap.add_argument("--requests", type=int, default=2000)
     ap.add_argument("--rate", type=float, default=50.0)
     ap.add_argument("--slots", type=int, default=8)
+    ap.add_argument("--cv", action="store_true",
+                    help="grouped 10-fold CV workload instead (n=2e6, p=500, group lasso + lasso + MCP)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="after the steps, copy X once with a plain device copy (traffic calibration)")
     return ap.parse_args()
@@ -168,6 +170,107 @@ def run_form(oem, torch, X, y, precision, steps, warm, nlambda):
                 updates=int(np.abs(iters).sum()), beta=beta)
 
 
+CV_PENALTIES = [dict(kind="grp_lasso"), dict(kind="lasso"), dict(kind="mcp", gamma=3.0)]
+
+
+def cv_main(args):
+    """Grouped 10-fold CV workload: n = 2e6, p = 500, AR(1) rho = 0.3 FP32 X,
+    50 contiguous groups of 10 (5 active), sigma = 2; group lasso, lasso and
+    MCP (gamma 3), 100 lambdas.  A step is one Gram pass with fold sums
+    followed by oem_cv (10 folds + the full data = 33 paths, CV error and
+    selection), timed for the split-BF16 and the FP64 forms."""
+    import numpy as np
+    import torch
+    import paper_1801_09661_amd as oem
+    import workloads
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    oem.load_library()
+    n = 2_000_000 if args.n == 1_000_000 else args.n
+    p = 500 if args.p == 100 else args.p
+    K = 10
+    pr = workloads.cv_grouped(n=n, p=p)
+    X = torch.from_numpy(pr.X).cuda()
+    y = torch.from_numpy(pr.y).cuda()
+    groups = pr.groups
+    del pr
+    torch.cuda.synchronize()
+    steps = args.profile_steps or args.steps
+    warm = 0 if args.profile_steps else args.warmup
+    forms = [args.precision] if args.profile_steps else [args.precision, "fp64"]
+    if args.precision == "fp64":
+        forms = ["fp64"]
+    stream = torch.cuda.current_stream()
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    runs = {}
+    for form in forms:
+        g = oem.Gram(p, K, form, X.dtype, 180109661)
+
+        def step(rec=None):
+            oem.oem_gram_reset(g.h)
+            if rec is not None:
+                rec[0].record(stream)
+            g.add(X, y)
+            if rec is not None:
+                rec[1].record(stream)
+            r = g.cv(CV_PENALTIES, nlambda=args.nlambda, lambda_min_ratio=1e-3, tol=1e-10,
+                     groups=groups, sync=False)
+            if rec is not None:
+                rec[2].record(stream)
+            return r
+
+        for _ in range(warm):
+            step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            res = step()
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        rec = [ev(), ev(), ev()]
+        res = step(rec)
+        torch.cuda.synchronize()
+        runs[form] = dict(ms_per_step=1e3 * t / steps, fits_per_s=(K + 1) * len(CV_PENALTIES) * steps / t,
+                          gram_ms=rec[0].elapsed_time(rec[1]), cv_ms=rec[1].elapsed_time(rec[2]),
+                          updates=int(np.abs(res["iters"].cpu().numpy()).sum()),
+                          beta=res["beta"].cpu().numpy())
+        g.close()
+    main_run = runs[args.precision]
+    x_bytes = n * p * X.element_size() + n * 8
+    out = {
+        "metric": METRIC,
+        "value": main_run["fits_per_s"],
+        "unit": "fits/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": warm,
+        "ms_per_step": main_run["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp64": "f64", "split_bf16": "split-bf16 Gram (f32 acc, f64 reduce) + f64 paths",
+                  "bf16": "bf16 Gram (f32 acc, f64 reduce) + f64 paths"}[args.precision],
+        "data": "synthetic",
+        "config": {"workload": "cv_grouped: n=2e6 p=500 AR(1) rho=0.3 FP32 X, 10 hashed folds, 50 groups "
+                               "of 10 (5 active), group lasso+lasso+MCP, 100 lambdas, tol 1e-10",
+                   "n": n, "p": p, "folds": K, "penalties": len(CV_PENALTIES), "nlambda": args.nlambda,
+                   "precision": args.precision},
+        "gram_ms_in_step": main_run["gram_ms"],
+        "cv_ms_in_step": main_run["cv_ms"],
+        "gram_gbps": x_bytes / (main_run["gram_ms"] * 1e-3) / 1e9,
+        "oem_updates": main_run["updates"],
+    }
+    if "fp64" in runs and args.precision != "fp64":
+        f64 = runs["fp64"]
+        out["fp64_form"] = dict(fits_per_s=f64["fits_per_s"], ms_per_step=f64["ms_per_step"],
+                                gram_ms_in_step=f64["gram_ms"], cv_ms_in_step=f64["cv_ms"])
+        out["mixed_vs_fp64_fits"] = main_run["fits_per_s"] / f64["fits_per_s"]
+        bm, bf = main_run["beta"], f64["beta"]
+        scale = np.maximum(np.abs(bf).max(axis=2), 1e-300)
+        out["mixed_coef_err_vs_fp64_form"] = float((np.abs(bm - bf).max(axis=2) / scale)[:, 1:].max())
+    print(json.dumps(out))
+
+
 def serve_main(args):
     """Serving workload: requests with Poisson arrivals at `rate`/s, p
     log-uniform in [10, 1000], n log-uniform in [1e4, 1e6] (n >= 10 p),
@@ -259,6 +362,8 @@ def main():
         sys.exit(2)
     if args.serve:
         return serve_main(args)
+    if args.cv:
+        return cv_main(args)
     import numpy as np
     import torch
     import paper_1801_09661_amd as oem
