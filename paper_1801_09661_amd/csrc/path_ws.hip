@@ -87,8 +87,8 @@ __global__ __launch_bounds__(64 * NW) void path_ws_kernel(const PathDesc *__rest
     double *key = r1 + pcap;                  // [PSC] s_j / r_j, -1 when j needs W
     double *ab = key + PSC;                   // [C] values of the nonzero coordinates
     double *cl = ab + C;                      // [pcap] c
-    double *sl_ = cl + pcap;                  // [pcap] column scales
-    double *wl = sl_ + pcap;                  // [pcap] penalty weights
+    double *scl = cl + pcap;                  // [pcap] column scales
+    double *wl = scl + pcap;                  // [pcap] penalty weights
     double *gls = wl + pcap;                  // [pcap pcap] G (one-wave kernel only)
     int *kid = reinterpret_cast<int *>(gls + (NW == 1 ? pcap * pcap : 0));   // [PSC] coordinate (group) of each key
     int *slot_of = kid + PSC;                 // [pcap] slot of each coordinate, -1 outside W
@@ -144,7 +144,7 @@ __global__ __launch_bounds__(64 * NW) void path_ws_kernel(const PathDesc *__rest
 
     for (int j = t; j < p; j += NT) {
         cl[j] = c_g[j];
-        sl_[j] = s_g[j];
+        scl[j] = s_g[j];
         wl[j] = w_g ? w_g[j] : 1.0;
     }
     if constexpr (NW == 1) {
@@ -341,7 +341,7 @@ __global__ __launch_bounds__(64 * NW) void path_ws_kernel(const PathDesc *__rest
                     penv += pen_value(P.kind, b, lw, P.alpha, P.gamma);
                     quad += b * g;
                     lin += cj * b;
-                    beta_g[(size_t)l_end * p + j] = b / sl_[j];
+                    beta_g[(size_t)l_end * p + j] = b / scl[j];
                     if (beta_std_g) beta_std_g[(size_t)l_end * p + j] = b;
                     bws[j] = b;
                 }
@@ -374,7 +374,7 @@ __global__ __launch_bounds__(64 * NW) void path_ws_kernel(const PathDesc *__rest
                     if (lam_end >= 0.0) {
                         quad += b * gv;
                         lin += cj * b;
-                        beta_g[(size_t)l_end * p + j] = b / sl_[j];
+                        beta_g[(size_t)l_end * p + j] = b / scl[j];
                         if (beta_std_g) beta_std_g[(size_t)l_end * p + j] = b;
                         bws[j] = b;
                     }
