@@ -65,15 +65,16 @@ size_t path_ws_lds_bytes(int NW, int pcap)
     return dbl * sizeof(double) + ints * sizeof(int) + 64;
 }
 
-template <int NW>
-__global__ __launch_bounds__(64 * NW) void path_ws_kernel(const PathDesc *__restrict__ descs,
-                                                          const int *__restrict__ order, int first,
-                                                          int pcap)
+// The path of one workgroup.  KIND >= 0: the penalty kind as a compile-time
+// constant (the update and the penalty terms then carry no branches on it);
+// KIND < 0: the kind is read from the descriptor.
+template <int NW, int KIND>
+__device__ __forceinline__ void path_ws_body(const PathDesc &P, int first, int pcap)
 {
     constexpr int CB = kWsCB, C = NW * CB, HC = C / 2, NT = 64 * NW;
-    const PathDesc P = descs[order[blockIdx.x]];
     const int p = P.p, L = P.L;
-    const bool grp = (P.kind == OEM_GRP_LASSO);
+    const int kind = KIND >= 0 ? KIND : P.kind;
+    const bool grp = (kind == OEM_GRP_LASSO);
     const int nkeys = grp ? P.ngroups : p;
     const int PS = ws_pow2(nkeys), PSC = ws_pow2(pcap);
 
@@ -118,7 +119,7 @@ __global__ __launch_bounds__(64 * NW) void path_ws_kernel(const PathDesc *__rest
     const double d = *P.d;
     const double yyn = *P.yyn;
     const double inv_d = 1.0 / d;
-    const double thr_scale = (P.kind == OEM_ENET) ? P.alpha : 1.0;
+    const double thr_scale = (kind == OEM_ENET) ? P.alpha : 1.0;
 
     // Workgroup barrier.  A one-wave workgroup needs none: its LDS operations
     // complete in order, so a wavefront-scope fence (which also keeps global
@@ -223,7 +224,7 @@ __global__ __launch_bounds__(64 * NW) void path_ws_kernel(const PathDesc *__rest
         return fmax(readlane_d(v, 0), readlane_d(v, 16));
     };
     auto set_upd = [&](double lam) {
-        q = make_upd(P.kind, wt * lam, d, P.alpha, P.gamma);
+        q = make_upd(kind, wt * lam, d, P.alpha, P.gamma);
         lamc = (grp && jc >= 0) ? cgw[gof[jc]] * lam : 0.0;
     };
 
@@ -337,8 +338,8 @@ __global__ __launch_bounds__(64 * NW) void path_ws_kernel(const PathDesc *__rest
                     if (b == 0.0)
                         kv = nmax(kv, pos(fabs(gr) - thr_scale * lw));
                     else
-                        kv = nmax(kv, fabs(gr + sgn(b) * pen_deriv(P.kind, fabs(b), lw, P.alpha, P.gamma)));
-                    penv += pen_value(P.kind, b, lw, P.alpha, P.gamma);
+                        kv = nmax(kv, fabs(gr + sgn(b) * pen_deriv(kind, fabs(b), lw, P.alpha, P.gamma)));
+                    penv += pen_value(kind, b, lw, P.alpha, P.gamma);
                     quad += b * g;
                     lin += cj * b;
                     beta_g[(size_t)l_end * p + j] = b / scl[j];
@@ -415,10 +416,12 @@ __global__ __launch_bounds__(64 * NW) void path_ws_kernel(const PathDesc *__rest
                 kid[i] = -1;
             }
         // block reductions: max kv, sums penv quad lin, min smin, sum nneed
-        kv = wave_max(kv);
-        penv = wave_sum(penv);
-        quad = wave_sum(quad);
-        lin = wave_sum(lin);
+        if (lam_end >= 0.0) {   // the outputs of a finished lambda only
+            kv = wave_max(kv);
+            penv = wave_sum(penv);
+            quad = wave_sum(quad);
+            lin = wave_sum(lin);
+        }
         smin = -wave_max(-smin);
         const double nn = wave_sum((double)nneed);
         if (lane == 0) {
@@ -631,7 +634,7 @@ __global__ __launch_bounds__(64 * NW) void path_ws_kernel(const PathDesc *__rest
                 const double f = nrm > 0.0 ? 1.0 - lamc / nrm : 0.0;
                 bn = (jc >= 0 && f > 0.0) ? (u * inv_d) * f : 0.0;
             } else {
-                bn = jc >= 0 ? update_fast(P.kind, u, q, P.gamma) : 0.0;
+                bn = jc >= 0 ? update_fast(kind, u, q, P.gamma) : 0.0;
             }
             const double dl = fabs(bn - bt), mx = fabs(bn), dr = fabs(bn - bref);
             bt = bn;
@@ -700,6 +703,28 @@ __global__ __launch_bounds__(64 * NW) void path_ws_kernel(const PathDesc *__rest
         lam_cur = lnext;
     }
     if (t == 0) *P.lstart = L;
+}
+
+template <int NW>
+__global__ __launch_bounds__(64 * NW) void path_ws_kernel(const PathDesc *__restrict__ descs,
+                                                          const int *__restrict__ order, int first,
+                                                          int pcap)
+{
+    const PathDesc P = descs[order[blockIdx.x]];
+    if constexpr (NW == 1) {
+        // one copy of the path per penalty kind (measured faster here; the
+        // larger kernels keep one copy, which holds their register use down)
+        switch (P.kind) {
+        case OEM_LASSO: path_ws_body<NW, OEM_LASSO>(P, first, pcap); break;
+        case OEM_ENET: path_ws_body<NW, OEM_ENET>(P, first, pcap); break;
+        case OEM_MCP: path_ws_body<NW, OEM_MCP>(P, first, pcap); break;
+        case OEM_SCAD: path_ws_body<NW, OEM_SCAD>(P, first, pcap); break;
+        case OEM_GRP_LASSO: path_ws_body<NW, OEM_GRP_LASSO>(P, first, pcap); break;
+        default: break;
+        }
+    } else {
+        path_ws_body<NW, -1>(P, first, pcap);
+    }
 }
 
 int launch_paths_ws(const PathDesc *d_desc, const int *d_order, int count, int nw, int first, int pmax,
