@@ -349,7 +349,7 @@ void oem_gram_free(oem_handle h)
     (void)hipDeviceSynchronize();
     for (DevBuf *b : {&h->Gk, &h->bk, &h->yyk, &h->nk, &h->Gs, &h->Gs32, &h->cs, &h->sc, &h->yyn,
                       &h->dq, &h->ntrain, &h->lzsteps, &h->partial, &h->partial_n, &h->rowlist, &h->lanczos,
-                      &h->paths, &h->order, &h->lam, &h->betaw, &h->groupbuf, &h->cvw, &h->flag, &h->pathws})
+                      &h->paths, &h->order, &h->lam, &h->betaw, &h->groupbuf, &h->cvw, &h->flag, &h->pathws, &h->lzjobs})
         b->release();
     delete h;
 }

@@ -12,6 +12,8 @@
 // 1e-12 of the Ritz value, or the Krylov space is invariant, or it spans
 // every dimension; d = theta * (1 + 1e-10).
 #include <algorithm>
+#include <cmath>
+#include <cstdlib>
 
 #include "path_common.h"
 
@@ -871,10 +873,7 @@ static int lz_class(int p)
 
 int lanczos_mmax(int p) { return p <= 128 ? p : std::min(p, 1024); }
 
-size_t lanczos_workspace_doubles(int p)
-{
-    return p <= 128 ? 0 : (size_t)(lanczos_mmax(p) + 1) * p;
-}
+
 
 // One launch of `count` problems of one class: strided arrays (jobs == NULL)
 // or rows of a job table; pmax bounds the p of every problem in the launch.
@@ -917,13 +916,355 @@ static int launch_lz_class(int cls, int count, int pmax, int p_all, const double
     return OEM_OK;
 }
 
+// ------------------------------------------------------------ multi-workgroup Lanczos
+// For large p (above kMbMinP) one workgroup per problem is held to one CU's
+// share of L2 bandwidth while G alone is several MB per step.  This kernel
+// runs the same Lanczos recurrence (full reorthogonalisation, the top Ritz
+// value tested on the same schedule, same stopping rule and Gershgorin
+// fallback) with one problem spread over B = ceil(p / 64) workgroups:
+// workgroup b owns rows [64 b, 64 b + 64) of w = G v and of every basis
+// vector.  Lane l of each wave holds row 64 b + l; the four waves split the
+// columns of G (and the basis vectors in the dot products).  A step needs
+// three reductions over the rows: two classical Gram-Schmidt passes (the
+// first also gives alpha = v_j^T w) and the final norm.  Each goes through
+// per-workgroup partials in memory, summed by every workgroup in the same
+// order after a barrier across the problem's workgroups, so all of them
+// compute identical alpha, beta and stopping decisions.  The barrier is an
+// arrival counter per problem with a bounded wait (a wait that runs out
+// makes d NaN); it needs every workgroup of the launch resident at once,
+// which the launcher checks against the occupancy of the GPU.  Measured at
+// p = 500 the barriers (device-scope release/acquire, which write back and
+// invalidate the L2 of every XCD) cost more than the wider reads save, so
+// smaller problems keep one workgroup.
+constexpr int kMbRows = 64;
+constexpr int kMbWaves = 4;
+constexpr int kMbThreads = 64 * kMbWaves;
+constexpr int kMbMinP = 1024;
+constexpr unsigned kMbSpinMax = 1u << 22;   // about a second of waiting per barrier
+
+static __host__ __device__ inline int lanczos_mb_blocks(int p) { return (p + kMbRows - 1) / kMbRows; }
+
+// per problem, after its basis V ((mmax + 1) p): the unnormalised next vector
+// (2 p), two pass partials (2 B (mmax + 2)), norm partials (B), then two
+// 32-bit counters in one more double
+static __host__ __device__ inline size_t lanczos_mb_scratch_doubles(int p)
+{
+    const size_t B = lanczos_mb_blocks(p), m = p <= 128 ? p : (p < 1024 ? p : 1024);   // lanczos_mmax
+    return 2 * (size_t)p + 2 * B * (m + 2) + B + 1;
+}
+
+static size_t lanczos_mb_lds_bytes(int p, int mmax)
+{
+    return ((size_t)p + (mmax + 2) + 4 * (size_t)mmax + kMbWaves * 64 + 64 + 64) * sizeof(double);
+}
+
+// zero the barrier counters of every problem of a launch
+__global__ void lanczos_mb_reset_kernel(int count, const LzJob *__restrict__ jobs)
+{
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= count) return;
+    const LzJob J = jobs[q];
+    double *scr = J.V + (size_t)(J.mmax + 1) * J.p;
+    unsigned *ctr = reinterpret_cast<unsigned *>(scr + lanczos_mb_scratch_doubles(J.p) - 1);
+    ctr[0] = 0u;
+    ctr[1] = 0u;
+}
+
+__global__ __launch_bounds__(kMbThreads) void lanczos_mb_kernel(int B, const LzJob *__restrict__ jobs)
+{
+    const int q = blockIdx.x / B, b = blockIdx.x % B;
+    const LzJob J = jobs[q];
+    const int p = J.p, mmax = J.mmax;
+    const int Bq = lanczos_mb_blocks(p);
+    if (b >= Bq) return;   // a smaller problem of the launch: not part of its barriers
+    const auto G = gmem(J.G);
+    const auto V = gmem(J.V);
+    double *scr = J.V + (size_t)(mmax + 1) * p;
+    const int S = mmax + 2;                       // row length of the pass partials
+    const auto Wb = gmem(scr);                    // [2][p]
+    const auto P0 = gmem(scr + 2 * p);            // [Bq][S] first pass
+    const auto P1 = gmem(scr + 2 * p + (size_t)Bq * S);       // [Bq][S] second pass
+    const auto P2 = gmem(scr + 2 * p + 2 * (size_t)Bq * S);   // [Bq] final norm
+    unsigned *ctr = reinterpret_cast<unsigned *>(scr + lanczos_mb_scratch_doubles(p) - 1);
+
+    extern __shared__ double sm[];
+    double *v = sm;                 // p: current basis vector (all rows)
+    double *coef = v + p;           // mmax + 2
+    double *al = coef + mmax + 2;   // mmax
+    double *be = al + mmax;         // mmax
+    double *tx = be + mmax;         // mmax
+    double *tw = tx + mmax;         // mmax
+    double *part = tw + mmax;       // [kMbWaves][64]
+    double *wv = part + kMbWaves * 64;   // 64: this workgroup's rows of w
+    double *red = wv + 64;               // 64
+    __shared__ int s_flag, s_fail;
+    __shared__ double s_theta;
+
+    const int t = threadIdx.x, lane = t % kWave, wave = t / kWave;
+    const int row = b * kMbRows + lane;
+    const bool mine = row < p;
+    const int rc = mine ? row : p - 1;
+    if (t == 0) {
+        s_flag = 0;
+        s_fail = 0;
+    }
+
+    unsigned nbar = 0;
+    // barrier across the problem's workgroups: every thread releases its
+    // writes, thread 0 arrives and waits (bounded), every thread acquires
+    auto gbar = [&]() {
+        ++nbar;
+        __threadfence();
+        __syncthreads();
+        if (t == 0 && !s_fail) {
+            atomicAdd(ctr, 1u);
+            const unsigned target = nbar * (unsigned)Bq;
+            unsigned spins = 0;
+            while (__hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+                __builtin_amdgcn_s_sleep(8);
+                if (++spins > kMbSpinMax) {
+                    s_fail = 1;
+                    atomicOr(ctr + 1, 1u);
+                    break;
+                }
+            }
+        }
+        __syncthreads();
+        __threadfence();
+    };
+    auto bsum = [&](double x) -> double {
+        x = wave_sum(x);
+        __syncthreads();
+        if (lane == 0) red[wave] = x;
+        __syncthreads();
+        return (red[0] + red[1]) + (red[2] + red[3]);
+    };
+    // sum of the workgroups' partials in[.][m], m in [0, n), in workgroup order
+    auto gather = [&](decltype(P0) in, int n) {
+        for (int m = t; m < n; m += kMbThreads) {
+            double a = 0.0;
+            for (int bb = 0; bb < Bq; ++bb) a += in[(size_t)bb * S + m];
+            coef[m] = a;
+        }
+        __syncthreads();
+    };
+    // partials of V_m^T w over this workgroup's rows, m = 0..j (v_j from
+    // LDS), and of |w|^2
+    auto dots = [&](decltype(P0) out, int j) {
+        const double wl = wv[lane];
+        for (int m = wave; m <= j; m += kMbWaves) {
+            const double x = mine ? (m == j ? v[row] : V[(size_t)m * p + row]) : 0.0;
+            const double sdot = wave_sum(x * wl);
+            if (lane == 0) out[(size_t)b * S + m] = sdot;
+        }
+        if (wave == 0) {
+            const double sn = wave_sum(wl * wl);
+            if (lane == 0) out[(size_t)b * S + j + 1] = sn;
+        }
+    };
+    // w -= sum_m coef[m] V_m over this workgroup's rows
+    auto subtract = [&](int j) {
+        double acc = 0.0;
+        for (int m = wave; m <= j; m += kMbWaves) {
+            const double x = mine ? (m == j ? v[row] : V[(size_t)m * p + row]) : 0.0;
+            acc += coef[m] * x;
+        }
+        part[wave * 64 + lane] = acc;
+        __syncthreads();
+        if (wave == 0) {
+            const double sub = (part[lane] + part[64 + lane]) + (part[128 + lane] + part[192 + lane]);
+            wv[lane] = mine ? wv[lane] - sub : 0.0;
+        }
+        __syncthreads();
+    };
+
+    // v0: the start vector of the single-workgroup kernels, normalised (every
+    // workgroup forms all of it); own rows of V_0 to memory
+    double ss = 0.0;
+    for (int i = t; i < p; i += kMbThreads) {
+        const double x = start_component(i);
+        v[i] = x;
+        ss += x * x;
+    }
+    const double nrm0 = sqrt(bsum(ss));
+    for (int i = t; i < p; i += kMbThreads) v[i] = v[i] / nrm0;
+    __syncthreads();
+    if (wave == 0 && mine) V[row] = v[row];
+
+    double gnorm = 0.0, theta = 0.0, floor = -INFINITY;
+    int m = 0, next_test = 8;
+    const int cq = (p + kMbWaves - 1) / kMbWaves;
+    const int c0 = wave * cq, c1 = min(p, c0 + cq);
+    for (int j = 0; j < mmax; ++j) {
+        // w = G v over this workgroup's rows; wave w takes columns [c0, c1)
+        {
+            double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+            int c = c0;
+            for (; c + 8 <= c1; c += 8) {
+                double g[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) g[u] = G[(size_t)(c + u) * p + rc];
+                a0 += g[0] * v[c] + g[4] * v[c + 4];
+                a1 += g[1] * v[c + 1] + g[5] * v[c + 5];
+                a2 += g[2] * v[c + 2] + g[6] * v[c + 6];
+                a3 += g[3] * v[c + 3] + g[7] * v[c + 7];
+            }
+            for (; c < c1; ++c) a0 += G[(size_t)c * p + rc] * v[c];
+            part[wave * 64 + lane] = (a0 + a1) + (a2 + a3);
+        }
+        __syncthreads();
+        if (wave == 0)
+            wv[lane] = mine ? (part[lane] + part[64 + lane]) + (part[128 + lane] + part[192 + lane]) : 0.0;
+        __syncthreads();
+        // first Gram-Schmidt pass
+        dots(P0, j);
+        gbar();
+        if (s_fail) break;
+        gather(P0, j + 2);
+        const double alpha = coef[j];
+        gnorm = fmax(gnorm, fabs(alpha));
+        subtract(j);
+        // second pass
+        dots(P1, j);
+        gbar();
+        if (s_fail) break;
+        gather(P1, j + 1);
+        subtract(j);
+        // final norm; the unnormalised next vector goes to memory
+        if (wave == 0) {
+            const double sn = wave_sum(wv[lane] * wv[lane]);
+            if (lane == 0) P2[b] = sn;
+            if (mine) Wb[(size_t)((j + 1) & 1) * p + row] = wv[lane];
+        }
+        gbar();
+        if (s_fail) break;
+        if (t < Bq) red[t] = P2[t];
+        __syncthreads();
+        double nb = 0.0;
+        for (int bb = 0; bb < Bq; ++bb) nb += red[bb];
+        const double beta = sqrt(nb);
+        if (t == 0) {
+            al[j] = alpha;
+            be[j] = beta;
+        }
+        m = j + 1;
+        const bool invariant = (beta <= 1e-14 * fmax(gnorm, 1e-300)) || (m == p);
+        const bool test_now = invariant || (m == next_test) || (m == mmax);
+        __syncthreads();
+        if (test_now) {
+            next_test = m + max(8, m / 4);
+            if (t < kWave) {
+                double lo, hi;
+                tri_top_fast(al, be, m, floor, &lo, &hi);
+                if (t == 0) {
+                    const double th = 0.5 * (lo + hi);
+                    const double shift = hi + (hi - lo) + 1e-13 * fabs(hi) + 1e-300;
+                    const double res = invariant ? 0.0 : tri_residual(al, be, m, shift, beta, tx, tw);
+                    s_theta = th;
+                    s_flag = invariant || (res <= 1e-12 * fabs(th));
+                }
+            }
+            __syncthreads();
+            theta = s_theta;
+            floor = theta * (1.0 - 1e-14);
+            if (s_flag) break;
+        }
+        // next basis vector (all rows) from the unnormalised one
+        for (int i = t; i < p; i += kMbThreads) v[i] = Wb[(size_t)((j + 1) & 1) * p + i] / beta;
+        __syncthreads();
+        if (wave == 0 && mine) V[(size_t)(j + 1) * p + row] = v[row];
+    }
+    // not settled within mmax steps: Gershgorin bound, as in the other kernels
+    double dval = theta * (1.0 + 1e-10);
+    const bool ok = s_flag != 0 && !s_fail;
+    if (!ok && !s_fail) {
+        double rs = 0.0;
+        if (wave == 0 && mine)
+            for (int c = 0; c < p; ++c) rs += fabs(G[(size_t)c * p + row]);
+        double gm = wave == 0 ? wave_max(rs) : 0.0;
+        if (t == 0) P2[b] = gm;
+        gbar();
+        if (!s_fail) {
+            if (t < Bq) red[t] = P2[t];
+            __syncthreads();
+            for (int bb = 0; bb < Bq; ++bb) gm = fmax(gm, red[bb]);
+            dval = fmax(dval, gm);
+        }
+    }
+    if (s_fail) dval = NAN;
+    if (b == 0 && t == 0) {
+        *J.d = dval;
+        if (J.steps) *J.steps = ok ? m : -m;
+    }
+}
+
+size_t lanczos_workspace_doubles(int p)
+{
+    if (p <= 128) return 0;
+    const size_t basis = (size_t)(lanczos_mmax(p) + 1) * p;
+    // large p: room after the basis for the multi-workgroup kernel's scratch
+    return p > 1024 && p <= 2048 ? basis + lanczos_mb_scratch_doubles(p) : basis;
+}
+
+thread_local bool lanczos_single_workgroup = false;
+
+static bool lanczos_mb_enabled()
+{
+    static const bool on = [] {
+        const char *e = getenv("OEM_LANCZOS_MB");
+        return !(e && e[0] == '0');
+    }();
+    return on;
+}
+
+// Launch the multi-workgroup kernel over a device job table (count problems,
+// largest pmax).  Returns 1 (nothing launched) when it does not apply:
+// switched off (OEM_LANCZOS_MB=0, or lanczos_single_workgroup on this thread:
+// launches from several streams at once could hold each other's workgroups
+// off the GPU), p outside (kMbMinP, 2048], or the grid cannot be resident at
+// once.  Every job's V must have lanczos_mb_scratch_doubles(p) more doubles
+// after its (mmax + 1) p basis.
+static int launch_lanczos_mb(const LzJob *d_jobs, int count, int pmax, hipStream_t s)
+{
+    if (!lanczos_mb_enabled() || lanczos_single_workgroup || pmax <= kMbMinP || pmax > 2048) return 1;
+    const int mmax = lanczos_mmax(pmax), B = lanczos_mb_blocks(pmax);
+    const size_t lds = lanczos_mb_lds_bytes(pmax, mmax);
+    const void *kern = (const void *)lanczos_mb_kernel;
+    OEM_HIP_CHECK(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    int per_cu = 0, ncu = 0, dev = 0;
+    OEM_HIP_CHECK(hipGetDevice(&dev));
+    OEM_HIP_CHECK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    OEM_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kMbThreads, lds));
+    const long grid = (long)count * B;
+    if (per_cu < 1 || grid > (long)per_cu * ncu) return 1;
+    hipLaunchKernelGGL(lanczos_mb_reset_kernel, dim3((count + 63) / 64), dim3(64), 0, s, count, d_jobs);
+    OEM_HIP_CHECK(hipGetLastError());
+    int b_arg = B;
+    void *args[] = {(void *)&b_arg, (void *)&d_jobs};
+    OEM_HIP_CHECK(hipLaunchKernel(kern, dim3((unsigned)grid), dim3(kMbThreads), args, lds, s));
+    return OEM_OK;
+}
+
 int launch_lanczos(oem_gram_s *h, hipStream_t s)
 {
     const int p = h->p, nq = (h->K == 1) ? 1 : h->K + 1;
     const size_t ws = lanczos_workspace_doubles(p);
     if (ws) {
-        int rc = h->lanczos.ensure((size_t)nq * ws * sizeof(double));
+        int rc = h->lanczos.ensure((size_t)nq * ws * sizeof(double) + 64);
         if (rc) return rc;
+        if (p > kMbMinP && p <= 2048 && lanczos_mb_enabled() && !lanczos_single_workgroup) {
+            // a small job table on the device, one job per problem
+            std::vector<LzJob> jobs(nq);
+            for (int q = 0; q < nq; ++q)
+                jobs[q] = LzJob{h->Gs.as<double>() + (size_t)q * p * p, h->lanczos.as<double>() + (size_t)q * ws,
+                                h->dq.as<double>() + q, h->lzsteps.as<int32_t>() + q, p, lanczos_mmax(p)};
+            rc = h->lzjobs.ensure(nq * sizeof(LzJob));
+            if (rc) return rc;
+            OEM_HIP_CHECK(hipMemcpyAsync(h->lzjobs.ptr, jobs.data(), nq * sizeof(LzJob), hipMemcpyHostToDevice, s));
+            OEM_HIP_CHECK(hipStreamSynchronize(s));
+            rc = launch_lanczos_mb(h->lzjobs.as<LzJob>(), nq, p, s);
+            if (rc <= 0) return rc;   // launched, or an error
+        }
     }
     return launch_lz_class(lz_class(p), nq, p, p, h->Gs.as<double>(), ws ? h->lanczos.as<double>() : nullptr,
                            h->dq.as<double>(), h->lzsteps.as<int32_t>(), nullptr, s);
@@ -947,7 +1288,15 @@ void lanczos_job_plan(std::vector<LzJob> &jobs, std::vector<LzLaunch> &launches)
 int launch_lanczos_jobs(const LzJob *d_jobs, const std::vector<LzLaunch> &launches, hipStream_t s)
 {
     for (const LzLaunch &L : launches) {
-        int rc = launch_lz_class(L.cls, L.count, L.pmax, 0, nullptr, nullptr, nullptr, nullptr,
+        int rc = 1;
+        // the largest class: one problem over many workgroups when every
+        // problem of the launch is above the threshold
+        if (L.cls == 4) {
+            rc = launch_lanczos_mb(d_jobs + L.first, L.count, L.pmax, s);
+            if (rc < 0) return rc;
+        }
+        if (rc == 1)
+            rc = launch_lz_class(L.cls, L.count, L.pmax, 0, nullptr, nullptr, nullptr, nullptr,
                                  d_jobs + L.first, s);
         if (rc) return rc;
     }

@@ -145,7 +145,7 @@ struct oem_gram_s {
     std::vector<int32_t> lz_host;      // Lanczos steps (negative: not converged)
     int64_t rows_seen = 0;
     // workspaces
-    oem::DevBuf partial, partial_n, rowlist, lanczos, paths, order, lam, betaw, groupbuf, cvw, flag, pathws;
+    oem::DevBuf partial, partial_n, rowlist, lanczos, paths, order, lam, betaw, groupbuf, cvw, flag, pathws, lzjobs;
 };
 
 namespace oem {
@@ -162,6 +162,9 @@ int launch_gram_bf16(oem_gram_s *g, const void *X, int64_t n, int64_t ldx, const
                      int64_t row_offset, const uint8_t *foldid, hipStream_t s);
 int launch_combine(oem_gram_s *g, int standardize, hipStream_t s);
 int launch_lanczos(oem_gram_s *g, hipStream_t s);
+// Set on a thread whose Lanczos launches may run beside launches from other
+// streams: every problem then uses one workgroup (no barrier across workgroups).
+extern thread_local bool lanczos_single_workgroup;
 int lanczos_mmax(int p);
 size_t lanczos_workspace_doubles(int p);
 // sort jobs by kernel class and cut them into launches

@@ -143,6 +143,7 @@ int run_request(oem_server_s *S, Worker &W, const oem_request &r)
 void worker_main(oem_server_s *S, int slot)
 {
     (void)hipSetDevice(S->device);
+    oem::lanczos_single_workgroup = true;   // several workers run on the GPU at once
     Worker W;
     W.h = new oem_gram_s();
     W.h->device = S->device;

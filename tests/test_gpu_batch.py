@@ -138,3 +138,38 @@ def test_autotune_keeps_results_exact():
             Go, bo, yyo, nko = oracle.gram_folds(X, y, 1)
             assert np.array_equal(G.cpu().numpy(), Go) and np.array_equal(b.cpu().numpy(), bo)
             assert nk.item() == n
+
+
+def test_batch_large_p_graph_and_single_fit_agree():
+    """Problems with p > 1024 take d from the multi-workgroup Lanczos, both in
+    the batch's job tables (eager and hipGraph replay, with its barrier
+    counters cleared by a kernel inside the graph) and in a single fit; the
+    three must give the same coefficients (d itself is checked against
+    Jacobi in test_gpu_path)."""
+    oem = _oem()
+    print("case: batch large p [1100, 1300] graph + single fit", flush=True)
+    prs = _problems([1100, 1300], rows_per_col=3, seed_tag=6)
+    dev = [(torch.from_numpy(pr.X).cuda(), torch.from_numpy(pr.y).cuda()) for pr in prs]
+    s = torch.cuda.Stream()
+    kw = dict(nlambda=4, lambda_min_ratio=0.3, tol=TOL)
+    with oem.Batch(dev, ["lasso"], **kw) as b:
+        with torch.cuda.stream(s):
+            b.run(stream=s)
+        s.synchronize()
+        assert b.status(stream=s) == oem.OEM_OK
+        eager = [o["beta"].cpu().numpy().copy() for o in b.out]
+        for rep in range(2):
+            for o in b.out:
+                o["beta"].zero_()
+            torch.cuda.synchronize()
+            with torch.cuda.stream(s):
+                b.run(graph=True, stream=s)
+            s.synchronize()
+            assert b.status(stream=s) == oem.OEM_OK
+            for k, o in enumerate(b.out):
+                assert np.array_equal(o["beta"].cpu().numpy(), eager[k]), f"replay {rep} problem {k}"
+            assert all(np.all(o["kkt"].cpu().numpy() <= 1e-8) for o in b.out)
+    for k, (X, y) in enumerate(dev):
+        one = oem.fit(X, y, ["lasso"], **kw)
+        _assert_close(one["beta"].cpu().numpy(), eager[k], TOL, f"single fit p={X.shape[1]}")
+        assert np.isfinite(one["d"].item())
