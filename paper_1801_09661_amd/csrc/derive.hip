@@ -1010,17 +1010,23 @@ __global__ __launch_bounds__(kMbThreads) void lanczos_mb_kernel(int B, const LzJ
     }
 
     unsigned nbar = 0;
-    // barrier across the problem's workgroups: every thread releases its
-    // writes, thread 0 arrives and waits (bounded), every thread acquires
+    // barrier across the problem's workgroups: every wave waits for its own
+    // stores to complete; thread 0 then releases (the L2 write-back covers
+    // all of them), arrives, waits (bounded) and acquires (the invalidation
+    // of this CU's and XCD's caches serves every wave after the workgroup
+    // barrier)
     auto gbar = [&]() {
         ++nbar;
-        __threadfence();
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         __syncthreads();
         if (t == 0 && !s_fail) {
+            __threadfence();
             atomicAdd(ctr, 1u);
             const unsigned target = nbar * (unsigned)Bq;
             unsigned spins = 0;
-            while (__hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            // relaxed loads while waiting (an acquire per poll would invalidate
+            // the caches every time); one acquire fence after the wait
+            while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
                 __builtin_amdgcn_s_sleep(8);
                 if (++spins > kMbSpinMax) {
                     s_fail = 1;
@@ -1028,9 +1034,9 @@ __global__ __launch_bounds__(kMbThreads) void lanczos_mb_kernel(int B, const LzJ
                     break;
                 }
             }
+            __threadfence();
         }
         __syncthreads();
-        __threadfence();
     };
     auto bsum = [&](double x) -> double {
         x = wave_sum(x);
