@@ -939,7 +939,7 @@ static int launch_lz_class(int cls, int count, int pmax, int p_all, const double
 constexpr int kMbRows = 64;
 constexpr int kMbWaves = 4;
 constexpr int kMbThreads = 64 * kMbWaves;
-constexpr int kMbMinP = 1024;
+constexpr int kMbMinP = 128;
 constexpr unsigned kMbSpinMax = 1u << 22;   // about a second of waiting per barrier
 
 static __host__ __device__ inline int lanczos_mb_blocks(int p) { return (p + kMbRows - 1) / kMbRows; }
@@ -1209,7 +1209,7 @@ size_t lanczos_workspace_doubles(int p)
     if (p <= 128) return 0;
     const size_t basis = (size_t)(lanczos_mmax(p) + 1) * p;
     // large p: room after the basis for the multi-workgroup kernel's scratch
-    return p > 1024 && p <= 2048 ? basis + lanczos_mb_scratch_doubles(p) : basis;
+    return p > kMbMinP && p <= 2048 ? basis + lanczos_mb_scratch_doubles(p) : basis;
 }
 
 thread_local bool lanczos_single_workgroup = false;
@@ -1297,7 +1297,7 @@ int launch_lanczos_jobs(const LzJob *d_jobs, const std::vector<LzLaunch> &launch
         int rc = 1;
         // the largest class: one problem over many workgroups when every
         // problem of the launch is above the threshold
-        if (L.cls == 4) {
+        if (L.cls >= 2 && L.cls <= 4) {
             rc = launch_lanczos_mb(d_jobs + L.first, L.count, L.pmax, s);
             if (rc < 0) return rc;
         }
