@@ -269,43 +269,46 @@ __device__ __forceinline__ void path_ws_body(const PathDesc &P, int first, int p
         }
         if (nact > C) return 1;
         // G beta for every coordinate from the columns of the nonzero ones
-        if constexpr (NW == 1) {
-            // at most two coordinates per lane: the indices and values of
-            // the nonzero coordinates are read once per chunk of 16
-            constexpr int JM = (kWsLdsGMaxP + NT - 1) / NT;
-            double acc[JM];
+        if constexpr (NW <= 2) {
+            // rows in chunks of JM NT (one chunk for the one-wave kernel); the
+            // indices and values of the nonzero coordinates are read once per
+            // 16 columns, and each thread keeps 16 JM loads of G in flight
+            constexpr int JM = NW == 1 ? (kWsLdsGMaxP + NT - 1) / NT : 4;
+            for (int j0 = 0; j0 < p; j0 += JM * NT) {
+                double acc[JM];
 #pragma unroll
-            for (int jj = 0; jj < JM; ++jj) acc[jj] = 0.0;
-            for (int e0 = 0; e0 < nact; e0 += 16) {
-                int je[16];
-                double be[16];
+                for (int jj = 0; jj < JM; ++jj) acc[jj] = 0.0;
+                for (int e0 = 0; e0 < nact; e0 += 16) {
+                    int je[16];
+                    double be[16];
 #pragma unroll
-                for (int u = 0; u < 16; ++u) {
-                    const int e = min(e0 + u, nact - 1);
-                    be[u] = (e0 + u < nact) ? ab[e] : 0.0;
-                    je[u] = aj[e];
-                }
-#pragma unroll
-                for (int jj = 0; jj < JM; ++jj) {
-                    if (jj * NT >= p) break;
-                    const int j = min(t + jj * NT, p - 1);
-                    double gv[16];
-#pragma unroll
-                    for (int u = 0; u < 16; ++u) gv[u] = gat((size_t)je[u] * p + j);
-                    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-#pragma unroll
-                    for (int u = 0; u < 16; u += 4) {
-                        a0 += gv[u] * be[u];
-                        a1 += gv[u + 1] * be[u + 1];
-                        a2 += gv[u + 2] * be[u + 2];
-                        a3 += gv[u + 3] * be[u + 3];
+                    for (int u = 0; u < 16; ++u) {
+                        const int e = min(e0 + u, nact - 1);
+                        be[u] = (e0 + u < nact) ? ab[e] : 0.0;
+                        je[u] = aj[e];
                     }
-                    acc[jj] += (a0 + a1) + (a2 + a3);
-                }
-            }
 #pragma unroll
-            for (int jj = 0; jj < JM; ++jj)
-                if (t + jj * NT < p) gfull[t + jj * NT] = acc[jj];
+                    for (int jj = 0; jj < JM; ++jj) {
+                        if (j0 + jj * NT >= p) break;
+                        const int j = min(j0 + t + jj * NT, p - 1);
+                        double gv[16];
+#pragma unroll
+                        for (int u = 0; u < 16; ++u) gv[u] = gat((size_t)je[u] * p + j);
+                        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+#pragma unroll
+                        for (int u = 0; u < 16; u += 4) {
+                            a0 += gv[u] * be[u];
+                            a1 += gv[u + 1] * be[u + 1];
+                            a2 += gv[u + 2] * be[u + 2];
+                            a3 += gv[u + 3] * be[u + 3];
+                        }
+                        acc[jj] += (a0 + a1) + (a2 + a3);
+                    }
+                }
+#pragma unroll
+                for (int jj = 0; jj < JM; ++jj)
+                    if (j0 + t + jj * NT < p) gfull[j0 + t + jj * NT] = acc[jj];
+            }
         } else {
             for (int j = t; j < p; j += NT) {
                 double a[4] = {0.0, 0.0, 0.0, 0.0};
