@@ -35,6 +35,17 @@
  *   - stream: a hipStream_t passed as void* (NULL = the null stream).  Work
  *     is enqueued on it; device outputs are valid after the stream is
  *     synchronised.  A handle must not be used from two threads at once.
+ *   - Host waits.  oem_gram, oem_gram_reset, oem_gram_import,
+ *     oem_gram_export and oem_batch_run(_graph) enqueue work and return
+ *     without waiting for the GPU.  oem_fit_path and oem_cv wait for
+ *     `stream` (i) once after the statistics changed, to read back d and
+ *     the row counts they validate (penalty conditions gamma d > 1, empty
+ *     folds), and (ii) after each upload of their small host tables (lambda
+ *     values, groups, path descriptors, a few KB); the path, CV and
+ *     selection kernels themselves are enqueued and the call returns before
+ *     they finish unless opts->sync = 1.  oem_gram_autotune,
+ *     oem_batch_create, oem_batch_status and the free functions wait for
+ *     the device.
  *   - Matrices are row-major.  Sizes are element counts.
  */
 #ifndef OEM_H
@@ -60,8 +71,10 @@ enum {
  *   OEM_FP64        X widened to FP64, FP64 matrix-core products, FP64 paths.
  *   OEM_SPLIT_BF16  x = hi + lo (two BF16 parts), three BF16 products
  *                   (hi*hi + hi*lo + lo*hi) accumulated in FP32 on the matrix
- *                   cores, flushed to FP64; the diagonal, X^T y and y^T y in
- *                   FP64.  Paths iterate in FP32 with an FP64 finish.
+ *                   cores, flushed to FP64 and summed over row splits in
+ *                   FP64; the diagonal, X^T y and y^T y in FP64.  Everything
+ *                   after the Gram pass (standardisation, d, the paths, CV)
+ *                   is FP64, exactly as in OEM_FP64, on this Gram.
  *   OEM_BF16        as SPLIT_BF16 with the hi part only (reported variant). */
 enum { OEM_FP64 = 0, OEM_SPLIT_BF16 = 1, OEM_BF16 = 2 };
 
@@ -163,10 +176,14 @@ int oem_gram_export(oem_handle g, double *G, double *b, double *yy, int64_t *nk,
  *     kkt     npen x L       max stationarity violation (standardised scale)
  *     obj     npen x L       objective value
  *     d_out   1              the d used
+ * d: when the Lanczos iteration does not settle within its step limit, d is
+ * the Gershgorin bound max_i sum_j |G_ij| instead (still >= lambda_1).
  * Errors: OEM_E_INVAL (fold out of range, n of the selected rows = 0, bad
  * penalty parameters: alpha not in (0,1], MCP gamma <= 1 or gamma d <= 1,
- * SCAD gamma <= 2 or (gamma-1) d <= 1, bad groups, L < 1, maxit < 1),
- * OEM_E_STATE (no rows accumulated), OEM_E_HIP. */
+ * SCAD gamma <= 2 or (gamma-1) d <= 1, bad groups, L < 1, maxit < 1; d not
+ * a finite positive number, i.e. non-finite or all-zero statistics),
+ * OEM_E_STATE (no rows accumulated), OEM_E_HIP (including an eigenvalue
+ * solve whose workgroups could not all run at once). */
 int oem_fit_path(oem_handle g, int32_t fold, const oem_penalty *pen, int32_t npen,
                  const oem_path_opts *opts, double *beta, double *lambda, int32_t *iters,
                  double *kkt, double *obj, double *d_out, void *stream);
@@ -186,7 +203,8 @@ int oem_fit_path(oem_handle g, int32_t fold, const oem_penalty *pen, int32_t npe
  *     cvm, cvsd  npen x L
  *     i_min, i_1se npen;  best 1
  *     iters      (K + 1) x npen x L  (slot 0 = full data)
- * Requires nfolds >= 2.  Errors as oem_fit_path. */
+ * Requires nfolds >= 2.  Errors as oem_fit_path, and OEM_E_INVAL when a fold
+ * has no held-out rows (n_k = 0, e.g. a fold-id array that skips an id). */
 int oem_cv(oem_handle g, const oem_penalty *pen, int32_t npen, const oem_path_opts *opts,
            double *beta_full, double *beta_folds, double *lambda, double *cvm, double *cvsd,
            int32_t *i_min, int32_t *i_1se, int32_t *best, int32_t *iters, void *stream);

@@ -9,8 +9,11 @@ a GPU, every call raises.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
+import sys
+import weakref
 from dataclasses import dataclass
 from typing import Optional, Sequence
 
@@ -138,6 +141,31 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     L.oem_version.argtypes = []
     _lib = L
     return L
+
+
+# Owning wrappers (Gram, Batch, Server) register here.  At interpreter exit
+# every live one is closed while the HIP runtime is still whole (the
+# library's free calls wait for the device); finalizers that run later,
+# during interpreter shutdown, make no library call at all.
+_live = weakref.WeakSet()
+
+
+@atexit.register
+def _close_live() -> None:
+    for obj in list(_live):
+        try:
+            obj.close()
+        except Exception:
+            pass
+
+
+def _finalize(obj) -> None:
+    if sys.is_finalizing():
+        return
+    try:
+        obj.close()
+    except Exception:
+        pass
 
 
 def _check(rc: int, allow_not_converged: bool = True) -> int:
@@ -314,10 +342,12 @@ class Gram:
         xd = OEM_X_F64 if x_dtype in (torch.float64, "f64", OEM_X_F64) else OEM_X_F32
         self.p, self.nfolds, self.precision = p, nfolds, precision
         self.h = oem_gram_create(p, nfolds, PRECISION[precision], xd, fold_seed)
+        _live.add(self)
 
     def close(self):
-        oem_gram_free(self.h)
-        self.h = None
+        if getattr(self, "h", None):
+            oem_gram_free(self.h)
+            self.h = None
 
     def __enter__(self):
         return self
@@ -326,11 +356,7 @@ class Gram:
         self.close()
 
     def __del__(self):
-        try:
-            if getattr(self, "h", None):
-                self.close()
-        except Exception:
-            pass
+        _finalize(self)
 
     def add(self, X, y, row_offset: int = 0, foldid=None, stream=None):
         oem_gram(self.h, X, y, row_offset, foldid, stream)
@@ -402,6 +428,7 @@ class Batch:
                                                self.pen_arr, self.npen, C.byref(self.opts.c),
                                                C.byref(h)))
         self.h = h
+        _live.add(self)
 
     def run(self, graph: bool = False, stream=None) -> None:
         f = load_library().oem_batch_run_graph if graph else load_library().oem_batch_run
@@ -422,10 +449,7 @@ class Batch:
         self.close()
 
     def __del__(self):
-        try:
-            self.close()
-        except Exception:
-            pass
+        _finalize(self)
 
 
 class Server:
@@ -447,6 +471,7 @@ class Server:
         self.h = h
         self.live = {}
         self.results = {}
+        _live.add(self)
 
     @staticmethod
     def now() -> float:
@@ -502,7 +527,4 @@ class Server:
         self.close()
 
     def __del__(self):
-        try:
-            self.close()
-        except Exception:
-            pass
+        _finalize(self)

@@ -145,6 +145,18 @@ static int ensure_derived(oem_gram_s *h, int standardize, hipStream_t s)
     OEM_HIP_CHECK(hipMemcpyAsync(h->lz_host.data(), h->lzsteps.ptr, nq * sizeof(int32_t),
                                  hipMemcpyDeviceToHost, s));
     OEM_HIP_CHECK(hipStreamSynchronize(s));
+    // d must be a finite positive upper bound of lambda_1 for the iteration
+    // to be defined (Section 2.1).  A negative step count with a finite d is
+    // the documented fallback (Lanczos did not settle: d is a Gershgorin
+    // bound, still >= lambda_1).
+    for (int q = 0; q < nq; ++q) {
+        if (h->lz_host[q] == kLanczosTimedOut)
+            return fail(OEM_E_HIP, "eigenvalue bound of problem " + std::to_string(q) +
+                                       ": the multi-workgroup Lanczos timed out waiting for its workgroups");
+        if (h->n_host[q] > 0 && !(std::isfinite(h->d_host[q]) && h->d_host[q] > 0.0))
+            return fail(OEM_E_INVAL, "eigenvalue bound d of problem " + std::to_string(q) +
+                                         " is not a finite positive number (non-finite or all-zero statistics)");
+    }
     h->derived_valid = true;
     h->derived_std = standardize;
     return OEM_OK;
@@ -216,7 +228,6 @@ static PathDesc make_desc(oem_gram_s *h, int q, const oem_penalty &pn, const oem
     const size_t pp = (size_t)h->p * h->p;
     PathDesc d{};
     d.G = h->Gs.as<double>() + q * pp;
-    d.G32 = nullptr;
     d.c = h->cs.as<double>() + (size_t)q * h->p;
     d.s = h->sc.as<double>() + (size_t)q * h->p;
     d.yyn = h->yyn.as<double>() + q;
@@ -241,7 +252,6 @@ static PathDesc make_desc(oem_gram_s *h, int q, const oem_penalty &pn, const oem
     d.gamma = pn.gamma;
     d.tol = o->tol;
     d.maxit = o->maxit;
-    d.prec = PATH_FP64;
     return d;
 }
 
@@ -347,7 +357,7 @@ void oem_gram_free(oem_handle h)
 {
     if (!h) return;
     (void)hipDeviceSynchronize();
-    for (DevBuf *b : {&h->Gk, &h->bk, &h->yyk, &h->nk, &h->Gs, &h->Gs32, &h->cs, &h->sc, &h->yyn,
+    for (DevBuf *b : {&h->Gk, &h->bk, &h->yyk, &h->nk, &h->Gs, &h->cs, &h->sc, &h->yyn,
                       &h->dq, &h->ntrain, &h->lzsteps, &h->partial, &h->partial_n, &h->rowlist, &h->lanczos,
                       &h->paths, &h->order, &h->lam, &h->betaw, &h->groupbuf, &h->cvw, &h->flag, &h->pathws, &h->lzjobs})
         b->release();
@@ -491,6 +501,11 @@ int oem_cv(oem_handle h, const oem_penalty *pen, int32_t npen, const oem_path_op
     const int K = h->K, p = h->p, L = opts->nlambda;
     for (int q = 0; q <= K; ++q)
         if (h->n_host[q] <= 0) return fail(OEM_E_INVAL, "a fold leaves no training rows");
+    // held-out rows of fold k: all rows less its training rows (Section 3 CV
+    // error divides by their count)
+    for (int k = 0; k < K; ++k)
+        if (h->n_host[0] - h->n_host[1 + k] <= 0)
+            return fail(OEM_E_INVAL, "fold " + std::to_string(k) + " has no held-out rows");
     bool need_groups = false;
     for (int i = 0; i < npen; ++i) {
         for (int q = 0; q <= K; ++q) {

@@ -63,11 +63,10 @@ __global__ void combine_scale_kernel(int p, int K, int standardize, const double
     }
 }
 
-// phase 2: Gs = (G / n) / (s_i s_j); also an FP32 copy for mixed paths
+// phase 2: Gs = (G / n) / (s_i s_j)
 __global__ void combine_gram_kernel(int p, int K, const double *__restrict__ Gk,
                                     const int64_t *__restrict__ ntrain,
-                                    const double *__restrict__ sc, double *__restrict__ Gs,
-                                    float *__restrict__ Gs32)
+                                    const double *__restrict__ sc, double *__restrict__ Gs)
 {
     const int q = blockIdx.y;
     int skip;
@@ -85,7 +84,6 @@ __global__ void combine_gram_kernel(int p, int K, const double *__restrict__ Gk,
         v = v / dn;
         const double r = v / (sc[(size_t)q * p + i] * sc[(size_t)q * p + j]);
         Gs[(size_t)q * pp + e] = r;
-        if (Gs32) Gs32[(size_t)q * pp + e] = (float)r;
     }
 }
 
@@ -101,8 +99,7 @@ int launch_combine(oem_gram_s *h, int standardize, hipStream_t s)
     const size_t pp = (size_t)p * p;
     dim3 g2((unsigned)std::min<size_t>((pp + 255) / 256, 2048), nq);
     hipLaunchKernelGGL(combine_gram_kernel, g2, dim3(256), 0, s, p, K, h->Gk.as<double>(),
-                       h->ntrain.as<int64_t>(), h->sc.as<double>(), h->Gs.as<double>(),
-                       h->Gs32.as<float>());
+                       h->ntrain.as<int64_t>(), h->sc.as<double>(), h->Gs.as<double>());
     OEM_HIP_CHECK(hipGetLastError());
     return OEM_OK;
 }
@@ -1200,7 +1197,7 @@ __global__ __launch_bounds__(kMbThreads) void lanczos_mb_kernel(int B, const LzJ
     if (s_fail) dval = NAN;
     if (b == 0 && t == 0) {
         *J.d = dval;
-        if (J.steps) *J.steps = ok ? m : -m;
+        if (J.steps) *J.steps = s_fail ? kLanczosTimedOut : (ok ? m : -m);
     }
 }
 

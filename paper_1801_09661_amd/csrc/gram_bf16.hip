@@ -73,12 +73,11 @@ template <bool VEC>
 __device__ inline void load_block(float (&x)[8][4], const float *__restrict__ X, int64_t ldx, int p,
                                   int col, const int64_t (&row)[8])
 {
-    // 16-byte loads need only 4-byte alignment on gfx950; a group past p
-    // loads columns 0..3 instead, and the one group that straddles p (p % 4
-    // != 0) loads its columns one by one, clamped to p - 1.
-    const bool vec = VEC && (col + 3 < p || col >= p);
-    if (vec) {
-        const int cv = (col + 3 < p) ? col : 0;
+    // 16-byte loads need only 4-byte alignment on gfx950 (column choice:
+    // gram_col_plan).
+    const GramColPlan cp = gram_col_plan(VEC, col, p);
+    if (cp.vec) {
+        const int cv = cp.first;
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
             const f32x4_t v = *reinterpret_cast<const f32x4_t *>(X + row[e] * ldx + cv);
@@ -88,7 +87,7 @@ __device__ inline void load_block(float (&x)[8][4], const float *__restrict__ X,
     } else {
         int cj[4];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) cj[j] = min(col + j, p - 1);
+        for (int j = 0; j < 4; ++j) cj[j] = gram_col_read(cp, col, j, p);
 #pragma unroll
         for (int e = 0; e < 8; ++e)
 #pragma unroll

@@ -83,6 +83,30 @@ __device__ inline int64_t row_at(int64_t first, const int32_t *list, int64_t i)
     return list ? (int64_t)list[i] : first + i;
 }
 
+// Columns a Gram loader thread reads for its group of four columns
+// col .. col + 3 of a row of p elements.  vec: one 16-byte load of columns
+// first .. first + 3 (the group lies inside the row, or lies wholly past its
+// end and p >= 4, so columns 0..3 exist and are read instead); otherwise
+// each column is read on its own, clamped to p - 1.  Either way every index
+// read is below p.
+struct GramColPlan {
+    bool vec;
+    int first;
+};
+
+__host__ __device__ inline GramColPlan gram_col_plan(bool vec_ok, int col, int p)
+{
+    GramColPlan c;
+    c.vec = vec_ok && (col + 3 < p || (col >= p && p >= 4));
+    c.first = (col + 3 < p) ? col : 0;
+    return c;
+}
+
+__host__ __device__ inline int gram_col_read(const GramColPlan &c, int col, int j, int p)
+{
+    return c.vec ? c.first + j : (col + j < p - 1 ? col + j : p - 1);
+}
+
 // ---- host-side launchers (gram_common.hip) ----
 // Target number of workgroups of a Gram pass (about two per CU by default;
 // oem_gram_autotune may pick another for a shape).

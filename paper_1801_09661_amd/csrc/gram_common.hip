@@ -195,3 +195,13 @@ int build_row_lists(oem_gram_s *h, const GramGeom &g, int64_t n, int64_t row_off
 }
 
 } // namespace oem
+
+// Test hook (include/oem_debug.h): the four column indices the Gram loaders
+// read for the group col .. col + 3 of a row of p elements.
+extern "C" int oem_debug_gram_load_columns(int32_t p, int32_t col, int32_t vec_ok, int32_t *cols)
+{
+    if (p < 1 || col < 0 || !cols) return OEM_E_INVAL;
+    const oem::GramColPlan c = oem::gram_col_plan(vec_ok != 0, col, p);
+    for (int j = 0; j < 4; ++j) cols[j] = oem::gram_col_read(c, col, j, p);
+    return c.vec ? 1 : 0;
+}

@@ -69,12 +69,9 @@ struct GramGeom {
 };
 
 // ------------------------------------------------------------------ paths
-enum PathPrec : int32_t { PATH_FP64 = 0, PATH_MIXED = 1 };
-
 // One warm-started lambda path: a (problem, penalty) pair.
 struct PathDesc {
     const double *G;      // p x p standardised Gram (scaled by 1/n)
-    const float *G32;     // FP32 copy (mixed paths) or null
     const double *c;      // p
     const double *s;      // p column scales (beta = beta_std / s)
     const double *yyn;    // 1
@@ -97,7 +94,6 @@ struct PathDesc {
     double gamma;
     double tol;
     int32_t maxit;
-    int32_t prec;
     // hand-over between the kernels of one path's launch chain: the first
     // lambda index the next kernel computes, and the standardised
     // coefficients of the lambda before it (p)
@@ -115,6 +111,9 @@ struct LzJob {
     int p;
     int mmax;
 };
+// Step count written when the multi-workgroup kernel gave up waiting for its
+// workgroups (d is then NaN).
+constexpr int32_t kLanczosTimedOut = INT32_MIN;
 struct LzLaunch {
     int cls, first, count, pmax;
 };
@@ -137,7 +136,7 @@ struct oem_gram_s {
     // raw per-fold sums
     oem::DevBuf Gk, bk, yyk, nk;       // K p^2, K p, K, K (int64)
     // derived problems: q = 0 full data, q = 1 + k training rows of fold k
-    oem::DevBuf Gs, Gs32, cs, sc, yyn, dq, ntrain, lzsteps;  // (K+1) p^2, (K+1) p^2 f32, (K+1) p, ...
+    oem::DevBuf Gs, cs, sc, yyn, dq, ntrain, lzsteps;  // (K+1) p^2, (K+1) p, ...
     bool derived_valid = false;
     int derived_std = -1;
     std::vector<double> d_host;        // d per problem (valid with derived_valid)

@@ -72,3 +72,22 @@ def test_no_cpu_fallback_without_gpu():
         pytest.skip("GPU present")
     with pytest.raises(oem.OemError):
         oem.oem_gram_create(10)
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4, 5, 7, 100, 129])
+def test_gram_loader_columns_stay_in_row(lib, p):
+    """The Gram loaders' column choice (shared with the kernels) never reads
+    past column p - 1 of a row, for every 4-column group of the padded
+    panels, with and without 16-byte loads; so the last row's reads end
+    inside X: largest index < (n - 1) ldx + p."""
+    f = lib.oem_debug_gram_load_columns
+    f.restype = ctypes.c_int
+    f.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
+    cols = (ctypes.c_int32 * 4)()
+    for vec_ok in (0, 1):
+        for col in range(0, ((p + 127) // 128) * 128 + 128, 4):
+            rc = f(p, col, vec_ok, cols)
+            assert rc in (0, 1)
+            assert all(0 <= c < p for c in cols), (p, col, vec_ok, list(cols))
+            if col + 3 < p:
+                assert list(cols) == [col, col + 1, col + 2, col + 3]

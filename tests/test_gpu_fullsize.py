@@ -128,3 +128,55 @@ def test_grouped_cv_full_size():
         err = _rel_paths(rm["beta"].cpu().numpy(), res["beta"].cpu().numpy())
         print(f"  mixed form worst coefficient error vs FP64 form {err:.3e}")
         assert err <= 1e-6
+
+
+def _lib_gram_rows(X, y, mask=None, chunk=1 << 18):
+    """FP64 sums over the rows selected by mask, by a library matrix product
+    in row chunks (the oracle's own row loops would take minutes here)."""
+    p = X.shape[1]
+    G = np.zeros((p, p)); b = np.zeros(p); yy = 0.0; cnt = 0
+    for r0 in range(0, X.shape[0], chunk):
+        Xc, yc = X[r0:r0 + chunk], y[r0:r0 + chunk]
+        if mask is not None:
+            m = mask[r0:r0 + chunk]
+            Xc, yc = Xc[m], yc[m]
+        X64 = Xc.astype(np.float64)
+        G += X64.T @ X64
+        b += X64.T @ yc
+        yy += float(yc @ yc)
+        cnt += len(yc)
+    return G, b, yy, cnt
+
+
+def test_grouped_cv_full_size_coefficients():
+    """n = 2e6, p = 500, K = 10: the full-data paths and fold 0's training-row
+    paths (group lasso, lasso, MCP x 100 lambdas) from oem_cv against the
+    oracle's path pipeline (standardisation, Jacobi d, OEM loops) on the FP64
+    Gram of the same rows; fold membership from the oracle's own hash."""
+    oem = _oem()
+    K, seed = 10, 180109661
+    print("case: cv_grouped full size coefficients n=2e6 p=500 K=10", flush=True)
+    pr = workloads.cv_grouped()
+    n, p = pr.X.shape
+    pens = ["grp_lasso", "lasso", dict(kind="mcp", gamma=3.0)]
+    Xd, yd = torch.from_numpy(pr.X).cuda(), torch.from_numpy(pr.y).cuda()
+    with oem.Gram(p, K, "fp64", Xd.dtype, seed) as g:
+        g.add(Xd, yd)
+        res = g.cv(pens, nlambda=100, tol=TOL, groups=pr.groups)
+        torch.cuda.synchronize()
+    assert res["status"] == oem.OEM_OK
+    del Xd, yd
+    lam = res["lambda_"].cpu().numpy()
+    f = oracle.fold_ids(seed, n, K)
+    for label, mask, got in [("full", None, res["beta"].cpu().numpy()),
+                             ("fold 0", f != 0, res["beta_folds"].cpu().numpy()[0])]:
+        G, b, yy, cnt = _lib_gram_rows(pr.X, pr.y, mask)
+        st = oracle.prepare(G, b, yy, cnt)
+        if mask is None:
+            ref_lam = oracle.lambda_sequences(st["cs"], pens, 100, 1e-3, groups=pr.groups)
+            assert np.allclose(lam, ref_lam, rtol=1e-13, atol=0)
+        ref = oracle.fit_from_stats(st, pens, lam, groups=pr.groups, tol=TOL)
+        err = _rel_paths(got, ref["beta"])
+        print(f"  {label}: worst coefficient error {err:.3e}", flush=True)
+        assert err <= TOL, label
+        assert np.array_equal(got != 0, ref["beta"] != 0), label

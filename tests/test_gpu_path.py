@@ -214,6 +214,16 @@ def test_cv_parity_grouped_workload_scaled():
         assert a == b or abs(ref["cvm"][q, a] - ref["cvm"][q, b]) <= 1e-9 * ref["cvm"][q, b]
     assert res["best"].item() == ref["best"] or abs(
         ref["cvm"][res["best"].item()].min() - ref["cvm"][ref["best"]].min()) <= 1e-9
+    # lambda_1se: the first index whose cvm is within one standard error of
+    # the minimum; the GPU's index must satisfy the oracle's rule, and any
+    # index before it must not (ties within 1e-9 accepted either way)
+    i1 = res["i_1se"].cpu().numpy()
+    for q in range(3):
+        a, b = int(i1[q]), int(ref["i_1se"][q])
+        thr = ref["cvm"][q, ref["i_min"][q]] + ref["cvsd"][q, ref["i_min"][q]]
+        assert a == b or abs(ref["cvm"][q, a] - thr) <= 1e-9 * thr or abs(
+            ref["cvm"][q, b] - thr) <= 1e-9 * thr, (q, a, b)
+        assert ref["cvm"][q, a] <= thr * (1 + 1e-9)
 
 
 def test_cv_parity_grouped_large_p():

@@ -233,6 +233,15 @@ def test_group_lasso_matches_block_coordinate_descent():
         got = r["beta_std"][0, l]
         assert np.max(np.abs(got - ref)) <= 1e-8 * np.abs(ref).max()
         assert np.array_equal(got != 0, ref != 0)
+        # the oracle's group stationarity check: ~0 at the block-descent
+        # solution, and the violation of a moved coefficient is at least the
+        # change of the gradient in its group less the change of the
+        # subgradient direction term (here: a clearly positive value)
+        assert oracle.kkt(st["Gs"], st["cs"], pen, lam[l], ref, groups) <= 1e-9 * np.abs(ref).max()
+        j = int(np.flatnonzero(ref)[0])
+        bad = ref.copy()
+        bad[j] += 0.05 * np.abs(ref).max()
+        assert oracle.kkt(st["Gs"], st["cs"], pen, lam[l], bad, groups) >= 1e-3 * np.abs(ref).max()
 
 
 # ------------------------------------------------------------ stationarity, MM
