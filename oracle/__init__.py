@@ -30,9 +30,11 @@ import numpy as np
 
 from . import build as _build
 
-LASSO, ENET, MCP, SCAD, GRP_LASSO = 0, 1, 2, 3, 4
+LASSO, ENET, MCP, SCAD, GRP_LASSO, GRP_MCP, GRP_SCAD, SGL = 0, 1, 2, 3, 4, 5, 6, 7
 KIND = {"lasso": LASSO, "enet": ENET, "elastic_net": ENET, "mcp": MCP, "scad": SCAD,
-        "grp_lasso": GRP_LASSO, "group_lasso": GRP_LASSO}
+        "grp_lasso": GRP_LASSO, "group_lasso": GRP_LASSO, "grp_mcp": GRP_MCP,
+        "grp_scad": GRP_SCAD, "sgl": SGL, "sparse_grp_lasso": SGL}
+GROUP_KINDS = ("grp_lasso", "group_lasso", "grp_mcp", "grp_scad", "sgl", "sparse_grp_lasso")
 
 
 class _Pen(C.Structure):
@@ -88,6 +90,9 @@ def lib():
         L.oracle_prox1.argtypes = [pp, C.c_double, C.c_double, C.c_double]
         L.oracle_prox_group.restype = None
         L.oracle_prox_group.argtypes = [C.c_int32, dp, C.c_double, C.c_double, dp]
+        L.oracle_prox_group_pen.restype = None
+        L.oracle_prox_group_pen.argtypes = [pp, C.c_int32, dp, dp, C.c_double, C.c_double,
+                                            C.c_double, dp]
         L.oracle_lambda_max.restype = C.c_double
         L.oracle_lambda_max.argtypes = [C.c_int32, dp, pp, ip, C.c_int32, dp, dp]
         L.oracle_lambda_grid.restype = None
@@ -222,6 +227,17 @@ def prox_group(u: np.ndarray, lam_c: float, d: float) -> np.ndarray:
     u = _f64(u)
     out = np.empty_like(u)
     lib().oracle_prox_group(len(u), _d(u), lam_c, d, _d(out))
+    return out
+
+
+def prox_group_pen(pen: Penalty, u: np.ndarray, cgk: float, lam: float, d: float,
+                   w: Optional[np.ndarray] = None) -> np.ndarray:
+    """Update of one group for any group penalty (group weight cgk, level lam)."""
+    u = _f64(u)
+    out = np.empty_like(u)
+    pc = pen.c()
+    lib().oracle_prox_group_pen(C.byref(pc), len(u), _d(u), _d(_f64(w)), float(cgk), float(lam),
+                                float(d), _d(out))
     return out
 
 

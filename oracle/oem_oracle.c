@@ -231,6 +231,42 @@ void oracle_prox_group(int32_t m, const double *u, double lam_c, double d, doubl
     for (int32_t j = 0; j < m; ++j) out[j] = f > 0.0 ? (u[j] / d) * f : 0.0;
 }
 
+static int is_group_kind(int32_t kind)
+{
+    return kind == ORACLE_GRP_LASSO || kind == ORACLE_GRP_MCP || kind == ORACLE_GRP_SCAD ||
+           kind == ORACLE_SGL;
+}
+
+void oracle_prox_group_pen(const oracle_penalty *pen, int32_t m, const double *u, const double *w,
+                           double cgk, double lambda, double d, double *out)
+{
+    if (pen->kind == ORACLE_GRP_LASSO) {
+        oracle_prox_group(m, u, cgk * lambda, d, out);
+        return;
+    }
+    if (pen->kind == ORACLE_SGL) {
+        /* eq. (sglasso) with the proximal map of the nested penalty taken
+         * as written out: inner soft threshold at w_j lambda tau without the
+         * 1/d, then G(v, c_k lambda (1 - tau), d). */
+        double *v = (double *)malloc(sizeof(double) * (size_t)(m > 0 ? m : 1));
+        for (int32_t j = 0; j < m; ++j) {
+            double t = (w ? w[j] : 1.0) * lambda * pen->tau;
+            v[j] = sgn(u[j]) * pos(fabs(u[j]) - t);
+        }
+        oracle_prox_group(m, v, cgk * lambda * (1.0 - pen->tau), d, out);
+        free(v);
+        return;
+    }
+    /* eqs. (gmcp), (gscad): M or C of ||u|| at c_k lambda, direction u/||u|| */
+    double ss = 0.0;
+    for (int32_t j = 0; j < m; ++j) ss += u[j] * u[j];
+    double nrm = sqrt(ss);
+    oracle_penalty scalar = *pen;
+    scalar.kind = pen->kind == ORACLE_GRP_MCP ? ORACLE_MCP : ORACLE_SCAD;
+    double t = nrm > 0.0 ? oracle_prox1(&scalar, nrm, cgk * lambda, d) : 0.0;
+    for (int32_t j = 0; j < m; ++j) out[j] = t > 0.0 ? t * (u[j] / nrm) : 0.0;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Group bookkeeping                                                          */
 /* ------------------------------------------------------------------------ */
@@ -283,13 +319,18 @@ static void prox_all(int32_t p, const oracle_penalty *pen, const groupmap *gm, c
                      const double *cg, double lambda, double d, const double *u, double *out,
                      double *tmp_u, double *tmp_o)
 {
-    if (pen->kind == ORACLE_GRP_LASSO) {
+    if (is_group_kind(pen->kind)) {
+        double *wg = (double *)malloc(sizeof(double) * (size_t)p);
         for (int32_t g = 0; g < gm->ng; ++g) {
             int32_t m = gm->start[g + 1] - gm->start[g];
-            for (int32_t t = 0; t < m; ++t) tmp_u[t] = u[gm->idx[gm->start[g] + t]];
-            oracle_prox_group(m, tmp_u, cg_of(cg, gm, g) * lambda, d, tmp_o);
+            for (int32_t t = 0; t < m; ++t) {
+                tmp_u[t] = u[gm->idx[gm->start[g] + t]];
+                wg[t] = w_of(w, gm->idx[gm->start[g] + t]);
+            }
+            oracle_prox_group_pen(pen, m, tmp_u, wg, cg_of(cg, gm, g), lambda, d, tmp_o);
             for (int32_t t = 0; t < m; ++t) out[gm->idx[gm->start[g] + t]] = tmp_o[t];
         }
+        free(wg);
     } else {
         for (int32_t j = 0; j < p; ++j) out[j] = oracle_prox1(pen, u[j], w_of(w, j) * lambda, d);
     }
@@ -299,12 +340,74 @@ static void prox_all(int32_t p, const oracle_penalty *pen, const groupmap *gm, c
 /* lambda sequence                                                            */
 /* ------------------------------------------------------------------------ */
 
+/* Does the sparse group lasso update of group g map beta = 0 (so u = cs) to
+ * a nonzero vector at this lambda?  The test is the update's own: inner
+ * soft threshold, then the group factor 1 - c_k lambda (1 - tau) / ||v||. */
+static int sgl_group_nonzero(const groupmap *gm, int32_t g, const double *cs, const double *w,
+                             double cgk, double tau, double lambda)
+{
+    double ss = 0.0;
+    for (int32_t t = gm->start[g]; t < gm->start[g + 1]; ++t) {
+        int32_t j = gm->idx[t];
+        double v = pos(fabs(cs[j]) - w_of(w, j) * lambda * tau);
+        ss += v * v;
+    }
+    double nrm = sqrt(ss);
+    return nrm > 0.0 && 1.0 - cgk * lambda * (1.0 - tau) / nrm > 0.0;
+}
+
+/* Smallest lambda at which group g's sparse group lasso update maps beta = 0
+ * to 0.  tau = 1 is the lasso: each penalised member's own threshold.
+ * Otherwise ||soft(c_g, w lambda tau)|| - c_k lambda (1 - tau) decreases in
+ * lambda and is <= 0 at ||c_g|| / (c_k (1 - tau)); the crossing is found by
+ * bisection over doubles down to adjacent values. */
+static double sgl_group_lambda_max(const groupmap *gm, int32_t g, const double *cs, const double *w,
+                                   double cgk, double tau)
+{
+    if (tau >= 1.0) {
+        double lg = 0.0;
+        for (int32_t t = gm->start[g]; t < gm->start[g + 1]; ++t) {
+            int32_t j = gm->idx[t];
+            double wj = w_of(w, j);
+            if (wj <= 0.0) continue;
+            double lj = fabs(cs[j]) / wj;
+            while (fabs(cs[j]) - wj * lj > 0.0) lj = nextafter(lj, INFINITY);
+            if (lj > lg) lg = lj;
+        }
+        return lg;
+    }
+    double ss = 0.0;
+    for (int32_t t = gm->start[g]; t < gm->start[g + 1]; ++t) ss += cs[gm->idx[t]] * cs[gm->idx[t]];
+    double lo = 0.0, hi = sqrt(ss) / (cgk * (1.0 - tau));
+    if (!sgl_group_nonzero(gm, g, cs, w, cgk, tau, lo)) return 0.0;
+    while (sgl_group_nonzero(gm, g, cs, w, cgk, tau, hi)) hi = nextafter(hi, INFINITY);
+    for (;;) {
+        double mid = lo + 0.5 * (hi - lo);
+        if (!(mid > lo && mid < hi)) break;
+        if (sgl_group_nonzero(gm, g, cs, w, cgk, tau, mid))
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return hi;
+}
+
 double oracle_lambda_max(int32_t p, const double *cs, const oracle_penalty *pen,
                          const int32_t *groups, int32_t ngroups, const double *w,
                          const double *cg)
 {
     double lmax = 0.0;
-    if (pen->kind == ORACLE_GRP_LASSO) {
+    if (pen->kind == ORACLE_SGL) {
+        groupmap gm;
+        if (!groups || groupmap_build(p, groups, ngroups, &gm) != 0) return -1.0;
+        for (int32_t g = 0; g < gm.ng; ++g) {
+            double lg = sgl_group_lambda_max(&gm, g, cs, w, cg_of(cg, &gm, g), pen->tau);
+            if (lg > lmax) lmax = lg;
+        }
+        groupmap_free(&gm);
+        return lmax;
+    }
+    if (is_group_kind(pen->kind)) {
         groupmap gm;
         if (!groups || groupmap_build(p, groups, ngroups, &gm) != 0) return -1.0;
         for (int32_t g = 0; g < gm.ng; ++g) {
@@ -312,8 +415,13 @@ double oracle_lambda_max(int32_t p, const double *cs, const oracle_penalty *pen,
             for (int32_t t = gm.start[g]; t < gm.start[g + 1]; ++t) ss += cs[gm.idx[t]] * cs[gm.idx[t]];
             double nrm = sqrt(ss), c = cg_of(cg, &gm, g);
             double lg = nrm / c;
-            /* smallest lambda the group update itself maps to zero */
-            while (nrm > 0.0 && 1.0 - c * lg / nrm > 0.0) lg = nextafter(lg, INFINITY);
+            /* smallest lambda the group update itself maps to zero: the
+             * group lasso factor 1 - c lambda / ||u||, or the soft part
+             * ||u|| - c lambda of the MCP / SCAD update of ||u|| */
+            if (pen->kind == ORACLE_GRP_LASSO)
+                while (nrm > 0.0 && 1.0 - c * lg / nrm > 0.0) lg = nextafter(lg, INFINITY);
+            else
+                while (nrm - c * lg > 0.0) lg = nextafter(lg, INFINITY);
             if (lg > lmax) lmax = lg;
         }
         groupmap_free(&gm);
@@ -361,12 +469,21 @@ static double penalty_value(int32_t p, const oracle_penalty *pen, const groupmap
                             const double *w, const double *cg, double lambda, const double *beta)
 {
     double s = 0.0;
-    if (pen->kind == ORACLE_GRP_LASSO) {
+    if (is_group_kind(pen->kind)) {
+        /* penalty table; group MCP / SCAD read as sum_k P_{lambda c_k, gamma}(||beta_g||) */
         for (int32_t g = 0; g < gm->ng; ++g) {
-            double ss = 0.0;
-            for (int32_t t = gm->start[g]; t < gm->start[g + 1]; ++t)
+            double ss = 0.0, l1 = 0.0;
+            for (int32_t t = gm->start[g]; t < gm->start[g + 1]; ++t) {
                 ss += beta[gm->idx[t]] * beta[gm->idx[t]];
-            s += lambda * cg_of(cg, gm, g) * sqrt(ss);
+                l1 += w_of(w, gm->idx[t]) * fabs(beta[gm->idx[t]]);
+            }
+            double lc = lambda * cg_of(cg, gm, g), bn = sqrt(ss);
+            switch (pen->kind) {
+            case ORACLE_GRP_LASSO: s += lc * bn; break;
+            case ORACLE_GRP_MCP: s += mcp_value(bn, lc, pen->gamma); break;
+            case ORACLE_GRP_SCAD: s += scad_value(bn, lc, pen->gamma); break;
+            default: s += (1.0 - pen->tau) * lc * bn + pen->tau * lambda * l1; break;
+            }
         }
         return s;
     }
@@ -412,6 +529,68 @@ static double kkt_gm(int32_t p, const double *Gs, const double *cs, const oracle
         gr[a] = row - cs[a];
     }
     double viol = 0.0;
+    if (pen->kind == ORACLE_SGL) {
+        /* 0 in grad_g + lambda (1 - tau) c_k dN(beta_g) + lambda tau w * d|beta_g|,
+         * N the Euclidean norm.  Zero group: the distance of -grad_g to the
+         * sum of the box and the ball is ||soft(grad_g, lambda tau w)||
+         * less the ball radius.  Nonzero group: per member, the residual with
+         * the norm's gradient beta_j / ||beta_g||; zero members take the
+         * distance of their residual to [-lambda tau w_j, lambda tau w_j]. */
+        for (int32_t g = 0; g < gm->ng; ++g) {
+            double lc = lambda * (1.0 - pen->tau) * cg_of(cg, gm, g), bn = 0.0;
+            for (int32_t t = gm->start[g]; t < gm->start[g + 1]; ++t)
+                bn += beta[gm->idx[t]] * beta[gm->idx[t]];
+            bn = sqrt(bn);
+            double ss = 0.0, v;
+            for (int32_t t = gm->start[g]; t < gm->start[g + 1]; ++t) {
+                int32_t j = gm->idx[t];
+                double lt = lambda * pen->tau * w_of(w, j), r;
+                if (bn == 0.0)
+                    r = pos(fabs(gr[j]) - lt);
+                else if (beta[j] == 0.0)
+                    r = pos(fabs(gr[j]) - lt);
+                else
+                    r = gr[j] + lc * beta[j] / bn + lt * sgn(beta[j]);
+                ss += r * r;
+            }
+            v = bn == 0.0 ? pos(sqrt(ss) - lc) : sqrt(ss);
+            if (v > viol) viol = v;
+        }
+        free(gr);
+        return viol;
+    }
+    if (pen->kind == ORACLE_GRP_MCP || pen->kind == ORACLE_GRP_SCAD) {
+        /* 0 in grad_g + P'(||beta_g||) beta_g / ||beta_g|| (nonzero group),
+         * ||grad_g|| <= lambda c_k (zero group: P'(0+) = lambda c_k) */
+        for (int32_t g = 0; g < gm->ng; ++g) {
+            double lc = lambda * cg_of(cg, gm, g), bn = 0.0, gn = 0.0, v;
+            for (int32_t t = gm->start[g]; t < gm->start[g + 1]; ++t) {
+                bn += beta[gm->idx[t]] * beta[gm->idx[t]];
+                gn += gr[gm->idx[t]] * gr[gm->idx[t]];
+            }
+            bn = sqrt(bn);
+            gn = sqrt(gn);
+            if (bn > 0.0) {
+                double gam = pen->gamma, dp;
+                if (pen->kind == ORACLE_GRP_MCP)
+                    dp = pos(lc - bn / gam);
+                else
+                    dp = bn <= lc ? lc : (bn <= gam * lc ? (gam * lc - bn) / (gam - 1.0) : 0.0);
+                double ss = 0.0;
+                for (int32_t t = gm->start[g]; t < gm->start[g + 1]; ++t) {
+                    int32_t j = gm->idx[t];
+                    double r = gr[j] + dp * beta[j] / bn;
+                    ss += r * r;
+                }
+                v = sqrt(ss);
+            } else {
+                v = pos(gn - lc);
+            }
+            if (v > viol) viol = v;
+        }
+        free(gr);
+        return viol;
+    }
     if (pen->kind == ORACLE_GRP_LASSO) {
         for (int32_t g = 0; g < gm->ng; ++g) {
             double lc = lambda * cg_of(cg, gm, g), bn = 0.0, gn = 0.0;
@@ -467,10 +646,10 @@ double oracle_objective(int32_t p, const double *Gs, const double *cs, double yy
                         const double *w, const double *cg, double lambda, const double *beta)
 {
     groupmap gm = {0, NULL, NULL};
-    if (pen->kind == ORACLE_GRP_LASSO && (!groups || groupmap_build(p, groups, ngroups, &gm) != 0))
+    if (is_group_kind(pen->kind) && (!groups || groupmap_build(p, groups, ngroups, &gm) != 0))
         return NAN;
     double f = objective_gm(p, Gs, cs, yyn, pen, &gm, w, cg, lambda, beta);
-    if (pen->kind == ORACLE_GRP_LASSO) groupmap_free(&gm);
+    if (is_group_kind(pen->kind)) groupmap_free(&gm);
     return f;
 }
 
@@ -479,10 +658,10 @@ double oracle_kkt(int32_t p, const double *Gs, const double *cs, const oracle_pe
                   double lambda, const double *beta)
 {
     groupmap gm = {0, NULL, NULL};
-    if (pen->kind == ORACLE_GRP_LASSO && (!groups || groupmap_build(p, groups, ngroups, &gm) != 0))
+    if (is_group_kind(pen->kind) && (!groups || groupmap_build(p, groups, ngroups, &gm) != 0))
         return NAN;
     double v = kkt_gm(p, Gs, cs, pen, &gm, w, cg, lambda, beta);
-    if (pen->kind == ORACLE_GRP_LASSO) groupmap_free(&gm);
+    if (is_group_kind(pen->kind)) groupmap_free(&gm);
     return v;
 }
 
@@ -495,8 +674,10 @@ static int check_penalty(const oracle_penalty *pen, double d)
     switch (pen->kind) {
     case ORACLE_LASSO: case ORACLE_GRP_LASSO: return 0;
     case ORACLE_ENET: return (pen->alpha > 0.0 && pen->alpha <= 1.0) ? 0 : -1;
-    case ORACLE_MCP: return (pen->gamma > 1.0 && pen->gamma * d > 1.0) ? 0 : -1;
-    case ORACLE_SCAD: return (pen->gamma > 2.0 && (pen->gamma - 1.0) * d > 1.0) ? 0 : -1;
+    case ORACLE_MCP: case ORACLE_GRP_MCP: return (pen->gamma > 1.0 && pen->gamma * d > 1.0) ? 0 : -1;
+    case ORACLE_SCAD: case ORACLE_GRP_SCAD:
+        return (pen->gamma > 2.0 && (pen->gamma - 1.0) * d > 1.0) ? 0 : -1;
+    case ORACLE_SGL: return (pen->tau >= 0.0 && pen->tau <= 1.0) ? 0 : -1;
     default: return -1;
     }
 }
@@ -552,7 +733,7 @@ int oracle_fit_path(int32_t p, const double *Gs, const double *cs, double yyn, d
 {
     if (p <= 0 || L < 1 || maxit < 1 || !(d > 0.0) || check_penalty(pen, d) != 0) return -1;
     groupmap gm = {0, NULL, NULL};
-    if (pen->kind == ORACLE_GRP_LASSO && (!groups || groupmap_build(p, groups, ngroups, &gm) != 0))
+    if (is_group_kind(pen->kind) && (!groups || groupmap_build(p, groups, ngroups, &gm) != 0))
         return -1;
     scratch s;
     if (scratch_alloc(p, &s) != 0) return -2;
@@ -574,7 +755,7 @@ int oracle_fit_path(int32_t p, const double *Gs, const double *cs, double yyn, d
     }
     free(cur);
     scratch_free(&s);
-    if (pen->kind == ORACLE_GRP_LASSO) groupmap_free(&gm);
+    if (is_group_kind(pen->kind)) groupmap_free(&gm);
     return status;
 }
 
@@ -585,7 +766,7 @@ int oracle_oem_steps(int32_t p, const double *Gs, const double *cs, double yyn, 
 {
     if (p <= 0 || !(d > 0.0) || check_penalty(pen, d) != 0) return -1;
     groupmap gm = {0, NULL, NULL};
-    if (pen->kind == ORACLE_GRP_LASSO && (!groups || groupmap_build(p, groups, ngroups, &gm) != 0))
+    if (is_group_kind(pen->kind) && (!groups || groupmap_build(p, groups, ngroups, &gm) != 0))
         return -1;
     scratch s;
     if (scratch_alloc(p, &s) != 0) return -2;
@@ -595,7 +776,7 @@ int oracle_oem_steps(int32_t p, const double *Gs, const double *cs, double yyn, 
         if (obj_trace) obj_trace[t] = objective_gm(p, Gs, cs, yyn, pen, &gm, w, cg, lambda, beta);
     }
     scratch_free(&s);
-    if (pen->kind == ORACLE_GRP_LASSO) groupmap_free(&gm);
+    if (is_group_kind(pen->kind)) groupmap_free(&gm);
     return 0;
 }
 

@@ -26,13 +26,14 @@
 extern "C" {
 #endif
 
-enum { ORACLE_LASSO = 0, ORACLE_ENET = 1, ORACLE_MCP = 2, ORACLE_SCAD = 3, ORACLE_GRP_LASSO = 4 };
+enum { ORACLE_LASSO = 0, ORACLE_ENET = 1, ORACLE_MCP = 2, ORACLE_SCAD = 3, ORACLE_GRP_LASSO = 4,
+       ORACLE_GRP_MCP = 5, ORACLE_GRP_SCAD = 6, ORACLE_SGL = 7 };
 
 typedef struct {
     int32_t kind;   /* ORACLE_* */
     double alpha;   /* elastic net mixing, 0 < alpha <= 1 */
-    double gamma;   /* MCP (> 1) or SCAD (> 2) concavity */
-    double tau;     /* reserved (sparse group lasso) */
+    double gamma;   /* MCP / group MCP (> 1) or SCAD / group SCAD (> 2) concavity */
+    double tau;     /* sparse group lasso mixing, 0 <= tau <= 1 */
 } oracle_penalty;
 
 /* ---- fold assignment (Section 3: rows randomly partitioned into K folds) ----
@@ -78,6 +79,16 @@ double oracle_oem_d(int32_t p, const double *A);
 double oracle_prox1(const oracle_penalty *pen, double u, double lam_w, double d);
 /* Group lasso update of one group of length m: out = (u/d)(1 - lam_c/||u||)_+ */
 void oracle_prox_group(int32_t m, const double *u, double lam_c, double d, double *out);
+/* Update of one group of length m for any group penalty (Section 2.2, eqs.
+ * glasso, gmcp, gscad, sglasso): group weight cgk, variable weights w (m
+ * values, NULL = 1), penalty level lambda.  Group MCP / SCAD scale u by the
+ * scalar MCP / SCAD update of ||u|| at c_k lambda.  The sparse group lasso
+ * soft-thresholds each u_j at w_j lambda tau (no division by d) and then
+ * applies the group lasso update at c_k lambda (1 - tau) with the same d; the
+ * printed form divides by d in the inner step and uses 1 in the outer one,
+ * which is not the proximal map unless d = 1. */
+void oracle_prox_group_pen(const oracle_penalty *pen, int32_t m, const double *u, const double *w,
+                           double cgk, double lambda, double d, double *out);
 
 /* ---- lambda sequence ----
  * lambda_max: smallest lambda at which the update maps beta = 0 to 0 (tested

@@ -141,9 +141,9 @@ def tall_multi(n: int = 1_000_000, p: int = 100, seed_tag: int = 2) -> Problem:
 
 
 def cv_grouped(n: int = 2_000_000, p: int = 500, group_size: int = 10,
-               active_groups: int = 5, seed_tag: int = 3) -> Problem:
+               active_groups: int = 5, seed_tag: int = 3, rho: float = 0.3) -> Problem:
     """n=2e6, p=500, AR(1) rho=0.3 FP32 X, contiguous groups, sigma=2."""
-    X = draw_rows(n, p, 0.3, np.float32, subseed(seed_tag, 0))
+    X = draw_rows(n, p, rho, np.float32, subseed(seed_tag, 0))
     ngroups = (p + group_size - 1) // group_size
     groups = np.arange(p) // group_size
     g = _rng(subseed(seed_tag, 3))
@@ -151,7 +151,7 @@ def cv_grouped(n: int = 2_000_000, p: int = 500, group_size: int = 10,
     pos = np.concatenate([np.arange(a * group_size, min(p, (a + 1) * group_size)) for a in act])
     b = sparse_beta(p, len(pos), subseed(seed_tag, 1), positions=pos)
     y = response(X, b, 2.0, subseed(seed_tag, 2))
-    return Problem(X, y, b, 0.3, groups=groups.astype(np.int32),
+    return Problem(X, y, b, rho, groups=groups.astype(np.int32),
                    meta=dict(workload="cv_grouped", n=n, p=p))
 
 
