@@ -179,4 +179,19 @@ def test_grouped_cv_full_size_coefficients():
         err = _rel_paths(got, ref["beta"])
         print(f"  {label}: worst coefficient error {err:.3e}", flush=True)
         assert err <= TOL, label
-        assert np.array_equal(got != 0, ref["beta"] != 0), label
+        # on the full data the first lambda is lambda_max of the GPU's Gram, a
+        # knife edge for the differently rounded library Gram: coefficients
+        # there need only be at rounding level.  Fold paths use the full-data
+        # grid, so their first lambda is an ordinary one.
+        l0 = 1 if mask is None else 0
+        if mask is None:
+            for q in range(len(pens)):
+                nxt = np.abs(ref["beta"][q, 1]).max()
+                assert np.abs(got[q, 0]).max() <= 1e-10 * nxt
+                assert np.abs(ref["beta"][q, 0]).max() <= 1e-10 * nxt
+        else:
+            for q in range(len(pens)):
+                s0 = np.abs(ref["beta"][q, 0]).max()
+                assert np.abs(got[q, 0] - ref["beta"][q, 0]).max() <= TOL * max(s0, 1e-300)
+        diff = (got[:, l0:] != 0) != (ref["beta"][:, l0:] != 0)
+        assert not diff.any(), (label, np.argwhere(diff)[:10])
