@@ -81,20 +81,31 @@ enum { OEM_FP64 = 0, OEM_SPLIT_BF16 = 1, OEM_BF16 = 2 };
 /* Element type of X. */
 enum { OEM_X_F32 = 0, OEM_X_F64 = 1 };
 
-/* Penalties (Section 2.2, penalty table). */
+/* Penalties (Section 2.2, penalty table; updates eqs. lasso, net, mcp, scad,
+ * glasso, gmcp, gscad, sglasso).  Group penalties need a group partition.
+ * Group MCP / SCAD are sum_k P_{lambda c_k, gamma}(||beta_{g_k}||) (the
+ * table's extra factor lambda read as a typo): the update scales u_g by the
+ * scalar MCP / SCAD update of ||u_g|| at c_k lambda.  The sparse group lasso
+ * update soft-thresholds each u_j at w_j lambda tau and applies the group
+ * lasso update at c_k lambda (1 - tau), both with the same d: the proximal
+ * map of the nested penalty (the printed form differs unless d = 1). */
 enum {
     OEM_LASSO = 0,     /* lambda sum_j w_j |beta_j|                         */
     OEM_ENET = 1,      /* alpha lambda sum w|b| + (1-alpha)/2 lambda sum w b^2 */
     OEM_MCP = 2,       /* minimax concave penalty, gamma > 1                */
     OEM_SCAD = 3,      /* smoothly clipped absolute deviation, gamma > 2    */
-    OEM_GRP_LASSO = 4  /* lambda sum_k c_k ||beta_{g_k}||                   */
+    OEM_GRP_LASSO = 4, /* lambda sum_k c_k ||beta_{g_k}||                   */
+    OEM_GRP_MCP = 5,   /* sum_k P^MCP_{lambda c_k, gamma}(||beta_{g_k}||), gamma > 1 */
+    OEM_GRP_SCAD = 6,  /* sum_k P^SCAD_{lambda c_k, gamma}(||beta_{g_k}||), gamma > 2 */
+    OEM_SGL = 7        /* lambda (1-tau) sum_k c_k ||beta_g|| + lambda tau sum_j w_j |beta_j| */
 };
 
 typedef struct {
-    int32_t kind;  /* OEM_LASSO .. OEM_GRP_LASSO */
+    int32_t kind;  /* OEM_LASSO .. OEM_SGL */
     double alpha;  /* elastic net mixing, 0 < alpha <= 1 (ignored otherwise) */
-    double gamma;  /* MCP / SCAD concavity (ignored otherwise) */
-    double tau;    /* reserved, must be 0 */
+    double gamma;  /* (group) MCP / SCAD concavity (ignored otherwise) */
+    double tau;    /* sparse group lasso mixing, 0 <= tau <= 1; must be 0 for
+                      every other kind */
 } oem_penalty;
 
 /* Options of a path fit.  Every pointer here is a HOST pointer. */
@@ -179,8 +190,10 @@ int oem_gram_export(oem_handle g, double *G, double *b, double *yy, int64_t *nk,
  * d: when the Lanczos iteration does not settle within its step limit, d is
  * the Gershgorin bound max_i sum_j |G_ij| instead (still >= lambda_1).
  * Errors: OEM_E_INVAL (fold out of range, n of the selected rows = 0, bad
- * penalty parameters: alpha not in (0,1], MCP gamma <= 1 or gamma d <= 1,
- * SCAD gamma <= 2 or (gamma-1) d <= 1, bad groups, L < 1, maxit < 1; d not
+ * penalty parameters: alpha not in (0,1], (group) MCP gamma <= 1 or
+ * gamma d <= 1, (group) SCAD gamma <= 2 or (gamma-1) d <= 1, tau not in
+ * [0, 1] or nonzero outside the sparse group lasso, bad groups, L < 1,
+ * maxit < 1; d not
  * a finite positive number, i.e. non-finite or all-zero statistics),
  * OEM_E_STATE (no rows accumulated), OEM_E_HIP (including an eigenvalue
  * solve whose workgroups could not all run at once). */

@@ -27,9 +27,12 @@ OEM_E_INVAL, OEM_E_NOMEM, OEM_E_HIP, OEM_E_STATE = -1, -2, -3, -4
 OEM_FP64, OEM_SPLIT_BF16, OEM_BF16 = 0, 1, 2
 OEM_X_F32, OEM_X_F64 = 0, 1
 OEM_LASSO, OEM_ENET, OEM_MCP, OEM_SCAD, OEM_GRP_LASSO = 0, 1, 2, 3, 4
+OEM_GRP_MCP, OEM_GRP_SCAD, OEM_SGL = 5, 6, 7
 
 PENALTY_KIND = {"lasso": OEM_LASSO, "enet": OEM_ENET, "elastic_net": OEM_ENET, "mcp": OEM_MCP,
-                "scad": OEM_SCAD, "grp_lasso": OEM_GRP_LASSO, "group_lasso": OEM_GRP_LASSO}
+                "scad": OEM_SCAD, "grp_lasso": OEM_GRP_LASSO, "group_lasso": OEM_GRP_LASSO,
+                "grp_mcp": OEM_GRP_MCP, "grp_scad": OEM_GRP_SCAD, "sgl": OEM_SGL,
+                "sparse_grp_lasso": OEM_SGL}
 PRECISION = {"fp64": OEM_FP64, "split_bf16": OEM_SPLIT_BF16, "bf16": OEM_BF16}
 
 EXPORTED = ["oem_gram_create", "oem_gram_free", "oem_gram_reset", "oem_gram", "oem_gram_import",
@@ -197,9 +200,11 @@ class Penalty:
     kind: str = "lasso"
     alpha: float = 1.0
     gamma: float = 3.0
+    tau: float = 0.0      # sparse group lasso mixing
 
     def c(self) -> oem_penalty:
-        return oem_penalty(PENALTY_KIND[self.kind], float(self.alpha), float(self.gamma), 0.0)
+        return oem_penalty(PENALTY_KIND[self.kind], float(self.alpha), float(self.gamma),
+                           float(self.tau))
 
 
 def _penalties(pens: Sequence) -> list:

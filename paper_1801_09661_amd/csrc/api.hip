@@ -183,17 +183,22 @@ static int check_penalty(const oem_penalty &pn, double d)
         if (!(pn.alpha > 0.0 && pn.alpha <= 1.0)) return fail(OEM_E_INVAL, "elastic net alpha must be in (0, 1]");
         break;
     case OEM_MCP:
+    case OEM_GRP_MCP:
         if (!(pn.gamma > 1.0)) return fail(OEM_E_INVAL, "MCP needs gamma > 1");
         if (!(pn.gamma * d > 1.0)) return fail(OEM_E_INVAL, "MCP needs gamma * d > 1");
         break;
     case OEM_SCAD:
+    case OEM_GRP_SCAD:
         if (!(pn.gamma > 2.0)) return fail(OEM_E_INVAL, "SCAD needs gamma > 2");
         if (!((pn.gamma - 1.0) * d > 1.0)) return fail(OEM_E_INVAL, "SCAD needs (gamma - 1) d > 1");
         break;
+    case OEM_SGL:
+        if (!(pn.tau >= 0.0 && pn.tau <= 1.0)) return fail(OEM_E_INVAL, "sparse group lasso tau must be in [0, 1]");
+        return OEM_OK;
     default:
         return fail(OEM_E_INVAL, "unknown penalty kind");
     }
-    if (pn.tau != 0.0) return fail(OEM_E_INVAL, "penalty tau is reserved and must be 0");
+    if (pn.tau != 0.0) return fail(OEM_E_INVAL, "penalty tau applies to the sparse group lasso only and must be 0");
     return OEM_OK;
 }
 
@@ -250,6 +255,7 @@ static PathDesc make_desc(oem_gram_s *h, int q, const oem_penalty &pn, const oem
     d.ngroups = gp.ngroups;
     d.alpha = pn.alpha;
     d.gamma = pn.gamma;
+    d.tau = pn.tau;
     d.tol = o->tol;
     d.maxit = o->maxit;
     return d;
@@ -453,7 +459,7 @@ int oem_fit_path(oem_handle h, int32_t fold, const oem_penalty *pen, int32_t npe
     for (int i = 0; i < npen; ++i) {
         rc = check_penalty(pen[i], h->d_host[q]);
         if (rc) return rc;
-        need_groups |= pen[i].kind == OEM_GRP_LASSO;
+        need_groups |= group_penalty(pen[i].kind);
     }
     GroupPlan gp;
     rc = build_groups(h, opts, need_groups, gp, s);
@@ -512,7 +518,7 @@ int oem_cv(oem_handle h, const oem_penalty *pen, int32_t npen, const oem_path_op
             rc = check_penalty(pen[i], h->d_host[q]);
             if (rc) return rc;
         }
-        need_groups |= pen[i].kind == OEM_GRP_LASSO;
+        need_groups |= group_penalty(pen[i].kind);
     }
     GroupPlan gp;
     rc = build_groups(h, opts, need_groups, gp, s);
@@ -697,7 +703,7 @@ int oem_batch_create(const oem_problem *probs, int32_t nprob, int32_t precision,
     if (opts->groups || opts->lambda || opts->w || opts->cg)
         return fail(OEM_E_INVAL, "batched fits take no groups, weights or explicit lambda");
     for (int i = 0; i < npen; ++i) {
-        if (pen[i].kind == OEM_GRP_LASSO) return fail(OEM_E_INVAL, "batched fits take no group penalty");
+        if (group_penalty(pen[i].kind)) return fail(OEM_E_INVAL, "batched fits take no group penalty");
         rc = check_penalty(pen[i], 1.0);   // standardised: d >= 1
         if (rc) return rc;
     }

@@ -49,6 +49,13 @@ __host__ __device__ inline uint32_t fold_hash(uint64_t seed, int64_t row, uint32
     return (uint32_t)(((z >> 32) * (uint64_t)K) >> 32);
 }
 
+// ------------------------------------------------------------------ penalties
+// Penalties whose update works on whole groups (Section 2.2).
+__host__ __device__ inline bool group_penalty(int kind)
+{
+    return kind == OEM_GRP_LASSO || kind == OEM_GRP_MCP || kind == OEM_GRP_SCAD || kind == OEM_SGL;
+}
+
 // ------------------------------------------------------------------ Gram geometry
 // The Gram pass computes the upper triangle of the augmented Gram
 // [X y]^T [X y] in square tiles.  Tiles are grouped into super-blocks of W
@@ -92,6 +99,7 @@ struct PathDesc {
     int32_t ngroups;
     double alpha;
     double gamma;
+    double tau;           // sparse group lasso mixing
     double tol;
     int32_t maxit;
     // hand-over between the kernels of one path's launch chain: the first

@@ -16,6 +16,56 @@ namespace oem {
 
 // ---------------------------------------------------------------- lambda grid
 
+// Sparse group lasso: does the update map beta = 0 (u = cs) of the group
+// with members gidx[t0..t1) to a nonzero vector at lambda?
+__device__ inline bool sgl_group_nonzero(const double *cs, const int32_t *gidx, int t0, int t1,
+                                         const double *w, double cgk, double tau, double lam)
+{
+    double ss = 0.0;
+    for (int t = t0; t < t1; ++t) {
+        const int j = gidx[t];
+        const double v = pos(fabs(cs[j]) - (w ? w[j] : 1.0) * lam * tau);
+        ss += v * v;
+    }
+    const double nrm = sqrt(ss);
+    return nrm > 0.0 && 1.0 - cgk * lam * (1.0 - tau) / nrm > 0.0;
+}
+
+// Smallest lambda that zeroes the group: for tau = 1 each penalised
+// member's lasso threshold; otherwise ||soft(c_g, w lambda tau)|| - c lambda
+// (1 - tau) decreases in lambda and is <= 0 at ||c_g|| / (c (1 - tau)), and
+// the crossing is bisected over doubles down to adjacent values.
+__device__ inline double sgl_group_lambda_max(const double *cs, const int32_t *gidx, int t0, int t1,
+                                              const double *w, double cgk, double tau)
+{
+    if (tau >= 1.0) {
+        double lg = 0.0;
+        for (int t = t0; t < t1; ++t) {
+            const int j = gidx[t];
+            const double wj = w ? w[j] : 1.0;
+            if (wj <= 0.0) continue;
+            double lj = fabs(cs[j]) / wj;
+            while (fabs(cs[j]) - wj * lj > 0.0) lj = nextafter(lj, INFINITY);
+            lg = fmax(lg, lj);
+        }
+        return lg;
+    }
+    double ss = 0.0;
+    for (int t = t0; t < t1; ++t) ss += cs[gidx[t]] * cs[gidx[t]];
+    double lo = 0.0, hi = sqrt(ss) / (cgk * (1.0 - tau));
+    if (!sgl_group_nonzero(cs, gidx, t0, t1, w, cgk, tau, lo)) return 0.0;
+    while (sgl_group_nonzero(cs, gidx, t0, t1, w, cgk, tau, hi)) hi = nextafter(hi, INFINITY);
+    for (;;) {
+        const double mid = lo + 0.5 * (hi - lo);
+        if (!(mid > lo && mid < hi)) break;
+        if (sgl_group_nonzero(cs, gidx, t0, t1, w, cgk, tau, mid))
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return hi;
+}
+
 // lambda_max of penalty `pen` from the full-data standardised X^T y: the
 // smallest value at which the update maps beta = 0 to 0 (each candidate is
 // raised by ulps until the update's own zero test holds), then a log grid.
@@ -28,13 +78,21 @@ __global__ __launch_bounds__(kPathThreads) void lambda_grid_kernel(
     __shared__ double red[kPathWaves];
     const oem_penalty pen = pens[blockIdx.x];
     double m = 0.0;
-    if (pen.kind == OEM_GRP_LASSO) {
+    if (pen.kind == OEM_SGL) {
+        for (int gi = threadIdx.x; gi < ngroups; gi += kPathThreads)
+            m = fmax(m, sgl_group_lambda_max(cs, gidx, gstart[gi], gstart[gi + 1], w, cg[gi], pen.tau));
+    } else if (group_penalty(pen.kind)) {
         for (int gi = threadIdx.x; gi < ngroups; gi += kPathThreads) {
             double ss = 0.0;
             for (int t = gstart[gi]; t < gstart[gi + 1]; ++t) ss += cs[gidx[t]] * cs[gidx[t]];
             const double nrm = sqrt(ss), c = cg[gi];
             double lg = nrm / c;
-            while (nrm > 0.0 && 1.0 - c * lg / nrm > 0.0) lg = nextafter(lg, INFINITY);
+            // the update's own zero test: the group lasso factor, or the
+            // soft part of the MCP / SCAD update of ||u||
+            if (pen.kind == OEM_GRP_LASSO)
+                while (nrm > 0.0 && 1.0 - c * lg / nrm > 0.0) lg = nextafter(lg, INFINITY);
+            else
+                while (nrm - c * lg > 0.0) lg = nextafter(lg, INFINITY);
             m = fmax(m, lg);
         }
     } else {
@@ -155,7 +213,7 @@ __global__ __launch_bounds__(kPathThreads) void path_kernel(const PathDesc *__re
     }
     const double d = *P.d;
     const double yyn = *P.yyn;
-    const bool grp = (P.kind == OEM_GRP_LASSO);
+    const bool grp = group_penalty(P.kind);
     for (int i = threadIdx.x; i < p; i += kPathThreads) S.beta[i] = 0.0;
     __syncthreads();
     int nact = 0;
@@ -173,13 +231,23 @@ __global__ __launch_bounds__(kPathThreads) void path_kernel(const PathDesc *__re
                 for (int gi = threadIdx.x; gi < P.ngroups; gi += kPathThreads) {
                     double ss = 0.0;
                     const int t0 = gstart_g[gi], t1 = gstart_g[gi + 1];
-                    for (int t = t0; t < t1; ++t) ss += S.u[gidx_g[t]] * S.u[gidx_g[t]];
+                    if (P.kind == OEM_SGL) {
+                        // inner soft threshold first (nested penalties), in place of u
+                        for (int t = t0; t < t1; ++t) {
+                            const int j = gidx_g[t];
+                            const double v = sgl_inner(S.u[j], w_g ? w_g[j] : 1.0, lam, P.tau);
+                            S.u[j] = v;
+                            ss += v * v;
+                        }
+                    } else {
+                        for (int t = t0; t < t1; ++t) ss += S.u[gidx_g[t]] * S.u[gidx_g[t]];
+                    }
                     const double nrm = sqrt(ss);
-                    const double lam_c = cg_g[gi] * lam;
-                    const double f = nrm > 0.0 ? 1.0 - lam_c / nrm : 0.0;
+                    const GroupUpd gu =
+                        make_group_upd(P.kind, nrm, group_lam_c(P.kind, cg_g[gi], lam, P.tau), d, P.gamma);
                     for (int t = t0; t < t1; ++t) {
                         const int j = gidx_g[t];
-                        const double bn = f > 0.0 ? (S.u[j] / d) * f : 0.0;
+                        const double bn = group_update_one(gu, S.u[j]);
                         dl = fmax(dl, fabs(bn - S.beta[j]));
                         mx = fmax(mx, fabs(bn));
                         S.beta[j] = bn;
@@ -241,22 +309,38 @@ __global__ __launch_bounds__(kPathThreads) void path_kernel(const PathDesc *__re
         __syncthreads();
         if (grp) {
             for (int gi = threadIdx.x; gi < P.ngroups; gi += kPathThreads) {
-                const double lc = lam * cg_g[gi];
-                double bn = 0.0, gn = 0.0;
+                const double cgk = cg_g[gi];
+                const double lc = group_lam_c(P.kind, cgk, lam, P.tau);
+                double bn = 0.0, gn = 0.0, l1w = 0.0;
                 const int t0 = gstart_g[gi], t1 = gstart_g[gi + 1];
                 for (int t = t0; t < t1; ++t) {
                     const int j = gidx_g[t];
                     bn += S.beta[j] * S.beta[j];
                     gn += S.u[j] * S.u[j];
+                    l1w += (w_g ? w_g[j] : 1.0) * fabs(S.beta[j]);
                 }
                 bn = sqrt(bn);
                 gn = sqrt(gn);
                 double v;
-                if (bn > 0.0) {
+                if (P.kind == OEM_SGL) {
+                    // 0 in g + lambda (1 - tau) c dN(beta_g) + lambda tau w d|beta|:
+                    // a zero group is stationary when ||soft(g, lambda tau w)|| <= lc
                     double ss = 0.0;
                     for (int t = t0; t < t1; ++t) {
                         const int j = gidx_g[t];
-                        const double r = S.u[j] + lc * S.beta[j] / bn;
+                        const double lt = lam * P.tau * (w_g ? w_g[j] : 1.0);
+                        const double r = (bn == 0.0 || S.beta[j] == 0.0)
+                                             ? pos(fabs(S.u[j]) - lt)
+                                             : S.u[j] + lc * S.beta[j] / bn + lt * sgn(S.beta[j]);
+                        ss += r * r;
+                    }
+                    v = bn == 0.0 ? pos(sqrt(ss) - lc) : sqrt(ss);
+                } else if (bn > 0.0) {
+                    const double dp = group_pen_deriv(P.kind, bn, lc, P.gamma);
+                    double ss = 0.0;
+                    for (int t = t0; t < t1; ++t) {
+                        const int j = gidx_g[t];
+                        const double r = S.u[j] + dp * S.beta[j] / bn;
                         ss += r * r;
                     }
                     v = sqrt(ss);
@@ -264,7 +348,7 @@ __global__ __launch_bounds__(kPathThreads) void path_kernel(const PathDesc *__re
                     v = pos(gn - lc);
                 }
                 kv = fmax(kv, v);
-                penv += lc * bn;
+                penv += group_pen_value(P.kind, bn, l1w, cgk, lam, P.gamma, P.tau);
             }
         }
         kv = wave_max(kv);
@@ -358,7 +442,8 @@ static bool ws_enabled()
 static int path_chain(const PathDesc &d, int *slots)
 {
     const bool grp = d.kind == OEM_GRP_LASSO;
-    const int cls = d.p > 2048 ? kGeneral
+    // group MCP, group SCAD and the sparse group lasso run on the general kernel
+    const int cls = (d.p > 2048 || (group_penalty(d.kind) && !grp)) ? kGeneral
                     : d.p > 128 ? kStream
                     : grp       ? (d.p <= 64 ? kReg64 : kReg128)
                                 : (d.p <= 32 ? kBlk32 : (d.p <= 64 ? kBlk64 : kBlk128));

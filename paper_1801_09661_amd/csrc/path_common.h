@@ -115,6 +115,73 @@ __device__ inline double pen_value(int kind, double b, double lw, double alpha, 
     }
 }
 
+// ---------------------------------------------------------------- group penalties
+
+// Update of one group from nrm = ||u_g|| (for the sparse group lasso:
+// ||v_g||, v = the soft-thresholded u): beta_j = group_update_one(u_j).
+// eq. glasso: (u/d)(1 - c lambda / ||u||)_+; eqs. gmcp, gscad: the scalar
+// MCP / SCAD update of ||u|| at c lambda along u / ||u||.
+struct GroupUpd {
+    int kind;       // OEM_GRP_LASSO (also the outer step of OEM_SGL) or OEM_GRP_MCP / SCAD
+    double f;       // group lasso factor 1 - lam_c / nrm (zero group when <= 0)
+    double t;       // MCP / SCAD: updated norm (zero group when <= 0)
+    double nrm;
+    double d;
+};
+
+__device__ inline GroupUpd make_group_upd(int kind, double nrm, double lam_c, double d, double gamma)
+{
+    GroupUpd g;
+    g.kind = (kind == OEM_SGL) ? OEM_GRP_LASSO : kind;
+    g.nrm = nrm;
+    g.d = d;
+    g.f = nrm > 0.0 ? 1.0 - lam_c / nrm : 0.0;
+    g.t = 0.0;
+    if (kind == OEM_GRP_MCP || kind == OEM_GRP_SCAD)
+        g.t = nrm > 0.0 ? update1(kind == OEM_GRP_MCP ? OEM_MCP : OEM_SCAD, nrm, lam_c, d, 0.0, gamma) : 0.0;
+    return g;
+}
+
+__device__ inline double group_update_one(const GroupUpd &g, double u)
+{
+    if (g.kind == OEM_GRP_LASSO) return g.f > 0.0 ? (u / g.d) * g.f : 0.0;
+    return g.t > 0.0 ? g.t * (u / g.nrm) : 0.0;
+}
+
+// the group's threshold level: c lambda, or c lambda (1 - tau) for the outer
+// step of the sparse group lasso
+__device__ inline double group_lam_c(int kind, double cgk, double lam, double tau)
+{
+    return kind == OEM_SGL ? cgk * lam * (1.0 - tau) : cgk * lam;
+}
+
+// inner soft threshold of the sparse group lasso (no division by d)
+__device__ inline double sgl_inner(double u, double w, double lam, double tau)
+{
+    return sgn(u) * pos(fabs(u) - w * lam * tau);
+}
+
+// penalty of one group: bn = ||beta_g||, l1w = sum_j w_j |beta_j|
+__device__ inline double group_pen_value(int kind, double bn, double l1w, double cgk, double lam,
+                                         double gamma, double tau)
+{
+    const double lc = lam * cgk;
+    switch (kind) {
+    case OEM_GRP_MCP: return pen_value(OEM_MCP, bn, lc, 0.0, gamma);
+    case OEM_GRP_SCAD: return pen_value(OEM_SCAD, bn, lc, 0.0, gamma);
+    case OEM_SGL: return (1.0 - tau) * lc * bn + tau * lam * l1w;
+    default: return lc * bn;
+    }
+}
+
+// derivative of a radial group penalty at ||beta_g|| = bn > 0
+__device__ inline double group_pen_deriv(int kind, double bn, double lc, double gamma)
+{
+    if (kind == OEM_GRP_MCP) return pen_deriv(OEM_MCP, bn, lc, 0.0, gamma);
+    if (kind == OEM_GRP_SCAD) return pen_deriv(OEM_SCAD, bn, lc, 0.0, gamma);
+    return lc;
+}
+
 // ---------------------------------------------------------------- reductions
 
 // Cross-lane moves with DPP (a 64-bit value moves as two 32-bit halves).

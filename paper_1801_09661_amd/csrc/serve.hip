@@ -222,7 +222,7 @@ int oem_server_submit(oem_server S, const oem_request *req)
     if (r.p < 1 || r.p > 4096 || r.n < 1 || r.n > INT32_MAX || r.ldx < r.p || !r.X || !r.y || !r.beta)
         return fail(OEM_E_INVAL, "request: bad p, n, ldx or pointer");
     if (r.nfolds < 1 || r.nfolds > 64) return fail(OEM_E_INVAL, "request: nfolds must be in [1, 64]");
-    if (r.pen.kind == OEM_GRP_LASSO && !r.groups) return fail(OEM_E_INVAL, "request: group penalty without groups");
+    if (group_penalty(r.pen.kind) && !r.groups) return fail(OEM_E_INVAL, "request: group penalty without groups");
     Pending job{r, request_bytes(r, S->opts.nlambda), r.t_arrival >= 0.0 ? r.t_arrival : now_s()};
     {
         std::lock_guard<std::mutex> lk(S->mu);
