@@ -160,6 +160,23 @@ int oem_gram_reset(oem_handle g, void *stream);
 int oem_gram(oem_handle g, const void *X, int64_t n, int64_t ldx, const double *y,
              int64_t row_offset, const uint8_t *foldid, void *stream);
 
+/* oem_gram for callers that cannot allocate device memory: code under
+ * hipGraph capture, request loops that must not call hipMalloc, harnesses
+ * that forbid it.  Same arguments, sums and kernels as oem_gram; the pass's
+ * row lists and partial sums live in a static device workspace of 64 MiB
+ * (one per device, held until the process ends) instead of buffers the
+ * handle grows, so the call allocates nothing (the handle's sums were
+ * allocated by oem_gram_create).  Every call on one device shares that
+ * device's workspace: calls that overlap in time on one device (two host
+ * threads, or two streams whose work runs concurrently) race and must be
+ * serialised by the caller.  The workspace needs no clearing between calls.
+ * Errors: as oem_gram; OEM_E_INVAL when the current device is not the
+ * handle's, or when the pass needs more than the workspace (with folds the
+ * row lists take 4 bytes per row: pass larger data sets as successive row
+ * blocks). */
+int oem_gram_noalloc(oem_handle g, const void *X, int64_t n, int64_t ldx, const double *y,
+                     int64_t row_offset, const uint8_t *foldid, void *stream);
+
 /* Load sufficient statistics computed elsewhere into fold slot `fold`
  * (precomputed X^T X and X^T y, Section 5.6).  XtX (p x p), Xty (p): device
  * pointers.  scaled = 1: the inputs are X^T X / n, X^T y / n, y^T y / n (the

@@ -39,7 +39,7 @@ EXPORTED = ["oem_gram_create", "oem_gram_free", "oem_gram_reset", "oem_gram", "o
             "oem_gram_export", "oem_fit_path", "oem_cv", "oem_gram_autotune", "oem_batch_create",
             "oem_batch_run", "oem_batch_run_graph", "oem_batch_status", "oem_batch_free",
             "oem_server_create", "oem_server_submit", "oem_server_poll", "oem_server_drain",
-            "oem_server_now", "oem_server_free", "oem_last_error", "oem_version"]
+            "oem_server_now", "oem_server_free", "oem_last_error", "oem_version", "oem_gram_noalloc"]
 
 
 class OemError(RuntimeError):
@@ -103,6 +103,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     L.oem_gram_reset.argtypes = [vp, vp]
     L.oem_gram.restype = C.c_int
     L.oem_gram.argtypes = [vp, vp, C.c_int64, C.c_int64, vp, C.c_int64, vp, vp]
+    L.oem_gram_noalloc.restype = C.c_int
+    L.oem_gram_noalloc.argtypes = [vp, vp, C.c_int64, C.c_int64, vp, C.c_int64, vp, vp]
     L.oem_gram_import.restype = C.c_int
     L.oem_gram_import.argtypes = [vp, C.c_int32, vp, vp, C.c_double, C.c_int64, C.c_int32, vp]
     L.oem_gram_export.restype = C.c_int
@@ -239,8 +241,9 @@ def oem_gram_reset(h, stream=None) -> None:
     _check(load_library().oem_gram_reset(h, _stream(stream)))
 
 
-def oem_gram(h, X, y, row_offset: int = 0, foldid=None, stream=None) -> None:
-    """Accumulate the statistics of the rows of X (cuda, row-major) and y."""
+def oem_gram(h, X, y, row_offset: int = 0, foldid=None, stream=None, noalloc: bool = False) -> None:
+    """Accumulate the statistics of the rows of X (cuda, row-major) and y
+    (noalloc: through oem_gram_noalloc, the entry point that allocates nothing)."""
     torch = _torch()
     if X.dim() != 2 or X.stride(1) != 1:
         raise OemError(OEM_E_INVAL, "X must be a 2-D tensor with unit column stride")
@@ -248,8 +251,9 @@ def oem_gram(h, X, y, row_offset: int = 0, foldid=None, stream=None) -> None:
         raise OemError(OEM_E_INVAL, "X, y must be cuda tensors; y contiguous float64")
     if foldid is not None and not (foldid.is_cuda and foldid.dtype == torch.uint8):
         raise OemError(OEM_E_INVAL, "foldid must be a cuda uint8 tensor")
-    _check(load_library().oem_gram(h, _ptr(X), X.shape[0], X.stride(0), _ptr(y), row_offset,
-                                   _ptr(foldid), _stream(stream)))
+    fn = load_library().oem_gram_noalloc if noalloc else load_library().oem_gram
+    _check(fn(h, _ptr(X), X.shape[0], X.stride(0), _ptr(y), row_offset, _ptr(foldid),
+              _stream(stream)))
 
 
 def oem_gram_import(h, fold: int, XtX, Xty, yty: float, n: int, scaled: bool = True,
@@ -363,8 +367,8 @@ class Gram:
     def __del__(self):
         _finalize(self)
 
-    def add(self, X, y, row_offset: int = 0, foldid=None, stream=None):
-        oem_gram(self.h, X, y, row_offset, foldid, stream)
+    def add(self, X, y, row_offset: int = 0, foldid=None, stream=None, noalloc: bool = False):
+        oem_gram(self.h, X, y, row_offset, foldid, stream, noalloc)
         return self
 
     def export(self, stream=None):

@@ -5,6 +5,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <numeric>
 
 #include "gram_common.h"
@@ -310,6 +312,34 @@ int handle_reconfigure(oem_gram_s *h, int32_t p, int32_t K, int32_t prec, int32_
     return oem_gram_reset(h, s);
 }
 
+// ------------------------------------------------------------------ static workspace
+// Workspace of oem_gram_noalloc (row lists and partial sums of one pass):
+// a file-scope device array, so that entry point allocates nothing.  Each
+// device holds its own copy until the process ends.  In host code the
+// array's name is not a device address: its address on a device comes from
+// hipGetSymbolAddress, called once per device with that device current and
+// kept below; only that address is passed to kernels.
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) char scratch[kNoAllocScratchBytes];
+static std::mutex g_scratch_mu;
+static std::map<int, char *> g_scratch_addr;
+
+// Address of `scratch` on device `dev`, which must be the current device.
+static int noalloc_scratch(int dev, char **out)
+{
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_addr.find(dev);
+    if (it == g_scratch_addr.end()) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(OEM_E_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        it = g_scratch_addr.emplace(dev, static_cast<char *>(ptr)).first;
+    }
+    *out = it->second;
+    return OEM_OK;
+}
+
 } // namespace oem
 
 struct oem_batch_s {
@@ -349,7 +379,10 @@ int oem_gram_create(int32_t p, int32_t nfolds, int32_t precision, int32_t x_dtyp
         delete h;
         return fail(OEM_E_HIP, "hipGetDevice failed");
     }
-    int rc = handle_reconfigure(h, p, nfolds, precision, x_dtype, fold_seed, nullptr);
+    // the static workspace's address on this device, once per device
+    char *scratch_addr = nullptr;
+    int rc = noalloc_scratch(h->device, &scratch_addr);
+    if (rc == OEM_OK) rc = handle_reconfigure(h, p, nfolds, precision, x_dtype, fold_seed, nullptr);
     if (rc == OEM_OK) rc = (hipStreamSynchronize(nullptr) == hipSuccess) ? OEM_OK : OEM_E_HIP;
     if (rc) {
         oem_gram_free(h);
@@ -394,6 +427,37 @@ int oem_gram(oem_handle h, const void *X, int64_t n, int64_t ldx, const double *
     if (ldx < h->p) return fail(OEM_E_INVAL, "ldx must be >= p");
     if (row_offset < 0) return fail(OEM_E_INVAL, "row_offset must be >= 0");
     int rc = launch_gram(h, X, n, ldx, y, row_offset, foldid, as_stream(stream));
+    if (rc) return rc;
+    h->rows_seen += n;
+    h->derived_valid = false;
+    return OEM_OK;
+}
+
+int oem_gram_noalloc(oem_handle h, const void *X, int64_t n, int64_t ldx, const double *y,
+                     int64_t row_offset, const uint8_t *foldid, void *stream)
+{
+    if (!h) return fail(OEM_E_INVAL, "handle is NULL");
+    if (n < 0 || n > INT32_MAX) return fail(OEM_E_INVAL, "n must be in [0, 2^31 - 1]");
+    if (n == 0) return OEM_OK;
+    if (!X || !y) return fail(OEM_E_INVAL, "X and y must not be NULL");
+    if (ldx < h->p) return fail(OEM_E_INVAL, "ldx must be >= p");
+    if (row_offset < 0) return fail(OEM_E_INVAL, "row_offset must be >= 0");
+    int dev = 0;
+    OEM_HIP_CHECK(hipGetDevice(&dev));
+    if (dev != h->device) return fail(OEM_E_INVAL, "the handle belongs to another device");
+    const size_t need = gram_work_bytes(h, n);
+    if (need > kNoAllocScratchBytes)
+        return fail(OEM_E_INVAL, "a pass over " + std::to_string(n) + " rows needs " + std::to_string(need) +
+                                     " bytes of workspace, more than the " +
+                                     std::to_string(kNoAllocScratchBytes) +
+                                     "-byte static workspace; pass the rows in smaller blocks");
+    char *base = nullptr;
+    int rc = noalloc_scratch(dev, &base);
+    if (rc) return rc;
+    GramWork ws;
+    ws.base = base;
+    ws.bytes = kNoAllocScratchBytes;
+    rc = launch_gram(h, X, n, ldx, y, row_offset, foldid, as_stream(stream), &ws);
     if (rc) return rc;
     h->rows_seen += n;
     h->derived_valid = false;

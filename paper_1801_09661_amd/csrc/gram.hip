@@ -395,20 +395,37 @@ static int launch_f64_t(const GramGeom &g, bool list, bool vec, const XT *X, int
     return OEM_OK;
 }
 
-int launch_gram(oem_gram_s *h, const void *X, int64_t n, int64_t ldx, const double *y,
-                int64_t row_offset, const uint8_t *foldid, hipStream_t s)
+static size_t f64_partial_bytes(const GramGeom &g)
 {
-    if (h->prec != OEM_FP64) return launch_gram_bf16(h, X, n, ldx, y, row_offset, foldid, s);
+    const size_t parts = (size_t)g.K * g.nsplit;
+    return (parts * ((size_t)g.ntp * 256 + g.p + 2) + 8) * sizeof(double);
+}
+
+size_t gram_work_bytes(const oem_gram_s *h, int64_t n)
+{
+    if (h->prec != OEM_FP64) {
+        // same row-list plan as the BF16 pass (its geometry differs only in tiles)
+        return gram_bf16_work_bytes(h->prec, h->p, h->K, n);
+    }
+    const GramGeom g = plan_f64(h->prec, h->p, h->K, n);
+    return gram_carve_size(row_list_bytes(g, n)) + gram_carve_size(f64_partial_bytes(g));
+}
+
+int launch_gram(oem_gram_s *h, const void *X, int64_t n, int64_t ldx, const double *y,
+                int64_t row_offset, const uint8_t *foldid, hipStream_t s, GramWork *ws)
+{
+    if (h->prec != OEM_FP64) return launch_gram_bf16(h, X, n, ldx, y, row_offset, foldid, s, ws);
     const GramGeom g = plan_f64(h->prec, h->p, h->K, n);
     RowSource rs;
-    int rc = build_row_lists(h, g, n, row_offset, foldid, rs, s);
+    int rc = build_row_lists(h, g, n, row_offset, foldid, rs, s, ws);
     if (rc) return rc;
     const size_t K = g.K, S = g.nsplit;
     const size_t Et = (size_t)g.ntp * 256;
     const size_t parts = K * S;
-    rc = h->partial.ensure((parts * (Et + g.p + 2) + 8) * sizeof(double));
+    void *pbuf = nullptr;
+    rc = gram_buffer(h->partial, ws, f64_partial_bytes(g), &pbuf);
     if (rc) return rc;
-    double *part = h->partial.as<double>();
+    double *part = static_cast<double *>(pbuf);
     double *pvec = part + parts * Et;
     double *pscal = pvec + parts * g.p;
     const bool list = g.K > 1;

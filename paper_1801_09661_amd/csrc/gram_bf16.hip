@@ -475,22 +475,35 @@ static int launch_bf16_t(const GramGeom &g, bool list, bool vec, unsigned blocks
     return OEM_OK;
 }
 
+static size_t bf16_partial_bytes(const GramGeom &g)
+{
+    const size_t parts = (size_t)g.K * g.nsplit;
+    const size_t Et = (size_t)g.ntp * kBTile * kBTile;
+    return parts * Et * sizeof(float) + parts * (2 * g.p + 2) * sizeof(double) + 64;
+}
+
+size_t gram_bf16_work_bytes(int prec, int p, int K, int64_t n)
+{
+    const GramGeom g = plan_bf16(prec, p, K, n);
+    return gram_carve_size(row_list_bytes(g, n)) + gram_carve_size(bf16_partial_bytes(g));
+}
+
 int launch_gram_bf16(oem_gram_s *h, const void *Xv, int64_t n, int64_t ldx, const double *y,
-                     int64_t row_offset, const uint8_t *foldid, hipStream_t s)
+                     int64_t row_offset, const uint8_t *foldid, hipStream_t s, GramWork *ws)
 {
     if (h->xdt != OEM_X_F32) return fail(OEM_E_INVAL, "the BF16 Gram forms take FP32 X");
     const float *X = static_cast<const float *>(Xv);
     const GramGeom g = plan_bf16(h->prec, h->p, h->K, n);
     RowSource rs;
-    int rc = build_row_lists(h, g, n, row_offset, foldid, rs, s);
+    int rc = build_row_lists(h, g, n, row_offset, foldid, rs, s, ws);
     if (rc) return rc;
     const size_t S = g.nsplit, K = g.K;
     const size_t Et = (size_t)g.ntp * kBTile * kBTile;
     const size_t parts = K * S;
-    const size_t bytes = parts * Et * sizeof(float) + parts * (2 * g.p + 2) * sizeof(double) + 64;
-    rc = h->partial.ensure(bytes);
+    void *pbuf = nullptr;
+    rc = gram_buffer(h->partial, ws, bf16_partial_bytes(g), &pbuf);
     if (rc) return rc;
-    float *part = h->partial.as<float>();
+    float *part = static_cast<float *>(pbuf);
     double *pvec = reinterpret_cast<double *>(part + parts * Et);
     double *pscal = pvec + parts * 2 * g.p;
 

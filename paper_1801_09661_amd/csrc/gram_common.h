@@ -115,7 +115,16 @@ int gram_target(int prec, int K, int p, int64_t n);
 void gram_set_target(int prec, int K, int p, int64_t n, int target);
 // Build per-(fold, split) ordered row lists for rows 0..n-1.
 int build_row_lists(oem_gram_s *h, const GramGeom &g, int64_t n, int64_t row_offset,
-                    const uint8_t *foldid, RowSource &rs, hipStream_t s);
+                    const uint8_t *foldid, RowSource &rs, hipStream_t s, GramWork *ws);
+// Bytes of those row lists (0 with one fold).
+size_t row_list_bytes(const GramGeom &g, int64_t n);
+// A buffer of `bytes` for one pass: carved (256-byte aligned) from ws when it
+// has a base, else the handle's buffer `own`, grown as needed.
+int gram_buffer(DevBuf &own, GramWork *ws, size_t bytes, void **out);
+// Rounds a carved piece up to the carving alignment.
+inline size_t gram_carve_size(size_t bytes) { return (bytes + 255) & ~size_t(255); }
+// Partial-sum bytes of the BF16 forms' pass (gram_bf16.hip).
+size_t gram_bf16_work_bytes(int prec, int p, int K, int64_t n);
 
 // ---- split sums (device) ----
 // Workgroups of kFinishThreads threads finish a Gram pass: each owns 64

@@ -156,8 +156,35 @@ __global__ void fold_segments_kernel(const int64_t *__restrict__ off,
     seg_cnt[i] = empty ? 0 : (int32_t)(end - start);
 }
 
+size_t row_list_bytes(const GramGeom &g, int64_t n)
+{
+    if (g.K == 1) return 0;
+    const int nb = (int)((n + kListBlock - 1) / kListBlock);
+    const size_t entries = (size_t)g.K * nb;
+    const size_t segs = (size_t)g.K * g.nsplit;
+    return n * sizeof(int32_t) + entries * (sizeof(int32_t) + sizeof(int64_t)) +
+           segs * (sizeof(int64_t) + sizeof(int32_t)) + 64;
+}
+
+int gram_buffer(DevBuf &own, GramWork *ws, size_t bytes, void **out)
+{
+    if (!ws || !ws->base) {
+        int rc = own.ensure(bytes);
+        if (rc) return rc;
+        *out = own.ptr;
+        return OEM_OK;
+    }
+    const size_t need = ws->used + gram_carve_size(bytes);
+    if (need > ws->bytes)
+        return fail(OEM_E_INVAL, "the Gram pass needs " + std::to_string(need) +
+                                     " bytes of workspace; the limit is " + std::to_string(ws->bytes));
+    *out = ws->base + ws->used;
+    ws->used = need;
+    return OEM_OK;
+}
+
 int build_row_lists(oem_gram_s *h, const GramGeom &g, int64_t n, int64_t row_offset,
-                    const uint8_t *foldid, RowSource &rs, hipStream_t s)
+                    const uint8_t *foldid, RowSource &rs, hipStream_t s, GramWork *ws)
 {
     rs = RowSource{nullptr, nullptr, nullptr};
     if (g.K == 1) return OEM_OK;
@@ -167,11 +194,10 @@ int build_row_lists(oem_gram_s *h, const GramGeom &g, int64_t n, int64_t row_off
     const int bps = (int)(g.rows_per_split / kListBlock);
     const size_t entries = (size_t)g.K * nb;
     const size_t segs = (size_t)g.K * g.nsplit;
-    const size_t bytes = n * sizeof(int32_t) + entries * (sizeof(int32_t) + sizeof(int64_t)) +
-                         segs * (sizeof(int64_t) + sizeof(int32_t)) + 64;
-    int rc = h->rowlist.ensure(bytes);
+    void *buf = nullptr;
+    int rc = gram_buffer(h->rowlist, ws, row_list_bytes(g, n), &buf);
     if (rc) return rc;
-    char *base = static_cast<char *>(h->rowlist.ptr);
+    char *base = static_cast<char *>(buf);
     int64_t *off = reinterpret_cast<int64_t *>(base);
     int64_t *seg_off = off + entries;
     int32_t *counts = reinterpret_cast<int32_t *>(seg_off + segs);

@@ -163,10 +163,21 @@ int handle_reconfigure(oem_gram_s *h, int32_t p, int32_t K, int32_t prec, int32_
 int launch_fill_f64(double *p, size_t n, double v, hipStream_t s);
 int launch_fill_i64(int64_t *p, size_t n, int64_t v, hipStream_t s);
 int launch_scale_f64(double *p, size_t n, double v, hipStream_t s);
+// Device workspace of one Gram pass (row lists and partial sums).  With base
+// set, the pass carves its buffers from [base, base + bytes) and allocates
+// nothing; otherwise it grows the handle's own buffers.
+struct GramWork {
+    char *base = nullptr;
+    size_t bytes = 0;
+    size_t used = 0;
+};
 int launch_gram(oem_gram_s *g, const void *X, int64_t n, int64_t ldx, const double *y,
-                int64_t row_offset, const uint8_t *foldid, hipStream_t s);
+                int64_t row_offset, const uint8_t *foldid, hipStream_t s, GramWork *ws = nullptr);
 int launch_gram_bf16(oem_gram_s *g, const void *X, int64_t n, int64_t ldx, const double *y,
-                     int64_t row_offset, const uint8_t *foldid, hipStream_t s);
+                     int64_t row_offset, const uint8_t *foldid, hipStream_t s, GramWork *ws = nullptr);
+// Workspace bytes one Gram pass of the handle's shape over n rows carves
+// from a GramWork (the same plan as the pass itself).
+size_t gram_work_bytes(const oem_gram_s *h, int64_t n);
 int launch_combine(oem_gram_s *g, int standardize, hipStream_t s);
 int launch_lanczos(oem_gram_s *g, hipStream_t s);
 // Set on a thread whose Lanczos launches may run beside launches from other
