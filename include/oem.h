@@ -160,6 +160,26 @@ int oem_gram_reset(oem_handle g, void *stream);
 int oem_gram(oem_handle g, const void *X, int64_t n, int64_t ldx, const double *y,
              int64_t row_offset, const uint8_t *foldid, void *stream);
 
+/* Out-of-core pass (Section 5.7: data larger than memory, e.g. a memory-
+ * mapped file): the rows 0..n-1 of host-resident X (HOST pointer: ordinary,
+ * memory-mapped or pinned memory; n x p, row stride ldx >= p) and y (host,
+ * n FP64), with optional host fold ids, stream through two pinned staging
+ * slots and two device slots of chunk_rows rows each.  Packing a chunk on
+ * the CPU (skipped when X is pinned), its host-to-device copy on a copy
+ * stream of the handle and the Gram kernels of the previous chunk on
+ * `stream` overlap.  Each chunk is one accumulating pass with its global row
+ * offset (row_offset + its first row), so the sums are those of oem_gram
+ * called on the same blocks, and n may exceed 2^31 - 1.  Device memory: two
+ * chunks (chunk_rows (p sizeof(x) + 9) bytes each) plus the pass workspace,
+ * not n p.  Returns once every chunk has been copied (the host arrays are
+ * not read afterwards); the Gram kernels may still run on `stream`.  The
+ * first call (or a new chunk size) allocates the staging: pinned host and
+ * device memory, kept with the handle until oem_gram_free.
+ * Errors: as oem_gram; OEM_E_INVAL also when X, y or foldid is device memory
+ * or chunk_rows is not in [1, 2^31 - 1]; OEM_E_NOMEM. */
+int oem_gram_host(oem_handle g, const void *X, int64_t n, int64_t ldx, const double *y,
+                  int64_t row_offset, const uint8_t *foldid, int64_t chunk_rows, void *stream);
+
 /* oem_gram for callers that cannot allocate device memory: code under
  * hipGraph capture, request loops that must not call hipMalloc, harnesses
  * that forbid it.  Same arguments, sums and kernels as oem_gram; the pass's

@@ -39,7 +39,8 @@ EXPORTED = ["oem_gram_create", "oem_gram_free", "oem_gram_reset", "oem_gram", "o
             "oem_gram_export", "oem_fit_path", "oem_cv", "oem_gram_autotune", "oem_batch_create",
             "oem_batch_run", "oem_batch_run_graph", "oem_batch_status", "oem_batch_free",
             "oem_server_create", "oem_server_submit", "oem_server_poll", "oem_server_drain",
-            "oem_server_now", "oem_server_free", "oem_last_error", "oem_version", "oem_gram_noalloc"]
+            "oem_server_now", "oem_server_free", "oem_last_error", "oem_version", "oem_gram_noalloc",
+            "oem_gram_host"]
 
 
 class OemError(RuntimeError):
@@ -103,6 +104,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     L.oem_gram_reset.argtypes = [vp, vp]
     L.oem_gram.restype = C.c_int
     L.oem_gram.argtypes = [vp, vp, C.c_int64, C.c_int64, vp, C.c_int64, vp, vp]
+    L.oem_gram_host.restype = C.c_int
+    L.oem_gram_host.argtypes = [vp, vp, C.c_int64, C.c_int64, vp, C.c_int64, vp, C.c_int64, vp]
     L.oem_gram_noalloc.restype = C.c_int
     L.oem_gram_noalloc.argtypes = [vp, vp, C.c_int64, C.c_int64, vp, C.c_int64, vp, vp]
     L.oem_gram_import.restype = C.c_int
@@ -371,6 +374,12 @@ class Gram:
         oem_gram(self.h, X, y, row_offset, foldid, stream, noalloc)
         return self
 
+    def add_host(self, X, y, chunk_rows: int, row_offset: int = 0, foldid=None, stream=None):
+        """Out-of-core pass over host rows (numpy arrays, memory maps or pinned
+        tensors) streamed in chunks of chunk_rows rows."""
+        oem_gram_host(self.h, X, y, chunk_rows, row_offset, foldid, stream)
+        return self
+
     def export(self, stream=None):
         return oem_gram_export(self.h, self.p, self.nfolds, stream)
 
@@ -394,6 +403,30 @@ def cv(X, y, nfolds: int, fold_seed: int, penalties, precision: str = "fp64", fo
     with Gram(X.shape[1], nfolds, precision, X.dtype, fold_seed) as g:
         g.add(X, y, foldid=foldid)
         return g.cv(penalties, **kw)
+
+
+def _host_array(a, dtypes):
+    """(pointer, shape, row stride in elements) of a host array: a numpy array
+    or memory map, or a CPU (possibly pinned) torch tensor."""
+    if hasattr(a, "data_ptr"):       # the library itself rejects device memory
+        if str(a.dtype).replace("torch.", "") not in dtypes or a.stride(-1) != 1:
+            raise OemError(OEM_E_INVAL, "unsupported host tensor")
+        return a.data_ptr(), tuple(a.shape), (a.stride(0) if a.dim() == 2 else 1)
+    import numpy as np
+    if a.dtype.name not in dtypes or a.strides[-1] != a.itemsize:
+        raise OemError(OEM_E_INVAL, "unsupported host array")
+    return a.ctypes.data, a.shape, (a.strides[0] // a.itemsize if a.ndim == 2 else 1)
+
+
+def oem_gram_host(h, X, y, chunk_rows: int, row_offset: int = 0, foldid=None, stream=None) -> None:
+    """Out-of-core Gram pass over host-resident rows (oem_gram_host)."""
+    xp, xs, ldx = _host_array(X, ("float32", "float64"))
+    yp, ys, _ = _host_array(y, ("float64",))
+    if ys[0] != xs[0]:
+        raise OemError(OEM_E_INVAL, "X and y row counts differ")
+    fp = None if foldid is None else C.c_void_p(_host_array(foldid, ("uint8",))[0])
+    _check(load_library().oem_gram_host(h, C.c_void_p(xp), xs[0], ldx, C.c_void_p(yp), row_offset,
+                                        fp, chunk_rows, _stream(stream)))
 
 
 def oem_gram_autotune(h, X, y, stream=None) -> None:

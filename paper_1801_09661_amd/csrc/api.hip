@@ -396,6 +396,7 @@ void oem_gram_free(oem_handle h)
 {
     if (!h) return;
     (void)hipDeviceSynchronize();
+    free_host_stage(h);
     for (DevBuf *b : {&h->Gk, &h->bk, &h->yyk, &h->nk, &h->Gs, &h->cs, &h->sc, &h->yyn,
                       &h->dq, &h->ntrain, &h->lzsteps, &h->partial, &h->partial_n, &h->rowlist, &h->lanczos,
                       &h->paths, &h->order, &h->lam, &h->betaw, &h->groupbuf, &h->cvw, &h->flag, &h->pathws, &h->lzjobs})
@@ -431,6 +432,20 @@ int oem_gram(oem_handle h, const void *X, int64_t n, int64_t ldx, const double *
     h->rows_seen += n;
     h->derived_valid = false;
     return OEM_OK;
+}
+
+int oem_gram_host(oem_handle h, const void *X, int64_t n, int64_t ldx, const double *y,
+                  int64_t row_offset, const uint8_t *foldid, int64_t chunk_rows, void *stream)
+{
+    if (!h) return fail(OEM_E_INVAL, "handle is NULL");
+    if (n < 0) return fail(OEM_E_INVAL, "n must be >= 0");
+    if (n == 0) return OEM_OK;
+    if (!X || !y) return fail(OEM_E_INVAL, "X and y must not be NULL");
+    if (ldx < h->p) return fail(OEM_E_INVAL, "ldx must be >= p");
+    if (row_offset < 0) return fail(OEM_E_INVAL, "row_offset must be >= 0");
+    if (chunk_rows < 1 || chunk_rows > INT32_MAX) return fail(OEM_E_INVAL, "chunk_rows must be in [1, 2^31 - 1]");
+    if (h->prec != OEM_FP64 && h->xdt != OEM_X_F32) return fail(OEM_E_INVAL, "the BF16 Gram forms take FP32 X");
+    return gram_from_host(h, X, n, ldx, y, row_offset, foldid, chunk_rows, as_stream(stream));
 }
 
 int oem_gram_noalloc(oem_handle h, const void *X, int64_t n, int64_t ldx, const double *y,

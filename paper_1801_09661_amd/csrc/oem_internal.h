@@ -135,6 +135,8 @@ struct DevBuf {
     template <typename T> T *as() const { return static_cast<T *>(ptr); }
 };
 
+struct HostStage;   // staging of the out-of-core Gram pass (stream_host.hip)
+
 } // namespace oem
 
 struct oem_gram_s {
@@ -153,6 +155,7 @@ struct oem_gram_s {
     int64_t rows_seen = 0;
     // workspaces
     oem::DevBuf partial, partial_n, rowlist, lanczos, paths, order, lam, betaw, groupbuf, cvw, flag, pathws, lzjobs;
+    oem::HostStage *stage = nullptr;   // out-of-core staging, created on first use
 };
 
 namespace oem {
@@ -175,6 +178,11 @@ int launch_gram(oem_gram_s *g, const void *X, int64_t n, int64_t ldx, const doub
                 int64_t row_offset, const uint8_t *foldid, hipStream_t s, GramWork *ws = nullptr);
 int launch_gram_bf16(oem_gram_s *g, const void *X, int64_t n, int64_t ldx, const double *y,
                      int64_t row_offset, const uint8_t *foldid, hipStream_t s, GramWork *ws = nullptr);
+// Out-of-core pass: rows of host-resident X (pageable, memory-mapped or
+// pinned) streamed through pinned and device staging in chunks.
+int gram_from_host(oem_gram_s *h, const void *X, int64_t n, int64_t ldx, const double *y,
+                   int64_t row_offset, const uint8_t *foldid, int64_t chunk_rows, hipStream_t s);
+void free_host_stage(oem_gram_s *h);
 // Workspace bytes one Gram pass of the handle's shape over n rows carves
 // from a GramWork (the same plan as the pass itself).
 size_t gram_work_bytes(const oem_gram_s *h, int64_t n);
