@@ -112,7 +112,7 @@ def lib():
         L.oracle_heldout_mse.restype = C.c_int
         L.oracle_heldout_mse.argtypes = [vp, C.c_int32, C.c_int64, C.c_int64, C.c_int32, dp,
                                          C.c_int64, C.c_int32, C.c_uint64, u8p, C.c_int32,
-                                         C.c_int32, dp, dp]
+                                         C.c_int32, dp, dp, dp]
         _lib = L
     return _lib
 
@@ -310,7 +310,7 @@ def kkt(Gs, cs, pen: Penalty, lam, beta, groups=None, w=None, cg=None) -> float:
 
 
 def heldout_mse(X, y, k: int, K: int, fold_seed: int, beta_orig: np.ndarray, foldid=None,
-                row_offset: int = 0) -> np.ndarray:
+                row_offset: int = 0, beta0=None) -> np.ndarray:
     n, p = X.shape
     xp, isf64, ldx = _x(X)
     y = _f64(y); b = _f64(beta_orig)
@@ -319,7 +319,7 @@ def heldout_mse(X, y, k: int, K: int, fold_seed: int, beta_orig: np.ndarray, fol
     fid = None if foldid is None else np.ascontiguousarray(foldid, dtype=np.uint8)
     rc = lib().oracle_heldout_mse(xp, isf64, n, ldx, p, _d(y), row_offset, K,
                                   C.c_uint64(fold_seed & (2**64 - 1)), _u8(fid), k, L, _d(b),
-                                  _d(mse))
+                                  _d(_f64(beta0)), _d(mse))
     if rc != 0:
         raise ValueError("oracle_heldout_mse: empty fold or bad input")
     return mse
@@ -373,17 +373,38 @@ def fit_from_stats(st: dict, penalties, lambdas: np.ndarray, groups=None, w=None
     return res
 
 
+def centred(X, y, rows=None):
+    """X and y in FP64 with the means of the selected rows (all rows when
+    rows is None) subtracted: fitting an unpenalised intercept by its plain
+    definition.  Returns (Xc, yc, xbar, ybar)."""
+    X64 = np.asarray(X, dtype=np.float64)
+    y64 = np.asarray(y, dtype=np.float64)
+    sel = slice(None) if rows is None else rows
+    xbar = X64[sel].mean(axis=0)
+    ybar = float(y64[sel].mean())
+    return np.ascontiguousarray(X64 - xbar), y64 - ybar, xbar, ybar
+
+
 def fit(X, y, penalties: Sequence, groups=None, w=None, cg=None, nlambda=100,
-        lambda_min_ratio=1e-3, lambdas=None, tol=1e-10, maxit=100000, standardize=True) -> dict:
-    """Full-data OEM paths (the oem() call of Section 5.1)."""
+        lambda_min_ratio=1e-3, lambdas=None, tol=1e-10, maxit=100000, standardize=True,
+        intercept=False) -> dict:
+    """Full-data OEM paths (the oem() call of Section 5.1).  intercept: the
+    columns and y are centred first and beta0 = ybar - xbar^T beta."""
     penalties = [_as_pen(p) for p in penalties]
-    G, b, yy, n = gram_train(X, y, -1)
+    if intercept:
+        Xc, yc, xbar, ybar = centred(X, y)
+        G, b, yy, n = gram_train(Xc, yc, -1)
+    else:
+        G, b, yy, n = gram_train(X, y, -1)
     st = prepare(G, b, yy, n, standardize)
     if lambdas is None:
         lambdas = lambda_sequences(st["cs"], penalties, nlambda, lambda_min_ratio, groups, w, cg)
     res = fit_from_stats(st, penalties, np.asarray(lambdas, dtype=np.float64), groups, w, cg, tol,
                          maxit)
     res["stats"] = st
+    if intercept:
+        res["beta0"] = ybar - res["beta"] @ xbar
+        res["xbar"], res["ybar"] = xbar, ybar
     return res
 
 
@@ -407,21 +428,32 @@ def select(mse: np.ndarray, nk: np.ndarray) -> dict:
 
 def cv(X, y, K: int, fold_seed: int, penalties: Sequence, groups=None, w=None, cg=None,
        nlambda=100, lambda_min_ratio=1e-3, lambdas=None, tol=1e-10, maxit=100000,
-       standardize=True, foldid=None) -> dict:
-    """K-fold CV (Section 3): training Grams per fold, paths, held-out error."""
+       standardize=True, foldid=None, intercept=False) -> dict:
+    """K-fold CV (Section 3): training Grams per fold, paths, held-out error.
+    intercept: each fold's training rows are centred with their own means and
+    its held-out residuals are y - beta0 - x^T beta."""
     penalties = [_as_pen(p) for p in penalties]
     full = fit(X, y, penalties, groups, w, cg, nlambda, lambda_min_ratio, lambdas, tol, maxit,
-               standardize)
+               standardize, intercept)
     lam = full["lambda"]
     folds = []
     mse = np.zeros((len(penalties), K, lam.shape[1]))
     nk = np.zeros(K, dtype=np.int64)
+    fid = (np.ascontiguousarray(foldid, dtype=np.uint8) if foldid is not None
+           else fold_ids(fold_seed, X.shape[0], K))
     for k in range(K):
-        G, b, yy, nt = gram_train(X, y, k, K, fold_seed, foldid)
+        if intercept:
+            Xc, yc, xbar, ybar = centred(X, y, fid != k)
+            G, b, yy, nt = gram_train(Xc, yc, k, K, fold_seed, foldid)
+        else:
+            G, b, yy, nt = gram_train(X, y, k, K, fold_seed, foldid)
         st = prepare(G, b, yy, nt, standardize)
         r = fit_from_stats(st, penalties, lam, groups, w, cg, tol, maxit)
+        if intercept:
+            r["beta0"] = ybar - r["beta"] @ xbar
         for q in range(len(penalties)):
-            mse[q, k] = heldout_mse(X, y, k, K, fold_seed, r["beta"][q], foldid)
+            mse[q, k] = heldout_mse(X, y, k, K, fold_seed, r["beta"][q], foldid,
+                                    beta0=r["beta0"][q] if intercept else None)
         nk[k] = X.shape[0] - nt
         folds.append(r)
     sel = select(mse, nk)

@@ -787,7 +787,7 @@ int oracle_oem_steps(int32_t p, const double *Gs, const double *cs, double yyn, 
 int oracle_heldout_mse(const void *X, int32_t x_is_f64, int64_t n, int64_t ldx, int32_t p,
                        const double *y, int64_t row_offset, int32_t K, uint64_t fold_seed,
                        const uint8_t *foldid, int32_t k, int32_t L, const double *beta,
-                       double *mse)
+                       const double *beta0, double *mse)
 {
     if (p <= 0 || L < 1) return -1;
     int64_t nk = 0;
@@ -796,7 +796,7 @@ int oracle_heldout_mse(const void *X, int32_t x_is_f64, int64_t n, int64_t ldx, 
         if (row_fold(i, row_offset, K, fold_seed, foldid) != k) continue;
         ++nk;
         for (int32_t l = 0; l < L; ++l) {
-            double pred = 0.0;
+            double pred = beta0 ? beta0[l] : 0.0;
             for (int32_t j = 0; j < p; ++j) pred += x_at(X, x_is_f64, ldx, i, j) * beta[(size_t)l * p + j];
             double r = y[i] - pred;
             mse[l] += r * r;

@@ -129,11 +129,12 @@ double oracle_kkt(int32_t p, const double *Gs, const double *cs, const oracle_pe
 
 /* ---- cross validation (Section 3; outputs of Section 5.5) ----
  * Held-out mean squared error of fold k computed row by row:
- * mse[l] = sum_{i in k} (y_i - x_i^T beta_l)^2 / n_k, beta on original scale. */
+ * mse[l] = sum_{i in k} (y_i - beta0_l - x_i^T beta_l)^2 / n_k, beta on
+ * original scale; beta0 (L intercepts) may be NULL (no intercept). */
 int oracle_heldout_mse(const void *X, int32_t x_is_f64, int64_t n, int64_t ldx, int32_t p,
                        const double *y, int64_t row_offset, int32_t K, uint64_t fold_seed,
                        const uint8_t *foldid, int32_t k, int32_t L, const double *beta,
-                       double *mse);
+                       const double *beta0, double *mse);
 
 #ifdef __cplusplus
 }
