@@ -108,7 +108,8 @@ typedef struct {
                       every other kind */
 } oem_penalty;
 
-/* Options of a path fit.  Every pointer here is a HOST pointer. */
+/* Options of a path fit.  Every pointer here is a HOST pointer, except beta0
+ * (a device output). */
 typedef struct {
     int32_t nlambda;          /* L >= 1 values per penalty                        */
     double lambda_min_ratio;  /* lambda_L / lambda_1 in (0, 1] when lambda == NULL */
@@ -123,6 +124,20 @@ typedef struct {
     const double *cg;         /* ngroups group weights > 0, NULL = sqrt(size)     */
     int32_t sync;             /* 1: wait for the stream and return
                                  OEM_NOT_CONVERGED when some lambda hit maxit     */
+    int32_t intercept;        /* 1: unpenalised intercept.  The columns and y are
+                                 centred with the means of the rows fitted (the
+                                 training rows of a fold), from the column sums
+                                 the Gram pass accumulates: G/n - xbar xbar^T,
+                                 X^T y/n - xbar ybar, y^T y/n - ybar^2 (no
+                                 intercept in the model of Section 2.1; this is
+                                 the glmnet-style option).  Standardisation then
+                                 uses the centred column norms.  Cancellation:
+                                 relative accuracy of the centred Gram is about
+                                 1e-16 (xbar^2 / variance).  Not available after
+                                 oem_gram_import (no column sums).  0: none.     */
+    double *beta0;            /* DEVICE output npen x L: intercepts
+                                 ybar - xbar^T beta (original scale) of the
+                                 full-data or fold paths fitted; NULL allowed    */
 } oem_path_opts;
 
 typedef struct oem_gram_s *oem_handle;
@@ -208,6 +223,12 @@ int oem_gram_import(oem_handle g, int32_t fold, const double *XtX, const double 
 /* Copy the raw per-fold sums out: G (nfolds x p x p), b (nfolds x p), yy
  * (nfolds), nk (nfolds).  Device pointers; any may be NULL. */
 int oem_gram_export(oem_handle g, double *G, double *b, double *yy, int64_t *nk, void *stream);
+
+/* Copy the per-fold column sums sum_{i in k} x_i (nfolds x p) and sums of y
+ * (nfolds) out (device pointers, either may be NULL); the intercept option
+ * centres with them.  Errors: OEM_E_STATE after oem_gram_import (imported
+ * statistics carry no column sums). */
+int oem_gram_export_colsums(oem_handle g, double *colsum, double *ysum, void *stream);
 
 /* Warm-started OEM paths (Section 2.1 iteration, Section 2.2 updates) for
  * npen penalties (host array) on the full data (fold = -1) or on the rows

@@ -40,7 +40,7 @@ EXPORTED = ["oem_gram_create", "oem_gram_free", "oem_gram_reset", "oem_gram", "o
             "oem_batch_run", "oem_batch_run_graph", "oem_batch_status", "oem_batch_free",
             "oem_server_create", "oem_server_submit", "oem_server_poll", "oem_server_drain",
             "oem_server_now", "oem_server_free", "oem_last_error", "oem_version", "oem_gram_noalloc",
-            "oem_gram_host"]
+            "oem_gram_host", "oem_gram_export_colsums"]
 
 
 class OemError(RuntimeError):
@@ -59,7 +59,7 @@ class oem_path_opts(C.Structure):
                 ("lambda_", C.POINTER(C.c_double)), ("tol", C.c_double), ("maxit", C.c_int32),
                 ("standardize", C.c_int32), ("groups", C.POINTER(C.c_int32)),
                 ("w", C.POINTER(C.c_double)), ("cg", C.POINTER(C.c_double)),
-                ("sync", C.c_int32)]
+                ("sync", C.c_int32), ("intercept", C.c_int32), ("beta0", C.c_void_p)]
 
 
 class oem_problem(C.Structure):
@@ -112,6 +112,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     L.oem_gram_import.argtypes = [vp, C.c_int32, vp, vp, C.c_double, C.c_int64, C.c_int32, vp]
     L.oem_gram_export.restype = C.c_int
     L.oem_gram_export.argtypes = [vp, vp, vp, vp, vp, vp]
+    L.oem_gram_export_colsums.restype = C.c_int
+    L.oem_gram_export_colsums.argtypes = [vp, vp, vp, vp]
     L.oem_fit_path.restype = C.c_int
     L.oem_fit_path.argtypes = [vp, C.c_int32, C.POINTER(oem_penalty), C.c_int32,
                                C.POINTER(oem_path_opts), vp, vp, vp, vp, vp, vp, vp]
@@ -279,7 +281,7 @@ class _Opts:
     """Keeps the host arrays referenced by an oem_path_opts alive."""
 
     def __init__(self, nlambda, lambda_min_ratio, lambdas, tol, maxit, standardize, groups, w, cg,
-                 sync):
+                 sync, intercept=False, beta0=None):
         self.lam = None if lambdas is None else np.ascontiguousarray(lambdas, dtype=np.float64)
         self.groups = None if groups is None else np.ascontiguousarray(groups, dtype=np.int32)
         self.w = None if w is None else np.ascontiguousarray(w, dtype=np.float64)
@@ -289,20 +291,24 @@ class _Opts:
                                int(maxit), int(standardize),
                                None if self.groups is None else
                                self.groups.ctypes.data_as(C.POINTER(C.c_int32)),
-                               dp(self.w), dp(self.cg), int(sync))
+                               dp(self.w), dp(self.cg), int(sync), int(bool(intercept)),
+                               None if beta0 is None else beta0.data_ptr())
 
 
 def oem_fit_path(h, p: int, penalties: Sequence, fold: int = -1, nlambda: int = 100,
                  lambda_min_ratio: float = 1e-3, lambdas=None, tol: float = 1e-10,
                  maxit: int = 100000, standardize: bool = True, groups=None, w=None, cg=None,
-                 sync: bool = True, stream=None) -> dict:
-    """Warm-started OEM paths; returns cuda tensors and the status code."""
+                 sync: bool = True, stream=None, intercept: bool = False) -> dict:
+    """Warm-started OEM paths; returns cuda tensors and the status code
+    (with intercept=True also beta0, npen x L)."""
     torch = _torch()
     pens = _penalties(penalties)
     npen = len(pens)
     arr = (oem_penalty * npen)(*[q.c() for q in pens])
-    o = _Opts(nlambda, lambda_min_ratio, lambdas, tol, maxit, standardize, groups, w, cg, sync)
     f64 = dict(dtype=torch.float64, device="cuda")
+    beta0 = torch.empty((npen, nlambda), **f64) if intercept else None
+    o = _Opts(nlambda, lambda_min_ratio, lambdas, tol, maxit, standardize, groups, w, cg, sync,
+              intercept, beta0)
     beta = torch.empty((npen, nlambda, p), **f64)
     lam = torch.empty((npen, nlambda), **f64)
     iters = torch.empty((npen, nlambda), dtype=torch.int32, device="cuda")
@@ -312,20 +318,22 @@ def oem_fit_path(h, p: int, penalties: Sequence, fold: int = -1, nlambda: int = 
     rc = _check(load_library().oem_fit_path(h, fold, arr, npen, C.byref(o.c), _ptr(beta), _ptr(lam),
                                             _ptr(iters), _ptr(kkt), _ptr(obj), _ptr(d),
                                             _stream(stream)))
-    return dict(beta=beta, lambda_=lam, iters=iters, kkt=kkt, obj=obj, d=d, status=rc)
+    return dict(beta=beta, lambda_=lam, iters=iters, kkt=kkt, obj=obj, d=d, status=rc, beta0=beta0)
 
 
 def oem_cv(h, p: int, nfolds: int, penalties: Sequence, nlambda: int = 100,
            lambda_min_ratio: float = 1e-3, lambdas=None, tol: float = 1e-10, maxit: int = 100000,
            standardize: bool = True, groups=None, w=None, cg=None, sync: bool = True,
-           stream=None) -> dict:
+           stream=None, intercept: bool = False) -> dict:
     """K-fold cross validation from the fold statistics; cuda tensors out."""
     torch = _torch()
     pens = _penalties(penalties)
     npen = len(pens)
     arr = (oem_penalty * npen)(*[q.c() for q in pens])
-    o = _Opts(nlambda, lambda_min_ratio, lambdas, tol, maxit, standardize, groups, w, cg, sync)
     f64 = dict(dtype=torch.float64, device="cuda")
+    beta0 = torch.empty((npen, nlambda), **f64) if intercept else None
+    o = _Opts(nlambda, lambda_min_ratio, lambdas, tol, maxit, standardize, groups, w, cg, sync,
+              intercept, beta0)
     i32 = dict(dtype=torch.int32, device="cuda")
     beta_full = torch.empty((npen, nlambda, p), **f64)
     beta_folds = torch.empty((nfolds, npen, nlambda, p), **f64)
@@ -340,7 +348,7 @@ def oem_cv(h, p: int, nfolds: int, penalties: Sequence, nlambda: int = 100,
                                       _ptr(lam), _ptr(cvm), _ptr(cvsd), _ptr(i_min), _ptr(i_1se),
                                       _ptr(best), _ptr(iters), _stream(stream)))
     return dict(beta=beta_full, beta_folds=beta_folds, lambda_=lam, cvm=cvm, cvsd=cvsd,
-                i_min=i_min, i_1se=i_1se, best=best, iters=iters, status=rc)
+                i_min=i_min, i_1se=i_1se, best=best, iters=iters, status=rc, beta0=beta0)
 
 
 # ------------------------------------------------------------------ convenience
@@ -382,6 +390,14 @@ class Gram:
 
     def export(self, stream=None):
         return oem_gram_export(self.h, self.p, self.nfolds, stream)
+
+    def export_colsums(self, stream=None):
+        """(column sums nfolds x p, sums of y nfolds) as cuda tensors."""
+        torch = _torch()
+        cs = torch.empty((self.nfolds, self.p), dtype=torch.float64, device="cuda")
+        ys = torch.empty(self.nfolds, dtype=torch.float64, device="cuda")
+        _check(load_library().oem_gram_export_colsums(self.h, _ptr(cs), _ptr(ys), _stream(stream)))
+        return cs, ys
 
     def fit_path(self, penalties, fold: int = -1, **kw) -> dict:
         return oem_fit_path(self.h, self.p, penalties, fold=fold, **kw)

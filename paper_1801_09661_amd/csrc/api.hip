@@ -128,11 +128,13 @@ static int build_groups(oem_gram_s *h, const oem_path_opts *o, bool need_groups,
 
 // Combine, standardise and compute d for every problem, once per change of
 // the accumulated statistics; copies d and the row counts to the host.
-static int ensure_derived(oem_gram_s *h, int standardize, hipStream_t s)
+static int ensure_derived(oem_gram_s *h, int standardize, int intercept, hipStream_t s)
 {
-    if (h->derived_valid && h->derived_std == standardize) return OEM_OK;
+    if (h->derived_valid && h->derived_std == standardize && h->derived_icpt == intercept) return OEM_OK;
     if (h->rows_seen <= 0) return fail(OEM_E_STATE, "no rows accumulated");
-    int rc = launch_combine(h, standardize, s);
+    if (intercept && !h->colsums_known)
+        return fail(OEM_E_STATE, "an intercept needs the column sums, which imported statistics lack");
+    int rc = launch_combine(h, standardize, intercept, s);
     if (rc) return rc;
     rc = launch_lanczos(h, s);
     if (rc) return rc;
@@ -161,6 +163,7 @@ static int ensure_derived(oem_gram_s *h, int standardize, hipStream_t s)
     }
     h->derived_valid = true;
     h->derived_std = standardize;
+    h->derived_icpt = intercept;
     return OEM_OK;
 }
 
@@ -170,6 +173,7 @@ static int check_opts(const oem_path_opts *o)
     if (o->nlambda < 1) return fail(OEM_E_INVAL, "nlambda must be >= 1");
     if (o->maxit < 1) return fail(OEM_E_INVAL, "maxit must be >= 1");
     if (!(o->tol >= 0.0)) return fail(OEM_E_INVAL, "tol must be >= 0");
+    if (o->intercept != 0 && o->intercept != 1) return fail(OEM_E_INVAL, "intercept must be 0 or 1");
     if (!o->lambda && !(o->lambda_min_ratio > 0.0 && o->lambda_min_ratio <= 1.0))
         return fail(OEM_E_INVAL, "lambda_min_ratio must be in (0, 1]");
     return OEM_OK;
@@ -260,6 +264,9 @@ static PathDesc make_desc(oem_gram_s *h, int q, const oem_penalty &pn, const oem
     d.tau = pn.tau;
     d.tol = o->tol;
     d.maxit = o->maxit;
+    d.xbar = h->xbar.as<double>() + (size_t)q * h->p;
+    d.ybar = h->ybar.as<double>() + q;
+    d.beta0 = nullptr;
     return d;
 }
 
@@ -301,6 +308,10 @@ int handle_reconfigure(oem_gram_s *h, int32_t p, int32_t K, int32_t prec, int32_
     rc = rc ? rc : h->bk.ensure((size_t)K * p * sizeof(double));
     rc = rc ? rc : h->yyk.ensure((size_t)K * sizeof(double));
     rc = rc ? rc : h->nk.ensure((size_t)K * sizeof(int64_t));
+    rc = rc ? rc : h->csk.ensure((size_t)K * p * sizeof(double));
+    rc = rc ? rc : h->ysk.ensure((size_t)K * sizeof(double));
+    rc = rc ? rc : h->xbar.ensure(nq * p * sizeof(double));
+    rc = rc ? rc : h->ybar.ensure(nq * sizeof(double));
     rc = rc ? rc : h->Gs.ensure(nq * pp * sizeof(double));
     rc = rc ? rc : h->cs.ensure(nq * p * sizeof(double));
     rc = rc ? rc : h->sc.ensure(nq * p * sizeof(double));
@@ -397,7 +408,7 @@ void oem_gram_free(oem_handle h)
     if (!h) return;
     (void)hipDeviceSynchronize();
     free_host_stage(h);
-    for (DevBuf *b : {&h->Gk, &h->bk, &h->yyk, &h->nk, &h->Gs, &h->cs, &h->sc, &h->yyn,
+    for (DevBuf *b : {&h->Gk, &h->bk, &h->yyk, &h->nk, &h->csk, &h->ysk, &h->xbar, &h->ybar, &h->Gs, &h->cs, &h->sc, &h->yyn,
                       &h->dq, &h->ntrain, &h->lzsteps, &h->partial, &h->partial_n, &h->rowlist, &h->lanczos,
                       &h->paths, &h->order, &h->lam, &h->betaw, &h->groupbuf, &h->cvw, &h->flag, &h->pathws, &h->lzjobs})
         b->release();
@@ -413,7 +424,10 @@ int oem_gram_reset(oem_handle h, void *stream)
     rc = rc ? rc : launch_fill_f64(h->bk.as<double>(), K * h->p, 0.0, s);
     rc = rc ? rc : launch_fill_f64(h->yyk.as<double>(), K, 0.0, s);
     rc = rc ? rc : launch_fill_i64(h->nk.as<int64_t>(), K, 0, s);
+    rc = rc ? rc : launch_fill_f64(h->csk.as<double>(), K * h->p, 0.0, s);
+    rc = rc ? rc : launch_fill_f64(h->ysk.as<double>(), K, 0.0, s);
     h->derived_valid = false;
+    h->colsums_known = true;
     h->rows_seen = 0;
     return rc;
 }
@@ -502,6 +516,19 @@ int oem_gram_import(oem_handle h, int32_t fold, const double *XtX, const double 
     }
     h->rows_seen += n;
     h->derived_valid = false;
+    h->colsums_known = false;   // no column sums come with imported statistics
+    return OEM_OK;
+}
+
+int oem_gram_export_colsums(oem_handle h, double *colsum, double *ysum, void *stream)
+{
+    if (!h) return fail(OEM_E_INVAL, "handle is NULL");
+    if (!h->colsums_known) return fail(OEM_E_STATE, "imported statistics carry no column sums");
+    hipStream_t s = as_stream(stream);
+    const size_t K = h->K;
+    if (colsum)
+        OEM_HIP_CHECK(hipMemcpyAsync(colsum, h->csk.ptr, K * h->p * sizeof(double), hipMemcpyDeviceToDevice, s));
+    if (ysum) OEM_HIP_CHECK(hipMemcpyAsync(ysum, h->ysk.ptr, K * sizeof(double), hipMemcpyDeviceToDevice, s));
     return OEM_OK;
 }
 
@@ -529,7 +556,7 @@ int oem_fit_path(oem_handle h, int32_t fold, const oem_penalty *pen, int32_t npe
     if (fold < -1 || fold >= h->K || (h->K == 1 && fold != -1))
         return fail(OEM_E_INVAL, "fold out of range");
     hipStream_t s = as_stream(stream);
-    rc = ensure_derived(h, opts->standardize ? 1 : 0, s);
+    rc = ensure_derived(h, opts->standardize ? 1 : 0, opts->intercept, s);
     if (rc) return rc;
     const int q = (fold < 0) ? 0 : 1 + fold;
     if (h->n_host[q] <= 0) return fail(OEM_E_INVAL, "the selected rows are empty");
@@ -556,12 +583,18 @@ int oem_fit_path(oem_handle h, int32_t fold, const oem_penalty *pen, int32_t npe
                                   beta + (size_t)i * L * h->p, it + (size_t)i * L,
                                   kkt ? kkt + (size_t)i * L : nullptr,
                                   obj ? obj + (size_t)i * L : nullptr));
+    if (opts->intercept && opts->beta0)
+        for (int i = 0; i < npen; ++i) descs[i].beta0 = opts->beta0 + (size_t)i * L;
     rc = attach_path_handover(descs, h->pathws);
     if (rc) return rc;
     rc = upload_descs(h, descs, s);
     if (rc) return rc;
     rc = launch_paths(h->paths.as<PathDesc>(), descs, h->order, s);
     if (rc) return rc;
+    if (opts->intercept && opts->beta0) {
+        rc = launch_intercepts(h->paths.as<PathDesc>(), (int)descs.size(), s);
+        if (rc) return rc;
+    }
     if (lambda)
         OEM_HIP_CHECK(hipMemcpyAsync(lambda, h->lam.ptr, nl * sizeof(double), hipMemcpyDeviceToDevice, s));
     if (d_out)
@@ -581,7 +614,7 @@ int oem_cv(oem_handle h, const oem_penalty *pen, int32_t npen, const oem_path_op
     int rc = check_opts(opts);
     if (rc) return rc;
     hipStream_t s = as_stream(stream);
-    rc = ensure_derived(h, opts->standardize ? 1 : 0, s);
+    rc = ensure_derived(h, opts->standardize ? 1 : 0, opts->intercept, s);
     if (rc) return rc;
     const int K = h->K, p = h->p, L = opts->nlambda;
     for (int q = 0; q <= K; ++q)
@@ -615,11 +648,14 @@ int oem_cv(oem_handle h, const oem_penalty *pen, int32_t npen, const oem_path_op
     rc = h->flag.ensure((size_t)(K + 1) * nl * sizeof(int32_t));
     if (rc) return rc;
     int32_t *it = iters ? iters : h->flag.as<int32_t>();
-    // scratch: per-fold MSE (npen x K x L), cvm/cvsd if not requested, selection
-    rc = h->cvw.ensure((nl * K + 2 * nl) * sizeof(double) + 4 * npen * sizeof(int32_t) + 64);
+    // scratch: per-fold MSE (npen x K x L), cvm/cvsd if not requested, the
+    // intercepts of the full data (npen x L) and of the folds (K x npen x L)
+    rc = h->cvw.ensure((nl * K + 2 * nl + nl + nl * K) * sizeof(double) + 64);
     if (rc) return rc;
     double *mse = h->cvw.as<double>();
     double *cvsd_w = cvsd ? cvsd : mse + nl * K;
+    double *b0_full = (opts->intercept && opts->beta0) ? opts->beta0 : mse + nl * K + 2 * nl;
+    double *b0_folds = mse + nl * K + 3 * nl;
     std::vector<PathDesc> descs;
     for (int q = 0; q <= K; ++q)
         for (int i = 0; i < npen; ++i) {
@@ -627,6 +663,9 @@ int oem_cv(oem_handle h, const oem_penalty *pen, int32_t npen, const oem_path_op
                                  : bf + ((size_t)(q - 1) * npen + i) * L * p;
             descs.push_back(make_desc(h, q, pen[i], opts, gp, h->lam.as<double>() + (size_t)i * L, b,
                                       it + ((size_t)q * npen + i) * L, nullptr, nullptr));
+            if (opts->intercept)
+                descs.back().beta0 = (q == 0) ? b0_full + (size_t)i * L
+                                              : b0_folds + ((size_t)(q - 1) * npen + i) * L;
         }
     rc = attach_path_handover(descs, h->pathws);
     if (rc) return rc;
@@ -634,7 +673,12 @@ int oem_cv(oem_handle h, const oem_penalty *pen, int32_t npen, const oem_path_op
     if (rc) return rc;
     rc = launch_paths(h->paths.as<PathDesc>(), descs, h->order, s);
     if (rc) return rc;
+    if (opts->intercept) {
+        rc = launch_intercepts(h->paths.as<PathDesc>(), (int)descs.size(), s);
+        if (rc) return rc;
+    }
     rc = launch_cv(h->Gk.as<double>(), h->bk.as<double>(), h->yyk.as<double>(), h->nk.as<int64_t>(),
+                   h->csk.as<double>(), h->ysk.as<double>(), opts->intercept ? b0_folds : nullptr,
                    K, p, npen, L, bf, mse, cvm, cvsd_w, i_min, i_1se, best, s);
     if (rc) return rc;
     if (lambda)
@@ -708,7 +752,7 @@ int oem_batch_run(oem_batch b, void *stream)
         const oem_problem &pr = b->probs[i];
         int rc = oem_gram_reset(h, stream);
         rc = rc ? rc : launch_gram(h, pr.X, pr.n, pr.ldx, pr.y, 0, nullptr, s);
-        rc = rc ? rc : launch_combine(h, 1, s);
+        rc = rc ? rc : launch_combine(h, 1, 0, s);
         if (rc) return rc;
     }
     int rc = launch_lanczos_jobs(b->jobs.as<LzJob>(), b->lz, s);
@@ -781,6 +825,7 @@ int oem_batch_create(const oem_problem *probs, int32_t nprob, int32_t precision,
     if (!opts->standardize) return fail(OEM_E_INVAL, "batched fits need standardize = 1");
     if (opts->groups || opts->lambda || opts->w || opts->cg)
         return fail(OEM_E_INVAL, "batched fits take no groups, weights or explicit lambda");
+    if (opts->intercept) return fail(OEM_E_INVAL, "batched fits take no intercept");
     for (int i = 0; i < npen; ++i) {
         if (group_penalty(pen[i].kind)) return fail(OEM_E_INVAL, "batched fits take no group penalty");
         rc = check_penalty(pen[i], 1.0);   // standardised: d >= 1

@@ -24,38 +24,53 @@ __device__ inline void problem_rows(int q, int K, int *skip)
     *skip = (q == 0) ? -1 : q - 1;
 }
 
-// phase 1: per problem, the scaled diagonal gives s; c, yy/n, n_q
-__global__ void combine_scale_kernel(int p, int K, int standardize, const double *__restrict__ Gk,
-                                     const double *__restrict__ bk,
-                                     const double *__restrict__ yyk,
-                                     const int64_t *__restrict__ nk, double *__restrict__ cs,
-                                     double *__restrict__ sc, double *__restrict__ yyn,
-                                     int64_t *__restrict__ ntrain)
+// phase 1: per problem, the scaled diagonal gives s; c, yy/n, n_q.  With an
+// intercept the problem's columns and y are centred with the means of its
+// rows (from the column sums): G/n - xbar xbar^T, X^T y/n - xbar ybar,
+// y^T y/n - ybar^2; the intercept itself is unpenalised and follows from
+// the solution as ybar - xbar^T beta.
+__global__ void combine_scale_kernel(int p, int K, int standardize, int intercept,
+                                     const double *__restrict__ Gk, const double *__restrict__ bk,
+                                     const double *__restrict__ yyk, const int64_t *__restrict__ nk,
+                                     const double *__restrict__ csk, const double *__restrict__ ysk,
+                                     double *__restrict__ cs, double *__restrict__ sc,
+                                     double *__restrict__ yyn, int64_t *__restrict__ ntrain,
+                                     double *__restrict__ xbar, double *__restrict__ ybar)
 {
     const int q = blockIdx.y;
     int skip;
     problem_rows(q, K, &skip);
     int64_t nq = 0;
-    double yy = 0.0;
+    double yy = 0.0, ys = 0.0;
     for (int c = 0; c < K; ++c) {
         if (c == skip) continue;
         nq += nk[c];
         yy += yyk[c];
+        ys += ysk[c];
     }
     const double dn = (double)nq;
+    const double ym = intercept ? ys / dn : 0.0;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-        yyn[q] = yy / dn;
+        yyn[q] = intercept ? yy / dn - ym * ym : yy / dn;
+        ybar[q] = ym;
         ntrain[q] = nq;
     }
     for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < p; j += gridDim.x * blockDim.x) {
-        double gjj = 0.0, bj = 0.0;
+        double gjj = 0.0, bj = 0.0, sj = 0.0;
         for (int c = 0; c < K; ++c) {
             if (c == skip) continue;
             gjj += Gk[(size_t)c * p * p + (size_t)j * p + j];
             bj += bk[(size_t)c * p + j];
+            sj += csk[(size_t)c * p + j];
         }
         gjj = gjj / dn;
-        const double cj = bj / dn;
+        double cj = bj / dn;
+        const double xm = intercept ? sj / dn : 0.0;
+        if (intercept) {
+            gjj -= xm * xm;
+            cj -= xm * ym;
+        }
+        xbar[(size_t)q * p + j] = xm;
         double s = 1.0;
         if (standardize) s = gjj > 0.0 ? sqrt(gjj) : 1.0;
         sc[(size_t)q * p + j] = s;
@@ -64,8 +79,8 @@ __global__ void combine_scale_kernel(int p, int K, int standardize, const double
 }
 
 // phase 2: Gs = (G / n) / (s_i s_j)
-__global__ void combine_gram_kernel(int p, int K, const double *__restrict__ Gk,
-                                    const int64_t *__restrict__ ntrain,
+__global__ void combine_gram_kernel(int p, int K, int intercept, const double *__restrict__ Gk,
+                                    const int64_t *__restrict__ ntrain, const double *__restrict__ xbar,
                                     const double *__restrict__ sc, double *__restrict__ Gs)
 {
     const int q = blockIdx.y;
@@ -82,24 +97,27 @@ __global__ void combine_gram_kernel(int p, int K, const double *__restrict__ Gk,
             v += Gk[(size_t)c * pp + e];
         }
         v = v / dn;
+        if (intercept) v -= xbar[(size_t)q * p + i] * xbar[(size_t)q * p + j];
         const double r = v / (sc[(size_t)q * p + i] * sc[(size_t)q * p + j]);
         Gs[(size_t)q * pp + e] = r;
     }
 }
 
-int launch_combine(oem_gram_s *h, int standardize, hipStream_t s)
+int launch_combine(oem_gram_s *h, int standardize, int intercept, hipStream_t s)
 {
     const int p = h->p, K = h->K, nq = (K == 1) ? 1 : K + 1;
     dim3 g1((p + 255) / 256, nq);
-    hipLaunchKernelGGL(combine_scale_kernel, g1, dim3(256), 0, s, p, K, standardize,
+    hipLaunchKernelGGL(combine_scale_kernel, g1, dim3(256), 0, s, p, K, standardize, intercept,
                        h->Gk.as<double>(), h->bk.as<double>(), h->yyk.as<double>(),
-                       h->nk.as<int64_t>(), h->cs.as<double>(), h->sc.as<double>(),
-                       h->yyn.as<double>(), h->ntrain.as<int64_t>());
+                       h->nk.as<int64_t>(), h->csk.as<double>(), h->ysk.as<double>(),
+                       h->cs.as<double>(), h->sc.as<double>(), h->yyn.as<double>(),
+                       h->ntrain.as<int64_t>(), h->xbar.as<double>(), h->ybar.as<double>());
     OEM_HIP_CHECK(hipGetLastError());
     const size_t pp = (size_t)p * p;
     dim3 g2((unsigned)std::min<size_t>((pp + 255) / 256, 2048), nq);
-    hipLaunchKernelGGL(combine_gram_kernel, g2, dim3(256), 0, s, p, K, h->Gk.as<double>(),
-                       h->ntrain.as<int64_t>(), h->sc.as<double>(), h->Gs.as<double>());
+    hipLaunchKernelGGL(combine_gram_kernel, g2, dim3(256), 0, s, p, K, intercept, h->Gk.as<double>(),
+                       h->ntrain.as<int64_t>(), h->xbar.as<double>(), h->sc.as<double>(),
+                       h->Gs.as<double>());
     OEM_HIP_CHECK(hipGetLastError());
     return OEM_OK;
 }

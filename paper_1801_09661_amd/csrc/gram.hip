@@ -146,6 +146,7 @@ __global__ __launch_bounds__(kGramThreads) void gram_f64_kernel(
     const int nchunks = (int)((count + kRows - 1) / kRows);
     const int colA = I * g.W * 16 + 4 * q4, colB = J * g.W * 16 + 4 * q4;
     double sxy[4] = {0.0, 0.0, 0.0, 0.0}, syy = 0.0;
+    double sx[4] = {0.0, 0.0, 0.0, 0.0}, sy = 0.0;   // column sums and sum of y
 
     XT xa[8][4], xb[8][4];
     double yv[8];
@@ -191,8 +192,12 @@ __global__ __launch_bounds__(kGramThreads) void gram_f64_kernel(
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
 #pragma unroll
-                for (int j = 0; j < 4; ++j) sxy[j] += (double)xa[e][j] * yv[e];
+                for (int j = 0; j < 4; ++j) {
+                    sxy[j] += (double)xa[e][j] * yv[e];
+                    sx[j] += (double)xa[e][j];
+                }
                 syy += yv[e] * yv[e];
+                sy += yv[e];
             }
         }
     };
@@ -239,49 +244,67 @@ __global__ __launch_bounds__(kGramThreads) void gram_f64_kernel(
             for (int r = 0; r < 4; ++r) dst[(4 * r + lane / 16) * 16 + (lane % 16)] = acc[t][r];
         }
     }
-    // X^T y and y^T y: the 8 row groups of a column combined in order
+    // X^T y, column sums, y^T y and sum y: the 8 row groups of a column
+    // combined in order; pvec = [part][xy p | colsum p], pscal = [part][yy, n, sum y]
     if (diag) {
-        double *vred = smem;   // 8 x kPanelCols + 8
+        double *vred = smem;   // 16 x kPanelCols + 16
 #pragma unroll
-        for (int j = 0; j < 4; ++j) vred[rg * kPanelCols + 4 * q4 + j] = sxy[j];
-        if (q4 == 0) vred[8 * kPanelCols + rg] = syy;
+        for (int j = 0; j < 4; ++j) {
+            vred[rg * kPanelCols + 4 * q4 + j] = sxy[j];
+            vred[8 * kPanelCols + rg * kPanelCols + 4 * q4 + j] = sx[j];
+        }
+        if (q4 == 0) {
+            vred[16 * kPanelCols + rg] = syy;
+            vred[16 * kPanelCols + 8 + rg] = sy;
+        }
         __syncthreads();
         if (threadIdx.x < kPanelCols) {
             const int col = I * g.W * 16 + threadIdx.x;
-            double b = 0.0;
-            for (int r = 0; r < 8; ++r) b += vred[r * kPanelCols + threadIdx.x];
-            if (col < g.p) pvec[part_id * g.p + col] = b;
+            double b = 0.0, c = 0.0;
+            for (int r = 0; r < 8; ++r) {
+                b += vred[r * kPanelCols + threadIdx.x];
+                c += vred[8 * kPanelCols + r * kPanelCols + threadIdx.x];
+            }
+            if (col < g.p) {
+                pvec[part_id * 2 * g.p + col] = b;
+                pvec[part_id * 2 * g.p + g.p + col] = c;
+            }
         }
         if (first_block && threadIdx.x == 0) {
-            double t = 0.0;
-            for (int r = 0; r < 8; ++r) t += vred[8 * kPanelCols + r];
-            pscal[part_id * 2] = t;
-            pscal[part_id * 2 + 1] = (double)count;
+            double t = 0.0, u = 0.0;
+            for (int r = 0; r < 8; ++r) {
+                t += vred[16 * kPanelCols + r];
+                u += vred[16 * kPanelCols + 8 + r];
+            }
+            pscal[part_id * 3] = t;
+            pscal[part_id * 3 + 1] = (double)count;
+            pscal[part_id * 3 + 2] = u;
         }
     }
 }
 
 // Finish the pass: sum each statistic over the row splits (fixed order) and
 // add it into the running sums: upper-triangle tile entries mirrored into the
-// lower triangle (G stays exactly symmetric), then X^T y, then y^T y and n.
-// Grid (statistic blocks of 64, folds).
+// lower triangle (G stays exactly symmetric), then X^T y and the column sums,
+// then y^T y, n and sum y.  Grid (statistic blocks of 64, folds).
 __global__ __launch_bounds__(kFinishThreads) void gram_f64_finish_kernel(
     GramGeom g, const double *__restrict__ tiles, const double *__restrict__ vec,
     const double *__restrict__ scal, double *__restrict__ Gk, double *__restrict__ bk,
-    double *__restrict__ yyk, int64_t *__restrict__ nk)
+    double *__restrict__ yyk, int64_t *__restrict__ nk, double *__restrict__ csk,
+    double *__restrict__ ysk)
 {
     __shared__ double red[kFinishThreads];
     const int p = g.p, S = g.nsplit, k = blockIdx.y;
     const size_t Et = (size_t)g.ntp * 256;
-    const size_t per_k = Et + p + 2;
+    const size_t per_k = Et + 2 * (size_t)p + 3;
     const size_t e = (size_t)blockIdx.x * kWave + threadIdx.x % kWave;
     double v = 0.0;
     if (e < Et)
         v = split_sum(tiles + (size_t)k * S * Et + e, Et, S);
-    else if (e < Et + p)
-        v = split_sum(vec + (size_t)k * S * p + (e - Et), (size_t)p, S);
+    else if (e < Et + 2 * (size_t)p)
+        v = split_sum(vec + (size_t)k * S * 2 * p + (e - Et), 2 * (size_t)p, S);
     else if (e < per_k)
-        v = split_sum(scal + (size_t)k * S * 2 + (e - Et - p), 2, S);
+        v = split_sum(scal + (size_t)k * S * 3 + (e - Et - 2 * p), 3, S);
     v = finish_combine(v, red);
     if (threadIdx.x >= kWave || e >= per_k) return;
     if (e < Et) {
@@ -298,10 +321,14 @@ __global__ __launch_bounds__(kFinishThreads) void gram_f64_finish_kernel(
         if (i != j) G[(size_t)j * p + i] += v;
     } else if (e < Et + p) {
         bk[(size_t)k * p + (e - Et)] += v;
-    } else if (e == Et + p) {
+    } else if (e < Et + 2 * (size_t)p) {
+        csk[(size_t)k * p + (e - Et - p)] += v;
+    } else if (e == Et + 2 * (size_t)p) {
         yyk[k] += v;
-    } else {
+    } else if (e == Et + 2 * (size_t)p + 1) {
         nk[k] += (int64_t)v;
+    } else {
+        ysk[k] += v;
     }
 }
 
@@ -383,7 +410,7 @@ static int launch_f64_t(const GramGeom &g, bool list, bool vec, const XT *X, int
 {
     const int npanels = (g.nsb == 1) ? 1 : 2;
     const size_t lds = std::max((size_t)npanels * kRows * panel_pitch<XT>() * sizeof(XT),
-                                (size_t)(8 * kPanelCols + 8) * sizeof(double));
+                                (size_t)(16 * kPanelCols + 16) * sizeof(double));
     const void *kern;
     if (list) kern = vec ? (const void *)gram_f64_kernel<XT, true, true> : (const void *)gram_f64_kernel<XT, true, false>;
     else kern = vec ? (const void *)gram_f64_kernel<XT, false, true> : (const void *)gram_f64_kernel<XT, false, false>;
@@ -398,7 +425,7 @@ static int launch_f64_t(const GramGeom &g, bool list, bool vec, const XT *X, int
 static size_t f64_partial_bytes(const GramGeom &g)
 {
     const size_t parts = (size_t)g.K * g.nsplit;
-    return (parts * ((size_t)g.ntp * 256 + g.p + 2) + 8) * sizeof(double);
+    return (parts * ((size_t)g.ntp * 256 + 2 * (size_t)g.p + 3) + 8) * sizeof(double);
 }
 
 size_t gram_work_bytes(const oem_gram_s *h, int64_t n)
@@ -427,7 +454,7 @@ int launch_gram(oem_gram_s *h, const void *X, int64_t n, int64_t ldx, const doub
     if (rc) return rc;
     double *part = static_cast<double *>(pbuf);
     double *pvec = part + parts * Et;
-    double *pscal = pvec + parts * g.p;
+    double *pscal = pvec + parts * 2 * g.p;
     const bool list = g.K > 1;
     if (h->xdt == OEM_X_F32) {
         const float *Xf = static_cast<const float *>(X);
@@ -439,10 +466,11 @@ int launch_gram(oem_gram_s *h, const void *X, int64_t n, int64_t ldx, const doub
         rc = launch_f64_t<double>(g, list, vec, Xd, n, ldx, y, rs, part, pvec, pscal, s);
     }
     if (rc) return rc;
-    const size_t per_k = Et + g.p + 2;
+    const size_t per_k = Et + 2 * (size_t)g.p + 3;
     const dim3 fgrid((unsigned)((per_k + kWave - 1) / kWave), (unsigned)K);
     hipLaunchKernelGGL(gram_f64_finish_kernel, fgrid, dim3(kFinishThreads), 0, s, g, part, pvec, pscal,
-                       h->Gk.as<double>(), h->bk.as<double>(), h->yyk.as<double>(), h->nk.as<int64_t>());
+                       h->Gk.as<double>(), h->bk.as<double>(), h->yyk.as<double>(), h->nk.as<int64_t>(),
+                       h->csk.as<double>(), h->ysk.as<double>());
     OEM_HIP_CHECK(hipGetLastError());
     return OEM_OK;
 }

@@ -186,6 +186,7 @@ __global__ __launch_bounds__(kBThreads) void gram_bf16_kernel(
     const int nchunks = (int)((count + kBRows - 1) / kBRows);
     const int colA = I * g.W * kBTile + 4 * q4, colB = J * g.W * kBTile + 4 * q4;
     double sd[4] = {0.0, 0.0, 0.0, 0.0}, sxy[4] = {0.0, 0.0, 0.0, 0.0}, syy = 0.0;
+    double sx[4] = {0.0, 0.0, 0.0, 0.0}, sy = 0.0;   // column sums and sum of y
 
     float xa[8][4], xb[8][4];
     double yv[8];
@@ -239,8 +240,10 @@ __global__ __launch_bounds__(kBThreads) void gram_bf16_kernel(
                     const double xd = (double)xa[e][j];
                     sd[j] += xd * xd;
                     sxy[j] += xd * yv[e];
+                    sx[j] += xd;
                 }
                 syy += yv[e] * yv[e];
+                sy += yv[e];
             }
         }
     };
@@ -346,60 +349,73 @@ __global__ __launch_bounds__(kBThreads) void gram_bf16_kernel(
         }
     }
 
-    // FP64 diagonal, X^T y, y^T y: the 8 row groups of a column are combined
-    // in order; pvec = [part][diag p | xy p], pscal = [part][yy, n]
+    // FP64 diagonal, X^T y, column sums, y^T y, sum y: the 8 row groups of a
+    // column are combined in order; pvec = [part][diag p | xy p | colsum p],
+    // pscal = [part][yy, n, sum y]
     if (DIAG) {
         double *vred = reinterpret_cast<double *>(smem_raw);
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             vred[rg * kBPanel + 4 * q4 + j] = sd[j];
             vred[8 * kBPanel + rg * kBPanel + 4 * q4 + j] = sxy[j];
+            vred[16 * kBPanel + rg * kBPanel + 4 * q4 + j] = sx[j];
         }
-        if (q4 == 0) vred[16 * kBPanel + rg] = syy;
+        if (q4 == 0) {
+            vred[24 * kBPanel + rg] = syy;
+            vred[24 * kBPanel + 8 + rg] = sy;
+        }
         __syncthreads();
         if (threadIdx.x < kBPanel) {
             const int col = I * g.W * kBTile + threadIdx.x;
-            double d = 0.0, b = 0.0;
+            double d = 0.0, b = 0.0, c = 0.0;
             for (int r = 0; r < 8; ++r) {
                 d += vred[r * kBPanel + threadIdx.x];
                 b += vred[8 * kBPanel + r * kBPanel + threadIdx.x];
+                c += vred[16 * kBPanel + r * kBPanel + threadIdx.x];
             }
             if (col < g.p) {
-                pvec[part_id * 2 * g.p + col] = d;
-                pvec[part_id * 2 * g.p + g.p + col] = b;
+                pvec[part_id * 3 * g.p + col] = d;
+                pvec[part_id * 3 * g.p + g.p + col] = b;
+                pvec[part_id * 3 * g.p + 2 * g.p + col] = c;
             }
         }
         if (first_block && threadIdx.x == 0) {
-            double t = 0.0;
-            for (int r = 0; r < 8; ++r) t += vred[16 * kBPanel + r];
-            pscal[part_id * 2] = t;
-            pscal[part_id * 2 + 1] = (double)count;
+            double t = 0.0, u = 0.0;
+            for (int r = 0; r < 8; ++r) {
+                t += vred[24 * kBPanel + r];
+                u += vred[24 * kBPanel + 8 + r];
+            }
+            pscal[part_id * 3] = t;
+            pscal[part_id * 3 + 1] = (double)count;
+            pscal[part_id * 3 + 2] = u;
         }
     }
 }
 
 // Finish the pass: sum each statistic over the row splits (fixed order) and
 // add it into the running sums: off-diagonal tile entries (upper triangle,
-// mirrored so G stays exactly symmetric), then the FP64 diagonal and X^T y,
-// then y^T y and n.  Grid (statistic blocks of 64, folds).
+// mirrored so G stays exactly symmetric), then the FP64 diagonal, X^T y and
+// the column sums, then y^T y, n and sum y.  Grid (statistic blocks of 64,
+// folds).
 __global__ __launch_bounds__(kFinishThreads) void gram_bf16_finish_kernel(
     GramGeom g, const float *__restrict__ tiles, const double *__restrict__ vec,
     const double *__restrict__ scal, double *__restrict__ Gk, double *__restrict__ bk,
-    double *__restrict__ yyk, int64_t *__restrict__ nk)
+    double *__restrict__ yyk, int64_t *__restrict__ nk, double *__restrict__ csk,
+    double *__restrict__ ysk)
 {
     __shared__ double red[kFinishThreads];
     const int p = g.p, S = g.nsplit, k = blockIdx.y;
     const size_t tile = kBTile * kBTile;
     const size_t Et = (size_t)g.ntp * tile;
-    const size_t per_k = Et + 2 * (size_t)p + 2;
+    const size_t per_k = Et + 3 * (size_t)p + 3;
     const size_t e = (size_t)blockIdx.x * kWave + threadIdx.x % kWave;
     double v = 0.0;
     if (e < Et)
         v = split_sum(tiles + (size_t)k * S * Et + e, Et, S);
-    else if (e < Et + 2 * (size_t)p)
-        v = split_sum(vec + (size_t)k * S * 2 * p + (e - Et), 2 * (size_t)p, S);
+    else if (e < Et + 3 * (size_t)p)
+        v = split_sum(vec + (size_t)k * S * 3 * p + (e - Et), 3 * (size_t)p, S);
     else if (e < per_k)
-        v = split_sum(scal + (size_t)k * S * 2 + (e - Et - 2 * p), 2, S);
+        v = split_sum(scal + (size_t)k * S * 3 + (e - Et - 3 * p), 3, S);
     v = finish_combine(v, red);
     if (threadIdx.x >= kWave || e >= per_k) return;
     double *G = Gk + (size_t)k * p * p;
@@ -414,14 +430,17 @@ __global__ __launch_bounds__(kFinishThreads) void gram_bf16_finish_kernel(
         if (i >= p || j >= p) return;
         G[(size_t)i * p + j] += v;
         G[(size_t)j * p + i] += v;
-    } else if (e < Et + 2 * (size_t)p) {
+    } else if (e < Et + 3 * (size_t)p) {
         const size_t c = e - Et;
         if (c < (size_t)p) G[c * p + c] += v;
-        else bk[(size_t)k * p + (c - p)] += v;
-    } else if (e == Et + 2 * (size_t)p) {
+        else if (c < 2 * (size_t)p) bk[(size_t)k * p + (c - p)] += v;
+        else csk[(size_t)k * p + (c - 2 * p)] += v;
+    } else if (e == Et + 3 * (size_t)p) {
         yyk[k] += v;
-    } else {
+    } else if (e == Et + 3 * (size_t)p + 1) {
         nk[k] += (int64_t)v;
+    } else {
+        ysk[k] += v;
     }
 }
 
@@ -453,7 +472,7 @@ static size_t bf16_lds_bytes(bool diag)
 {
     const int npanels = diag ? 2 : 4;
     const size_t panels = (size_t)npanels * kBPanel * kBRows * sizeof(__bf16);
-    const size_t red = std::max((size_t)2 * 1024 * sizeof(float), (size_t)(16 * kBPanel + 8) * sizeof(double));
+    const size_t red = std::max((size_t)2 * 1024 * sizeof(float), (size_t)(24 * kBPanel + 16) * sizeof(double));
     return std::max(panels, red);
 }
 
@@ -479,7 +498,7 @@ static size_t bf16_partial_bytes(const GramGeom &g)
 {
     const size_t parts = (size_t)g.K * g.nsplit;
     const size_t Et = (size_t)g.ntp * kBTile * kBTile;
-    return parts * Et * sizeof(float) + parts * (2 * g.p + 2) * sizeof(double) + 64;
+    return parts * Et * sizeof(float) + parts * (3 * (size_t)g.p + 3) * sizeof(double) + 64;
 }
 
 size_t gram_bf16_work_bytes(int prec, int p, int K, int64_t n)
@@ -505,7 +524,7 @@ int launch_gram_bf16(oem_gram_s *h, const void *Xv, int64_t n, int64_t ldx, cons
     if (rc) return rc;
     float *part = static_cast<float *>(pbuf);
     double *pvec = reinterpret_cast<double *>(part + parts * Et);
-    double *pscal = pvec + parts * 2 * g.p;
+    double *pscal = pvec + parts * 3 * g.p;
 
     const bool split = (h->prec == OEM_SPLIT_BF16);
     const bool list = g.K > 1;
@@ -520,10 +539,11 @@ int launch_gram_bf16(oem_gram_s *h, const void *Xv, int64_t n, int64_t ldx, cons
                    : launch_bf16_t<false, false>(g, list, vec, no, X, n, ldx, y, rs, part, pvec, pscal, s);
         if (rc) return rc;
     }
-    const size_t per_k = Et + 2 * (size_t)g.p + 2;
+    const size_t per_k = Et + 3 * (size_t)g.p + 3;
     const dim3 fgrid((unsigned)((per_k + kWave - 1) / kWave), (unsigned)K);
     hipLaunchKernelGGL(gram_bf16_finish_kernel, fgrid, dim3(kFinishThreads), 0, s, g, part, pvec, pscal,
-                       h->Gk.as<double>(), h->bk.as<double>(), h->yyk.as<double>(), h->nk.as<int64_t>());
+                       h->Gk.as<double>(), h->bk.as<double>(), h->yyk.as<double>(), h->nk.as<int64_t>(),
+                       h->csk.as<double>(), h->ysk.as<double>());
     OEM_HIP_CHECK(hipGetLastError());
     return OEM_OK;
 }

@@ -107,6 +107,11 @@ struct PathDesc {
     // coefficients of the lambda before it (p)
     int32_t *lstart;
     double *bws;
+    // intercept (centred problems): means of the problem's rows, and the
+    // output ybar - xbar^T beta per lambda (L), or null
+    const double *xbar;
+    const double *ybar;
+    double *beta0;
 };
 
 // ------------------------------------------------------------------ Lanczos jobs
@@ -145,10 +150,14 @@ struct oem_gram_s {
     int device = 0;
     // raw per-fold sums
     oem::DevBuf Gk, bk, yyk, nk;       // K p^2, K p, K, K (int64)
+    oem::DevBuf csk, ysk;              // column sums K p, sums of y K
+    bool colsums_known = true;         // false once a fold was imported without them
     // derived problems: q = 0 full data, q = 1 + k training rows of fold k
     oem::DevBuf Gs, cs, sc, yyn, dq, ntrain, lzsteps;  // (K+1) p^2, (K+1) p, ...
+    oem::DevBuf xbar, ybar;            // (K+1) p, K+1: means of the problem's rows (intercept)
     bool derived_valid = false;
     int derived_std = -1;
+    int derived_icpt = -1;
     std::vector<double> d_host;        // d per problem (valid with derived_valid)
     std::vector<int64_t> n_host;       // rows per problem
     std::vector<int32_t> lz_host;      // Lanczos steps (negative: not converged)
@@ -186,7 +195,7 @@ void free_host_stage(oem_gram_s *h);
 // Workspace bytes one Gram pass of the handle's shape over n rows carves
 // from a GramWork (the same plan as the pass itself).
 size_t gram_work_bytes(const oem_gram_s *h, int64_t n);
-int launch_combine(oem_gram_s *g, int standardize, hipStream_t s);
+int launch_combine(oem_gram_s *g, int standardize, int intercept, hipStream_t s);
 int launch_lanczos(oem_gram_s *g, hipStream_t s);
 // Set on a thread whose Lanczos launches may run beside launches from other
 // streams: every problem then uses one workgroup (no barrier across workgroups).
@@ -218,8 +227,11 @@ int attach_path_handover(std::vector<PathDesc> &descs, DevBuf &buf);
 int launch_paths_planned(const PathDesc *d_desc, const int *d_order, const PathPlan &plan,
                          hipStream_t s);
 int launch_cv(const double *Gk, const double *bk, const double *yyk, const int64_t *nk,
+              const double *csk, const double *ysk, const double *beta0_folds,
               int K, int p, int npen, int L, const double *beta_folds, double *mse,
               double *cvm, double *cvsd, int32_t *i_min, int32_t *i_1se, int32_t *best,
               hipStream_t s);
+// intercepts ybar - xbar^T beta of every path whose descriptor asks for them
+int launch_intercepts(const PathDesc *d_desc, int count, hipStream_t s);
 
 } // namespace oem

@@ -565,22 +565,61 @@ int launch_lambda_grid(const double *cs_full, int p, const int32_t *gstart, cons
     return OEM_OK;
 }
 
+// ---------------------------------------------------------------- intercepts
+
+// beta0_l = ybar - xbar^T beta_l (original scale), the unpenalised intercept
+// of a centred problem; one workgroup per path, sums in a fixed order.
+__global__ __launch_bounds__(kPathThreads) void intercept_kernel(const PathDesc *__restrict__ descs)
+{
+    __shared__ double red[kPathWaves];
+    const PathDesc P = descs[blockIdx.x];
+    if (!P.beta0) return;
+    const auto beta_g = gmem(P.beta);
+    const auto xbar_g = gmem(P.xbar);
+    const double ym = *gmem(P.ybar);
+    for (int l = 0; l < P.L; ++l) {
+        double acc = 0.0;
+        for (int i = threadIdx.x; i < P.p; i += kPathThreads) acc += xbar_g[i] * beta_g[(size_t)l * P.p + i];
+        acc = wave_sum(acc);
+        if (threadIdx.x % kWave == 0) red[threadIdx.x / kWave] = acc;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double t = 0.0;
+            for (int w = 0; w < kPathWaves; ++w) t += red[w];
+            gmem(P.beta0)[l] = ym - t;
+        }
+        __syncthreads();
+    }
+}
+
+int launch_intercepts(const PathDesc *d_desc, int count, hipStream_t s)
+{
+    if (count <= 0) return OEM_OK;
+    hipLaunchKernelGGL(intercept_kernel, dim3(count), dim3(kPathThreads), 0, s, d_desc);
+    OEM_HIP_CHECK(hipGetLastError());
+    return OEM_OK;
+}
+
 // ---------------------------------------------------------------- CV error
 
 // MSE_{k,l} = (yy_k - 2 beta^T b_k + beta^T G_k beta) / n_k from held-out
-// sums; one workgroup per (fold, penalty, lambda).
+// sums; with an intercept b0 the residual is y - b0 - x^T beta, which adds
+// n_k b0^2 - 2 b0 sum_k y + 2 b0 beta^T colsum_k.  One workgroup per (fold,
+// penalty, lambda).
 __global__ __launch_bounds__(kPathThreads) void cv_mse_kernel(
     const double *__restrict__ Gk, const double *__restrict__ bk, const double *__restrict__ yyk,
-    const int64_t *__restrict__ nk, int K, int p, int npen, int L,
+    const int64_t *__restrict__ nk, const double *__restrict__ csk, const double *__restrict__ ysk,
+    const double *__restrict__ beta0_folds, int K, int p, int npen, int L,
     const double *__restrict__ beta_folds, double *__restrict__ mse)
 {
-    __shared__ double red[2 * kPathWaves];
+    __shared__ double red[3 * kPathWaves];
     const int l = blockIdx.x % L;
     const int pen = (blockIdx.x / L) % npen;
     const int k = blockIdx.x / (L * npen);
-    const double *beta = beta_folds + (((size_t)k * npen + pen) * L + l) * p;
+    const size_t path_l = ((size_t)k * npen + pen) * L + l;
+    const double *beta = beta_folds + path_l * p;
     const double *G = Gk + (size_t)k * p * p;
-    double quad = 0.0, lin = 0.0;
+    double quad = 0.0, lin = 0.0, mix = 0.0;
     for (int i = threadIdx.x; i < p; i += kPathThreads) {
         double acc = 0.0;
         for (int j = 0; j < p; ++j) {
@@ -589,21 +628,30 @@ __global__ __launch_bounds__(kPathThreads) void cv_mse_kernel(
         }
         quad += beta[i] * acc;
         lin += beta[i] * bk[(size_t)k * p + i];
+        if (beta0_folds) mix += beta[i] * csk[(size_t)k * p + i];
     }
     quad = wave_sum(quad);
     lin = wave_sum(lin);
+    mix = wave_sum(mix);
     if (threadIdx.x % kWave == 0) {
         red[threadIdx.x / kWave] = quad;
         red[kPathWaves + threadIdx.x / kWave] = lin;
+        red[2 * kPathWaves + threadIdx.x / kWave] = mix;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        double q2 = 0.0, l2 = 0.0;
+        double q2 = 0.0, l2 = 0.0, m2 = 0.0;
         for (int w = 0; w < kPathWaves; ++w) {
             q2 += red[w];
             l2 += red[kPathWaves + w];
+            m2 += red[2 * kPathWaves + w];
         }
-        mse[((size_t)pen * K + k) * L + l] = (yyk[k] - 2.0 * l2 + q2) / (double)nk[k];
+        double sse = yyk[k] - 2.0 * l2 + q2;
+        if (beta0_folds) {
+            const double b0 = beta0_folds[path_l];
+            sse += (double)nk[k] * b0 * b0 - 2.0 * b0 * ysk[k] + 2.0 * b0 * m2;
+        }
+        mse[((size_t)pen * K + k) * L + l] = sse / (double)nk[k];
     }
 }
 
@@ -654,12 +702,13 @@ __global__ void cv_select_kernel(const double *__restrict__ mse, const int64_t *
     }
 }
 
-int launch_cv(const double *Gk, const double *bk, const double *yyk, const int64_t *nk, int K,
+int launch_cv(const double *Gk, const double *bk, const double *yyk, const int64_t *nk,
+              const double *csk, const double *ysk, const double *beta0_folds, int K,
               int p, int npen, int L, const double *beta_folds, double *mse, double *cvm,
               double *cvsd, int32_t *i_min, int32_t *i_1se, int32_t *best, hipStream_t s)
 {
     hipLaunchKernelGGL(cv_mse_kernel, dim3(K * npen * L), dim3(kPathThreads), 0, s, Gk, bk, yyk, nk,
-                       K, p, npen, L, beta_folds, mse);
+                       csk, ysk, beta0_folds, K, p, npen, L, beta_folds, mse);
     OEM_HIP_CHECK(hipGetLastError());
     hipLaunchKernelGGL(cv_select_kernel, dim3(1), dim3(256), 0, s, mse, nk, K, npen, L, cvm, cvsd,
                        i_min, i_1se, best);

@@ -199,6 +199,7 @@ int oem_server_create(int32_t nslots, int64_t device_bytes, int32_t precision,
     if (!opts || opts->nlambda < 1 || opts->maxit < 1 || !(opts->tol >= 0.0) ||
         !(opts->lambda_min_ratio > 0.0 && opts->lambda_min_ratio <= 1.0))
         return fail(OEM_E_INVAL, "bad path options");
+    if (opts->intercept || opts->beta0) return fail(OEM_E_INVAL, "server options take no intercept");
     if (opts->lambda || opts->groups || opts->w || opts->cg)
         return fail(OEM_E_INVAL, "server options take no lambda, groups or weights");
     oem_server_s *S = new oem_server_s();
