@@ -76,6 +76,9 @@ def lib():
         L.oracle_gram_folds.restype = C.c_int
         L.oracle_gram_folds.argtypes = [vp, C.c_int32, C.c_int64, C.c_int64, C.c_int32, dp,
                                         C.c_int64, C.c_int32, C.c_uint64, u8p, dp, dp, dp, i64p]
+        L.oracle_gram_csr.restype = C.c_int
+        L.oracle_gram_csr.argtypes = [i64p, ip, dp, C.c_int64, C.c_int32, dp, C.c_int64, C.c_int32,
+                                      C.c_uint64, u8p, dp, dp, dp, i64p]
         L.oracle_gram_train.restype = C.c_int
         L.oracle_gram_train.argtypes = [vp, C.c_int32, C.c_int64, C.c_int64, C.c_int32, dp,
                                         C.c_int64, C.c_int32, C.c_uint64, u8p, C.c_int32,
@@ -178,6 +181,26 @@ def gram_folds(X, y, K: int = 1, fold_seed: int = 0, foldid=None, row_offset: in
                                  _d(yy), nk.ctypes.data_as(C.POINTER(C.c_int64)))
     if rc != 0:
         raise ValueError("oracle_gram_folds rejected its input")
+    return G, b, yy, nk
+
+
+def gram_csr(rowptr, col, val, p: int, y, K: int = 1, fold_seed: int = 0, foldid=None,
+             row_offset: int = 0):
+    """Per-fold sums (G_k, b_k, yy_k, n_k) of sparse rows (CSR, FP64 values)."""
+    rp = np.ascontiguousarray(rowptr, dtype=np.int64)
+    ci = np.ascontiguousarray(col, dtype=np.int32)
+    v = np.ascontiguousarray(val, dtype=np.float64)
+    y = _f64(y)
+    n = len(rp) - 1
+    G = np.zeros((K, p, p)); b = np.zeros((K, p)); yy = np.zeros(K)
+    nk = np.zeros(K, dtype=np.int64)
+    fid = None if foldid is None else np.ascontiguousarray(foldid, dtype=np.uint8)
+    i64 = C.POINTER(C.c_int64)
+    rc = lib().oracle_gram_csr(rp.ctypes.data_as(i64), _i(ci), _d(v), n, p, _d(y), row_offset, K,
+                               C.c_uint64(fold_seed & (2**64 - 1)), _u8(fid), _d(G), _d(b), _d(yy),
+                               nk.ctypes.data_as(i64))
+    if rc != 0:
+        raise ValueError("oracle_gram_csr rejected its input")
     return G, b, yy, nk
 
 

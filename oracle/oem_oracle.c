@@ -82,6 +82,31 @@ int oracle_gram_folds(const void *X, int32_t x_is_f64, int64_t n, int64_t ldx, i
     return 0;
 }
 
+int oracle_gram_csr(const int64_t *rowptr, const int32_t *col, const double *val, int64_t n, int32_t p,
+                    const double *y, int64_t row_offset, int32_t K, uint64_t fold_seed,
+                    const uint8_t *foldid, double *G, double *b, double *yy, int64_t *nk)
+{
+    if (p <= 0 || K <= 0 || n < 0) return -1;
+    memset(G, 0, sizeof(double) * (size_t)K * p * p);
+    memset(b, 0, sizeof(double) * (size_t)K * p);
+    memset(yy, 0, sizeof(double) * (size_t)K);
+    memset(nk, 0, sizeof(int64_t) * (size_t)K);
+    for (int64_t i = 0; i < n; ++i) {
+        int32_t k = row_fold(i, row_offset, K, fold_seed, foldid);
+        if (k < 0 || k >= K || rowptr[i] > rowptr[i + 1]) return -1;
+        double *Gk = G + (size_t)k * p * p;
+        for (int64_t t = rowptr[i]; t < rowptr[i + 1]; ++t) {
+            if (col[t] < 0 || col[t] >= p) return -1;
+            for (int64_t u = rowptr[i]; u < rowptr[i + 1]; ++u)
+                Gk[(size_t)col[t] * p + col[u]] += val[t] * val[u];
+            b[(size_t)k * p + col[t]] += val[t] * y[i];
+        }
+        yy[k] += y[i] * y[i];
+        nk[k] += 1;
+    }
+    return 0;
+}
+
 int oracle_gram_train(const void *X, int32_t x_is_f64, int64_t n, int64_t ldx, int32_t p,
                       const double *y, int64_t row_offset, int32_t K, uint64_t fold_seed,
                       const uint8_t *foldid, int32_t k, double *G, double *b, double *yy,

@@ -55,6 +55,15 @@ int oracle_gram_folds(const void *X, int32_t x_is_f64, int64_t n, int64_t ldx, i
                       const double *y, int64_t row_offset, int32_t K, uint64_t fold_seed,
                       const uint8_t *foldid, double *G, double *b, double *yy, int64_t *nk);
 
+/* The same per-fold sums from sparse rows (Section 5.8) in compressed sparse
+ * row form: row i stores val[t] at column col[t] for t in [rowptr[i],
+ * rowptr[i + 1]); the products of every pair of stored entries of a row are
+ * added (repeated columns add).  Returns -1 for a column outside [0, p) or
+ * a decreasing rowptr. */
+int oracle_gram_csr(const int64_t *rowptr, const int32_t *col, const double *val, int64_t n, int32_t p,
+                    const double *y, int64_t row_offset, int32_t K, uint64_t fold_seed,
+                    const uint8_t *foldid, double *G, double *b, double *yy, int64_t *nk);
+
 /* Gram of the training rows of fold k directly (rows whose fold != k;
  * k = -1: every row).  One p x p output. */
 int oracle_gram_train(const void *X, int32_t x_is_f64, int64_t n, int64_t ldx, int32_t p,

@@ -241,6 +241,44 @@ def serving_response(req: Request, X: np.ndarray, seed_tag: int = 5):
     return y, b
 
 
+@dataclass
+class SparseProblem:
+    rowptr: np.ndarray     # n + 1 int64
+    col: np.ndarray        # nnz int32
+    val: np.ndarray        # nnz float64
+    y: np.ndarray          # n float64
+    p: int
+    beta: np.ndarray
+
+
+def sparse_rows(n: int = 100_000, p: int = 200, density: float = 0.01, seed_tag: int = 8,
+                dtype=np.float64, integer: bool = False) -> SparseProblem:
+    """Sparse design in compressed sparse row form, shaped like the paper's
+    sparse example (Section 5.8): round(density n p) positions drawn uniformly
+    without replacement, N(0, 1) values (integers in [-8, 8] with
+    integer=True), 15 nonzero coefficients U(-0.25, 0.25), y = X beta +
+    N(0, 3^2)."""
+    g = _rng(subseed(seed_tag, n, p))
+    nnz = int(round(density * n * p))
+    flat = np.sort(g.choice(n * p, size=nnz, replace=False))
+    rows, cols = flat // p, (flat % p).astype(np.int32)
+    if integer:
+        val = g.integers(-8, 9, size=nnz).astype(dtype)
+    else:
+        val = g.standard_normal(nnz).astype(dtype)
+    rowptr = np.zeros(n + 1, dtype=np.int64)
+    np.add.at(rowptr, rows + 1, 1)
+    rowptr = np.cumsum(rowptr)
+    beta = np.zeros(p)
+    beta[:15] = g.uniform(-0.25, 0.25, size=15)
+    xb = np.zeros(n)
+    np.add.at(xb, rows, val.astype(np.float64) * beta[cols])
+    y = xb + 3.0 * g.standard_normal(n)
+    if integer:
+        y = np.rint(y)
+    return SparseProblem(rowptr, cols, val, y, p, beta)
+
+
 def integer_rows(n: int, p: int, lo: int = -8, hi: int = 8, seed_tag: int = 6,
                  dtype=np.float32) -> np.ndarray:
     """Integer-valued X: every Gram product and partial sum is exact in FP32/BF16/FP64."""
