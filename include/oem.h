@@ -175,6 +175,23 @@ int oem_gram_reset(oem_handle g, void *stream);
 int oem_gram(oem_handle g, const void *X, int64_t n, int64_t ldx, const double *y,
              int64_t row_offset, const uint8_t *foldid, void *stream);
 
+/* One streaming pass over sparse rows (Section 5.8: sparse design
+ * matrices) in compressed sparse row form, FP64 Gram form only.  Row i
+ * (0 <= i < n) stores the entries t in [rowptr[i], rowptr[i + 1]) at
+ * columns colidx[t] with values values[t] (element type of the handle's
+ * x_dtype); columns outside [0, p) are ignored, repeated columns add.  Device
+ * pointers: rowptr (n + 1 int64), colidx and values (nnz), y (n), foldid
+ * (n, or NULL).  Each row block is densified in LDS and goes through the
+ * same matrix-core tiles as oem_gram, so the sums equal oem_gram's on the
+ * densified rows bit for bit; only the stored entries are read from memory.
+ * Entry ranges are clamped to [0, nnz), so a malformed rowptr gives
+ * meaningless sums but no out-of-range reads.  Accumulates like oem_gram.
+ * Errors: OEM_E_INVAL (NULL pointers, n or nnz negative, n > 2^31 - 1, a
+ * BF16 form), OEM_E_HIP. */
+int oem_gram_csr(oem_handle g, const int64_t *rowptr, const int32_t *colidx, const void *values,
+                 int64_t nnz, int64_t n, const double *y, int64_t row_offset, const uint8_t *foldid,
+                 void *stream);
+
 /* Out-of-core pass (Section 5.7: data larger than memory, e.g. a memory-
  * mapped file): the rows 0..n-1 of host-resident X (HOST pointer: ordinary,
  * memory-mapped or pinned memory; n x p, row stride ldx >= p) and y (host,

@@ -40,7 +40,7 @@ EXPORTED = ["oem_gram_create", "oem_gram_free", "oem_gram_reset", "oem_gram", "o
             "oem_batch_run", "oem_batch_run_graph", "oem_batch_status", "oem_batch_free",
             "oem_server_create", "oem_server_submit", "oem_server_poll", "oem_server_drain",
             "oem_server_now", "oem_server_free", "oem_last_error", "oem_version", "oem_gram_noalloc",
-            "oem_gram_host", "oem_gram_export_colsums"]
+            "oem_gram_host", "oem_gram_export_colsums", "oem_gram_csr"]
 
 
 class OemError(RuntimeError):
@@ -104,6 +104,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     L.oem_gram_reset.argtypes = [vp, vp]
     L.oem_gram.restype = C.c_int
     L.oem_gram.argtypes = [vp, vp, C.c_int64, C.c_int64, vp, C.c_int64, vp, vp]
+    L.oem_gram_csr.restype = C.c_int
+    L.oem_gram_csr.argtypes = [vp, vp, vp, vp, C.c_int64, C.c_int64, vp, C.c_int64, vp, vp]
     L.oem_gram_host.restype = C.c_int
     L.oem_gram_host.argtypes = [vp, vp, C.c_int64, C.c_int64, vp, C.c_int64, vp, C.c_int64, vp]
     L.oem_gram_noalloc.restype = C.c_int
@@ -380,6 +382,19 @@ class Gram:
 
     def add(self, X, y, row_offset: int = 0, foldid=None, stream=None, noalloc: bool = False):
         oem_gram(self.h, X, y, row_offset, foldid, stream, noalloc)
+        return self
+
+    def add_csr(self, rowptr, colidx, values, y, row_offset: int = 0, foldid=None, stream=None):
+        """Sparse rows in compressed sparse row form (cuda tensors: int64
+        rowptr, int32 colidx, values of the handle's element type)."""
+        torch = _torch()
+        if not (rowptr.is_cuda and rowptr.dtype == torch.int64 and colidx.dtype == torch.int32
+                and y.is_cuda and y.dtype == torch.float64):
+            raise OemError(OEM_E_INVAL, "rowptr int64, colidx int32, y float64 cuda tensors expected")
+        n = rowptr.numel() - 1
+        _check(load_library().oem_gram_csr(self.h, _ptr(rowptr), _ptr(colidx), _ptr(values),
+                                           values.numel(), n, _ptr(y), row_offset, _ptr(foldid),
+                                           _stream(stream)))
         return self
 
     def add_host(self, X, y, chunk_rows: int, row_offset: int = 0, foldid=None, stream=None):

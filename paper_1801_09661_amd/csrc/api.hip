@@ -448,6 +448,25 @@ int oem_gram(oem_handle h, const void *X, int64_t n, int64_t ldx, const double *
     return OEM_OK;
 }
 
+int oem_gram_csr(oem_handle h, const int64_t *rowptr, const int32_t *colidx, const void *values,
+                 int64_t nnz, int64_t n, const double *y, int64_t row_offset, const uint8_t *foldid,
+                 void *stream)
+{
+    if (!h) return fail(OEM_E_INVAL, "handle is NULL");
+    if (n < 0 || n > INT32_MAX) return fail(OEM_E_INVAL, "n must be in [0, 2^31 - 1]");
+    if (nnz < 0) return fail(OEM_E_INVAL, "nnz must be >= 0");
+    if (n == 0) return OEM_OK;
+    if (!rowptr || !y || (nnz > 0 && (!colidx || !values)))
+        return fail(OEM_E_INVAL, "rowptr, y (and colidx, values when nnz > 0) must not be NULL");
+    if (row_offset < 0) return fail(OEM_E_INVAL, "row_offset must be >= 0");
+    if (h->prec != OEM_FP64) return fail(OEM_E_INVAL, "sparse rows take the FP64 Gram form");
+    int rc = launch_gram_csr(h, rowptr, colidx, values, nnz, n, y, row_offset, foldid, as_stream(stream));
+    if (rc) return rc;
+    h->rows_seen += n;
+    h->derived_valid = false;
+    return OEM_OK;
+}
+
 int oem_gram_host(oem_handle h, const void *X, int64_t n, int64_t ldx, const double *y,
                   int64_t row_offset, const uint8_t *foldid, int64_t chunk_rows, void *stream)
 {

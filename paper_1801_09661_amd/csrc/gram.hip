@@ -76,6 +76,43 @@ __device__ inline void load_block64(XT (&x)[8][4], const XT *__restrict__ X, int
     }
 }
 
+// Rows of a sparse X in compressed sparse row form (Section 5.8): row r
+// stores entries t in [rowptr[r], rowptr[r + 1]) at columns col[t] with
+// values val[t].  Entry ranges are clamped to [0, nnz), so a malformed
+// rowptr cannot make a load leave the arrays.
+template <typename XT> struct CsrRows {
+    const int64_t *rowptr;
+    const int32_t *col;
+    const XT *val;
+    int64_t nnz;
+};
+
+// The same thread block as load_block64 from CSR rows: columns col .. col + 3
+// of the 8 rows, zero where a row stores no entry (repeated entries add).
+// Registers end up as in the dense loader for every column below p, so the
+// MFMA sums equal those of the densified rows bit for bit.
+template <typename XT>
+__device__ inline void load_block64_csr(XT (&x)[8][4], const CsrRows<XT> &A, int col, const int64_t (&row)[8])
+{
+#pragma unroll
+    for (int e = 0; e < 8; ++e)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) x[e][j] = XT(0);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        int64_t t0 = A.rowptr[row[e]], t1 = A.rowptr[row[e] + 1];
+        t0 = t0 < 0 ? 0 : (t0 > A.nnz ? A.nnz : t0);
+        t1 = t1 < t0 ? t0 : (t1 > A.nnz ? A.nnz : t1);
+        for (int64_t t = t0; t < t1; ++t) {
+            const int c = A.col[t] - col;
+            const XT v = A.val[t];
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (c == j) x[e][j] += v;
+        }
+    }
+}
+
 template <typename XT>
 __device__ inline void store_block64(const XT (&x)[8][4], XT *panel, int q, int rg)
 {
@@ -86,10 +123,11 @@ __device__ inline void store_block64(const XT (&x)[8][4], XT *panel, int q, int 
         for (int j = 0; j < 4; ++j) panel[(8 * rg + e) * PP + 4 * q + j] = x[e][j];
 }
 
-template <typename XT, bool LIST, bool VEC>
+template <typename XT, bool LIST, bool VEC, bool CSR>
 __global__ __launch_bounds__(kGramThreads) void gram_f64_kernel(
     const XT *__restrict__ X, int64_t n, int64_t ldx, const double *__restrict__ y, GramGeom g,
-    RowSource rs, double *__restrict__ partial, double *__restrict__ pvec, double *__restrict__ pscal)
+    RowSource rs, double *__restrict__ partial, double *__restrict__ pvec, double *__restrict__ pscal,
+    CsrRows<XT> csr)
 {
     constexpr int PP = panel_pitch<XT>();
     extern __shared__ double smem[];
@@ -164,8 +202,13 @@ __global__ __launch_bounds__(kGramThreads) void gram_f64_kernel(
             if constexpr (LIST) row[e] = nidx[e];
             else row[e] = first + min((int64_t)c * kRows + 8 * rg + e, count - 1);
         }
-        load_block64<XT, VEC>(xa, X, ldx, g.p, colA, row);
-        if (!diag) load_block64<XT, VEC>(xb, X, ldx, g.p, colB, row);
+        if constexpr (CSR) {
+            load_block64_csr<XT>(xa, csr, colA, row);
+            if (!diag) load_block64_csr<XT>(xb, csr, colB, row);
+        } else {
+            load_block64<XT, VEC>(xa, X, ldx, g.p, colA, row);
+            if (!diag) load_block64<XT, VEC>(xb, X, ldx, g.p, colB, row);
+        }
         if (diag) {
 #pragma unroll
             for (int e = 0; e < 8; ++e) yv[e] = y[row[e]];
@@ -406,21 +449,38 @@ static GramGeom plan_f64(int prec, int p, int K, int64_t n)
 template <typename XT>
 static int launch_f64_t(const GramGeom &g, bool list, bool vec, const XT *X, int64_t n, int64_t ldx,
                         const double *y, const RowSource &rs, double *part, double *pvec, double *pscal,
-                        hipStream_t s)
+                        hipStream_t s, const CsrRows<XT> *csr = nullptr)
 {
     const int npanels = (g.nsb == 1) ? 1 : 2;
     const size_t lds = std::max((size_t)npanels * kRows * panel_pitch<XT>() * sizeof(XT),
                                 (size_t)(16 * kPanelCols + 16) * sizeof(double));
     const void *kern;
-    if (list) kern = vec ? (const void *)gram_f64_kernel<XT, true, true> : (const void *)gram_f64_kernel<XT, true, false>;
-    else kern = vec ? (const void *)gram_f64_kernel<XT, false, true> : (const void *)gram_f64_kernel<XT, false, false>;
+    if (csr) kern = list ? (const void *)gram_f64_kernel<XT, true, false, true>
+                         : (const void *)gram_f64_kernel<XT, false, false, true>;
+    else if (list) kern = vec ? (const void *)gram_f64_kernel<XT, true, true, false>
+                              : (const void *)gram_f64_kernel<XT, true, false, false>;
+    else kern = vec ? (const void *)gram_f64_kernel<XT, false, true, false>
+                    : (const void *)gram_f64_kernel<XT, false, false, false>;
     const unsigned blocks = (unsigned)(g.K * g.nsplit * g.npsb);
     OEM_HIP_CHECK(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    CsrRows<XT> cr = csr ? *csr : CsrRows<XT>{nullptr, nullptr, nullptr, 0};
     void *args[] = {(void *)&X, (void *)&n, (void *)&ldx, (void *)&y, (void *)&g, (void *)&rs,
-                    (void *)&part, (void *)&pvec, (void *)&pscal};
+                    (void *)&part, (void *)&pvec, (void *)&pscal, (void *)&cr};
     OEM_HIP_CHECK(hipLaunchKernel(kern, dim3(blocks), dim3(kGramThreads), args, lds, s));
     return OEM_OK;
 }
+
+// Sparse rows handed to a pass (values of the handle's element type).
+struct CsrIn {
+    const int64_t *rowptr;
+    const int32_t *col;
+    const void *val;
+    int64_t nnz;
+};
+
+static int launch_gram_any(oem_gram_s *h, const void *X, int64_t n, int64_t ldx, const double *y,
+                           int64_t row_offset, const uint8_t *foldid, hipStream_t s, GramWork *ws,
+                           const CsrIn *csr);
 
 static size_t f64_partial_bytes(const GramGeom &g)
 {
@@ -441,6 +501,21 @@ size_t gram_work_bytes(const oem_gram_s *h, int64_t n)
 int launch_gram(oem_gram_s *h, const void *X, int64_t n, int64_t ldx, const double *y,
                 int64_t row_offset, const uint8_t *foldid, hipStream_t s, GramWork *ws)
 {
+    return launch_gram_any(h, X, n, ldx, y, row_offset, foldid, s, ws, nullptr);
+}
+
+int launch_gram_csr(oem_gram_s *h, const int64_t *rowptr, const int32_t *col, const void *val, int64_t nnz,
+                    int64_t n, const double *y, int64_t row_offset, const uint8_t *foldid, hipStream_t s)
+{
+    if (h->prec != OEM_FP64) return fail(OEM_E_INVAL, "sparse rows take the FP64 Gram form");
+    const CsrIn in{rowptr, col, val, nnz};
+    return launch_gram_any(h, val, n, h->p, y, row_offset, foldid, s, nullptr, &in);
+}
+
+static int launch_gram_any(oem_gram_s *h, const void *X, int64_t n, int64_t ldx, const double *y,
+                           int64_t row_offset, const uint8_t *foldid, hipStream_t s, GramWork *ws,
+                           const CsrIn *csr)
+{
     if (h->prec != OEM_FP64) return launch_gram_bf16(h, X, n, ldx, y, row_offset, foldid, s, ws);
     const GramGeom g = plan_f64(h->prec, h->p, h->K, n);
     RowSource rs;
@@ -459,11 +534,15 @@ int launch_gram(oem_gram_s *h, const void *X, int64_t n, int64_t ldx, const doub
     if (h->xdt == OEM_X_F32) {
         const float *Xf = static_cast<const float *>(X);
         const bool vec = (reinterpret_cast<uintptr_t>(Xf) & 3) == 0;
-        rc = launch_f64_t<float>(g, list, vec, Xf, n, ldx, y, rs, part, pvec, pscal, s);
+        const CsrRows<float> cr = csr ? CsrRows<float>{csr->rowptr, csr->col, static_cast<const float *>(csr->val), csr->nnz}
+                                      : CsrRows<float>{};
+        rc = launch_f64_t<float>(g, list, vec, Xf, n, ldx, y, rs, part, pvec, pscal, s, csr ? &cr : nullptr);
     } else {
         const double *Xd = static_cast<const double *>(X);
         const bool vec = (reinterpret_cast<uintptr_t>(Xd) & 7) == 0;
-        rc = launch_f64_t<double>(g, list, vec, Xd, n, ldx, y, rs, part, pvec, pscal, s);
+        const CsrRows<double> cr = csr ? CsrRows<double>{csr->rowptr, csr->col, static_cast<const double *>(csr->val), csr->nnz}
+                                       : CsrRows<double>{};
+        rc = launch_f64_t<double>(g, list, vec, Xd, n, ldx, y, rs, part, pvec, pscal, s, csr ? &cr : nullptr);
     }
     if (rc) return rc;
     const size_t per_k = Et + 2 * (size_t)g.p + 3;

@@ -187,6 +187,9 @@ int launch_gram(oem_gram_s *g, const void *X, int64_t n, int64_t ldx, const doub
                 int64_t row_offset, const uint8_t *foldid, hipStream_t s, GramWork *ws = nullptr);
 int launch_gram_bf16(oem_gram_s *g, const void *X, int64_t n, int64_t ldx, const double *y,
                      int64_t row_offset, const uint8_t *foldid, hipStream_t s, GramWork *ws = nullptr);
+// Pass over sparse rows in compressed sparse row form (FP64 form only).
+int launch_gram_csr(oem_gram_s *h, const int64_t *rowptr, const int32_t *col, const void *val, int64_t nnz,
+                    int64_t n, const double *y, int64_t row_offset, const uint8_t *foldid, hipStream_t s);
 // Out-of-core pass: rows of host-resident X (pageable, memory-mapped or
 // pinned) streamed through pinned and device staging in chunks.
 int gram_from_host(oem_gram_s *h, const void *X, int64_t n, int64_t ldx, const double *y,
