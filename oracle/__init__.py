@@ -116,6 +116,14 @@ def lib():
         L.oracle_heldout_mse.argtypes = [vp, C.c_int32, C.c_int64, C.c_int64, C.c_int32, dp,
                                          C.c_int64, C.c_int32, C.c_uint64, u8p, C.c_int32,
                                          C.c_int32, dp, dp, dp]
+        L.oracle_logistic_path.restype = C.c_int
+        L.oracle_logistic_path.argtypes = [vp, C.c_int32, C.c_int64, C.c_int64, C.c_int32, dp, pp,
+                                           ip, C.c_int32, dp, dp, C.c_int32, dp, C.c_int32,
+                                           C.c_double, C.c_int32, C.c_double, C.c_int32, dp, ip,
+                                           dp, dp]
+        L.oracle_logistic_lambda_max.restype = C.c_double
+        L.oracle_logistic_lambda_max.argtypes = [vp, C.c_int32, C.c_int64, C.c_int64, C.c_int32, dp,
+                                                 pp, ip, C.c_int32, dp, dp]
         _lib = L
     return _lib
 
@@ -481,3 +489,39 @@ def cv(X, y, K: int, fold_seed: int, penalties: Sequence, groups=None, w=None, c
         folds.append(r)
     sel = select(mse, nk)
     return dict(full=full, folds=folds, mse=mse, nk=nk, **sel)
+
+
+def logistic_path(X, y, penalties: Sequence, groups=None, w=None, cg=None, nlambda=100,
+                  lambda_min_ratio=1e-3, lambdas=None, hessian_bound=False, tol=1e-10,
+                  maxit=100000, newton_tol=1e-10, newton_maxit=100) -> dict:
+    """Penalised logistic regression paths (Section 4): proximal Newton with
+    an OEM inner loop.  y in {0, 1}; no intercept."""
+    penalties = [_as_pen(p) for p in penalties]
+    n, p = X.shape
+    xp, isf64, ldx = _x(X)
+    y = _f64(y)
+    g, ng = _groups(groups, p)
+    if lambdas is None:
+        lambdas = np.zeros((len(penalties), nlambda))
+        for i, pen in enumerate(penalties):
+            pc = pen.c()
+            lm = float(lib().oracle_logistic_lambda_max(xp, isf64, n, ldx, p, _d(y), C.byref(pc),
+                                                        _i(g), ng, _d(_f64(w)), _d(_f64(cg))))
+            lambdas[i] = lambda_grid(lm, nlambda, lambda_min_ratio)
+    lambdas = np.ascontiguousarray(lambdas, dtype=np.float64)
+    L = lambdas.shape[1]
+    out = dict(beta=np.zeros((len(penalties), L, p)), newton=np.zeros((len(penalties), L), np.int32),
+               kkt=np.zeros((len(penalties), L)), obj=np.zeros((len(penalties), L)), lambda_=lambdas,
+               status=0)
+    for i, pen in enumerate(penalties):
+        pc = pen.c()
+        b = np.zeros((L, p)); it = np.zeros(L, dtype=np.int32); kk = np.zeros(L); ob = np.zeros(L)
+        rc = lib().oracle_logistic_path(xp, isf64, n, ldx, p, _d(y), C.byref(pc), _i(g), ng,
+                                        _d(_f64(w)), _d(_f64(cg)), L, _d(lambdas[i]),
+                                        int(bool(hessian_bound)), tol, maxit, newton_tol,
+                                        newton_maxit, _d(b), _i(it), _d(kk), _d(ob))
+        if rc < 0:
+            raise ValueError("oracle_logistic_path rejected its input")
+        out["beta"][i], out["newton"][i], out["kkt"][i], out["obj"][i] = b, it, kk, ob
+        out["status"] = max(out["status"], rc)
+    return out

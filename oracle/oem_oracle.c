@@ -836,3 +836,137 @@ void oracle_fold_ids(uint64_t seed, int64_t row_offset, int64_t n, int32_t K, ui
 {
     for (int64_t i = 0; i < n; ++i) out[i] = (uint8_t)oracle_fold_of_row(seed, row_offset + i, K);
 }
+
+/* ------------------------------------------------------------------------ */
+/* Penalised logistic regression (Section 4)                                  */
+/* ------------------------------------------------------------------------ */
+
+/* log(1 + exp(t)) without overflow */
+static double softplus(double t) { return t > 0.0 ? t + log1p(exp(-t)) : log1p(exp(t)); }
+
+int oracle_logistic_path(const void *X, int32_t x_is_f64, int64_t n, int64_t ldx, int32_t p,
+                         const double *y, const oracle_penalty *pen, const int32_t *groups,
+                         int32_t ngroups, const double *w, const double *cg, int32_t L,
+                         const double *lambda, int32_t hessian_bound, double tol, int32_t maxit,
+                         double newton_tol, int32_t newton_maxit, double *beta, int32_t *newton_iters,
+                         double *kkt, double *obj)
+{
+    if (p <= 0 || n <= 0 || L < 1 || maxit < 1 || newton_maxit < 1) return -1;
+    groupmap gm = {0, NULL, NULL};
+    if (is_group_kind(pen->kind) && (!groups || groupmap_build(p, groups, ngroups, &gm) != 0)) return -1;
+    size_t pp = (size_t)p * p;
+    double *s = (double *)calloc((size_t)p, sizeof(double));
+    double *H = (double *)malloc(sizeof(double) * pp);
+    double *c = (double *)malloc(sizeof(double) * (size_t)p);
+    double *bt = (double *)calloc((size_t)p, sizeof(double));   /* standardised coefficients */
+    double *prev = (double *)malloc(sizeof(double) * (size_t)p);
+    double *eta = (double *)malloc(sizeof(double) * (size_t)n);
+    double *wt = (double *)malloc(sizeof(double) * (size_t)n);
+    double *z = (double *)malloc(sizeof(double) * (size_t)n);
+    double *gr = (double *)malloc(sizeof(double) * (size_t)p);
+    scratch sc;
+    if (!s || !H || !c || !bt || !prev || !eta || !wt || !z || !gr || scratch_alloc(p, &sc) != 0) return -2;
+    /* fixed column scales: unit mean square of each column (Section 2.1) */
+    for (int64_t i = 0; i < n; ++i)
+        for (int32_t j = 0; j < p; ++j) {
+            double v = x_at(X, x_is_f64, ldx, i, j);
+            s[j] += v * v;
+        }
+    for (int32_t j = 0; j < p; ++j) s[j] = s[j] > 0.0 ? sqrt(s[j] / (double)n) : 1.0;
+    int status = 0;
+    double d = 0.0;
+    for (int32_t l = 0; l < L; ++l) {
+        int32_t t = 0, conv = 0;
+        while (t < newton_maxit) {
+            /* working weights and responses at the current coefficients */
+            for (int64_t i = 0; i < n; ++i) {
+                double e = 0.0;
+                for (int32_t j = 0; j < p; ++j) e += x_at(X, x_is_f64, ldx, i, j) * (bt[j] / s[j]);
+                double mu = 1.0 / (1.0 + exp(-e));
+                eta[i] = e;
+                wt[i] = hessian_bound ? 0.25 : mu * (1.0 - mu);
+                z[i] = e + (y[i] - mu) / wt[i];
+            }
+            /* weighted least-squares statistics, standardised */
+            if (!hessian_bound || t == 0 || d == 0.0) {
+                for (size_t e = 0; e < pp; ++e) H[e] = 0.0;
+                for (int64_t i = 0; i < n; ++i)
+                    for (int32_t a = 0; a < p; ++a) {
+                        double xa = x_at(X, x_is_f64, ldx, i, a) / s[a];
+                        for (int32_t b2 = 0; b2 < p; ++b2)
+                            H[(size_t)a * p + b2] += wt[i] * xa * (x_at(X, x_is_f64, ldx, i, b2) / s[b2]);
+                    }
+                for (size_t e = 0; e < pp; ++e) H[e] /= (double)n;
+                d = oracle_oem_d(p, H);
+            }
+            for (int32_t a = 0; a < p; ++a) c[a] = 0.0;
+            for (int64_t i = 0; i < n; ++i)
+                for (int32_t a = 0; a < p; ++a) c[a] += wt[i] * (x_at(X, x_is_f64, ldx, i, a) / s[a]) * z[i];
+            for (int32_t a = 0; a < p; ++a) c[a] /= (double)n;
+            /* inner OEM iterations on the quadratic model, from the current point */
+            memcpy(prev, bt, sizeof(double) * (size_t)p);
+            for (int32_t it = 0; it < maxit; ++it) {
+                double dl, mx;
+                oem_step(p, H, c, d, pen, &gm, w, cg, lambda[l], bt, sc.u, sc.bn, sc.tu, sc.to, &dl, &mx);
+                if (dl <= tol * mx) break;
+            }
+            ++t;
+            double dl = 0.0, mx = 0.0;
+            for (int32_t j = 0; j < p; ++j) {
+                if (fabs(bt[j] - prev[j]) > dl) dl = fabs(bt[j] - prev[j]);
+                if (fabs(bt[j]) > mx) mx = fabs(bt[j]);
+            }
+            if (dl <= newton_tol * mx) { conv = 1; break; }
+        }
+        if (!conv) status = 1;
+        if (newton_iters) newton_iters[l] = conv ? t : -t;
+        for (int32_t j = 0; j < p; ++j) beta[(size_t)l * p + j] = bt[j] / s[j];
+        /* objective and stationarity of the logistic problem at the result:
+         * gradient of the mean negative log-likelihood, -X~^T (y - mu) / n */
+        double loss = 0.0;
+        for (int32_t j = 0; j < p; ++j) gr[j] = 0.0;
+        for (int64_t i = 0; i < n; ++i) {
+            double e = 0.0;
+            for (int32_t j = 0; j < p; ++j) e += x_at(X, x_is_f64, ldx, i, j) * (bt[j] / s[j]);
+            double mu = 1.0 / (1.0 + exp(-e));
+            loss += softplus(e) - y[i] * e;
+            for (int32_t j = 0; j < p; ++j) gr[j] -= (x_at(X, x_is_f64, ldx, i, j) / s[j]) * (y[i] - mu);
+        }
+        for (int32_t j = 0; j < p; ++j) gr[j] /= (double)n;
+        if (obj) obj[l] = loss / (double)n + penalty_value(p, pen, &gm, w, cg, lambda[l], bt);
+        if (kkt) {
+            /* stationarity with Gs = 0 and cs = -gr: the same rules as kkt_gm */
+            double *zero = (double *)calloc(pp, sizeof(double));
+            for (int32_t j = 0; j < p; ++j) c[j] = -gr[j];
+            kkt[l] = kkt_gm(p, zero, c, pen, &gm, w, cg, lambda[l], bt);
+            free(zero);
+        }
+    }
+    free(s); free(H); free(c); free(bt); free(prev); free(eta); free(wt); free(z); free(gr);
+    scratch_free(&sc);
+    if (is_group_kind(pen->kind)) groupmap_free(&gm);
+    return status;
+}
+
+/* lambda_max of the logistic path: at beta = 0, mu = 1/2 and the working
+ * statistics give c~ = X~^T (y - 1/2) / n; the penalty's own zero test. */
+double oracle_logistic_lambda_max(const void *X, int32_t x_is_f64, int64_t n, int64_t ldx, int32_t p,
+                                  const double *y, const oracle_penalty *pen, const int32_t *groups,
+                                  int32_t ngroups, const double *w, const double *cg)
+{
+    double *s = (double *)calloc((size_t)p, sizeof(double));
+    double *c = (double *)calloc((size_t)p, sizeof(double));
+    for (int64_t i = 0; i < n; ++i)
+        for (int32_t j = 0; j < p; ++j) {
+            double v = x_at(X, x_is_f64, ldx, i, j);
+            s[j] += v * v;
+        }
+    for (int32_t j = 0; j < p; ++j) s[j] = s[j] > 0.0 ? sqrt(s[j] / (double)n) : 1.0;
+    for (int64_t i = 0; i < n; ++i)
+        for (int32_t j = 0; j < p; ++j) c[j] += (x_at(X, x_is_f64, ldx, i, j) / s[j]) * (y[i] - 0.5);
+    for (int32_t j = 0; j < p; ++j) c[j] /= (double)n;
+    double lm = oracle_lambda_max(p, c, pen, groups, ngroups, w, cg);
+    free(s);
+    free(c);
+    return lm;
+}

@@ -145,6 +145,32 @@ int oracle_heldout_mse(const void *X, int32_t x_is_f64, int64_t n, int64_t ldx, 
                        const uint8_t *foldid, int32_t k, int32_t L, const double *beta,
                        const double *beta0, double *mse);
 
+/* ---- penalised logistic regression (Section 4) ----
+ * y in {0, 1}, Pr(y = 1 | x) = 1 / (1 + exp(-x^T beta)), no intercept;
+ * minimise (1/n) sum_i [log(1 + exp(x_i^T beta)) - y_i x_i^T beta] +
+ * P_lambda(beta) (the printed log-likelihood's signs read as the standard
+ * ones).  Proximal Newton with OEM as the inner solver: at the current
+ * beta, w_i = mu_i (1 - mu_i) (hessian_bound: 1/4 for every i) and
+ * z_i = x_i^T beta + (y_i - mu_i) / w_i; the quadratic model
+ * (1/2n) sum w_i (z_i - x_i^T beta)^2 + P_lambda(beta) is minimised by OEM
+ * updates (tol, maxit) from the current point on the standardised weighted
+ * Gram with d = lambda_1 (1 + 1e-10); Newton steps repeat until max|delta
+ * beta| <= newton_tol max|beta|.  Columns are standardised once, to unit
+ * mean square.  Warm starts along lambda.  Outputs per lambda: beta (L x p,
+ * original scale), Newton steps (negated at newton_maxit), the logistic
+ * problem's stationarity violation and objective.  Returns 0, 1 when some
+ * lambda hit newton_maxit, < 0 on bad input. */
+int oracle_logistic_path(const void *X, int32_t x_is_f64, int64_t n, int64_t ldx, int32_t p,
+                         const double *y, const oracle_penalty *pen, const int32_t *groups,
+                         int32_t ngroups, const double *w, const double *cg, int32_t L,
+                         const double *lambda, int32_t hessian_bound, double tol, int32_t maxit,
+                         double newton_tol, int32_t newton_maxit, double *beta, int32_t *newton_iters,
+                         double *kkt, double *obj);
+/* lambda_max of that path: the penalty's zero level for c = X~^T (y - 1/2)/n. */
+double oracle_logistic_lambda_max(const void *X, int32_t x_is_f64, int64_t n, int64_t ldx, int32_t p,
+                                  const double *y, const oracle_penalty *pen, const int32_t *groups,
+                                  int32_t ngroups, const double *w, const double *cg);
+
 #ifdef __cplusplus
 }
 #endif

@@ -241,6 +241,21 @@ def serving_response(req: Request, X: np.ndarray, seed_tag: int = 5):
     return y, b
 
 
+def logistic(n: int = 1_000_000, p: int = 100, rho: float = 0.5, k: int = 10, scale: float = 0.5,
+             seed_tag: int = 9, dtype=np.float32) -> Problem:
+    """Binary responses for the logistic model of Section 4: AR(1) rows, k
+    nonzero coefficients +-U(0.5, 2) times `scale`, y_i ~ Bernoulli(1 / (1 +
+    exp(-x_i^T beta))) from seeded uniforms."""
+    X = draw_rows(n, p, rho, dtype, subseed(seed_tag, 0))
+    b = sparse_beta(p, min(k, p), subseed(seed_tag, 1)) * scale
+    eta = np.zeros(n)
+    for r0 in range(0, n, CHUNK_ROWS):
+        eta[r0:r0 + CHUNK_ROWS] = X[r0:r0 + CHUNK_ROWS].astype(np.float64) @ b
+    u = _rng(subseed(seed_tag, 2)).random(n)
+    y = (u < 1.0 / (1.0 + np.exp(-eta))).astype(np.float64)
+    return Problem(X, y, b, rho, meta=dict(workload="logistic", n=n, p=p))
+
+
 @dataclass
 class SparseProblem:
     rowptr: np.ndarray     # n + 1 int64
