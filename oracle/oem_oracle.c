@@ -890,12 +890,11 @@ int oracle_logistic_path(const void *X, int32_t x_is_f64, int64_t n, int64_t ldx
             /* weighted least-squares statistics, standardised */
             if (!hessian_bound || t == 0 || d == 0.0) {
                 for (size_t e = 0; e < pp; ++e) H[e] = 0.0;
-                for (int64_t i = 0; i < n; ++i)
-                    for (int32_t a = 0; a < p; ++a) {
-                        double xa = x_at(X, x_is_f64, ldx, i, a) / s[a];
-                        for (int32_t b2 = 0; b2 < p; ++b2)
-                            H[(size_t)a * p + b2] += wt[i] * xa * (x_at(X, x_is_f64, ldx, i, b2) / s[b2]);
-                    }
+                for (int64_t i = 0; i < n; ++i) {
+                    for (int32_t a = 0; a < p; ++a) gr[a] = x_at(X, x_is_f64, ldx, i, a) / s[a];  /* row i, standardised */
+                    for (int32_t a = 0; a < p; ++a)
+                        for (int32_t b2 = 0; b2 < p; ++b2) H[(size_t)a * p + b2] += wt[i] * gr[a] * gr[b2];
+                }
                 for (size_t e = 0; e < pp; ++e) H[e] /= (double)n;
                 d = oracle_oem_d(p, H);
             }
