@@ -306,6 +306,44 @@ int oem_cv(oem_handle g, const oem_penalty *pen, int32_t npen, const oem_path_op
 int oem_gram_autotune(oem_handle g, const void *X, int64_t n, int64_t ldx, const double *y,
                       void *stream);
 
+/* ------------------------------------------------------------------ logistic
+ * Penalised logistic regression (Section 4).  y_i in {0, 1}, Pr(y_i = 1) =
+ * 1 / (1 + exp(-x_i^T beta)), no intercept; minimise the mean negative
+ * log-likelihood (1/n) sum [log(1 + exp(x_i^T beta)) - y_i x_i^T beta] plus
+ * the penalty (the printed log-likelihood's signs read as the standard
+ * ones).  Proximal Newton (Friedman, Hastie & Tibshirani 2010) with OEM as
+ * the inner solver: at the current beta the working weights mu (1 - mu)
+ * (hessian_bound = 1: the bound 1/4 for every row, which keeps one Gram for
+ * the whole path and turns the steps into a majorise-minimise iteration)
+ * give the weighted least-squares model, minimised by OEM updates (opts tol
+ * and maxit) from the current point with d = lambda_1 (1 + 1e-10) of its
+ * standardised Hessian; Newton steps repeat until max|delta beta| <=
+ * newton_tol max|beta|.  Columns are standardised once to unit mean square
+ * (opts->standardize must be 1).  Warm starts along lambda; one grid per
+ * penalty from lambda_max of X~^T (y - 1/2) / n unless opts->lambda is set. */
+typedef struct {
+    int32_t hessian_bound;  /* 1: w_i = 1/4; 0: exact weights mu (1 - mu)   */
+    double newton_tol;      /* > 0                                          */
+    int32_t newton_maxit;   /* >= 1                                         */
+} oem_logistic_opts;
+
+/* Logistic paths for npen penalties on X (device, n x p, row stride ldx,
+ * element type x_dtype) and y (device, n values in {0, 1}).  Device outputs
+ * (NULL allowed except beta): beta npen x L x p (original scale), lambda
+ * npen x L, newton_iters npen x L (Newton steps; negative at newton_maxit),
+ * kkt npen x L (stationarity violation of the logistic problem), obj npen x
+ * L.  Waits for `stream` after every Newton step (the stopping test) and
+ * before returning.  Allocates its workspace (a handle's buffers and n + 512
+ * p doubles) for the call.  p <= 2048.  Not covered: intercept, CV (the
+ * fold-Gram shortcut of Section 3 does not apply), the BF16 forms.
+ * Errors: OEM_E_INVAL (shapes, options, penalties as oem_fit_path, MCP /
+ * SCAD conditions checked against d at every step), OEM_E_NOMEM, OEM_E_HIP;
+ * OEM_NOT_CONVERGED when some lambda hit newton_maxit (outputs valid). */
+int oem_logistic_path(const void *X, int32_t x_dtype, int64_t n, int64_t ldx, int32_t p, const double *y,
+                      const oem_penalty *pen, int32_t npen, const oem_path_opts *opts,
+                      const oem_logistic_opts *lopts, double *beta, double *lambda, int32_t *newton_iters,
+                      double *kkt, double *obj, void *stream);
+
 /* ------------------------------------------------------------------ batches
  * Many independent tall problems of uneven p fitted together (the same
  * penalties and path options for all).  Each problem is the full-data fit of

@@ -40,7 +40,8 @@ EXPORTED = ["oem_gram_create", "oem_gram_free", "oem_gram_reset", "oem_gram", "o
             "oem_batch_run", "oem_batch_run_graph", "oem_batch_status", "oem_batch_free",
             "oem_server_create", "oem_server_submit", "oem_server_poll", "oem_server_drain",
             "oem_server_now", "oem_server_free", "oem_last_error", "oem_version", "oem_gram_noalloc",
-            "oem_gram_host", "oem_gram_export_colsums", "oem_gram_csr"]
+            "oem_gram_host", "oem_gram_export_colsums", "oem_gram_csr",
+            "oem_logistic_path"]
 
 
 class OemError(RuntimeError):
@@ -52,6 +53,10 @@ class OemError(RuntimeError):
 class oem_penalty(C.Structure):
     _fields_ = [("kind", C.c_int32), ("alpha", C.c_double), ("gamma", C.c_double),
                 ("tau", C.c_double)]
+
+
+class oem_logistic_opts(C.Structure):
+    _fields_ = [("hessian_bound", C.c_int32), ("newton_tol", C.c_double), ("newton_maxit", C.c_int32)]
 
 
 class oem_path_opts(C.Structure):
@@ -104,6 +109,10 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     L.oem_gram_reset.argtypes = [vp, vp]
     L.oem_gram.restype = C.c_int
     L.oem_gram.argtypes = [vp, vp, C.c_int64, C.c_int64, vp, C.c_int64, vp, vp]
+    L.oem_logistic_path.restype = C.c_int
+    L.oem_logistic_path.argtypes = [vp, C.c_int32, C.c_int64, C.c_int64, C.c_int32, vp,
+                                    C.POINTER(oem_penalty), C.c_int32, C.POINTER(oem_path_opts),
+                                    C.POINTER(oem_logistic_opts), vp, vp, vp, vp, vp, vp]
     L.oem_gram_csr.restype = C.c_int
     L.oem_gram_csr.argtypes = [vp, vp, vp, vp, C.c_int64, C.c_int64, vp, C.c_int64, vp, vp]
     L.oem_gram_host.restype = C.c_int
@@ -354,6 +363,36 @@ def oem_cv(h, p: int, nfolds: int, penalties: Sequence, nlambda: int = 100,
 
 
 # ------------------------------------------------------------------ convenience
+
+def logistic_path(X, y, penalties, nlambda: int = 100, lambda_min_ratio: float = 1e-3, lambdas=None,
+                  tol: float = 1e-10, maxit: int = 100000, groups=None, w=None, cg=None,
+                  hessian_bound: bool = False, newton_tol: float = 1e-10, newton_maxit: int = 100,
+                  stream=None) -> dict:
+    """Penalised logistic regression paths (oem_logistic_path, Section 4) on
+    cuda tensors X (n x p, row-major) and y (n, float64, values 0 / 1)."""
+    torch = _torch()
+    if X.dim() != 2 or X.stride(1) != 1 or not X.is_cuda:
+        raise OemError(OEM_E_INVAL, "X must be a 2-D cuda tensor with unit column stride")
+    if not (y.is_cuda and y.dtype == torch.float64 and y.is_contiguous()):
+        raise OemError(OEM_E_INVAL, "y must be a contiguous float64 cuda tensor")
+    n, p = X.shape
+    pens = _penalties(penalties)
+    npen = len(pens)
+    arr = (oem_penalty * npen)(*[q.c() for q in pens])
+    o = _Opts(nlambda, lambda_min_ratio, lambdas, tol, maxit, True, groups, w, cg, False)
+    lo = oem_logistic_opts(int(bool(hessian_bound)), float(newton_tol), int(newton_maxit))
+    f64 = dict(dtype=torch.float64, device="cuda")
+    beta = torch.empty((npen, nlambda, p), **f64)
+    lam = torch.empty((npen, nlambda), **f64)
+    newton = torch.empty((npen, nlambda), dtype=torch.int32, device="cuda")
+    kkt = torch.empty((npen, nlambda), **f64)
+    obj = torch.empty((npen, nlambda), **f64)
+    xd = OEM_X_F64 if X.dtype == torch.float64 else OEM_X_F32
+    rc = _check(load_library().oem_logistic_path(_ptr(X), xd, n, X.stride(0), p, _ptr(y), arr, npen,
+                                                 C.byref(o.c), C.byref(lo), _ptr(beta), _ptr(lam),
+                                                 _ptr(newton), _ptr(kkt), _ptr(obj), _stream(stream)))
+    return dict(beta=beta, lambda_=lam, newton=newton, kkt=kkt, obj=obj, status=rc)
+
 
 class Gram:
     """Owning wrapper of a library handle (statistics of one data set)."""

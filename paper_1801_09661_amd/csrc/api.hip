@@ -448,6 +448,44 @@ int oem_gram(oem_handle h, const void *X, int64_t n, int64_t ldx, const double *
     return OEM_OK;
 }
 
+int oem_logistic_path(const void *X, int32_t x_dtype, int64_t n, int64_t ldx, int32_t p, const double *y,
+                      const oem_penalty *pen, int32_t npen, const oem_path_opts *opts,
+                      const oem_logistic_opts *lo, double *beta, double *lambda, int32_t *newton_iters,
+                      double *kkt, double *obj, void *stream)
+{
+    if (!X || !y || !beta) return fail(OEM_E_INVAL, "X, y and beta must not be NULL");
+    if (p < 1 || p > 2048) return fail(OEM_E_INVAL, "logistic paths take p in [1, 2048]");
+    if (n < 1 || n > INT32_MAX) return fail(OEM_E_INVAL, "n must be in [1, 2^31 - 1]");
+    if (ldx < p) return fail(OEM_E_INVAL, "ldx must be >= p");
+    if (x_dtype != OEM_X_F32 && x_dtype != OEM_X_F64) return fail(OEM_E_INVAL, "unknown x_dtype");
+    if (!pen || npen < 1) return fail(OEM_E_INVAL, "need at least one penalty");
+    int rc = check_opts(opts);
+    if (rc) return rc;
+    if (!lo || !(lo->newton_tol > 0.0) || lo->newton_maxit < 1)
+        return fail(OEM_E_INVAL, "logistic options: newton_tol > 0 and newton_maxit >= 1");
+    if (!opts->standardize || opts->intercept)
+        return fail(OEM_E_INVAL, "logistic paths standardise and fit no intercept");
+    bool need_groups = false;
+    for (int i = 0; i < npen; ++i) {
+        rc = check_penalty(pen[i], INFINITY);   // gamma d conditions are checked at every step
+        if (rc) return rc;
+        need_groups |= group_penalty(pen[i].kind);
+    }
+    hipStream_t s = as_stream(stream);
+    oem_handle h = nullptr;
+    rc = oem_gram_create(p, 1, OEM_FP64, x_dtype, 0, &h);
+    if (rc) return rc;
+    GroupPlan gp;
+    rc = build_groups(h, opts, need_groups, gp, s);
+    if (rc == OEM_OK)
+        rc = logistic_path(h, X, n, ldx, y, pen, npen, opts, lo, gp.d_gstart, gp.d_gidx, gp.ngroups, gp.d_w,
+                           gp.d_cg, beta, lambda, newton_iters, kkt, obj, s);
+    const std::string err = rc ? std::string(oem_last_error()) : std::string();
+    oem_gram_free(h);
+    if (rc) set_error(err);
+    return rc;
+}
+
 int oem_gram_csr(oem_handle h, const int64_t *rowptr, const int32_t *colidx, const void *values,
                  int64_t nnz, int64_t n, const double *y, int64_t row_offset, const uint8_t *foldid,
                  void *stream)

@@ -123,11 +123,13 @@ __device__ inline void store_block64(const XT (&x)[8][4], XT *panel, int q, int 
         for (int j = 0; j < 4; ++j) panel[(8 * rg + e) * PP + 4 * q + j] = x[e][j];
 }
 
-template <typename XT, bool LIST, bool VEC, bool CSR>
+// WGT: row weights w (n): the tiles accumulate sum_i w_i x_i x_i^T (the
+// weighted Gram of a Newton step, Section 4); the other sums stay unweighted.
+template <typename XT, bool LIST, bool VEC, bool CSR, bool WGT>
 __global__ __launch_bounds__(kGramThreads) void gram_f64_kernel(
     const XT *__restrict__ X, int64_t n, int64_t ldx, const double *__restrict__ y, GramGeom g,
     RowSource rs, double *__restrict__ partial, double *__restrict__ pvec, double *__restrict__ pscal,
-    CsrRows<XT> csr)
+    CsrRows<XT> csr, const double *__restrict__ wts)
 {
     constexpr int PP = panel_pitch<XT>();
     extern __shared__ double smem[];
@@ -149,6 +151,8 @@ __global__ __launch_bounds__(kGramThreads) void gram_f64_kernel(
 
     XT *A = reinterpret_cast<XT *>(smem);
     XT *B = diag ? A : A + kRows * PP;
+    // row weights of the staged chunk (WGT), after the panels
+    double *wl = reinterpret_cast<double *>(A + (g.nsb == 1 ? 1 : 2) * kRows * PP);
 
     const int npairs = diag ? Wi * (Wi + 1) / 2 : Wi * Wj;
     int ta[kMaxSlots], tb[kMaxSlots];
@@ -188,6 +192,7 @@ __global__ __launch_bounds__(kGramThreads) void gram_f64_kernel(
 
     XT xa[8][4], xb[8][4];
     double yv[8];
+    double wv[8];
     int32_t nidx[8];
     auto load_index = [&](int c) {
         if constexpr (LIST) {
@@ -213,6 +218,10 @@ __global__ __launch_bounds__(kGramThreads) void gram_f64_kernel(
 #pragma unroll
             for (int e = 0; e < 8; ++e) yv[e] = y[row[e]];
         }
+        if constexpr (WGT) {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) wv[e] = wts[row[e]];
+        }
     };
     auto clear_tail = [&](int c) {
         const int64_t r0 = (int64_t)c * kRows + 8 * rg;
@@ -231,6 +240,12 @@ __global__ __launch_bounds__(kGramThreads) void gram_f64_kernel(
     auto stage_chunk = [&]() {
         store_block64<XT>(xa, A, q4, rg);
         if (!diag) store_block64<XT>(xb, B, q4, rg);
+        if constexpr (WGT) {
+            if (q4 == 0) {
+#pragma unroll
+                for (int e = 0; e < 8; ++e) wl[8 * rg + e] = wv[e];
+            }
+        }
         if (diag) {
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
@@ -251,7 +266,8 @@ __global__ __launch_bounds__(kGramThreads) void gram_f64_kernel(
 #pragma unroll
             for (int t = 0; t < kMaxSlots; ++t) {
                 if (t < nslots) {
-                    const double a = (double)A[r * PP + ta[t] * 16 + (lane % 16)];
+                    double a = (double)A[r * PP + ta[t] * 16 + (lane % 16)];
+                    if constexpr (WGT) a *= wl[r];
                     const double b = (double)B[r * PP + tb[t] * 16 + (lane % 16)];
                     acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[t], 0, 0, 0);
                 }
@@ -449,23 +465,25 @@ static GramGeom plan_f64(int prec, int p, int K, int64_t n)
 template <typename XT>
 static int launch_f64_t(const GramGeom &g, bool list, bool vec, const XT *X, int64_t n, int64_t ldx,
                         const double *y, const RowSource &rs, double *part, double *pvec, double *pscal,
-                        hipStream_t s, const CsrRows<XT> *csr = nullptr)
+                        hipStream_t s, const CsrRows<XT> *csr = nullptr, const double *wts = nullptr)
 {
     const int npanels = (g.nsb == 1) ? 1 : 2;
-    const size_t lds = std::max((size_t)npanels * kRows * panel_pitch<XT>() * sizeof(XT),
+    const size_t lds = std::max((size_t)npanels * kRows * panel_pitch<XT>() * sizeof(XT) + kRows * sizeof(double),
                                 (size_t)(16 * kPanelCols + 16) * sizeof(double));
     const void *kern;
-    if (csr) kern = list ? (const void *)gram_f64_kernel<XT, true, false, true>
-                         : (const void *)gram_f64_kernel<XT, false, false, true>;
-    else if (list) kern = vec ? (const void *)gram_f64_kernel<XT, true, true, false>
-                              : (const void *)gram_f64_kernel<XT, true, false, false>;
-    else kern = vec ? (const void *)gram_f64_kernel<XT, false, true, false>
-                    : (const void *)gram_f64_kernel<XT, false, false, false>;
+    if (wts) kern = vec ? (const void *)gram_f64_kernel<XT, false, true, false, true>
+                        : (const void *)gram_f64_kernel<XT, false, false, false, true>;
+    else if (csr) kern = list ? (const void *)gram_f64_kernel<XT, true, false, true, false>
+                              : (const void *)gram_f64_kernel<XT, false, false, true, false>;
+    else if (list) kern = vec ? (const void *)gram_f64_kernel<XT, true, true, false, false>
+                              : (const void *)gram_f64_kernel<XT, true, false, false, false>;
+    else kern = vec ? (const void *)gram_f64_kernel<XT, false, true, false, false>
+                    : (const void *)gram_f64_kernel<XT, false, false, false, false>;
     const unsigned blocks = (unsigned)(g.K * g.nsplit * g.npsb);
     OEM_HIP_CHECK(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     CsrRows<XT> cr = csr ? *csr : CsrRows<XT>{nullptr, nullptr, nullptr, 0};
     void *args[] = {(void *)&X, (void *)&n, (void *)&ldx, (void *)&y, (void *)&g, (void *)&rs,
-                    (void *)&part, (void *)&pvec, (void *)&pscal, (void *)&cr};
+                    (void *)&part, (void *)&pvec, (void *)&pscal, (void *)&cr, (void *)&wts};
     OEM_HIP_CHECK(hipLaunchKernel(kern, dim3(blocks), dim3(kGramThreads), args, lds, s));
     return OEM_OK;
 }
@@ -480,7 +498,7 @@ struct CsrIn {
 
 static int launch_gram_any(oem_gram_s *h, const void *X, int64_t n, int64_t ldx, const double *y,
                            int64_t row_offset, const uint8_t *foldid, hipStream_t s, GramWork *ws,
-                           const CsrIn *csr);
+                           const CsrIn *csr, const double *wts = nullptr);
 
 static size_t f64_partial_bytes(const GramGeom &g)
 {
@@ -512,9 +530,16 @@ int launch_gram_csr(oem_gram_s *h, const int64_t *rowptr, const int32_t *col, co
     return launch_gram_any(h, val, n, h->p, y, row_offset, foldid, s, nullptr, &in);
 }
 
+int launch_gram_weighted(oem_gram_s *h, const void *X, int64_t n, int64_t ldx, const double *y,
+                         const double *wts, hipStream_t s)
+{
+    if (h->prec != OEM_FP64 || h->K != 1) return fail(OEM_E_STATE, "the weighted Gram pass takes the FP64 form, one fold");
+    return launch_gram_any(h, X, n, ldx, y, 0, nullptr, s, nullptr, nullptr, wts);
+}
+
 static int launch_gram_any(oem_gram_s *h, const void *X, int64_t n, int64_t ldx, const double *y,
                            int64_t row_offset, const uint8_t *foldid, hipStream_t s, GramWork *ws,
-                           const CsrIn *csr)
+                           const CsrIn *csr, const double *wts)
 {
     if (h->prec != OEM_FP64) return launch_gram_bf16(h, X, n, ldx, y, row_offset, foldid, s, ws);
     const GramGeom g = plan_f64(h->prec, h->p, h->K, n);
@@ -536,13 +561,13 @@ static int launch_gram_any(oem_gram_s *h, const void *X, int64_t n, int64_t ldx,
         const bool vec = (reinterpret_cast<uintptr_t>(Xf) & 3) == 0;
         const CsrRows<float> cr = csr ? CsrRows<float>{csr->rowptr, csr->col, static_cast<const float *>(csr->val), csr->nnz}
                                       : CsrRows<float>{};
-        rc = launch_f64_t<float>(g, list, vec, Xf, n, ldx, y, rs, part, pvec, pscal, s, csr ? &cr : nullptr);
+        rc = launch_f64_t<float>(g, list, vec, Xf, n, ldx, y, rs, part, pvec, pscal, s, csr ? &cr : nullptr, wts);
     } else {
         const double *Xd = static_cast<const double *>(X);
         const bool vec = (reinterpret_cast<uintptr_t>(Xd) & 7) == 0;
         const CsrRows<double> cr = csr ? CsrRows<double>{csr->rowptr, csr->col, static_cast<const double *>(csr->val), csr->nnz}
                                        : CsrRows<double>{};
-        rc = launch_f64_t<double>(g, list, vec, Xd, n, ldx, y, rs, part, pvec, pscal, s, csr ? &cr : nullptr);
+        rc = launch_f64_t<double>(g, list, vec, Xd, n, ldx, y, rs, part, pvec, pscal, s, csr ? &cr : nullptr, wts);
     }
     if (rc) return rc;
     const size_t per_k = Et + 2 * (size_t)g.p + 3;

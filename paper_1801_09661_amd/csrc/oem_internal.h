@@ -112,6 +112,9 @@ struct PathDesc {
     const double *xbar;
     const double *ybar;
     double *beta0;
+    // warm start of the first lambda (standardised scale, p), or null for
+    // beta = 0; paths with a warm start run on the general kernel
+    const double *beta_init;
 };
 
 // ------------------------------------------------------------------ Lanczos jobs
@@ -187,6 +190,17 @@ int launch_gram(oem_gram_s *g, const void *X, int64_t n, int64_t ldx, const doub
                 int64_t row_offset, const uint8_t *foldid, hipStream_t s, GramWork *ws = nullptr);
 int launch_gram_bf16(oem_gram_s *g, const void *X, int64_t n, int64_t ldx, const double *y,
                      int64_t row_offset, const uint8_t *foldid, hipStream_t s, GramWork *ws = nullptr);
+// Weighted pass (FP64 form, one fold): the tiles accumulate sum_i w_i x_i x_i^T.
+int launch_gram_weighted(oem_gram_s *h, const void *X, int64_t n, int64_t ldx, const double *y,
+                         const double *wts, hipStream_t s);
+// Penalised logistic paths (Section 4) on the rows X (n x ldx, the handle's
+// element type), y in {0, 1}; the handle (p columns, one fold, FP64 form)
+// is the workspace of the Gram passes and of d.
+int logistic_path(oem_gram_s *h, const void *X, int64_t n, int64_t ldx, const double *y,
+                  const oem_penalty *pen, int npen, const oem_path_opts *o, const oem_logistic_opts *lo,
+                  const int32_t *d_gstart, const int32_t *d_gidx, int ngroups, const double *d_w,
+                  const double *d_cg, double *beta, double *lambda, int32_t *newton_iters, double *kkt,
+                  double *obj, hipStream_t s);
 // Pass over sparse rows in compressed sparse row form (FP64 form only).
 int launch_gram_csr(oem_gram_s *h, const int64_t *rowptr, const int32_t *col, const void *val, int64_t nnz,
                     int64_t n, const double *y, int64_t row_offset, const uint8_t *foldid, hipStream_t s);
@@ -234,6 +248,9 @@ int launch_cv(const double *Gk, const double *bk, const double *yyk, const int64
               int K, int p, int npen, int L, const double *beta_folds, double *mse,
               double *cvm, double *cvsd, int32_t *i_min, int32_t *i_1se, int32_t *best,
               hipStream_t s);
+// One path of the general kernel per descriptor d_desc[0 .. count) (no
+// order table), e.g. single-lambda solves from a warm start.
+int launch_paths_general(const PathDesc *d_desc, int count, int pmax, hipStream_t s);
 // intercepts ybar - xbar^T beta of every path whose descriptor asks for them
 int launch_intercepts(const PathDesc *d_desc, int count, hipStream_t s);
 

@@ -181,7 +181,7 @@ __global__ __launch_bounds__(kPathThreads) void path_kernel(const PathDesc *__re
                                                             int lds_g_max_p)
 {
     extern __shared__ double sm[];
-    const PathDesc P = descs[order[blockIdx.x]];
+    const PathDesc P = descs[order ? order[blockIdx.x] : blockIdx.x];
     const auto G_g = gmem(P.G);
     const auto lambda_g = gmem(P.lambda);
     const auto beta_g = gmem(P.beta);
@@ -214,9 +214,10 @@ __global__ __launch_bounds__(kPathThreads) void path_kernel(const PathDesc *__re
     const double d = *P.d;
     const double yyn = *P.yyn;
     const bool grp = group_penalty(P.kind);
-    for (int i = threadIdx.x; i < p; i += kPathThreads) S.beta[i] = 0.0;
+    const auto init_g = gmem(P.beta_init);
+    for (int i = threadIdx.x; i < p; i += kPathThreads) S.beta[i] = P.beta_init ? init_g[i] : 0.0;
     __syncthreads();
-    int nact = 0;
+    int nact = P.beta_init ? rebuild_active(S, p) : 0;
 
     for (int l = 0; l < P.L; ++l) {
         const double lam = lambda_g[l];
@@ -443,7 +444,7 @@ static int path_chain(const PathDesc &d, int *slots)
 {
     const bool grp = d.kind == OEM_GRP_LASSO;
     // group MCP, group SCAD and the sparse group lasso run on the general kernel
-    const int cls = (d.p > 2048 || (group_penalty(d.kind) && !grp)) ? kGeneral
+    const int cls = (d.p > 2048 || (group_penalty(d.kind) && !grp) || d.beta_init) ? kGeneral
                     : d.p > 128 ? kStream
                     : grp       ? (d.p <= 64 ? kReg64 : kReg128)
                                 : (d.p <= 32 ? kBlk32 : (d.p <= 64 ? kBlk64 : kBlk128));
@@ -501,6 +502,8 @@ int attach_path_handover(std::vector<PathDesc> &descs, DevBuf &buf)
     return OEM_OK;
 }
 
+static int launch_general(const PathDesc *d_desc, const int *ord, int count, int pmax, hipStream_t s);
+
 int launch_paths_planned(const PathDesc *d_desc, const int *d_order, const PathPlan &plan,
                          hipStream_t s)
 {
@@ -518,25 +521,33 @@ int launch_paths_planned(const PathDesc *d_desc, const int *d_order, const PathP
         case kReg64: rc = launch_paths_reg(d_desc, ord, L.count, 64, ch, s); break;
         case kReg128: rc = launch_paths_reg(d_desc, ord, L.count, 128, ch, s); break;
         case kStream: rc = launch_paths_stream(d_desc, ord, L.count, L.pmax, ch, s); break;
-        default: {
-            // keep G in LDS when the largest path's matrix fits next to its vectors
-            const size_t limit = 150 * 1024;
-            int lds_g_max_p = 0;
-            size_t lds = path_lds_bytes(L.pmax, false);
-            if (path_lds_bytes(L.pmax, true) <= limit) {
-                lds_g_max_p = L.pmax;
-                lds = path_lds_bytes(L.pmax, true);
-            }
-            OEM_HIP_CHECK(hipFuncSetAttribute((const void *)path_kernel,
-                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-            hipLaunchKernelGGL(path_kernel, dim3(L.count), dim3(kPathThreads), lds, s, d_desc, ord,
-                               lds_g_max_p);
-            OEM_HIP_CHECK(hipGetLastError());
-        }
+        default: rc = launch_general(d_desc, ord, L.count, L.pmax, s); break;
         }
         if (rc) return rc;
     }
     return OEM_OK;
+}
+
+static int launch_general(const PathDesc *d_desc, const int *ord, int count, int pmax, hipStream_t s)
+{
+    // keep G in LDS when the largest path's matrix fits next to its vectors
+    const size_t limit = 150 * 1024;
+    int lds_g_max_p = 0;
+    size_t lds = path_lds_bytes(pmax, false);
+    if (path_lds_bytes(pmax, true) <= limit) {
+        lds_g_max_p = pmax;
+        lds = path_lds_bytes(pmax, true);
+    }
+    OEM_HIP_CHECK(hipFuncSetAttribute((const void *)path_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      (int)lds));
+    hipLaunchKernelGGL(path_kernel, dim3(count), dim3(kPathThreads), lds, s, d_desc, ord, lds_g_max_p);
+    OEM_HIP_CHECK(hipGetLastError());
+    return OEM_OK;
+}
+
+int launch_paths_general(const PathDesc *d_desc, int count, int pmax, hipStream_t s)
+{
+    return count > 0 ? launch_general(d_desc, nullptr, count, pmax, s) : OEM_OK;
 }
 
 // One set of launches for paths of any p: the order table groups the paths
