@@ -934,23 +934,31 @@ static int launch_lz_class(int cls, int count, int pmax, int p_all, const double
 // ------------------------------------------------------------ multi-workgroup Lanczos
 // For large p (above kMbMinP) one workgroup per problem is held to one CU's
 // share of L2 bandwidth while G alone is several MB per step.  This kernel
-// runs the same Lanczos recurrence (full reorthogonalisation, the top Ritz
-// value tested on the same schedule, same stopping rule and Gershgorin
-// fallback) with one problem spread over B = ceil(p / 64) workgroups:
-// workgroup b owns rows [64 b, 64 b + 64) of w = G v and of every basis
-// vector.  Lane l of each wave holds row 64 b + l; the four waves split the
-// columns of G (and the basis vectors in the dot products).  A step needs
-// three reductions over the rows: two classical Gram-Schmidt passes (the
-// first also gives alpha = v_j^T w) and the final norm.  Each goes through
-// per-workgroup partials in memory, summed by every workgroup in the same
-// order after a barrier across the problem's workgroups, so all of them
-// compute identical alpha, beta and stopping decisions.  The barrier is an
-// arrival counter per problem with a bounded wait (a wait that runs out
-// makes d NaN); it needs every workgroup of the launch resident at once,
-// which the launcher checks against the occupancy of the GPU.  Measured at
-// p = 500 the barriers (device-scope release/acquire, which write back and
-// invalidate the L2 of every XCD) cost more than the wider reads save, so
-// smaller problems keep one workgroup.
+// spreads one problem over B = ceil(p / 64) workgroups: workgroup b owns
+// rows [64 b, 64 b + 64) of w = G v (lane l of each wave holds row 64 b + l;
+// the four waves split the columns).  For p <= 4 CPL those rows of G stay in
+// registers for the whole run; larger p reads them from memory every step.
+//
+// The recurrence is the plain three-term Lanczos recurrence, with no
+// reorthogonalisation: in floating point a Ritz value that has converged
+// approximates an eigenvalue of G to O(eps ||G||) (Paige 1976); loss of
+// orthogonality only adds copies of converged values, and the largest Ritz
+// value still increases monotonically towards lambda_1.  A step needs one
+// exchange between the workgroups: each writes its rows of w, and after one
+// barrier every workgroup reads the whole w and forms alpha = v^T w,
+// r = w - alpha v - beta_prev v_prev, beta = ||r|| and the next vector over all
+// p rows itself.  The sums run over the same data in the same order in every
+// workgroup, so all of them take identical alpha, beta and stopping
+// decisions without a second exchange.  The top Ritz value is tested on the
+// schedule of the single-workgroup kernels, with the same stopping rule
+// (residual of the top Ritz pair below 1e-12 of its value, or an invariant
+// subspace) and the Gershgorin fallback.
+//
+// The barrier is an arrival counter per problem with a bounded wait (a wait
+// that runs out makes d NaN): each wave waits for its own stores, thread 0
+// releases, arrives, polls with relaxed loads and acquires once.  It needs
+// every workgroup of the launch resident at once, which the launcher checks
+// against the occupancy of the GPU.
 constexpr int kMbRows = 64;
 constexpr int kMbWaves = 4;
 constexpr int kMbThreads = 64 * kMbWaves;
@@ -959,18 +967,23 @@ constexpr unsigned kMbSpinMax = 1u << 22;   // about a second of waiting per bar
 
 static __host__ __device__ inline int lanczos_mb_blocks(int p) { return (p + kMbRows - 1) / kMbRows; }
 
-// per problem, after its basis V ((mmax + 1) p): the unnormalised next vector
-// (2 p), two pass partials (2 B (mmax + 2)), norm partials (B), then two
-// 32-bit counters in one more double
+// Step limit of the plain recurrence: room for ghost copies past p.
+static __host__ __device__ inline int lanczos_mb_steps(int p) { return p < 128 ? 256 : (2 * p < 2048 ? 2 * p : 2048); }
+
+// per problem, after its (mmax + 1) p basis area: the two exchange buffers
+// of w (2 p), the Gershgorin partials (B), then two 32-bit counters in one
+// more double
 static __host__ __device__ inline size_t lanczos_mb_scratch_doubles(int p)
 {
-    const size_t B = lanczos_mb_blocks(p), m = p <= 128 ? p : (p < 1024 ? p : 1024);   // lanczos_mmax
-    return 2 * (size_t)p + 2 * B * (m + 2) + B + 1;
+    return 2 * (size_t)p + lanczos_mb_blocks(p) + 1;
 }
 
-static size_t lanczos_mb_lds_bytes(int p, int mmax)
+// vectors are padded with zeros to 4 ceil(p / 4) entries (whole column shares)
+static __host__ __device__ inline int lanczos_mb_pad(int p) { return 4 * ((p + kMbWaves - 1) / kMbWaves); }
+
+static size_t lanczos_mb_lds_bytes(int p, int mcap)
 {
-    return ((size_t)p + (mmax + 2) + 4 * (size_t)mmax + kMbWaves * 64 + 64 + 64) * sizeof(double);
+    return (3 * (size_t)lanczos_mb_pad(p) + 4 * (size_t)mcap + kMbWaves * 64 + 64) * sizeof(double);
 }
 
 // zero the barrier counters of every problem of a launch
@@ -985,6 +998,8 @@ __global__ void lanczos_mb_reset_kernel(int count, const LzJob *__restrict__ job
     ctr[1] = 0u;
 }
 
+// CPL > 0: each lane keeps CPL columns of its row of G in registers (p <= 4 CPL)
+template <int CPL>
 __global__ __launch_bounds__(kMbThreads) void lanczos_mb_kernel(int B, const LzJob *__restrict__ jobs)
 {
     const int q = blockIdx.x / B, b = blockIdx.x % B;
@@ -992,26 +1007,24 @@ __global__ __launch_bounds__(kMbThreads) void lanczos_mb_kernel(int B, const LzJ
     const int p = J.p, mmax = J.mmax;
     const int Bq = lanczos_mb_blocks(p);
     if (b >= Bq) return;   // a smaller problem of the launch: not part of its barriers
+    const int mcap = lanczos_mb_steps(p);
     const auto G = gmem(J.G);
-    const auto V = gmem(J.V);
     double *scr = J.V + (size_t)(mmax + 1) * p;
-    const int S = mmax + 2;                       // row length of the pass partials
-    const auto Wb = gmem(scr);                    // [2][p]
-    const auto P0 = gmem(scr + 2 * p);            // [Bq][S] first pass
-    const auto P1 = gmem(scr + 2 * p + (size_t)Bq * S);       // [Bq][S] second pass
-    const auto P2 = gmem(scr + 2 * p + 2 * (size_t)Bq * S);   // [Bq] final norm
+    const auto Wb = gmem(scr);                    // [2][p]: w of the last two steps
+    const auto P2 = gmem(scr + 2 * (size_t)p);    // [Bq]: Gershgorin partials
     unsigned *ctr = reinterpret_cast<unsigned *>(scr + lanczos_mb_scratch_doubles(p) - 1);
 
     extern __shared__ double sm[];
-    double *v = sm;                 // p: current basis vector (all rows)
-    double *coef = v + p;           // mmax + 2
-    double *al = coef + mmax + 2;   // mmax
-    double *be = al + mmax;         // mmax
-    double *tx = be + mmax;         // mmax
-    double *tw = tx + mmax;         // mmax
-    double *part = tw + mmax;       // [kMbWaves][64]
-    double *wv = part + kMbWaves * 64;   // 64: this workgroup's rows of w
-    double *red = wv + 64;               // 64
+    const int pv = lanczos_mb_pad(p);
+    double *va = sm;                // three vectors (pv, zero past p): v_prev, v, and w / r
+    double *vb = va + pv;
+    double *vc = vb + pv;
+    double *al = vc + pv;           // mcap
+    double *be = al + mcap;         // mcap
+    double *tx = be + mcap;         // mcap
+    double *tw = tx + mcap;         // mcap
+    double *part = tw + mcap;       // [kMbWaves][64]
+    double *red = part + kMbWaves * 64;   // 64
     __shared__ int s_flag, s_fail;
     __shared__ double s_theta;
 
@@ -1023,13 +1036,15 @@ __global__ __launch_bounds__(kMbThreads) void lanczos_mb_kernel(int B, const LzJ
         s_flag = 0;
         s_fail = 0;
     }
+    const int cq = (p + kMbWaves - 1) / kMbWaves;
+    const int c0 = wave * cq, c1 = min(p, c0 + cq);
+    double g[CPL > 0 ? CPL : 1];
+    if constexpr (CPL > 0) {
+#pragma unroll
+        for (int k = 0; k < CPL; ++k) g[k] = (c0 + k < c1) ? G[(size_t)(c0 + k) * p + rc] : 0.0;
+    }
 
     unsigned nbar = 0;
-    // barrier across the problem's workgroups: every wave waits for its own
-    // stores to complete; thread 0 then releases (the L2 write-back covers
-    // all of them), arrives, waits (bounded) and acquires (the invalidation
-    // of this CU's and XCD's caches serves every wave after the workgroup
-    // barrier)
     auto gbar = [&]() {
         ++nbar;
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
@@ -1053,6 +1068,7 @@ __global__ __launch_bounds__(kMbThreads) void lanczos_mb_kernel(int B, const LzJ
         }
         __syncthreads();
     };
+    // sum over the workgroup in a fixed order (the same in every workgroup)
     auto bsum = [&](double x) -> double {
         x = wave_sum(x);
         __syncthreads();
@@ -1060,117 +1076,82 @@ __global__ __launch_bounds__(kMbThreads) void lanczos_mb_kernel(int B, const LzJ
         __syncthreads();
         return (red[0] + red[1]) + (red[2] + red[3]);
     };
-    // sum of the workgroups' partials in[.][m], m in [0, n), in workgroup order
-    auto gather = [&](decltype(P0) in, int n) {
-        for (int m = t; m < n; m += kMbThreads) {
-            double a = 0.0;
-            for (int bb = 0; bb < Bq; ++bb) a += in[(size_t)bb * S + m];
-            coef[m] = a;
-        }
-        __syncthreads();
-    };
-    // partials of V_m^T w over this workgroup's rows, m = 0..j (v_j from
-    // LDS), and of |w|^2
-    auto dots = [&](decltype(P0) out, int j) {
-        const double wl = wv[lane];
-        for (int m = wave; m <= j; m += kMbWaves) {
-            const double x = mine ? (m == j ? v[row] : V[(size_t)m * p + row]) : 0.0;
-            const double sdot = wave_sum(x * wl);
-            if (lane == 0) out[(size_t)b * S + m] = sdot;
-        }
-        if (wave == 0) {
-            const double sn = wave_sum(wl * wl);
-            if (lane == 0) out[(size_t)b * S + j + 1] = sn;
-        }
-    };
-    // w -= sum_m coef[m] V_m over this workgroup's rows
-    auto subtract = [&](int j) {
-        double acc = 0.0;
-        for (int m = wave; m <= j; m += kMbWaves) {
-            const double x = mine ? (m == j ? v[row] : V[(size_t)m * p + row]) : 0.0;
-            acc += coef[m] * x;
-        }
-        part[wave * 64 + lane] = acc;
-        __syncthreads();
-        if (wave == 0) {
-            const double sub = (part[lane] + part[64 + lane]) + (part[128 + lane] + part[192 + lane]);
-            wv[lane] = mine ? wv[lane] - sub : 0.0;
-        }
-        __syncthreads();
-    };
 
-    // v0: the start vector of the single-workgroup kernels, normalised (every
-    // workgroup forms all of it); own rows of V_0 to memory
+    double *vprev = va, *v = vb, *w = vc;
+    // v0: the start vector of the single-workgroup kernels, normalised
     double ss = 0.0;
-    for (int i = t; i < p; i += kMbThreads) {
-        const double x = start_component(i);
+    for (int i = t; i < pv; i += kMbThreads) {
+        const double x = i < p ? start_component(i) : 0.0;
         v[i] = x;
+        vprev[i] = 0.0;
+        w[i] = 0.0;
         ss += x * x;
     }
     const double nrm0 = sqrt(bsum(ss));
     for (int i = t; i < p; i += kMbThreads) v[i] = v[i] / nrm0;
     __syncthreads();
-    if (wave == 0 && mine) V[row] = v[row];
 
-    double gnorm = 0.0, theta = 0.0, floor = -INFINITY;
+    double gnorm = 0.0, theta = 0.0, floor = -INFINITY, beta_prev = 0.0;
     int m = 0, next_test = 8;
-    const int cq = (p + kMbWaves - 1) / kMbWaves;
-    const int c0 = wave * cq, c1 = min(p, c0 + cq);
-    for (int j = 0; j < mmax; ++j) {
-        // w = G v over this workgroup's rows; wave w takes columns [c0, c1)
+    for (int j = 0; j < mcap; ++j) {
+        // this workgroup's rows of w = G v
         {
             double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-            int c = c0;
-            for (; c + 8 <= c1; c += 8) {
-                double g[8];
+            if constexpr (CPL > 0) {
+                // g is zero past this wave's columns and v is zero past p;
+                // c0 + k < c0 + cq <= pv for the k a wave owns
 #pragma unroll
-                for (int u = 0; u < 8; ++u) g[u] = G[(size_t)(c + u) * p + rc];
-                a0 += g[0] * v[c] + g[4] * v[c + 4];
-                a1 += g[1] * v[c + 1] + g[5] * v[c + 5];
-                a2 += g[2] * v[c + 2] + g[6] * v[c + 6];
-                a3 += g[3] * v[c + 3] + g[7] * v[c + 7];
+                for (int k = 0; k < CPL; k += 4) {
+                    if (k < cq) {
+                        a0 += g[k] * v[c0 + k];
+                        a1 += g[k + 1] * v[c0 + k + 1];
+                        a2 += g[k + 2] * v[c0 + k + 2];
+                        a3 += g[k + 3] * v[c0 + k + 3];
+                    }
+                }
+            } else {
+                int c = c0;
+                for (; c + 8 <= c1; c += 8) {
+                    double gg[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) gg[u] = G[(size_t)(c + u) * p + rc];
+                    a0 += gg[0] * v[c] + gg[4] * v[c + 4];
+                    a1 += gg[1] * v[c + 1] + gg[5] * v[c + 5];
+                    a2 += gg[2] * v[c + 2] + gg[6] * v[c + 6];
+                    a3 += gg[3] * v[c + 3] + gg[7] * v[c + 7];
+                }
+                for (; c < c1; ++c) a0 += G[(size_t)c * p + rc] * v[c];
             }
-            for (; c < c1; ++c) a0 += G[(size_t)c * p + rc] * v[c];
             part[wave * 64 + lane] = (a0 + a1) + (a2 + a3);
         }
         __syncthreads();
-        if (wave == 0)
-            wv[lane] = mine ? (part[lane] + part[64 + lane]) + (part[128 + lane] + part[192 + lane]) : 0.0;
-        __syncthreads();
-        // first Gram-Schmidt pass
-        dots(P0, j);
+        if (wave == 0 && mine)
+            Wb[(size_t)(j & 1) * p + row] = (part[lane] + part[64 + lane]) + (part[128 + lane] + part[192 + lane]);
         gbar();
         if (s_fail) break;
-        gather(P0, j + 2);
-        const double alpha = coef[j];
-        gnorm = fmax(gnorm, fabs(alpha));
-        subtract(j);
-        // second pass
-        dots(P1, j);
-        gbar();
-        if (s_fail) break;
-        gather(P1, j + 1);
-        subtract(j);
-        // final norm; the unnormalised next vector goes to memory
-        if (wave == 0) {
-            const double sn = wave_sum(wv[lane] * wv[lane]);
-            if (lane == 0) P2[b] = sn;
-            if (mine) Wb[(size_t)((j + 1) & 1) * p + row] = wv[lane];
+        // the whole w; alpha, r, beta over all rows (identical in every workgroup)
+        double sa = 0.0;
+        for (int i = t; i < p; i += kMbThreads) {
+            const double wi = Wb[(size_t)(j & 1) * p + i];
+            w[i] = wi;
+            sa += v[i] * wi;
         }
-        gbar();
-        if (s_fail) break;
-        if (t < Bq) red[t] = P2[t];
-        __syncthreads();
-        double nb = 0.0;
-        for (int bb = 0; bb < Bq; ++bb) nb += red[bb];
-        const double beta = sqrt(nb);
+        const double alpha = bsum(sa);
+        double sb = 0.0;
+        for (int i = t; i < p; i += kMbThreads) {
+            const double r = (w[i] - alpha * v[i]) - beta_prev * vprev[i];
+            w[i] = r;
+            sb += r * r;
+        }
+        const double beta = sqrt(bsum(sb));
+        gnorm = fmax(gnorm, fabs(alpha));
         if (t == 0) {
             al[j] = alpha;
             be[j] = beta;
         }
         m = j + 1;
-        const bool invariant = (beta <= 1e-14 * fmax(gnorm, 1e-300)) || (m == p);
-        const bool test_now = invariant || (m == next_test) || (m == mmax);
+        const bool invariant = beta <= 1e-14 * fmax(gnorm, 1e-300);
+        const bool test_now = invariant || (m == next_test) || (m == mcap);
         __syncthreads();
         if (test_now) {
             next_test = m + max(8, m / 4);
@@ -1190,12 +1171,16 @@ __global__ __launch_bounds__(kMbThreads) void lanczos_mb_kernel(int B, const LzJ
             floor = theta * (1.0 - 1e-14);
             if (s_flag) break;
         }
-        // next basis vector (all rows) from the unnormalised one
-        for (int i = t; i < p; i += kMbThreads) v[i] = Wb[(size_t)((j + 1) & 1) * p + i] / beta;
+        // next vector: v_prev <- v, v <- r / beta (buffers rotate)
+        for (int i = t; i < p; i += kMbThreads) w[i] = w[i] / beta;
+        double *tmp = vprev;
+        vprev = v;
+        v = w;
+        w = tmp;
+        beta_prev = beta;
         __syncthreads();
-        if (wave == 0 && mine) V[(size_t)(j + 1) * p + row] = v[row];
     }
-    // not settled within mmax steps: Gershgorin bound, as in the other kernels
+    // not settled within the step limit: Gershgorin bound, as in the other kernels
     double dval = theta * (1.0 + 1e-10);
     const bool ok = s_flag != 0 && !s_fail;
     if (!ok && !s_fail) {
@@ -1248,9 +1233,12 @@ static bool lanczos_mb_enabled()
 static int launch_lanczos_mb(const LzJob *d_jobs, int count, int pmax, hipStream_t s)
 {
     if (!lanczos_mb_enabled() || lanczos_single_workgroup || pmax <= kMbMinP || pmax > 2048) return 1;
-    const int mmax = lanczos_mmax(pmax), B = lanczos_mb_blocks(pmax);
-    const size_t lds = lanczos_mb_lds_bytes(pmax, mmax);
-    const void *kern = (const void *)lanczos_mb_kernel;
+    const int B = lanczos_mb_blocks(pmax);
+    const size_t lds = lanczos_mb_lds_bytes(pmax, lanczos_mb_steps(pmax));
+    // rows of G in registers while a lane's share of columns fits (p <= 4 CPL)
+    const void *kern = pmax <= 256 ? (const void *)lanczos_mb_kernel<64>
+                     : pmax <= 512 ? (const void *)lanczos_mb_kernel<128>
+                                   : (const void *)lanczos_mb_kernel<0>;
     OEM_HIP_CHECK(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     int per_cu = 0, ncu = 0, dev = 0;
     OEM_HIP_CHECK(hipGetDevice(&dev));
