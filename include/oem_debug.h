@@ -20,6 +20,13 @@ extern "C" {
  * OEM_E_INVAL on bad arguments.  Every index written is in [0, p). */
 int oem_debug_gram_load_columns(int32_t p, int32_t col, int32_t vec_ok, int32_t *cols);
 
+/* Measurement hook: the Lanczos step counts of the handle's derived
+ * problems (q = 0 full data, q = 1 + k training rows of fold k) from the
+ * last oem_fit_path / oem_cv, copied into steps (host, at most nq entries;
+ * negative: the Gershgorin fallback was used).  Returns the number of
+ * problems, or OEM_E_STATE when nothing has been derived yet. */
+int oem_debug_lanczos_steps(void *handle, int32_t *steps, int32_t nq);
+
 #ifdef __cplusplus
 }
 #endif

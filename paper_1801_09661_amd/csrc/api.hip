@@ -577,6 +577,16 @@ int oem_gram_import(oem_handle h, int32_t fold, const double *XtX, const double 
     return OEM_OK;
 }
 
+int oem_debug_lanczos_steps(void *handle, int32_t *steps, int32_t nq)
+{
+    oem_gram_s *h = static_cast<oem_gram_s *>(handle);
+    if (!h || !steps || nq < 0) return fail(OEM_E_INVAL, "bad arguments");
+    if (!h->derived_valid) return fail(OEM_E_STATE, "nothing derived yet");
+    const int n = std::min<int>(nq, (int)h->lz_host.size());
+    for (int i = 0; i < n; ++i) steps[i] = h->lz_host[i];
+    return (int)h->lz_host.size();
+}
+
 int oem_gram_export_colsums(oem_handle h, double *colsum, double *ysum, void *stream)
 {
     if (!h) return fail(OEM_E_INVAL, "handle is NULL");
