@@ -768,12 +768,21 @@ def batch_main(args):
         f64 = runs["fp64"]
         out["fp64_form"] = dict(fits_per_s=f64["fits_per_s"], ms_per_step=f64["ms_per_step"])
         out["mixed_vs_fp64_fits"] = main_run["fits_per_s"] / f64["fits_per_s"]
-        errs = []
-        for bm, bf in zip(main_run["beta"], f64["beta"]):
+        errs, worst = [], None
+        for i, (bm, bf) in enumerate(zip(main_run["beta"], f64["beta"])):
             scale = np.maximum(np.abs(bf).max(axis=2), 1e-300)
-            errs.append(float((np.abs(bm - bf).max(axis=2) / scale)[:, 1:].max()))
+            e = (np.abs(bm - bf).max(axis=2) / scale)[:, 1:]
+            errs.append(float(e.max()))
+            if worst is None or errs[-1] > worst["coef_err"]:
+                q, l = np.unravel_index(int(np.argmax(e)), e.shape)
+                j = int(np.argmax(np.abs(bm[q, l + 1] - bf[q, l + 1])))
+                worst = dict(coef_err=errs[-1], problem=i, p=int(bf.shape[2]), lambda_index=int(l + 1),
+                             coord=j, beta_fp64=float(bf[q, l + 1, j]), beta_mixed=float(bm[q, l + 1, j]),
+                             max_abs_beta=float(scale[q, l + 1]),
+                             active_set_mismatch=int(np.count_nonzero((bm[:, 1:] != 0) != (bf[:, 1:] != 0))))
         out["mixed_coef_err_vs_fp64_form_max"] = max(errs)
         out["mixed_coef_err_vs_fp64_form_median"] = float(np.median(errs))
+        out["mixed_coef_err_worst_problem"] = worst
     if not args.no_cpu_baseline and not args.profile_steps:
         out["cpu_baseline"] = cpu_baseline_batch(shapes)
     print(json.dumps(out))

@@ -180,10 +180,10 @@ def _close_live() -> None:
             pass
 
 
-def _finalize(obj) -> None:
-    if sys.is_finalizing():
-        return
+def _finalize(obj, _sys=sys) -> None:
     try:
+        if _sys.is_finalizing():
+            return
         obj.close()
     except Exception:
         pass
@@ -416,8 +416,10 @@ class Gram:
     def __exit__(self, *a):
         self.close()
 
-    def __del__(self):
-        _finalize(self)
+    def __del__(self, _fin=_finalize):
+        # bound at class creation: module globals may already be cleared
+        # when this runs during interpreter shutdown
+        _fin(self)
 
     def add(self, X, y, row_offset: int = 0, foldid=None, stream=None, noalloc: bool = False):
         oem_gram(self.h, X, y, row_offset, foldid, stream, noalloc)
@@ -560,8 +562,10 @@ class Batch:
     def __exit__(self, *a):
         self.close()
 
-    def __del__(self):
-        _finalize(self)
+    def __del__(self, _fin=_finalize):
+        # bound at class creation: module globals may already be cleared
+        # when this runs during interpreter shutdown
+        _fin(self)
 
 
 class Server:
@@ -638,5 +642,7 @@ class Server:
     def __exit__(self, *a):
         self.close()
 
-    def __del__(self):
-        _finalize(self)
+    def __del__(self, _fin=_finalize):
+        # bound at class creation: module globals may already be cleared
+        # when this runs during interpreter shutdown
+        _fin(self)

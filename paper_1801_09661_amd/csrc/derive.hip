@@ -255,50 +255,102 @@ __device__ inline double start_component(int i)
     return (double)(z >> 11) * (1.0 / 9007199254740992.0) + 0.5;  // in [0.5, 1.5)
 }
 
-// Reciprocal of a nonzero double: hardware estimate refined by two Newton
-// steps (relative error at the rounding level), cheaper than a division in
-// the long dependent chains below.
-__device__ inline double rcp_fast(double q)
-{
-    double r = __builtin_amdgcn_rcp(q);
-    r = fma(r, fma(-q, r, 1.0), r);
-    r = fma(r, fma(-q, r, 1.0), r);
-    return r;
-}
+// Leading principal minors of x I - T: p_0 = 1, p_1 = x - a_0,
+// p_i = (x - a_{i-1}) p_{i-1} - b_{i-2}^2 p_{i-2}.  x lies above every
+// eigenvalue of T exactly when x I - T is positive definite, i.e. when every
+// minor is positive (Sylvester's criterion).  The recurrence needs no
+// division (one fused multiply-add on the dependent chain per step, where
+// the pivot form p_i / p_{i-1} needs a reciprocal); only signs matter, so the
+// pair (p_{i-1}, p_i) is rescaled by a power of two after every block of 8
+// steps.  The entries of a block are loaded while the previous block
+// computes (the loop is otherwise bound by LDS latency).
+constexpr int kTriBlk = 8;
 
-__device__ inline int sturm_below_fast(const double *a, const double *b, int m, double x)
+__device__ inline bool tri_above_all(const double *a, const double *b, int m, double x)
 {
-    int cnt = 0;
-    double q = 1.0;
-    for (int i = 0; i < m; ++i) {
-        const double bb = (i > 0) ? b[i - 1] * b[i - 1] : 0.0;
-        q = (a[i] - x) - (i > 0 ? bb * rcp_fast(q) : 0.0);
-        if (q == 0.0) q = -1e-300;
-        if (q < 0.0) ++cnt;
+    double p2 = 1.0, p1 = x - a[0];
+    bool ok = p1 > 0.0;
+    const int nb = (m - 1) / kTriBlk;   // whole blocks of steps 1 .. nb * kTriBlk
+    double an[kTriBlk], bn[kTriBlk];
+    if (nb > 0) {
+#pragma unroll
+        for (int u = 0; u < kTriBlk; ++u) {
+            an[u] = a[1 + u];
+            bn[u] = b[u];
+        }
     }
-    return cnt;
+    for (int k = 0; k < nb && ok; ++k) {
+        double ac[kTriBlk], bc[kTriBlk];
+#pragma unroll
+        for (int u = 0; u < kTriBlk; ++u) {
+            ac[u] = an[u];
+            bc[u] = bn[u];
+        }
+        if (k + 1 < nb) {
+            const int i = 1 + (k + 1) * kTriBlk;
+#pragma unroll
+            for (int u = 0; u < kTriBlk; ++u) {
+                an[u] = a[i + u];
+                bn[u] = b[i + u - 1];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kTriBlk; ++u) {
+            const double pi = fma(x - ac[u], p1, -(bc[u] * bc[u]) * p2);
+            ok = ok & (pi > 0.0);
+            p2 = p1;
+            p1 = pi;
+        }
+        int e;
+        p1 = frexp(p1, &e);
+        p2 = ldexp(p2, -e);
+    }
+    for (int i = 1 + nb * kTriBlk; i < m && ok; ++i) {
+        const double pi = fma(x - a[i], p1, -(b[i - 1] * b[i - 1]) * p2);
+        ok = pi > 0.0;
+        p2 = p1;
+        p1 = pi;
+    }
+    return ok;
 }
 
-// tri_top with the fast Sturm count and a known lower bound `floor` for the
-// top eigenvalue (the previous top Ritz value: Ritz values only grow).
-__device__ inline void tri_top_fast(const double *a, const double *b, int m, double floor,
-                                    double *lo_out, double *hi_out)
+// Top eigenvalue of T (m x m) by multisection on one wave, given a lower
+// bound `floor` of it (the previous top Ritz value: Ritz values only grow
+// with m; -inf when there is none).  With a positive floor the first round
+// tests floor (1 + 2^(l - 52)) in lane l, which brackets the answer within
+// a factor 2 of its distance from the floor; then 64 equally spaced points
+// per round until the bracket is 2e-16 relative.  Returns [lo, hi].
+__device__ inline void tri_top_pd(const double *a, const double *b, int m, double floor,
+                                  double *lo_out, double *hi_out)
 {
     const int lane = threadIdx.x % kWave;
-    double lo = -INFINITY, hi = -INFINITY;
-    for (int i = 0; i < m; ++i) {
-        double r = fabs(i > 0 ? b[i - 1] : 0.0) + fabs(i < m - 1 ? b[i] : 0.0);
-        lo = fmax(lo, a[i]);
-        hi = fmax(hi, a[i] + r);
+    double glo = -INFINITY, ghi = -INFINITY;   // largest diagonal, Gershgorin bound
+    for (int i = lane; i < m; i += kWave) {
+        const double r = fabs(i > 0 ? b[i - 1] : 0.0) + fabs(i < m - 1 ? b[i] : 0.0);
+        glo = fmax(glo, a[i]);
+        ghi = fmax(ghi, a[i] + r);
     }
-    lo = fmax(lo, floor);
-    hi = hi + fabs(hi) * 1e-15 + 1e-300;
+    glo = wave_max(glo);
+    ghi = wave_max(ghi);
+    double lo = fmax(glo, floor);
+    double hi = ghi + fabs(ghi) * 1e-15 + 1e-300;
     lo = lo - fabs(lo) * 1e-15 - 1e-300;
+    if (floor > 0.0 && floor < INFINITY && lo > 0.0 && lo < hi) {
+        const double x = fmin(hi, lo + lo * ldexp(1.0, lane - 52));
+        const uint64_t above = __ballot(tri_above_all(a, b, m, x));
+        if (above) {
+            const int f = __ffsll((long long)above) - 1;
+            const double xf = fmin(hi, lo + lo * ldexp(1.0, f - 52));
+            if (f > 0) lo = lo + lo * ldexp(1.0, f - 53);
+            hi = xf;
+        } else {
+            lo = fmin(hi, lo + lo * ldexp(1.0, 11));
+        }
+    }
     for (int round = 0; round < 24; ++round) {
         if (hi - lo <= 2e-16 * fmax(fabs(lo), fabs(hi))) break;
         const double x = lo + (hi - lo) * (double)(lane + 1) / (double)(kWave + 1);
-        const int below = sturm_below_fast(a, b, m, x);
-        const uint64_t above = __ballot(below == m);
+        const uint64_t above = __ballot(tri_above_all(a, b, m, x));
         double nlo = lo, nhi = hi;
         if (above) {
             const int f = __ffsll((long long)above) - 1;
@@ -312,6 +364,189 @@ __device__ inline void tri_top_fast(const double *a, const double *b, int m, dou
     }
     *lo_out = lo;
     *hi_out = hi;
+}
+
+// Residual of the top Ritz pair as in tri_residual, with the pivots of
+// shift I - T = L D L^T taken from its leading minors (d_i = p_i / p_{i-1},
+// off the dependent chain) and reused by both inverse-iteration solves, each
+// of which is then one fused multiply-add per step in each direction:
+// y_i = s_i + (b_{i-1} / d_{i-1}) y_{i-1}, z_i = (y_i + b_i z_{i+1}) / d_i.
+// The entries are read in blocks of 8, one block ahead.  c[i] = b_i / d_i
+// and r[i] = 1 / d_i are kept; y holds the forward and then the backward
+// solution.  Infinity when a minor is not positive (shift not above every
+// eigenvalue).
+__device__ inline double tri_residual_pd(const double *a, const double *b, int m, double shift,
+                                         double beta_m, double *r, double *y)
+{
+    constexpr int B = kTriBlk;
+    double p2 = 1.0, p1 = shift - a[0];
+    if (!(p1 > 0.0)) return INFINITY;
+    r[0] = 1.0 / p1;
+    bool ok = true;
+    {
+        const int nb = (m - 1) / B;
+        double an[B], bn[B];
+        if (nb > 0) {
+#pragma unroll
+            for (int u = 0; u < B; ++u) {
+                an[u] = a[1 + u];
+                bn[u] = b[u];
+            }
+        }
+        for (int k = 0; k < nb && ok; ++k) {
+            const int i0 = 1 + k * B;
+            double ac[B], bc[B], rr[B];
+#pragma unroll
+            for (int u = 0; u < B; ++u) {
+                ac[u] = an[u];
+                bc[u] = bn[u];
+            }
+            if (k + 1 < nb) {
+#pragma unroll
+                for (int u = 0; u < B; ++u) {
+                    an[u] = a[i0 + B + u];
+                    bn[u] = b[i0 + B + u - 1];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < B; ++u) {
+                const double pi = fma(shift - ac[u], p1, -(bc[u] * bc[u]) * p2);
+                ok = ok & (pi > 0.0);
+                rr[u] = p1 / pi;
+                p2 = p1;
+                p1 = pi;
+            }
+#pragma unroll
+            for (int u = 0; u < B; ++u) r[i0 + u] = rr[u];
+            int e;
+            p1 = frexp(p1, &e);
+            p2 = ldexp(p2, -e);
+        }
+        for (int i = 1 + nb * B; i < m && ok; ++i) {
+            const double pi = fma(shift - a[i], p1, -(b[i - 1] * b[i - 1]) * p2);
+            ok = pi > 0.0;
+            r[i] = p1 / pi;
+            p2 = p1;
+            p1 = pi;
+        }
+    }
+    if (!ok) return INFINITY;
+    // forward solve L y = s (s = all ones, or y itself times `scale`)
+    auto forward = [&](bool ones, double scale) {
+        double yp = ones ? 1.0 : y[0] * scale;
+        y[0] = yp;
+        const int nb = (m - 1) / B;
+        double bn[B], rn[B], sn[B];
+        auto load = [&](int i0, double (&bb)[B], double (&rv)[B], double (&sv)[B]) {
+#pragma unroll
+            for (int u = 0; u < B; ++u) {
+                bb[u] = b[i0 + u - 1];
+                rv[u] = r[i0 + u - 1];
+                sv[u] = ones ? 1.0 : y[i0 + u] * scale;
+            }
+        };
+        if (nb > 0) load(1, bn, rn, sn);
+        for (int k = 0; k < nb; ++k) {
+            const int i0 = 1 + k * B;
+            double bc[B], rc[B], sc[B];
+#pragma unroll
+            for (int u = 0; u < B; ++u) {
+                bc[u] = bn[u];
+                rc[u] = rn[u];
+                sc[u] = sn[u];
+            }
+            if (k + 1 < nb) load(i0 + B, bn, rn, sn);
+#pragma unroll
+            for (int u = 0; u < B; ++u) {
+                yp = fma(bc[u] * rc[u], yp, sc[u]);
+                y[i0 + u] = yp;
+            }
+        }
+        for (int i = 1 + nb * B; i < m; ++i) {
+            yp = fma(b[i - 1] * r[i - 1], yp, ones ? 1.0 : y[i] * scale);
+            y[i] = yp;
+        }
+    };
+    // backward solve D L^T z = y into y; returns ||z||^2 and z_{m-1}
+    auto backward = [&](double &zlast) -> double {
+        double z = r[m - 1] * y[m - 1];
+        y[m - 1] = z;
+        zlast = z;
+        double nrm2 = z * z;
+        const int nb = (m - 1) / B;   // blocks of indices m-2 down to m-1-nb*B
+        double bn[B], rn[B], yn[B];
+        auto load = [&](int i0, double (&bb)[B], double (&rv)[B], double (&yv)[B]) {
+#pragma unroll
+            for (int u = 0; u < B; ++u) {
+                bb[u] = b[i0 - u];
+                rv[u] = r[i0 - u];
+                yv[u] = y[i0 - u];
+            }
+        };
+        if (nb > 0) load(m - 2, bn, rn, yn);
+        for (int k = 0; k < nb; ++k) {
+            const int i0 = m - 2 - k * B;
+            double bc[B], rc[B], yc[B];
+#pragma unroll
+            for (int u = 0; u < B; ++u) {
+                bc[u] = bn[u];
+                rc[u] = rn[u];
+                yc[u] = yn[u];
+            }
+            if (k + 1 < nb) load(i0 - B, bn, rn, yn);
+#pragma unroll
+            for (int u = 0; u < B; ++u) {
+                z = rc[u] * fma(bc[u], z, yc[u]);
+                y[i0 - u] = z;
+                nrm2 += z * z;
+            }
+        }
+        for (int i = m - 2 - nb * B; i >= 0; --i) {
+            z = r[i] * fma(b[i], z, y[i]);
+            y[i] = z;
+            nrm2 += z * z;
+        }
+        return nrm2;
+    };
+    double zl = 0.0;
+    forward(true, 1.0);
+    double nrm2 = backward(zl);
+    forward(false, 1.0 / sqrt(nrm2));   // the second solve starts from z / ||z||
+    nrm2 = backward(zl);
+    return fabs(beta_m * zl) / sqrt(nrm2);
+}
+
+// Convergence test of the top Ritz value, run by one wave: theta from the
+// multisection, then (lane 0) the residual of the top Ritz pair; stop when it
+// is below 1e-12 of theta or the Krylov space is invariant.  The next test
+// step is predicted from the residual's geometric decrease since the
+// previous test (0.8 of the predicted distance, between 2 and max(8, m / 2)
+// steps ahead; max(8, m / 4) before there is a decrease to go by).  Lane 0
+// writes the shared results.
+__device__ inline void lz_test(const double *al, const double *be, int m, double beta_m,
+                               bool invariant, double floor, double *rd, double *y, int &m_prev,
+                               double &r_prev, double *s_theta, int *s_flag, int *s_next)
+{
+    double lo, hi;
+    tri_top_pd(al, be, m, floor, &lo, &hi);
+    if (threadIdx.x % kWave == 0) {
+        const double th = 0.5 * (lo + hi);
+        const double shift = hi + (hi - lo) + 1e-13 * fabs(hi) + 1e-300;
+        const double res = invariant ? 0.0 : tri_residual_pd(al, be, m, shift, beta_m, rd, y);
+        const double target = 1e-12 * fabs(th);
+        *s_theta = th;
+        *s_flag = invariant || (res <= target);
+        int step = max(8, m / 4);
+        if (r_prev > 0.0 && res > 0.0 && res < r_prev && res < INFINITY) {
+            // 0.8 of the predicted distance, at most m / 2 ahead
+            const double rate = log(res / r_prev) / (double)(m - m_prev);   // < 0
+            const double need = log(target / res) / rate;                   // steps still needed
+            step = (int)fmin((double)max(8, m / 2), fmax(2.0, ceil(0.8 * need)));
+        }
+        *s_next = m + step;
+        m_prev = m;
+        r_prev = res;
+    }
 }
 
 constexpr int kLzWideWaves = 16;
@@ -360,7 +595,7 @@ __global__ __launch_bounds__(kLzWideThreads) void lanczos_wide_kernel(int p_all,
     double *tx = be + mmax;         // mmax
     double *tw = tx + mmax;         // mmax
     double *red = tw + mmax;        // kLzWideWaves
-    __shared__ int s_flag;
+    __shared__ int s_flag, s_next;
     __shared__ double s_theta;
 
     const auto G = gmem(J.G);
@@ -427,7 +662,8 @@ __global__ __launch_bounds__(kLzWideThreads) void lanczos_wide_kernel(int p_all,
     };
 
     double gnorm = 0.0, theta = 0.0, floor = -INFINITY;
-    int m = 0, next_test = 8;
+    int m = 0, next_test = 8, m_prev = 0;
+    double r_prev = 0.0;
     if (threadIdx.x == 0) s_flag = 0;
     for (int j = 0; j < mmax; ++j) {
         // w = G v_j: two column halves, summed in order
@@ -500,21 +736,13 @@ __global__ __launch_bounds__(kLzWideThreads) void lanczos_wide_kernel(int p_all,
         const bool test_now = invariant || (m == next_test) || (m == mmax);
         __syncthreads();
         if (test_now) {
-            next_test = m + max(8, m / 4);
-            if (threadIdx.x < kWave) {
-                double lo, hi;
-                tri_top_fast(al, be, m, floor, &lo, &hi);
-                if (threadIdx.x == 0) {
-                    const double th = 0.5 * (lo + hi);
-                    const double shift = hi + (hi - lo) + 1e-13 * fabs(hi) + 1e-300;
-                    const double res = invariant ? 0.0 : tri_residual(al, be, m, shift, b, tx, tw);
-                    s_theta = th;
-                    s_flag = invariant || (res <= 1e-12 * fabs(th));
-                }
-            }
+            if (threadIdx.x < kWave)
+                lz_test(al, be, m, b, invariant, floor, tx, tw, m_prev, r_prev, &s_theta, &s_flag,
+                        &s_next);
             __syncthreads();
             theta = s_theta;
             floor = theta * (1.0 - 1e-14);
+            next_test = s_next;
             if (s_flag) break;
         }
         for (int i = threadIdx.x; i < PR; i += kLzWideThreads) {
@@ -718,7 +946,7 @@ __global__ __launch_bounds__(64 * NW) void lanczos_reg_kernel(int p_all, int mma
     double *tx = coef + mmax + 1;             // mmax
     double *tw = tx + mmax;                   // mmax
     double *red = tw + mmax;                  // 2 NW
-    __shared__ int s_flag;
+    __shared__ int s_flag, s_next;
     __shared__ double s_theta;
 
     double Gr[R][CPW];
@@ -765,7 +993,8 @@ __global__ __launch_bounds__(64 * NW) void lanczos_reg_kernel(int p_all, int mma
     __syncthreads();
 
     double gnorm = 0.0, theta = 0.0, floor = -INFINITY;
-    int next_test = 8;
+    int next_test = 8, m_prev = 0;
+    double r_prev = 0.0;
     int m = 0;
     for (int j = 0; j < mmax; ++j) {
         const double *vj = V + (size_t)j * ldv;
@@ -833,22 +1062,14 @@ __global__ __launch_bounds__(64 * NW) void lanczos_reg_kernel(int p_all, int mma
         const bool invariant = (b <= 1e-14 * fmax(gnorm, 1e-300)) || (m == p);
         const bool test_now = invariant || (m == next_test) || (m == mmax);
         if (test_now) {
-            next_test = m + max(8, m / 4);
             __syncthreads();
-            if (t < kWave) {
-                double lo, hi;
-                tri_top_fast(al, be, m, floor, &lo, &hi);
-                if (t == 0) {
-                    const double th = 0.5 * (lo + hi);
-                    const double shift = hi + (hi - lo) + 1e-13 * fabs(hi) + 1e-300;
-                    const double res = invariant ? 0.0 : tri_residual(al, be, m, shift, b, tx, tw);
-                    s_theta = th;
-                    s_flag = invariant || (res <= 1e-12 * fabs(th));
-                }
-            }
+            if (t < kWave)
+                lz_test(al, be, m, b, invariant, floor, tx, tw, m_prev, r_prev, &s_theta, &s_flag,
+                        &s_next);
             __syncthreads();
             theta = s_theta;
             floor = theta * (1.0 - 1e-14);
+            next_test = s_next;
             if (s_flag) break;
         }
         if (mine) V[(size_t)(j + 1) * ldv + t] = wt / b;
@@ -1025,7 +1246,7 @@ __global__ __launch_bounds__(kMbThreads) void lanczos_mb_kernel(int B, const LzJ
     double *tw = tx + mcap;         // mcap
     double *part = tw + mcap;       // [kMbWaves][64]
     double *red = part + kMbWaves * 64;   // 64
-    __shared__ int s_flag, s_fail;
+    __shared__ int s_flag, s_fail, s_next;
     __shared__ double s_theta;
 
     const int t = threadIdx.x, lane = t % kWave, wave = t / kWave;
@@ -1050,8 +1271,8 @@ __global__ __launch_bounds__(kMbThreads) void lanczos_mb_kernel(int B, const LzJ
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         __syncthreads();
         if (t == 0 && !s_fail) {
-            __threadfence();
-            atomicAdd(ctr, 1u);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             const unsigned target = nbar * (unsigned)Bq;
             unsigned spins = 0;
             // relaxed loads while waiting (an acquire per poll would invalidate
@@ -1064,7 +1285,7 @@ __global__ __launch_bounds__(kMbThreads) void lanczos_mb_kernel(int B, const LzJ
                     break;
                 }
             }
-            __threadfence();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
         __syncthreads();
     };
@@ -1092,22 +1313,28 @@ __global__ __launch_bounds__(kMbThreads) void lanczos_mb_kernel(int B, const LzJ
     __syncthreads();
 
     double gnorm = 0.0, theta = 0.0, floor = -INFINITY, beta_prev = 0.0;
-    int m = 0, next_test = 8;
+    int m = 0, next_test = 8, m_prev = 0;
+    double r_prev = 0.0;
     for (int j = 0; j < mcap; ++j) {
         // this workgroup's rows of w = G v
         {
             double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
             if constexpr (CPL > 0) {
-                // g is zero past this wave's columns and v is zero past p;
-                // c0 + k < c0 + cq <= pv for the k a wave owns
+                // lane l holds v[c0 + 64 h + l]; each entry reaches the whole
+                // wave by readlane (no LDS traffic).  g and these registers
+                // are zero past the wave's cq columns.
+                double vr[CPL / 64];
+#pragma unroll
+                for (int h = 0; h < CPL / 64; ++h) vr[h] = (64 * h + lane < cq) ? v[c0 + 64 * h + lane] : 0.0;
 #pragma unroll
                 for (int k = 0; k < CPL; k += 4) {
-                    if (k < cq) {
-                        a0 += g[k] * v[c0 + k];
-                        a1 += g[k + 1] * v[c0 + k + 1];
-                        a2 += g[k + 2] * v[c0 + k + 2];
-                        a3 += g[k + 3] * v[c0 + k + 3];
-                    }
+                    a0 += g[k] * readlane_d(vr[k / 64], k % 64);
+                    a1 += g[k + 1] * readlane_d(vr[k / 64], (k + 1) % 64);
+                    a2 += g[k + 2] * readlane_d(vr[k / 64], (k + 2) % 64);
+                    a3 += g[k + 3] * readlane_d(vr[k / 64], (k + 3) % 64);
+                    // keep the scheduler from hoisting every readlane (their
+                    // scalar results would not fit in the scalar registers)
+                    if (k % 8 == 4) __builtin_amdgcn_sched_barrier(0);
                 }
             } else {
                 int c = c0;
@@ -1154,21 +1381,13 @@ __global__ __launch_bounds__(kMbThreads) void lanczos_mb_kernel(int B, const LzJ
         const bool test_now = invariant || (m == next_test) || (m == mcap);
         __syncthreads();
         if (test_now) {
-            next_test = m + max(8, m / 4);
-            if (t < kWave) {
-                double lo, hi;
-                tri_top_fast(al, be, m, floor, &lo, &hi);
-                if (t == 0) {
-                    const double th = 0.5 * (lo + hi);
-                    const double shift = hi + (hi - lo) + 1e-13 * fabs(hi) + 1e-300;
-                    const double res = invariant ? 0.0 : tri_residual(al, be, m, shift, beta, tx, tw);
-                    s_theta = th;
-                    s_flag = invariant || (res <= 1e-12 * fabs(th));
-                }
-            }
+            if (t < kWave)
+                lz_test(al, be, m, beta, invariant, floor, tx, tw, m_prev, r_prev, &s_theta, &s_flag,
+                        &s_next);
             __syncthreads();
             theta = s_theta;
             floor = theta * (1.0 - 1e-14);
+            next_test = s_next;
             if (s_flag) break;
         }
         // next vector: v_prev <- v, v <- r / beta (buffers rotate)
