@@ -74,7 +74,11 @@ enum {
  *                   cores, flushed to FP64 and summed over row splits in
  *                   FP64; the diagonal, X^T y and y^T y in FP64.  Everything
  *                   after the Gram pass (standardisation, d, the paths, CV)
- *                   is FP64, exactly as in OEM_FP64, on this Gram.
+ *                   is FP64, exactly as in OEM_FP64, on this Gram.  A pass
+ *                   (one oem_gram call, one out-of-core chunk) over fewer
+ *                   than 32768 rows forms its products in FP64 instead: the
+ *                   BF16 rounding errors average over too few rows there to
+ *                   keep coefficients within 1e-6 of the FP64 form.
  *   OEM_BF16        as SPLIT_BF16 with the hi part only (reported variant). */
 enum { OEM_FP64 = 0, OEM_SPLIT_BF16 = 1, OEM_BF16 = 2 };
 
@@ -346,43 +350,74 @@ int oem_logistic_path(const void *X, int32_t x_dtype, int64_t n, int64_t ldx, in
 
 /* ------------------------------------------------------------------ batches
  * Many independent tall problems of uneven p fitted together (the same
- * penalties and path options for all).  Each problem is the full-data fit of
- * oem_fit_path: Gram pass, standardisation, d, lambda grid, warm-started
- * paths.  All problems' d are found by one Lanczos launch per kernel class
- * and all (problem, penalty) paths by one path launch per kernel class, so
- * the launch count does not grow with the number of problems. */
+ * penalties and path options for all).  Each problem is either the
+ * full-data fit of oem_fit_path (Gram pass, standardisation, d, lambda grid,
+ * warm-started paths) or, with nfolds >= 2, the K-fold cross validation of
+ * oem_cv from per-fold Grams (Section 3: the fold sums of one pass give every
+ * training Gram; folds x penalties x lambda paths, held-out error and the
+ * selection).  All problems' d (every fold's too) are found by one Lanczos
+ * launch per kernel class and all (problem, fold, penalty) paths by one path
+ * launch per kernel class, so the launch count does not grow with the number
+ * of problems or folds. */
 typedef struct {
     int32_t p;            /* columns, 1..4096 */
     int64_t n;            /* rows, 1..2^31-1 */
     int64_t ldx;          /* row stride of X, >= p */
     const void *X;        /* device, n x ldx row-major, element type x_dtype */
     const double *y;      /* device, n */
-    double *beta;         /* device output, npen x L x p (original scale) */
+    double *beta;         /* device output, npen x L x p (original scale; the
+                             full-data paths) */
     double *lambda;       /* device output, npen x L, or NULL */
-    int32_t *iters;       /* device output, npen x L, or NULL */
-    double *kkt;          /* device output, npen x L, or NULL */
-    double *obj;          /* device output, npen x L, or NULL */
+    int32_t *iters;       /* device output, npen x L (nfolds <= 1) or
+                             (K + 1) x npen x L (full data first, as oem_cv),
+                             or NULL */
+    double *kkt;          /* device output, npen x L (full data), or NULL */
+    double *obj;          /* device output, npen x L (full data), or NULL */
+    /* cross validation, groups and explicit lambda (zero / NULL: none) */
+    int32_t nfolds;       /* 0 or 1: full-data fit; 2..64: K-fold CV */
+    uint64_t fold_seed;   /* fold hash seed (nfolds >= 2) */
+    const int32_t *groups;    /* host, p group ids in [0, ngroups), every id
+                                 used (needed by group penalties), or NULL;
+                                 read by oem_batch_create only */
+    const double *lambda_in;  /* host, npen x L lambda values >= 0 used
+                                 instead of the grid, or NULL; read by
+                                 oem_batch_create only */
+    double *beta_folds;   /* device output, K x npen x L x p (training rows
+                             of fold k), or NULL */
+    double *cvm;          /* device output, npen x L: CV error (required when
+                             nfolds >= 2) */
+    double *cvsd;         /* device output, npen x L, or NULL */
+    int32_t *i_min;       /* device output, npen, or NULL */
+    int32_t *i_1se;       /* device output, npen, or NULL */
+    int32_t *best;        /* device output, 1 value (penalty of the smallest
+                             cvm), or NULL */
 } oem_problem;
 
 typedef struct oem_batch_s *oem_batch;
 
 /* Plan a batch: copies the nprob problem records (their X, y and output
- * pointers must stay valid while the batch is used), creates every device
- * buffer, tunes the Gram pass of each problem shape with n p >= 2^22
- * (oem_gram_autotune), and runs the batch once on the null stream.
- * Restrictions: opts->standardize = 1 (then d >= 1, so MCP gamma > 1 and
- * SCAD gamma > 2 are valid for every problem), no group penalties and no
- * explicit lambda (opts->groups, opts->lambda NULL).
- * Errors: OEM_E_INVAL (bad problem record or option, nprob < 1),
- * OEM_E_NOMEM, OEM_E_HIP. */
+ * pointers must stay valid while the batch is used; groups and lambda_in are
+ * read here only), creates every device buffer, tunes the Gram pass of each
+ * problem shape with n p >= 2^22 (oem_gram_autotune), and runs the batch
+ * once on the null stream, after which every cross-validation problem's
+ * folds are checked for training and held-out rows.
+ * Restrictions: opts->standardize = 1 (then d >= 1, so the MCP and SCAD
+ * conditions on gamma d hold for every problem), no intercept, and the
+ * per-problem fields instead of opts->groups, opts->lambda, opts->w and
+ * opts->cg (which must be NULL; group weights are sqrt(group size)).  Group
+ * penalties need every problem's groups.
+ * Errors: OEM_E_INVAL (bad problem record or option, nprob < 1, a fold with
+ * no training or no held-out rows), OEM_E_NOMEM, OEM_E_HIP. */
 int oem_batch_create(const oem_problem *probs, int32_t nprob, int32_t precision, int32_t x_dtype,
                      const oem_penalty *pen, int32_t npen, const oem_path_opts *opts,
                      oem_batch *out);
 
 /* Enqueue the whole batch on `stream`: per problem a Gram pass from zero
- * sums and the standardisation, then the batched Lanczos, lambda-grid and
- * path launches.  Kernels and device-to-device copies only: no allocation
- * and no host wait, so the sequence may be captured into a hipGraph. */
+ * sums (with fold sums for CV problems) and the standardisation of every
+ * fold, then the batched Lanczos, lambda-grid and path launches, then per CV
+ * problem the held-out error and selection kernels.  Kernels and
+ * device-to-device copies only: no allocation and no host wait, so the
+ * sequence may be captured into a hipGraph. */
 int oem_batch_run(oem_batch b, void *stream);
 
 /* The work of oem_batch_run captured into a hipGraph on the first call (on

@@ -70,7 +70,11 @@ class oem_path_opts(C.Structure):
 class oem_problem(C.Structure):
     _fields_ = [("p", C.c_int32), ("n", C.c_int64), ("ldx", C.c_int64), ("X", C.c_void_p),
                 ("y", C.c_void_p), ("beta", C.c_void_p), ("lambda_", C.c_void_p),
-                ("iters", C.c_void_p), ("kkt", C.c_void_p), ("obj", C.c_void_p)]
+                ("iters", C.c_void_p), ("kkt", C.c_void_p), ("obj", C.c_void_p),
+                ("nfolds", C.c_int32), ("fold_seed", C.c_uint64), ("groups", C.c_void_p),
+                ("lambda_in", C.c_void_p), ("beta_folds", C.c_void_p), ("cvm", C.c_void_p),
+                ("cvsd", C.c_void_p), ("i_min", C.c_void_p), ("i_1se", C.c_void_p),
+                ("best", C.c_void_p)]
 
 
 class oem_request(C.Structure):
@@ -511,7 +515,11 @@ class Batch:
     """Many independent problems of uneven p fitted together (oem_batch_*).
 
     ``problems`` is a list of (X, y) cuda tensors (X row-major, FP32 or FP64
-    for all).  Outputs are cuda tensors per problem, refreshed by run()."""
+    for all) or of dicts with keys X, y and optionally nfolds (>= 2: K-fold
+    CV), fold_seed, groups (p ints) and lambdas (npen x nlambda values used
+    instead of the grid).  Outputs are cuda tensors per problem, refreshed by
+    run(); CV problems also get beta_folds, cvm, cvsd, i_min, i_1se and best,
+    and their iters cover the full data and every fold."""
 
     def __init__(self, problems, penalties, precision: str = "fp64", nlambda: int = 100,
                  lambda_min_ratio: float = 1e-3, tol: float = 1e-10, maxit: int = 100000):
@@ -521,21 +529,45 @@ class Batch:
         self.pen_arr = (oem_penalty * len(pens))(*[q.c() for q in pens])
         self.opts = _Opts(nlambda, lambda_min_ratio, None, tol, maxit, True, None, None, None, False)
         f64 = dict(dtype=torch.float64, device="cuda")
-        self.inputs = [(X, y) for X, y in problems]          # keep the device memory alive
-        xd = OEM_X_F64 if problems[0][0].dtype == torch.float64 else OEM_X_F32
+        i32 = dict(dtype=torch.int32, device="cuda")
+        probs = [pr if isinstance(pr, dict) else dict(X=pr[0], y=pr[1]) for pr in problems]
+        self.inputs = [(pr["X"], pr["y"]) for pr in probs]     # keep the device memory alive
+        xd = OEM_X_F64 if probs[0]["X"].dtype == torch.float64 else OEM_X_F32
         self.out = []
+        self._host = []                                        # host arrays read by create
         recs = []
-        for X, y in problems:
+        for pr in probs:
+            X, y = pr["X"], pr["y"]
             n, p = X.shape
+            K = int(pr.get("nfolds", 0) or 0)
+            nq = K + 1 if K >= 2 else 1
             o = dict(beta=torch.zeros((self.npen, nlambda, p), **f64),
                      lambda_=torch.zeros((self.npen, nlambda), **f64),
-                     iters=torch.zeros((self.npen, nlambda), dtype=torch.int32, device="cuda"),
+                     iters=torch.zeros((nq, self.npen, nlambda) if K >= 2 else (self.npen, nlambda), **i32),
                      kkt=torch.zeros((self.npen, nlambda), **f64),
                      obj=torch.zeros((self.npen, nlambda), **f64))
+            if K >= 2:
+                o.update(beta_folds=torch.zeros((K, self.npen, nlambda, p), **f64),
+                         cvm=torch.zeros((self.npen, nlambda), **f64),
+                         cvsd=torch.zeros((self.npen, nlambda), **f64),
+                         i_min=torch.zeros(self.npen, **i32), i_1se=torch.zeros(self.npen, **i32),
+                         best=torch.zeros(1, **i32))
             self.out.append(o)
+            g = pr.get("groups")
+            g = None if g is None else np.ascontiguousarray(g, dtype=np.int32)
+            lam = pr.get("lambdas")
+            lam = None if lam is None else np.ascontiguousarray(lam, dtype=np.float64)
+            if lam is not None and lam.size != self.npen * nlambda:
+                raise OemError(OEM_E_INVAL, "lambdas must hold npen x nlambda values")
+            self._host.append((g, lam))
+            dp = lambda t: t.data_ptr() if t is not None else None
+            hp = lambda a: a.ctypes.data if a is not None else None
             recs.append(oem_problem(p, n, X.stride(0), X.data_ptr(), y.data_ptr(), o["beta"].data_ptr(),
                                     o["lambda_"].data_ptr(), o["iters"].data_ptr(), o["kkt"].data_ptr(),
-                                    o["obj"].data_ptr()))
+                                    o["obj"].data_ptr(), K, int(pr.get("fold_seed", 0)) & (2**64 - 1),
+                                    hp(g), hp(lam), dp(o.get("beta_folds")), dp(o.get("cvm")),
+                                    dp(o.get("cvsd")), dp(o.get("i_min")), dp(o.get("i_1se")),
+                                    dp(o.get("best"))))
         self.recs = (oem_problem * len(recs))(*recs)
         h = C.c_void_p()
         _check(load_library().oem_batch_create(self.recs, len(recs), PRECISION[precision], xd,

@@ -363,6 +363,10 @@ struct oem_batch_s {
     std::vector<oem::LzLaunch> lz;
     oem::PathPlan plan;
     std::vector<int32_t *> iters_of;   // per problem: where its iteration counts go
+    std::vector<size_t> iters_len;     // and how many there are
+    std::vector<oem::GroupPlan> groups;   // per problem (device copies in its handle)
+    std::vector<char> explicit_lam;    // per problem: lambda_in given (no grid)
+    std::vector<double *> beta_folds;  // per CV problem: fold coefficients
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
 };
@@ -824,15 +828,31 @@ int oem_batch_run(oem_batch b, void *stream)
     }
     int rc = launch_lanczos_jobs(b->jobs.as<LzJob>(), b->lz, s);
     if (rc) return rc;
-    for (oem_gram_s *h : b->hs) {
+    for (size_t i = 0; i < b->hs.size(); ++i) {
+        if (b->explicit_lam[i]) continue;
+        oem_gram_s *h = b->hs[i];
+        const GroupPlan &gp = b->groups[i];
         double *dl = h->lam.as<double>();
-        rc = launch_lambda_grid(h->cs.as<double>(), h->p, nullptr, nullptr, 0, nullptr, nullptr,
-                                reinterpret_cast<const oem_penalty *>(dl + nl), npen, L,
+        rc = launch_lambda_grid(h->cs.as<double>(), h->p, gp.d_gstart, gp.d_gidx, gp.ngroups, gp.d_w,
+                                gp.d_cg, reinterpret_cast<const oem_penalty *>(dl + nl), npen, L,
                                 b->opts.lambda_min_ratio, dl, s);
         if (rc) return rc;
     }
     rc = launch_paths_planned(b->descs.as<PathDesc>(), b->order.as<int>(), b->plan, s);
     if (rc) return rc;
+    // held-out error and selection of the cross-validation problems
+    for (size_t i = 0; i < b->hs.size(); ++i) {
+        oem_gram_s *h = b->hs[i];
+        const oem_problem &pr = b->probs[i];
+        if (h->K < 2) continue;
+        const int K = h->K;
+        double *mse = h->cvw.as<double>();
+        double *cvsd = pr.cvsd ? pr.cvsd : mse + nl * K;
+        rc = launch_cv(h->Gk.as<double>(), h->bk.as<double>(), h->yyk.as<double>(), h->nk.as<int64_t>(),
+                       h->csk.as<double>(), h->ysk.as<double>(), nullptr, K, h->p, npen, L, b->beta_folds[i],
+                       mse, pr.cvm, cvsd, pr.i_min, pr.i_1se, pr.best, s);
+        if (rc) return rc;
+    }
     for (size_t i = 0; i < b->hs.size(); ++i)
         if (b->probs[i].lambda)
             OEM_HIP_CHECK(hipMemcpyAsync(b->probs[i].lambda, b->hs[i]->lam.ptr, nl * sizeof(double),
@@ -867,10 +887,9 @@ int oem_batch_status(oem_batch b, void *stream)
     if (!b) return fail(OEM_E_INVAL, "batch is NULL");
     hipStream_t s = as_stream(stream);
     OEM_HIP_CHECK(hipStreamSynchronize(s));
-    const size_t nl = (size_t)b->npen * b->opts.nlambda;
-    std::vector<int32_t> it(nl);
-    for (int32_t *d : b->iters_of) {
-        OEM_HIP_CHECK(hipMemcpy(it.data(), d, nl * sizeof(int32_t), hipMemcpyDeviceToHost));
+    for (size_t i = 0; i < b->iters_of.size(); ++i) {
+        std::vector<int32_t> it(b->iters_len[i]);
+        OEM_HIP_CHECK(hipMemcpy(it.data(), b->iters_of[i], it.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
         for (int32_t v : it)
             if (v < 0) {
                 set_error("some lambda of some problem reached maxit before the convergence test held");
@@ -891,17 +910,28 @@ int oem_batch_create(const oem_problem *probs, int32_t nprob, int32_t precision,
     if (rc) return rc;
     if (!opts->standardize) return fail(OEM_E_INVAL, "batched fits need standardize = 1");
     if (opts->groups || opts->lambda || opts->w || opts->cg)
-        return fail(OEM_E_INVAL, "batched fits take no groups, weights or explicit lambda");
+        return fail(OEM_E_INVAL, "batched fits take groups and lambda per problem (opts->groups, lambda, w, cg "
+                                 "must be NULL)");
     if (opts->intercept) return fail(OEM_E_INVAL, "batched fits take no intercept");
+    bool need_groups = false;
     for (int i = 0; i < npen; ++i) {
-        if (group_penalty(pen[i].kind)) return fail(OEM_E_INVAL, "batched fits take no group penalty");
         rc = check_penalty(pen[i], 1.0);   // standardised: d >= 1
         if (rc) return rc;
+        need_groups |= group_penalty(pen[i].kind);
     }
+    const int L = opts->nlambda;
+    const size_t nl = (size_t)npen * L;
     for (int i = 0; i < nprob; ++i) {
         const oem_problem &q = probs[i];
+        const std::string who = "problem " + std::to_string(i) + ": ";
         if (q.p < 1 || q.p > 4096 || q.n < 1 || q.n > INT32_MAX || q.ldx < q.p || !q.X || !q.y || !q.beta)
-            return fail(OEM_E_INVAL, "problem " + std::to_string(i) + ": bad p, n, ldx or pointer");
+            return fail(OEM_E_INVAL, who + "bad p, n, ldx or pointer");
+        if (q.nfolds < 0 || q.nfolds > 64) return fail(OEM_E_INVAL, who + "nfolds must be in [0, 64]");
+        if (q.nfolds >= 2 && !q.cvm) return fail(OEM_E_INVAL, who + "cross validation needs cvm");
+        if (need_groups && !q.groups) return fail(OEM_E_INVAL, who + "a group penalty needs groups");
+        if (q.lambda_in)
+            for (size_t e = 0; e < nl; ++e)
+                if (!(q.lambda_in[e] >= 0.0)) return fail(OEM_E_INVAL, who + "lambda values must be >= 0");
     }
     oem_batch_s *b = new oem_batch_s();
     b->probs.assign(probs, probs + nprob);
@@ -911,26 +941,27 @@ int oem_batch_create(const oem_problem *probs, int32_t nprob, int32_t precision,
     b->pens.assign(pen, pen + npen);
     b->opts = *opts;
     b->opts.sync = 0;
-    const int L = opts->nlambda;
-    const size_t nl = (size_t)npen * L;
     hipStream_t s = nullptr;
     auto bail = [&](int code) {
         oem_batch_free(b);
         return code;
     };
+    auto nq_of = [](const oem_problem &q) { return q.nfolds >= 2 ? q.nfolds + 1 : 1; };
     // handles, tuning, buffers sized by one pass each
     size_t own_iters = 0;
     for (int i = 0; i < nprob; ++i)
-        if (!probs[i].iters) own_iters += nl;
+        if (!probs[i].iters) own_iters += nq_of(probs[i]) * nl;
     rc = b->iters_own.ensure(std::max<size_t>(own_iters, 1) * sizeof(int32_t));
     if (rc) return bail(rc);
     size_t own_off = 0;
     std::vector<LzJob> jobs;
     std::vector<PathDesc> descs;
+    b->groups.resize(nprob);
     for (int i = 0; i < nprob; ++i) {
         const oem_problem &q = b->probs[i];
+        const int K = q.nfolds >= 2 ? q.nfolds : 1, nq = nq_of(q);
         oem_gram_s *h = nullptr;
-        rc = oem_gram_create(q.p, 1, precision, x_dtype, 0, &h);
+        rc = oem_gram_create(q.p, K, precision, x_dtype, q.fold_seed, &h);
         if (rc) return bail(rc);
         b->hs.push_back(h);
         if ((double)q.n * q.p >= 4194304.0) {
@@ -939,26 +970,57 @@ int oem_batch_create(const oem_problem *probs, int32_t nprob, int32_t precision,
         }
         rc = launch_gram(h, q.X, q.n, q.ldx, q.y, 0, nullptr, s);
         if (rc) return bail(rc);
-        const size_t ws = lanczos_workspace_doubles(q.p);
-        if (ws) {
-            rc = h->lanczos.ensure(ws * sizeof(double));
-            if (rc) return bail(rc);
-        }
+        // groups of this problem (device copies in the handle)
+        oem_path_opts po = b->opts;
+        po.groups = q.groups;
+        GroupPlan &gp = b->groups[i];
+        rc = build_groups(h, &po, need_groups, gp, s);
+        if (rc) return bail(rc);
+        // lambda: the problem's own values, or the grid of every run
         rc = h->lam.ensure(nl * sizeof(double) + npen * sizeof(oem_penalty) + 64);
         if (rc) return bail(rc);
+        if (q.lambda_in) {
+            if (hipMemcpy(h->lam.ptr, q.lambda_in, nl * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
+                return bail(fail(OEM_E_HIP, "copying the lambda values failed"));
+        }
+        b->explicit_lam.push_back(q.lambda_in ? 1 : 0);
         if (hipMemcpy(h->lam.as<double>() + nl, pen, npen * sizeof(oem_penalty), hipMemcpyHostToDevice) != hipSuccess)
             return bail(fail(OEM_E_HIP, "copying the penalties failed"));
-        jobs.push_back(LzJob{h->Gs.as<double>(), ws ? h->lanczos.as<double>() : nullptr, h->dq.as<double>(),
-                             h->lzsteps.as<int32_t>(), q.p, lanczos_mmax(q.p)});
+        // d of the full data and of every fold's training rows
+        const size_t ws = lanczos_workspace_doubles(q.p);
+        if (ws) {
+            rc = h->lanczos.ensure((size_t)nq * ws * sizeof(double) + 64);
+            if (rc) return bail(rc);
+        }
+        const size_t pp = (size_t)q.p * q.p;
+        for (int g = 0; g < nq; ++g)
+            jobs.push_back(LzJob{h->Gs.as<double>() + g * pp, ws ? h->lanczos.as<double>() + g * ws : nullptr,
+                                 h->dq.as<double>() + g, h->lzsteps.as<int32_t>() + g, q.p, lanczos_mmax(q.p)});
         int32_t *it = q.iters ? q.iters : b->iters_own.as<int32_t>() + own_off;
-        if (!q.iters) own_off += nl;
+        if (!q.iters) own_off += nq * nl;
         b->iters_of.push_back(it);
-        GroupPlan gp;
-        for (int k = 0; k < npen; ++k)
-            descs.push_back(make_desc(h, 0, pen[k], &b->opts, gp, h->lam.as<double>() + (size_t)k * L,
-                                      q.beta + (size_t)k * L * q.p, it + (size_t)k * L,
-                                      q.kkt ? q.kkt + (size_t)k * L : nullptr,
-                                      q.obj ? q.obj + (size_t)k * L : nullptr));
+        b->iters_len.push_back(nq * nl);
+        double *bf = nullptr;
+        if (K >= 2) {
+            // fold coefficients (the caller's or the handle's), held-out error scratch
+            bf = q.beta_folds;
+            if (!bf) {
+                rc = h->betaw.ensure((size_t)K * nl * q.p * sizeof(double));
+                if (rc) return bail(rc);
+                bf = h->betaw.as<double>();
+            }
+            rc = h->cvw.ensure((nl * K + 2 * nl) * sizeof(double) + 64);
+            if (rc) return bail(rc);
+        }
+        b->beta_folds.push_back(bf);
+        for (int g = 0; g < nq; ++g)
+            for (int k = 0; k < npen; ++k) {
+                double *beta = g == 0 ? q.beta + (size_t)k * L * q.p : bf + ((size_t)(g - 1) * npen + k) * L * q.p;
+                descs.push_back(make_desc(h, g, pen[k], &po, gp, h->lam.as<double>() + (size_t)k * L, beta,
+                                          it + ((size_t)g * npen + k) * L,
+                                          (g == 0 && q.kkt) ? q.kkt + (size_t)k * L : nullptr,
+                                          (g == 0 && q.obj) ? q.obj + (size_t)k * L : nullptr));
+            }
     }
     lanczos_job_plan(jobs, b->lz);
     rc = attach_path_handover(descs, b->pathws);
@@ -977,6 +1039,18 @@ int oem_batch_create(const oem_problem *probs, int32_t nprob, int32_t precision,
     rc = oem_batch_run(b, nullptr);
     if (rc) return bail(rc);
     if (hipDeviceSynchronize() != hipSuccess) return bail(fail(OEM_E_HIP, "the first batch run failed"));
+    // every fold of a CV problem needs training rows and held-out rows
+    for (int i = 0; i < nprob; ++i) {
+        oem_gram_s *h = b->hs[i];
+        if (h->K < 2) continue;
+        std::vector<int64_t> nt(h->K + 1);
+        if (hipMemcpy(nt.data(), h->ntrain.ptr, nt.size() * sizeof(int64_t), hipMemcpyDeviceToHost) != hipSuccess)
+            return bail(fail(OEM_E_HIP, "reading the fold row counts failed"));
+        for (int k = 0; k < h->K; ++k)
+            if (nt[1 + k] <= 0 || nt[0] - nt[1 + k] <= 0)
+                return bail(fail(OEM_E_INVAL, "problem " + std::to_string(i) + ": fold " + std::to_string(k) +
+                                                  " has no training or no held-out rows"));
+    }
     *out = b;
     return OEM_OK;
 }

@@ -1178,8 +1178,9 @@ static int launch_lz_class(int cls, int count, int pmax, int p_all, const double
 // The barrier is an arrival counter per problem with a bounded wait (a wait
 // that runs out makes d NaN): each wave waits for its own stores, thread 0
 // releases, arrives, polls with relaxed loads and acquires once.  It needs
-// every workgroup of the launch resident at once, which the launcher checks
-// against the occupancy of the GPU.
+// every workgroup of the launch resident at once: the launcher sizes each
+// launch from the occupancy of the GPU, splitting a table of many problems
+// into several launches.
 constexpr int kMbRows = 64;
 constexpr int kMbWaves = 4;
 constexpr int kMbThreads = 64 * kMbWaves;
@@ -1463,13 +1464,19 @@ static int launch_lanczos_mb(const LzJob *d_jobs, int count, int pmax, hipStream
     OEM_HIP_CHECK(hipGetDevice(&dev));
     OEM_HIP_CHECK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
     OEM_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kMbThreads, lds));
-    const long grid = (long)count * B;
-    if (per_cu < 1 || grid > (long)per_cu * ncu) return 1;
-    hipLaunchKernelGGL(lanczos_mb_reset_kernel, dim3((count + 63) / 64), dim3(64), 0, s, count, d_jobs);
-    OEM_HIP_CHECK(hipGetLastError());
-    int b_arg = B;
-    void *args[] = {(void *)&b_arg, (void *)&d_jobs};
-    OEM_HIP_CHECK(hipLaunchKernel(kern, dim3((unsigned)grid), dim3(kMbThreads), args, lds, s));
+    // every workgroup of a launch must be resident at once: the problems go
+    // in chunks of as many as the GPU holds, one launch after another
+    const long fit = per_cu < 1 ? 0 : (long)per_cu * ncu / B;
+    if (fit < 1) return 1;
+    for (int c0 = 0; c0 < count; c0 += (int)fit) {
+        const int cn = (int)std::min<long>(fit, count - c0);
+        const LzJob *cj = d_jobs + c0;
+        hipLaunchKernelGGL(lanczos_mb_reset_kernel, dim3((cn + 63) / 64), dim3(64), 0, s, cn, cj);
+        OEM_HIP_CHECK(hipGetLastError());
+        int b_arg = B;
+        void *args[] = {(void *)&b_arg, (void *)&cj};
+        OEM_HIP_CHECK(hipLaunchKernel(kern, dim3((unsigned)((long)cn * B)), dim3(kMbThreads), args, lds, s));
+    }
     return OEM_OK;
 }
 

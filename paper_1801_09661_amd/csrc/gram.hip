@@ -508,7 +508,7 @@ static size_t f64_partial_bytes(const GramGeom &g)
 
 size_t gram_work_bytes(const oem_gram_s *h, int64_t n)
 {
-    if (h->prec != OEM_FP64) {
+    if (!gram_pass_fp64(h->prec, n)) {
         // same row-list plan as the BF16 pass (its geometry differs only in tiles)
         return gram_bf16_work_bytes(h->prec, h->p, h->K, n);
     }
@@ -541,7 +541,7 @@ static int launch_gram_any(oem_gram_s *h, const void *X, int64_t n, int64_t ldx,
                            int64_t row_offset, const uint8_t *foldid, hipStream_t s, GramWork *ws,
                            const CsrIn *csr, const double *wts)
 {
-    if (h->prec != OEM_FP64) return launch_gram_bf16(h, X, n, ldx, y, row_offset, foldid, s, ws);
+    if (!gram_pass_fp64(h->prec, n)) return launch_gram_bf16(h, X, n, ldx, y, row_offset, foldid, s, ws);
     const GramGeom g = plan_f64(h->prec, h->p, h->K, n);
     RowSource rs;
     int rc = build_row_lists(h, g, n, row_offset, foldid, rs, s, ws);

@@ -111,6 +111,18 @@ __host__ __device__ inline int gram_col_read(const GramColPlan &c, int col, int 
 // Target number of workgroups of a Gram pass (about two per CU by default;
 // oem_gram_autotune may pick another for a shape).
 constexpr int kGramDefaultTarget = 512;
+// The split-BF16 form forms the products of a pass over fewer rows than this
+// in FP64: the rounding errors of its BF16 parts (about 2^-17 relative per
+// product, zero-mean) average over the rows of the pass, and below this many
+// rows they move coefficients by more than 1e-6 relative (up to 5e-6 at
+// 3600 rows, measured against the FP64 form), while the FP64 pass of so few
+// rows is cheap.
+constexpr int64_t kSplitMinRows = 32768;
+// Whether a pass of n rows of this handle runs on the FP64 kernels.
+inline bool gram_pass_fp64(int prec, int64_t n)
+{
+    return prec == OEM_FP64 || (prec == OEM_SPLIT_BF16 && n < kSplitMinRows);
+}
 int gram_target(int prec, int K, int p, int64_t n);
 void gram_set_target(int prec, int K, int p, int64_t n, int target);
 // Build per-(fold, split) ordered row lists for rows 0..n-1.

@@ -60,7 +60,7 @@ size_t path_ws_lds_bytes(int NW, int pcap)
 {
     const int C = NW * kWsCB, PSC = ws_pow2(pcap);
     const size_t gl = NW == 1 ? (size_t)pcap * pcap : 0;
-    const size_t dbl = 2 * (size_t)C + 8 * (size_t)NW + 4 * (size_t)NW + 6 * (size_t)pcap + PSC + C + gl;
+    const size_t dbl = 2 * (size_t)C + 8 * (size_t)NW + 4 * (size_t)NW + 6 * (size_t)pcap + PSC + 2 * (size_t)C + gl;
     const size_t ints = (size_t)PSC + 2 * (size_t)pcap + 2 * (size_t)C + 2 * (size_t)C + 16 + 2 * (size_t)NW;
     return dbl * sizeof(double) + ints * sizeof(int) + 64;
 }
@@ -90,7 +90,8 @@ __device__ __forceinline__ void path_ws_body(const PathDesc &P, int first, int p
     double *cl = ab + C;                      // [pcap] c
     double *scl = cl + pcap;                  // [pcap] column scales
     double *wl = scl + pcap;                  // [pcap] penalty weights
-    double *gls = wl + pcap;                  // [pcap pcap] G (one-wave kernel only)
+    double *usq = wl + pcap;                  // [NW][CB] u^2 of each wave's slots (group lasso)
+    double *gls = usq + C;                    // [pcap pcap] G (one-wave kernel only)
     int *kid = reinterpret_cast<int *>(gls + (NW == 1 ? pcap * pcap : 0));   // [PSC] coordinate (group) of each key
     int *slot_of = kid + PSC;                 // [pcap] slot of each coordinate, -1 outside W
     int *gof = slot_of + pcap;                // [pcap] group of each coordinate
@@ -199,14 +200,21 @@ __device__ __forceinline__ void path_ws_body(const PathDesc &P, int first, int p
     auto symv = [&](int buf) -> double {
         const double *bb = bsl + buf * C + half * HC;
         double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        // the operand reads of a block of 16 columns are issued together
+        // (one LDS latency per block rather than per pair of reads)
+        constexpr int SB = HC < 16 ? HC : 16;
 #pragma unroll
-        for (int c = 0; c < HC; c += 4) {
-            const double2 v0 = *reinterpret_cast<const double2 *>(bb + c);
-            const double2 v1 = *reinterpret_cast<const double2 *>(bb + c + 2);
-            a0 += Gr[c] * v0.x;
-            a1 += Gr[c + 1] * v0.y;
-            a2 += Gr[c + 2] * v1.x;
-            a3 += Gr[c + 3] * v1.y;
+        for (int c0 = 0; c0 < HC; c0 += SB) {
+            double2 vb[SB / 2];
+#pragma unroll
+            for (int u = 0; u < SB / 2; ++u) vb[u] = *reinterpret_cast<const double2 *>(bb + c0 + 2 * u);
+#pragma unroll
+            for (int u = 0; u < SB / 2; u += 2) {
+                a0 += Gr[c0 + 2 * u] * vb[u].x;
+                a1 += Gr[c0 + 2 * u + 1] * vb[u].y;
+                a2 += Gr[c0 + 2 * u + 2] * vb[u + 1].x;
+                a3 += Gr[c0 + 2 * u + 3] * vb[u + 1].y;
+            }
         }
         const double sh = (a0 + a1) + (a2 + a3);
         const int lo = __double2loint(sh), hi = __double2hiint(sh);
@@ -626,12 +634,20 @@ __device__ __forceinline__ void path_ws_body(const PathDesc &P, int first, int p
             const double u = ct + (d * bt - gb);
             double bn;
             if (grp) {
-                // the slot's group lies in lanes [gA, gB) of the first half
+                // the slot's group lies in lanes [gA, gB) of the first half;
+                // u^2 of the wave's slots goes through LDS and each lane reads
+                // its group's entries in blocks of 8 independent reads (LDS
+                // operations of one wave complete in order, so no barrier)
+                double *uq = usq + wave * CB;
+                if (half == 0) uq[lane] = u * u;
                 double ss = 0.0;
-                for (int k = 0; k < gmaxw; ++k) {
-                    const int src = min(gA + k, 63);
-                    const double v = __shfl(u, src);
-                    if (gA + k < gB) ss += v * v;
+                for (int k0 = 0; k0 < gmaxw; k0 += 8) {
+                    double qv[8];
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) qv[k] = uq[min(gA + k0 + k, CB - 1)];
+#pragma unroll
+                    for (int k = 0; k < 8; ++k)
+                        if (k0 + k < gmaxw && gA + k0 + k < gB) ss += qv[k];
                 }
                 const double nrm = sqrt(ss);
                 const double f = nrm > 0.0 ? 1.0 - lamc / nrm : 0.0;
@@ -665,16 +681,23 @@ __device__ __forceinline__ void path_ws_body(const PathDesc &P, int first, int p
                     dm[(nxt * NW + wave) * 4 + 2] = dw ? 1.0 : 0.0;
                 }
                 sync();
-                double DL = dm[nxt * NW * 4], MX = dm[nxt * NW * 4 + 1], DF = dm[nxt * NW * 4 + 2];
+                // the per-wave values are read, and the next product's
+                // operand reads go out with them (neither waits for the other)
+                double dmv[NW][3];
+#pragma unroll
+                for (int w = 0; w < NW; ++w)
+#pragma unroll
+                    for (int e = 0; e < 3; ++e) dmv[w][e] = dm[(nxt * NW + w) * 4 + e];
+                gb = symv(nxt);
+                double DL = dmv[0][0], MX = dmv[0][1], DF = dmv[0][2];
 #pragma unroll
                 for (int w = 1; w < NW; ++w) {
-                    DL = fmax(DL, dm[(nxt * NW + w) * 4]);
-                    MX = fmax(MX, dm[(nxt * NW + w) * 4 + 1]);
-                    DF = fmax(DF, dm[(nxt * NW + w) * 4 + 2]);
+                    DL = fmax(DL, dmv[w][0]);
+                    MX = fmax(MX, dmv[w][1]);
+                    DF = fmax(DF, dmv[w][2]);
                 }
                 conv = DL <= P.tol * MX;
                 drift = DF > 0.0;
-                gb = symv(nxt);
             }
             cur = nxt;
             if (!conv && it < P.maxit && drift) {

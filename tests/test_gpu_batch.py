@@ -173,3 +173,131 @@ def test_batch_large_p_graph_and_single_fit_agree():
         one = oem.fit(X, y, ["lasso"], **kw)
         _assert_close(one["beta"].cpu().numpy(), eager[k], TOL, f"single fit p={X.shape[1]}")
         assert np.isfinite(one["d"].item())
+
+
+# Cross validation, groups and explicit lambda inside one batch: each CV
+# problem is oem_cv's computation (per-fold training Grams from one pass,
+# fold paths on the full-data lambda, held-out error, selection), so the
+# tolerances of the single-handle CV test apply per problem; the plain
+# problem is a full-data fit.
+CV_SPECS = [  # (p, nfolds, fold seed, explicit lambda)
+    (40, 5, 101, False),
+    (130, 4, 202, True),
+    (70, 0, 0, False),
+    (260, 3, 303, False),
+]
+CV_PENS = ["lasso", dict(kind="grp_lasso"), dict(kind="mcp", gamma=3.0)]
+
+
+def _cv_select_ok(got, ref):
+    cvm = got["cvm"].cpu().numpy()
+    assert np.allclose(cvm, ref["cvm"], rtol=1e-9, atol=0)
+    assert np.allclose(got["cvsd"].cpu().numpy(), ref["cvsd"], rtol=1e-6, atol=1e-14)
+    im, i1 = got["i_min"].cpu().numpy(), got["i_1se"].cpu().numpy()
+    for q in range(cvm.shape[0]):
+        a, b = int(im[q]), int(ref["i_min"][q])
+        assert a == b or abs(ref["cvm"][q, a] - ref["cvm"][q, b]) <= 1e-9 * ref["cvm"][q, b]
+        thr = ref["cvm"][q, ref["i_min"][q]] + ref["cvsd"][q, ref["i_min"][q]]
+        a, b = int(i1[q]), int(ref["i_1se"][q])
+        assert a == b or abs(ref["cvm"][q, a] - thr) <= 1e-9 * thr or abs(ref["cvm"][q, b] - thr) <= 1e-9 * thr
+    bst = int(got["best"].item())
+    assert bst == ref["best"] or abs(ref["cvm"][bst].min() - ref["cvm"][ref["best"]].min()) <= 1e-9
+
+
+def test_batch_cv_groups_explicit_lambda_matches_oracle_and_replays():
+    oem = _oem()
+    L = 12
+    print(f"case: batch CV/groups/explicit lambda specs={CV_SPECS}", flush=True)
+    probs, refs = [], []
+    for i, (p, K, seed, explicit) in enumerate(CV_SPECS):
+        pr = workloads.batched_uneven_problem(40 + i, max(4000, 30 * p), p, seed_tag=9)
+        groups = (np.arange(p) // 5).astype(np.int32)
+        lam = None
+        if explicit:
+            lam = np.tile(np.geomspace(0.3, 0.003, L), (len(CV_PENS), 1))
+        d = dict(X=torch.from_numpy(pr.X).cuda(), y=torch.from_numpy(pr.y).cuda(), groups=groups)
+        if K >= 2:
+            d.update(nfolds=K, fold_seed=seed)
+            refs.append(oracle.cv(pr.X, pr.y, K, seed, CV_PENS, groups=groups, nlambda=L, lambdas=lam,
+                                  tol=1e-10))
+        else:
+            refs.append(oracle.fit(pr.X, pr.y, CV_PENS, groups=groups, nlambda=L, lambdas=lam, tol=1e-10))
+        if lam is not None:
+            d["lambdas"] = lam
+        probs.append(d)
+    with oem.Batch(probs, CV_PENS, precision="fp64", nlambda=L, tol=1e-10) as b:
+        assert b.status() == oem.OEM_OK
+        eager = [{k: v.clone() for k, v in o.items()} for o in b.out]
+        for (p, K, _, explicit), o, ref in zip(CV_SPECS, b.out, refs):
+            full = ref["full"] if K >= 2 else ref
+            assert np.allclose(o["lambda_"].cpu().numpy(), full["lambda"], rtol=1e-13, atol=0)
+            _assert_close(o["beta"].cpu().numpy(), full["beta"], TOL, f"p={p} full")
+            if K >= 2:
+                bf = o["beta_folds"].cpu().numpy()
+                for k in range(K):
+                    _assert_close(bf[k], ref["folds"][k]["beta"], TOL, f"p={p} fold {k}")
+                _cv_select_ok(o, ref)
+                assert o["iters"].shape == (K + 1, len(CV_PENS), L)
+            else:
+                assert np.all(o["kkt"].cpu().numpy() <= 1e-8)
+        # graph replays, with eager work of the program between them, give
+        # the eager run's outputs bit for bit
+        s = torch.cuda.Stream()
+        for rep in range(3):
+            with torch.cuda.stream(s):
+                b.run(graph=True, stream=s)
+            s.synchronize()
+            junk = torch.randn(1 << 20, device="cuda").sum().item()
+            assert np.isfinite(junk)
+            for o, e in zip(b.out, eager):
+                for k in e:
+                    assert torch.equal(o[k], e[k]), (rep, k)
+
+
+def test_batch_cv_rejects_bad_records():
+    oem = _oem()
+    pr = workloads.batched_uneven_problem(50, 3000, 20, seed_tag=9)
+    X, y = torch.from_numpy(pr.X).cuda(), torch.from_numpy(pr.y).cuda()
+    with pytest.raises(oem.OemError) as e:      # group penalty without groups
+        oem.Batch([dict(X=X, y=y)], [dict(kind="grp_lasso")], nlambda=5)
+    assert e.value.code == oem.OEM_E_INVAL
+    with pytest.raises(oem.OemError) as e:      # more folds than allowed
+        oem.Batch([dict(X=X, y=y, nfolds=65)], ["lasso"], nlambda=5)
+    assert e.value.code == oem.OEM_E_INVAL
+    with pytest.raises(oem.OemError) as e:      # negative explicit lambda
+        oem.Batch([dict(X=X, y=y, lambdas=-np.ones((1, 5)))], ["lasso"], nlambda=5)
+    assert e.value.code == oem.OEM_E_INVAL
+    with pytest.raises(oem.OemError) as e:      # a fold without held-out rows
+        oem.Batch([dict(X=X[:3], y=y[:3], nfolds=8, fold_seed=1)], ["lasso"], nlambda=5)
+    assert e.value.code == oem.OEM_E_INVAL
+
+
+def test_batch_config_shape_mixed_within_1e6_of_fp64_form():
+    """Problems of the batched uneven workload itself (n = 200 p, column
+    scales in [0.1, 10]): its smallest-n problems, where the split-BF16
+    rounding errors average over the fewest rows (up to 5e-6 at n = 3600
+    with BF16 products), and its largest; every problem's coefficients in the
+    split-BF16 form within 1e-6 (relative to each solution's largest) of the
+    FP64 form, lambda 2..L, with equal active sets."""
+    oem = _oem()
+    shapes = workloads.batched_uneven_shapes(64)
+    order = sorted(range(64), key=lambda i: shapes[i][1])
+    pick = order[:6] + order[-2:]
+    print(f"case: batch split-BF16 vs FP64 form, problems {pick}", flush=True)
+    dev = []
+    for i in pick:
+        n, p = shapes[i]
+        pr = workloads.batched_uneven_problem(i, n, p)
+        dev.append((torch.from_numpy(pr.X).cuda(), torch.from_numpy(pr.y).cuda()))
+        del pr
+    out = {}
+    for prec in ["fp64", "split_bf16"]:
+        with oem.Batch(dev, ["lasso"], precision=prec, nlambda=100, tol=TOL) as b:
+            assert b.status() == oem.OEM_OK
+            out[prec] = [o["beta"].cpu().numpy() for o in b.out]
+    for i, bf, bm in zip(pick, out["fp64"], out["split_bf16"]):
+        scale = np.maximum(np.abs(bf).max(axis=2), 1e-300)
+        err = (np.abs(bm - bf).max(axis=2) / scale)[:, 1:].max()
+        print(f"  problem {i} p={shapes[i][1]} n={shapes[i][0]}: {err:.2e}")
+        assert err <= 1e-6, (i, err)
+        assert np.array_equal(bm[:, 1:] != 0, bf[:, 1:] != 0), i
