@@ -894,6 +894,11 @@ def serve_main(args):
         "x_gb_per_s": xbytes / span / 1e9, "requests": len(done),
         "not_ok": int(sum(d["status"] != 0 for d in done)), "setup_s": t_setup,
         "coef_err_vs_fp64_oracle_sample": worst, "sample": len(sample),
+        "slowest_device": [dict(id=int(d["id"]), p=reqs[d["id"]].p, n=reqs[d["id"]].n,
+                                penalty=reqs[d["id"]].penalty, nfolds=reqs[d["id"]].nfolds,
+                                device_ms=float((d["t_done"] - d["t_admit"]) * 1e3))
+                           for d in sorted(done, key=lambda d: d["t_admit"] - d["t_done"])[:6]],
+        "device_s_total": float(dev.sum()),
         "cpu_baseline": dict(value=len(sample) / max(time.perf_counter() - t_oracle, 1e-9), unit="requests/s",
                              cores=1, kind="oracle",
                              sample=f"{len(sample)} plain fit requests with p <= 120, n <= 60000 (row-loop "

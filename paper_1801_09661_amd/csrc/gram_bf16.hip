@@ -25,8 +25,8 @@
 //          of the tile pairs, a k-group every other 16-row k-step, so each
 //          wave reads a tile's operands once per k-step for several pairs;
 //          the two k-groups' FP32 accumulators are added through LDS, in
-//          wave order, when the workgroup finishes.  Diagonal and
-//          off-diagonal super-block pairs are separate kernel launches.
+//          wave order, when the workgroup finishes.  One launch covers the
+//          diagonal and the off-diagonal super-block pairs.
 // Partial tiles are FP32 and are summed over row splits in FP64 in a fixed
 // order (deterministic, no floating-point atomics).
 #include "gram_common.h"
@@ -127,48 +127,36 @@ __device__ inline f32x16_t mfma3(f32x16_t acc, const bf16x8_t &ah, const bf16x8_
     return acc;
 }
 
-// SPLIT: split-BF16 (else single BF16).  DIAG: the launch over diagonal
-// super-blocks (which also accumulates the FP64 diagonal, X^T y, y^T y, n).
-// LIST: rows come from per-(fold, split) row lists (else the contiguous rows
-// of the split).  VEC: 16-byte loads (X 4-byte aligned).
+// The work of one workgroup: super-block pair (I, J) of row split s of fold
+// k.  SPLIT: split-BF16 (else single BF16).  DIAG: a diagonal super-block
+// (I = J; it also accumulates the FP64 diagonal, X^T y, y^T y, n and the
+// column sums).  LIST: rows come from per-(fold, split) row lists (else the
+// contiguous rows of the split).  VEC: 16-byte loads (X 4-byte aligned).
 template <bool SPLIT, bool DIAG, bool LIST, bool VEC>
-__global__ __launch_bounds__(kBThreads) void gram_bf16_kernel(
-    const float *__restrict__ X, int64_t n, int64_t ldx, const double *__restrict__ y, GramGeom g,
-    RowSource rs, float *__restrict__ partial, double *__restrict__ pvec, double *__restrict__ pscal)
+__device__ __forceinline__ void gram_bf16_block(
+    const float *__restrict__ X, int64_t n, int64_t ldx, const double *__restrict__ y, const GramGeom &g,
+    const RowSource &rs, float *__restrict__ partial, double *__restrict__ pvec, double *__restrict__ pscal,
+    int k, int s, int I, int J, bool first_block)
 {
     constexpr int NSLOT = DIAG ? 5 : 8;
     extern __shared__ char smem_raw[];
     const int lane = threadIdx.x % kWave;
     const int wave = threadIdx.x / kWave;
     const int q4 = threadIdx.x % 32, rg = threadIdx.x / 32;
-
-    // diagonal launch: blocks (k, s, I); off-diagonal launch: (k, s, I < J)
-    const int nq = DIAG ? g.nsb : g.npsb - g.nsb;
-    const int L = xcd_logical(blockIdx.x, gridDim.x);
-    const int qq = L % nq;
-    const int rest = L / nq;
-    const int s = rest % g.nsplit;
-    const int k = rest / g.nsplit;
-    int I = 0, J = 0;
-    if (DIAG) {
-        I = J = qq;
-    } else {
-        int t = qq;
-        for (I = 0; I < g.nsb; ++I) {
-            const int cnt = g.nsb - I - 1;
-            if (t < cnt) { J = I + 1 + t; break; }
-            t -= cnt;
-        }
-    }
-    const bool first_block = DIAG && (qq == 0);
     const int Wi = min(g.W, g.T - I * g.W);
     const int Wj = min(g.W, g.T - J * g.W);
 
     const int panel_elems = kBPanel * kBRows;
-    __bf16 *hiA = reinterpret_cast<__bf16 *>(smem_raw);
-    __bf16 *loA = hiA + panel_elems;
-    __bf16 *hiB = DIAG ? hiA : loA + panel_elems;
-    __bf16 *loB = DIAG ? loA : hiB + panel_elems;
+    // one staging buffer and one chunk of loads in flight (a second buffer
+    // and a second chunk of loads were measured to gain nothing here)
+    constexpr int NB = 1;
+    constexpr int npan = DIAG ? 2 : 4;
+    auto panels = [&](int b, __bf16 *&hA, __bf16 *&lA, __bf16 *&hB, __bf16 *&lB) {
+        hA = reinterpret_cast<__bf16 *>(smem_raw) + (size_t)b * npan * panel_elems;
+        lA = hA + panel_elems;
+        hB = DIAG ? hA : lA + panel_elems;
+        lB = DIAG ? lA : hB + panel_elems;
+    };
 
     // waves 2 pg, 2 pg + 1 form pair group pg and split the k-steps in two
     const int pg = wave / 2;
@@ -188,9 +176,10 @@ __global__ __launch_bounds__(kBThreads) void gram_bf16_kernel(
     double sd[4] = {0.0, 0.0, 0.0, 0.0}, sxy[4] = {0.0, 0.0, 0.0, 0.0}, syy = 0.0;
     double sx[4] = {0.0, 0.0, 0.0, 0.0}, sy = 0.0;   // column sums and sum of y
 
-    float xa[8][4], xb[8][4];
-    double yv[8];
-    int32_t nidx[8];      // row list entries of the next chunk (LIST)
+    // the loads of the chunk in flight (one register set: NB = 1)
+    float xa[NB][8][4], xb[NB][8][4];
+    double yv[NB][8];
+    int32_t nidx[8];      // row list entries of the next chunk to load (LIST)
     auto load_index = [&](int c) {
         if constexpr (LIST) {
 #pragma unroll
@@ -200,50 +189,52 @@ __global__ __launch_bounds__(kBThreads) void gram_bf16_kernel(
             }
         }
     };
-    auto load_chunk = [&](int c) {
+    auto load_chunk = [&](int c, int r) {
         int64_t row[8];
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
             if constexpr (LIST) row[e] = nidx[e];
             else row[e] = first + min((int64_t)c * kBRows + 8 * rg + e, count - 1);
         }
-        load_block<VEC>(xa, X, ldx, g.p, colA, row);
-        if (!DIAG) load_block<VEC>(xb, X, ldx, g.p, colB, row);
+        load_block<VEC>(xa[r], X, ldx, g.p, colA, row);
+        if (!DIAG) load_block<VEC>(xb[r], X, ldx, g.p, colB, row);
         if (DIAG) {
 #pragma unroll
-            for (int e = 0; e < 8; ++e) yv[e] = y[row[e]];
+            for (int e = 0; e < 8; ++e) yv[r][e] = y[row[e]];
         }
     };
     // rows past the end of the split were read as copies of its last row
-    auto clear_tail = [&](int c) {
+    auto clear_tail = [&](int c, int r) {
         const int64_t r0 = (int64_t)c * kBRows + 8 * rg;
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
             if (r0 + e >= count) {
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
-                    xa[e][j] = 0.0f;
-                    if (!DIAG) xb[e][j] = 0.0f;
+                    xa[r][e][j] = 0.0f;
+                    if (!DIAG) xb[r][e][j] = 0.0f;
                 }
-                if (DIAG) yv[e] = 0.0;
+                if (DIAG) yv[r][e] = 0.0;
             }
         }
     };
-    auto stage_chunk = [&]() {
-        stage_block<SPLIT>(xa, hiA, loA, q4, rg);
-        if (!DIAG) stage_block<SPLIT>(xb, hiB, loB, q4, rg);
+    auto stage_chunk = [&](int r) {
+        __bf16 *hA, *lA, *hB, *lB;
+        panels(r, hA, lA, hB, lB);
+        stage_block<SPLIT>(xa[r], hA, lA, q4, rg);
+        if (!DIAG) stage_block<SPLIT>(xb[r], hB, lB, q4, rg);
         if (DIAG) {
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
-                    const double xd = (double)xa[e][j];
+                    const double xd = (double)xa[r][e][j];
                     sd[j] += xd * xd;
-                    sxy[j] += xd * yv[e];
+                    sxy[j] += xd * yv[r][e];
                     sx[j] += xd;
                 }
-                syy += yv[e] * yv[e];
-                sy += yv[e];
+                syy += yv[r][e] * yv[r][e];
+                sy += yv[r][e];
             }
         }
     };
@@ -252,7 +243,9 @@ __global__ __launch_bounds__(kBThreads) void gram_bf16_kernel(
         const int slot = 2 * ks + lane / 32;
         return *reinterpret_cast<const bf16x8_t *>(panel + c * kBRows + 8 * (slot ^ bswz(c)));
     };
-    auto mma_chunk = [&]() {
+    auto mma_chunk = [&](int r) {
+        __bf16 *hiA, *loA, *hiB, *loB;
+        panels(r, hiA, loA, hiB, loB);
 #pragma unroll
         for (int kh = 0; kh < kBRows / 32; ++kh) {
             const int ks = 2 * kh + ks0;
@@ -302,21 +295,20 @@ __global__ __launch_bounds__(kBThreads) void gram_bf16_kernel(
             }
         }
     };
-
     if (nchunks > 0) {
         load_index(0);
-        load_chunk(0);
+        load_chunk(0, 0);
         load_index(1);
     }
     for (int c = 0; c < nchunks; ++c) {
-        if ((int64_t)(c + 1) * kBRows > count) clear_tail(c);
-        stage_chunk();
+        if ((int64_t)(c + 1) * kBRows > count) clear_tail(c, 0);
+        stage_chunk(0);
         __syncthreads();
         if (c + 1 < nchunks) {
-            load_chunk(c + 1);   // in flight during the MFMAs
+            load_chunk(c + 1, 0);   // in flight during the products
             load_index(c + 2);
         }
-        mma_chunk();
+        mma_chunk(0);
         __syncthreads();
     }
 
@@ -389,6 +381,36 @@ __global__ __launch_bounds__(kBThreads) void gram_bf16_kernel(
             pscal[part_id * 3 + 1] = (double)count;
             pscal[part_id * 3 + 2] = u;
         }
+    }
+}
+
+// One launch covers every (fold, row split, super-block pair).  The npsb
+// pairs of one (fold, split) read the same rows; they take consecutive
+// logical block numbers, which round-robin dispatch places on one XCD, so
+// they run side by side and the rows come from HBM about once and from that
+// XCD's L2 for the other pairs.  The diagonal pairs come first in each group.
+// OFF: the geometry has off-diagonal pairs (p > 128); without them the kernel
+// holds only the diagonal code and its smaller register set.
+template <bool SPLIT, bool LIST, bool VEC, bool OFF>
+__global__ __launch_bounds__(kBThreads) void gram_bf16_kernel(
+    const float *__restrict__ X, int64_t n, int64_t ldx, const double *__restrict__ y, GramGeom g,
+    RowSource rs, float *__restrict__ partial, double *__restrict__ pvec, double *__restrict__ pscal)
+{
+    const int L = xcd_logical(blockIdx.x, gridDim.x);
+    const int qq = L % g.npsb;
+    const int rest = L / g.npsb;
+    const int s = rest % g.nsplit;
+    const int k = rest / g.nsplit;
+    if (!OFF || qq < g.nsb) {
+        gram_bf16_block<SPLIT, true, LIST, VEC>(X, n, ldx, y, g, rs, partial, pvec, pscal, k, s, qq, qq, qq == 0);
+    } else if constexpr (OFF) {
+        int t = qq - g.nsb, I = 0, J = 0;
+        for (I = 0; I < g.nsb; ++I) {
+            const int cnt = g.nsb - I - 1;
+            if (t < cnt) { J = I + 1 + t; break; }
+            t -= cnt;
+        }
+        gram_bf16_block<SPLIT, false, LIST, VEC>(X, n, ldx, y, g, rs, partial, pvec, pscal, k, s, I, J, false);
     }
 }
 
@@ -468,25 +490,31 @@ static GramGeom plan_bf16(int prec, int p, int K, int64_t n)
     return g;
 }
 
-static size_t bf16_lds_bytes(bool diag)
+static size_t bf16_lds_bytes(bool off)
 {
-    const int npanels = diag ? 2 : 4;
-    const size_t panels = (size_t)npanels * kBPanel * kBRows * sizeof(__bf16);
+    // four panels with off-diagonal pairs (the diagonal ones use two), else
+    // two; or the reduction areas, whichever is larger
+    const size_t panels = (size_t)(off ? 4 : 2) * kBPanel * kBRows * sizeof(__bf16);
     const size_t red = std::max((size_t)2 * 1024 * sizeof(float), (size_t)(24 * kBPanel + 16) * sizeof(double));
     return std::max(panels, red);
 }
 
-template <bool SPLIT, bool DIAG>
+template <bool SPLIT, bool OFF>
+static const void *bf16_kernel(bool list, bool vec)
+{
+    if (list) return vec ? (const void *)gram_bf16_kernel<SPLIT, true, true, OFF>
+                         : (const void *)gram_bf16_kernel<SPLIT, true, false, OFF>;
+    return vec ? (const void *)gram_bf16_kernel<SPLIT, false, true, OFF>
+               : (const void *)gram_bf16_kernel<SPLIT, false, false, OFF>;
+}
+
+template <bool SPLIT>
 static int launch_bf16_t(const GramGeom &g, bool list, bool vec, unsigned blocks, const float *X,
                          int64_t n, int64_t ldx, const double *y, const RowSource &rs, float *part,
                          double *pvec, double *pscal, hipStream_t s)
 {
-    const void *kern;
-    if (list) kern = vec ? (const void *)gram_bf16_kernel<SPLIT, DIAG, true, true>
-                         : (const void *)gram_bf16_kernel<SPLIT, DIAG, true, false>;
-    else kern = vec ? (const void *)gram_bf16_kernel<SPLIT, DIAG, false, true>
-                    : (const void *)gram_bf16_kernel<SPLIT, DIAG, false, false>;
-    const size_t lds = bf16_lds_bytes(DIAG);
+    const void *kern = g.npsb > g.nsb ? bf16_kernel<SPLIT, true>(list, vec) : bf16_kernel<SPLIT, false>(list, vec);
+    const size_t lds = bf16_lds_bytes(g.npsb > g.nsb);
     OEM_HIP_CHECK(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     void *args[] = {(void *)&X, (void *)&n, (void *)&ldx, (void *)&y, (void *)&g, (void *)&rs,
                     (void *)&part, (void *)&pvec, (void *)&pscal};
@@ -529,16 +557,10 @@ int launch_gram_bf16(oem_gram_s *h, const void *Xv, int64_t n, int64_t ldx, cons
     const bool split = (h->prec == OEM_SPLIT_BF16);
     const bool list = g.K > 1;
     const bool vec = (reinterpret_cast<uintptr_t>(X) & 3) == 0;
-    const unsigned nd = (unsigned)(g.K * g.nsplit * g.nsb);
-    rc = split ? launch_bf16_t<true, true>(g, list, vec, nd, X, n, ldx, y, rs, part, pvec, pscal, s)
-               : launch_bf16_t<false, true>(g, list, vec, nd, X, n, ldx, y, rs, part, pvec, pscal, s);
+    const unsigned nb = (unsigned)(g.K * g.nsplit * g.npsb);
+    rc = split ? launch_bf16_t<true>(g, list, vec, nb, X, n, ldx, y, rs, part, pvec, pscal, s)
+               : launch_bf16_t<false>(g, list, vec, nb, X, n, ldx, y, rs, part, pvec, pscal, s);
     if (rc) return rc;
-    if (g.npsb > g.nsb) {
-        const unsigned no = (unsigned)(g.K * g.nsplit * (g.npsb - g.nsb));
-        rc = split ? launch_bf16_t<true, false>(g, list, vec, no, X, n, ldx, y, rs, part, pvec, pscal, s)
-                   : launch_bf16_t<false, false>(g, list, vec, no, X, n, ldx, y, rs, part, pvec, pscal, s);
-        if (rc) return rc;
-    }
     const size_t per_k = Et + 3 * (size_t)g.p + 3;
     const dim3 fgrid((unsigned)((per_k + kWave - 1) / kWave), (unsigned)K);
     hipLaunchKernelGGL(gram_bf16_finish_kernel, fgrid, dim3(kFinishThreads), 0, s, g, part, pvec, pscal,
