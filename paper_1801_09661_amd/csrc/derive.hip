@@ -920,32 +920,40 @@ __global__ __launch_bounds__(kLzThreads) void lanczos_kernel(int p_all, int mmax
 }
 
 // Lanczos for p <= 128: G spread over the registers of 64 NW threads (thread
-// (wave w, lane l) holds G[l + 64 r][NW c + w]), the Krylov basis V in LDS.
-// Same recurrence, reorthogonalisation and stopping rule as lanczos_kernel;
-// the top Ritz value is tested on the schedule of lanczos_wide_kernel.
-template <int NW, int R, int CPW>
-__global__ __launch_bounds__(64 * NW) void lanczos_reg_kernel(int p_all, int mmax_all,
-                                                              const double *__restrict__ Gs_all,
-                                                              double *__restrict__ d_out,
-                                                              int32_t *__restrict__ steps_out,
-                                                              const LzJob *__restrict__ jobs)
+// (wave w, lane l) holds G[l + 64 r][NW c + w]), three vectors in LDS.  The
+// plain three-term recurrence with the reasoning and stopping rule of
+// lanczos_mb_kernel (no basis and no reorthogonalisation: a converged Ritz
+// value is accurate to O(eps ||G||) whatever the loss of orthogonality), so
+// a step is one product from registers and two block sums.
+static __host__ __device__ inline int lanczos_small_steps(int p) { return 2 * p < 64 ? 64 : 2 * p; }
+
+static size_t lanczos_small_lds_bytes(int NW, int R, int p)
 {
-    constexpr int NT = 64 * NW;
+    return ((size_t)3 * (p + 1) + (size_t)NW * 64 * R + 4 * (size_t)lanczos_small_steps(p) + 2 * NW + 8) *
+           sizeof(double);
+}
+
+template <int NW, int R, int CPW>
+__global__ __launch_bounds__(64 * NW) void lanczos_small_kernel(int p_all, const double *__restrict__ Gs_all,
+                                                                double *__restrict__ d_out,
+                                                                int32_t *__restrict__ steps_out,
+                                                                const LzJob *__restrict__ jobs)
+{
     extern __shared__ double sm[];
-    const LzJob J = lz_job(jobs, p_all, mmax_all, Gs_all, nullptr, d_out, steps_out);
-    const int p = J.p, mmax = J.mmax;
+    const LzJob J = lz_job(jobs, p_all, 0, Gs_all, nullptr, d_out, steps_out);
+    const int p = J.p, mcap = lanczos_small_steps(p);
     const auto G = gmem(J.G);
     const int t = threadIdx.x, lane = t % kWave, wave = t / kWave;
-    const int ldv = p + 1;                    // padded row pitch of V
-    double *V = sm;                           // (mmax + 1) x ldv
-    double *ws = V + (size_t)(mmax + 1) * ldv;  // p
-    double *part = ws + p;                    // NW x 64 R
-    double *al = part + NW * 64 * R;          // mmax
-    double *be = al + mmax;                   // mmax
-    double *coef = be + mmax;                 // mmax + 1
-    double *tx = coef + mmax + 1;             // mmax
-    double *tw = tx + mmax;                   // mmax
-    double *red = tw + mmax;                  // 2 NW
+    const int ldv = p + 1;
+    double *va = sm;                          // three vectors: v_prev, v, next
+    double *vb = va + ldv;
+    double *vc = vb + ldv;
+    double *part = vc + ldv;                  // NW x 64 R
+    double *al = part + NW * 64 * R;          // mcap
+    double *be = al + mcap;                   // mcap
+    double *tx = be + mcap;                   // mcap
+    double *tw = tx + mcap;                   // mcap
+    double *red = tw + mcap;                  // 2 NW
     __shared__ int s_flag, s_next;
     __shared__ double s_theta;
 
@@ -958,6 +966,7 @@ __global__ __launch_bounds__(64 * NW) void lanczos_reg_kernel(int p_all, int mma
             Gr[r][c] = (i < p && j < p) ? G[(size_t)i * p + j] : 0.0;
         }
     const bool mine = t < p;
+    if (t == 0) s_flag = 0;
 
     auto bsum = [&](double v) -> double {
         v = wave_sum(v);
@@ -968,46 +977,31 @@ __global__ __launch_bounds__(64 * NW) void lanczos_reg_kernel(int p_all, int mma
         for (int w = 0; w < NW; ++w) a += red[w];
         return a;
     };
-    // two sums with one pair of barriers (red holds 2 NW values)
-    auto bsum2 = [&](double u, double v, double &su, double &sv) {
-        u = wave_sum(u);
-        v = wave_sum(v);
-        __syncthreads();
-        if (lane == 0) {
-            red[wave] = u;
-            red[NW + wave] = v;
-        }
-        __syncthreads();
-        su = 0.0;
-        sv = 0.0;
-        for (int w = 0; w < NW; ++w) {
-            su += red[w];
-            sv += red[NW + w];
-        }
-    };
 
-    // start vector
-    double v0 = mine ? start_component(t) : 0.0;
+    double *vprev = va, *v = vb, *vn = vc;
+    const double v0 = mine ? start_component(t) : 0.0;
     const double nrm0 = sqrt(bsum(v0 * v0));
-    if (mine) V[t] = v0 / nrm0;
+    if (mine) {
+        v[t] = v0 / nrm0;
+        vprev[t] = 0.0;
+    }
     __syncthreads();
 
-    double gnorm = 0.0, theta = 0.0, floor = -INFINITY;
-    int next_test = 8, m_prev = 0;
+    double gnorm = 0.0, theta = 0.0, floor = -INFINITY, beta_prev = 0.0;
+    int next_test = 8, m_prev = 0, m = 0;
     double r_prev = 0.0;
-    int m = 0;
-    for (int j = 0; j < mmax; ++j) {
-        const double *vj = V + (size_t)j * ldv;
-        // w = G v_j
+    bool nonfinite = false;
+    for (int j = 0; j < mcap; ++j) {
+        // w = G v
         double acc[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) acc[r] = 0.0;
 #pragma unroll
         for (int c = 0; c < CPW; ++c) {
             const int col = NW * c + wave;
-            const double vc = col < p ? vj[col] : 0.0;
+            const double vcl = col < p ? v[col] : 0.0;
 #pragma unroll
-            for (int r = 0; r < R; ++r) acc[r] += Gr[r][c] * vc;
+            for (int r = 0; r < R; ++r) acc[r] += Gr[r][c] * vcl;
         }
 #pragma unroll
         for (int r = 0; r < R; ++r) part[wave * 64 * R + lane + 64 * r] = acc[r];
@@ -1015,56 +1009,27 @@ __global__ __launch_bounds__(64 * NW) void lanczos_reg_kernel(int p_all, int mma
         double wt = 0.0;
         if (mine)
             for (int w = 0; w < NW; ++w) wt += part[w * 64 * R + t];
-        double a, before;
-        bsum2(mine ? wt * vj[t] : 0.0, wt * wt, a, before);
-        if (t == 0) al[j] = a;
-        gnorm = fmax(gnorm, fabs(a));
-        // full reorthogonalisation against v_0..v_j, repeated once when it
-        // removed most of w; each dot is split over the 4 lanes of a quad
-        for (int pass = 0; pass < 2; ++pass) {
-            if (mine) ws[t] = wt;
-            __syncthreads();
-            for (int mm = t / 4; mm <= j; mm += NT / 4) {
-                // one quad per vector: the 4 lanes of a quad always share mm
-                const double *vm = V + (size_t)mm * ldv;
-                double c0 = 0.0, c1 = 0.0;
-                int i = t % 4;
-                for (; i + 4 < p; i += 8) {
-                    c0 += vm[i] * ws[i];
-                    c1 += vm[i + 4] * ws[i + 4];
-                }
-                if (i < p) c0 += vm[i] * ws[i];
-                double c = c0 + c1;
-                c += dpp_mov<0xB1>(c);
-                c += dpp_mov<0x4E>(c);
-                if (t % 4 == 0) coef[mm] = c;
-            }
-            __syncthreads();
-            if (mine) {
-                double t0 = 0.0, t1 = 0.0, t2 = 0.0, t3 = 0.0;
-                int mm = 0;
-                for (; mm + 3 <= j; mm += 4) {
-                    t0 += coef[mm] * V[(size_t)mm * ldv + t];
-                    t1 += coef[mm + 1] * V[(size_t)(mm + 1) * ldv + t];
-                    t2 += coef[mm + 2] * V[(size_t)(mm + 2) * ldv + t];
-                    t3 += coef[mm + 3] * V[(size_t)(mm + 3) * ldv + t];
-                }
-                for (; mm <= j; ++mm) t0 += coef[mm] * V[(size_t)mm * ldv + t];
-                wt -= (t0 + t1) + (t2 + t3);
-            }
-            const double after = bsum(wt * wt);
-            if (after > 0.5 * before) break;
-            before = after;
+        const double alpha = bsum(mine ? wt * v[t] : 0.0);
+        const double rt = mine ? (wt - alpha * v[t]) - beta_prev * vprev[t] : 0.0;
+        const double beta = sqrt(bsum(rt * rt));
+        if (t == 0) {
+            al[j] = alpha;
+            be[j] = beta;
         }
-        const double b = sqrt(bsum(wt * wt));
-        if (t == 0) be[j] = b;
+        gnorm = fmax(gnorm, fabs(alpha));
         m = j + 1;
-        const bool invariant = (b <= 1e-14 * fmax(gnorm, 1e-300)) || (m == p);
-        const bool test_now = invariant || (m == next_test) || (m == mmax);
+        // non-finite statistics: no bound exists (d becomes NaN, which the
+        // caller reports); every thread holds the same alpha and beta
+        if (!isfinite(alpha) || !isfinite(beta)) {
+            nonfinite = true;
+            break;
+        }
+        const bool invariant = beta <= 1e-14 * fmax(gnorm, 1e-300);
+        const bool test_now = invariant || (m == next_test) || (m == mcap);
         if (test_now) {
             __syncthreads();
             if (t < kWave)
-                lz_test(al, be, m, b, invariant, floor, tx, tw, m_prev, r_prev, &s_theta, &s_flag,
+                lz_test(al, be, m, beta, invariant, floor, tx, tw, m_prev, r_prev, &s_theta, &s_flag,
                         &s_next);
             __syncthreads();
             theta = s_theta;
@@ -1072,12 +1037,21 @@ __global__ __launch_bounds__(64 * NW) void lanczos_reg_kernel(int p_all, int mma
             next_test = s_next;
             if (s_flag) break;
         }
-        if (mine) V[(size_t)(j + 1) * ldv + t] = wt / b;
+        // v_prev <- v, v <- r / beta (buffers rotate)
+        if (mine) vn[t] = rt / beta;
+        double *tmp = vprev;
+        vprev = v;
+        v = vn;
+        vn = tmp;
+        beta_prev = beta;
         __syncthreads();
     }
+    // not settled within the step limit: Gershgorin bound, as in the other kernels
     double dval = theta * (1.0 + 1e-10);
-    const bool settled = s_flag;
-    if (!settled) {
+    const bool settled = s_flag && !nonfinite;
+    if (nonfinite) {
+        dval = NAN;
+    } else if (!settled) {
         double gm = 0.0;
         if (mine)
             for (int c = 0; c < p; ++c) gm += fabs(G[(size_t)c * p + t]);
@@ -1125,12 +1099,11 @@ static int launch_lz_class(int cls, int count, int pmax, int p_all, const double
     size_t lds = 0;
     if (cls <= 1) {
         const int NW = cls == 0 ? 4 : 8, R = cls == 0 ? 1 : 2;
-        lds = ((size_t)(mmax + 1) * (pmax + 1) + pmax + NW * 64 * R + 5 * mmax + 1 + 2 * NW) * sizeof(double);
-        kern = cls == 0 ? (const void *)lanczos_reg_kernel<4, 1, 16> : (const void *)lanczos_reg_kernel<8, 2, 16>;
+        lds = lanczos_small_lds_bytes(NW, R, pmax);
+        kern = cls == 0 ? (const void *)lanczos_small_kernel<4, 1, 16> : (const void *)lanczos_small_kernel<8, 2, 16>;
         threads = 64 * NW;
         OEM_HIP_CHECK(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        void *args[] = {(void *)&p_arg, (void *)&m_arg, (void *)&Gs_all, (void *)&d_out, (void *)&steps_out,
-                        (void *)&jobs};
+        void *args[] = {(void *)&p_arg, (void *)&Gs_all, (void *)&d_out, (void *)&steps_out, (void *)&jobs};
         OEM_HIP_CHECK(hipLaunchKernel(kern, dim3(count), dim3(threads), args, lds, s));
         return OEM_OK;
     }
@@ -1316,6 +1289,7 @@ __global__ __launch_bounds__(kMbThreads) void lanczos_mb_kernel(int B, const LzJ
     double gnorm = 0.0, theta = 0.0, floor = -INFINITY, beta_prev = 0.0;
     int m = 0, next_test = 8, m_prev = 0;
     double r_prev = 0.0;
+    bool nonfinite = false;
     for (int j = 0; j < mcap; ++j) {
         // this workgroup's rows of w = G v
         {
@@ -1378,6 +1352,12 @@ __global__ __launch_bounds__(kMbThreads) void lanczos_mb_kernel(int B, const LzJ
             be[j] = beta;
         }
         m = j + 1;
+        // non-finite statistics: no bound (d becomes NaN); every workgroup
+        // takes this decision on the same values
+        if (!isfinite(alpha) || !isfinite(beta)) {
+            nonfinite = true;
+            break;
+        }
         const bool invariant = beta <= 1e-14 * fmax(gnorm, 1e-300);
         const bool test_now = invariant || (m == next_test) || (m == mcap);
         __syncthreads();
@@ -1402,8 +1382,8 @@ __global__ __launch_bounds__(kMbThreads) void lanczos_mb_kernel(int B, const LzJ
     }
     // not settled within the step limit: Gershgorin bound, as in the other kernels
     double dval = theta * (1.0 + 1e-10);
-    const bool ok = s_flag != 0 && !s_fail;
-    if (!ok && !s_fail) {
+    const bool ok = s_flag != 0 && !s_fail && !nonfinite;
+    if (!ok && !s_fail && !nonfinite) {
         double rs = 0.0;
         if (wave == 0 && mine)
             for (int c = 0; c < p; ++c) rs += fabs(G[(size_t)c * p + row]);
@@ -1417,7 +1397,7 @@ __global__ __launch_bounds__(kMbThreads) void lanczos_mb_kernel(int B, const LzJ
             dval = fmax(dval, gm);
         }
     }
-    if (s_fail) dval = NAN;
+    if (s_fail || nonfinite) dval = NAN;
     if (b == 0 && t == 0) {
         *J.d = dval;
         if (J.steps) *J.steps = s_fail ? kLanczosTimedOut : (ok ? m : -m);
