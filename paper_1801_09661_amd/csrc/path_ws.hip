@@ -636,18 +636,29 @@ __device__ __forceinline__ void path_ws_body(const PathDesc &P, int first, int p
             if (grp) {
                 // the slot's group lies in lanes [gA, gB) of the first half;
                 // u^2 of the wave's slots goes through LDS and each lane reads
-                // its group's entries in blocks of 8 independent reads (LDS
-                // operations of one wave complete in order, so no barrier)
+                // its group's entries with independent reads (LDS operations
+                // of one wave complete in order, so no barrier)
                 double *uq = usq + wave * CB;
                 if (half == 0) uq[lane] = u * u;
                 double ss = 0.0;
-                for (int k0 = 0; k0 < gmaxw; k0 += 8) {
-                    double qv[8];
+                if (gmaxw <= 16) {
+                    // groups of up to 16: one batch of reads, then the sum in
+                    // member order (the order of the lambda_max test)
+                    double qv[16];
 #pragma unroll
-                    for (int k = 0; k < 8; ++k) qv[k] = uq[min(gA + k0 + k, CB - 1)];
+                    for (int k = 0; k < 16; ++k) qv[k] = uq[min(gA + k, CB - 1)];
 #pragma unroll
-                    for (int k = 0; k < 8; ++k)
-                        if (k0 + k < gmaxw && gA + k0 + k < gB) ss += qv[k];
+                    for (int k = 0; k < 16; ++k)
+                        if (k < gmaxw && gA + k < gB) ss += qv[k];
+                } else {
+                    for (int k0 = 0; k0 < gmaxw; k0 += 8) {
+                        double qv[8];
+#pragma unroll
+                        for (int k = 0; k < 8; ++k) qv[k] = uq[min(gA + k0 + k, CB - 1)];
+#pragma unroll
+                        for (int k = 0; k < 8; ++k)
+                            if (k0 + k < gmaxw && gA + k0 + k < gB) ss += qv[k];
+                    }
                 }
                 const double nrm = sqrt(ss);
                 const double f = nrm > 0.0 ? 1.0 - lamc / nrm : 0.0;
