@@ -46,6 +46,18 @@
  *     they finish unless opts->sync = 1.  oem_gram_autotune,
  *     oem_batch_create, oem_batch_status and the free functions wait for
  *     the device.
+ *   - Concurrent streams.  For 128 < p <= 2048 the eigenvalue bound d is
+ *     computed by one launch whose workgroups exchange data every step, so
+ *     all of them must be resident at once; the launcher sizes it from the
+ *     occupancy of an otherwise idle device.  When the caller runs other
+ *     work on the device at the same time (fits of two handles on two
+ *     streams), that work can keep some of those workgroups waiting: their
+ *     partners' bounded waits then end and oem_fit_path / oem_cv return
+ *     OEM_E_HIP ("timed out waiting for its workgroups"), never a hang or a
+ *     wrong d.  Such callers set the environment variable OEM_LANCZOS_MB=0
+ *     before the first call (one workgroup per problem, no cross-workgroup
+ *     wait); the request loop's workers (oem_server_*) always use one
+ *     workgroup per problem.
  *   - Matrices are row-major.  Sizes are element counts.
  */
 #ifndef OEM_H
