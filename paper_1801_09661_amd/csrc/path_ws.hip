@@ -25,14 +25,18 @@
 // within tol times it, and whether any coordinate drifted past the screening
 // bound, are wave ballots.  The coordinates outside W are not touched while
 // the drift max_k |beta_k - beta_ref_k| stays below S = min over j outside W
-// of s_j / r_j.  At a check point - the start of the path, the end of every
-// lambda, and whenever the drift reaches S - the kernel forms G beta for all
-// p coordinates from the columns of the nonzero coordinates (from LDS in the
-// one-wave kernel, else from memory), which gives the exact u, the
-// stationarity check, the objective and new keys, and rebuilds W when a
-// coordinate outside it needs to enter.  The iterates are those of the full
-// update: the coordinates outside W are exactly the ones the full update
-// would leave at zero.
+// of s_j / r_j.  At a check point - the start of the path, and whenever the
+// drift reaches S - the kernel forms G beta for all p coordinates from the
+// columns of the nonzero coordinates (from LDS in the one-wave kernel, else
+// from memory), which gives the exact u, the stationarity check, the
+// objective and new keys, and rebuilds W when a coordinate outside it needs
+// to enter.  The iterates are those of the full update: the coordinates
+// outside W are exactly the ones the full update would leave at zero.  At
+// the end of a lambda the outputs need G beta on W only (every coordinate
+// outside W is zero and inside its threshold), and the slacks s_j of the
+// next lambda follow from the reference's |u_j| with the smaller threshold:
+// W and the reference carry on while the drift stays below the new S, and a
+// check point is taken only when it does not.
 //
 // When more than C coordinates need W, the kernel stops before that lambda:
 // *lstart receives the lambda index and bws the coefficients (standardised)
@@ -60,7 +64,7 @@ size_t path_ws_lds_bytes(int NW, int pcap)
 {
     const int C = NW * kWsCB, PSC = ws_pow2(pcap);
     const size_t gl = NW == 1 ? (size_t)pcap * pcap : 0;
-    const size_t dbl = 2 * (size_t)C + 8 * (size_t)NW + 4 * (size_t)NW + 6 * (size_t)pcap + PSC + 2 * (size_t)C + gl;
+    const size_t dbl = 2 * (size_t)C + 8 * (size_t)NW + 4 * (size_t)NW + 6 * (size_t)pcap + 2 * (size_t)PSC + 2 * (size_t)C + gl;
     const size_t ints = (size_t)PSC + 2 * (size_t)pcap + 2 * (size_t)C + 2 * (size_t)C + 16 + 2 * (size_t)NW;
     return dbl * sizeof(double) + ints * sizeof(int) + 64;
 }
@@ -84,14 +88,15 @@ __device__ __forceinline__ void path_ws_body(const PathDesc &P, int first, int p
     double *fin = dm + 8 * NW;                // [4][NW] per-wave check-point sums
     double *bfull = fin + 4 * NW;             // [pcap] beta (zero outside W)
     double *gfull = bfull + pcap;             // [pcap] G beta
-    double *r1 = gfull + pcap;                // [pcap] r_j = sum_k |G_jk| (group lasso), else 1 / r_j
+    double *r1 = gfull + pcap;                // [pcap] 1 / r of each key: 1 / r_j, r_j = sum_k |G_jk|; a group's 1 / sqrt(sum r_j^2)
     double *key = r1 + pcap;                  // [PSC] s_j / r_j, -1 when j needs W
     double *ab = key + PSC;                   // [C] values of the nonzero coordinates
     double *cl = ab + C;                      // [pcap] c
     double *scl = cl + pcap;                  // [pcap] column scales
     double *wl = scl + pcap;                  // [pcap] penalty weights
     double *usq = wl + pcap;                  // [NW][CB] u^2 of each wave's slots (group lasso)
-    double *gls = usq + C;                    // [pcap pcap] G (one-wave kernel only)
+    double *kref = usq + C;                   // [PSC] |u_j| (||u_g||) of each key at the reference beta
+    double *gls = kref + PSC;                 // [pcap pcap] G (one-wave kernel only)
     int *kid = reinterpret_cast<int *>(gls + (NW == 1 ? pcap * pcap : 0));   // [PSC] coordinate (group) of each key
     int *slot_of = kid + PSC;                 // [pcap] slot of each coordinate, -1 outside W
     int *gof = slot_of + pcap;                // [pcap] group of each coordinate
@@ -168,7 +173,7 @@ __device__ __forceinline__ void path_ws_body(const PathDesc &P, int first, int p
         }
         for (; k < p; ++k) a0 += fabs(gat((size_t)k * p + j));
         const double rj = (a0 + a1) + (a2 + a3);
-        r1[j] = grp ? rj : 1.0 / rj;   // 1 / r_j (inf for a zero column) for separable penalties
+        r1[j] = grp ? rj : 1.0 / rj;   // 1 / r_j (inf for a zero column); groups: r_j for now
         bfull[j] = l0 > 0 ? bws[j] : 0.0;
         slot_of[j] = -1;
     }
@@ -180,6 +185,17 @@ __device__ __forceinline__ void path_ws_body(const PathDesc &P, int first, int p
         for (int g = t; g < P.ngroups; g += NT)
             for (int q = gstart[g]; q < gstart[g + 1]; ++q) gof[gidx[q]] = g;
     sync();
+    if (grp) {
+        // a group's bound: ||u_g(beta) - u_g(beta')|| <= sqrt(sum_{j in g} r_j^2) max_k |beta_k - beta'_k|
+        for (int g = t; g < P.ngroups; g += NT) {
+            double rr = 0.0;
+            for (int q = gstart[g]; q < gstart[g + 1]; ++q) rr += r1[gidx[q]] * r1[gidx[q]];
+            kref[g] = 1.0 / sqrt(rr);
+        }
+        sync();
+        for (int g = t; g < P.ngroups; g += NT) r1[g] = kref[g];
+        sync();
+    }
 
     // per-slot state of the owning lanes (the same in both)
     double Gr[HC];                // row W(os) of G_WW, columns [half HC, half HC + HC)
@@ -234,6 +250,13 @@ __device__ __forceinline__ void path_ws_body(const PathDesc &P, int first, int p
     auto set_upd = [&](double lam) {
         q = make_upd(kind, wt * lam, d, P.alpha, P.gamma);
         lamc = (grp && jc >= 0) ? cgw[gof[jc]] * lam : 0.0;
+    };
+
+    // The keys in W get kref = -inf: no bound for the next lambda comes
+    // from them (after the check point's own writes of kref).
+    auto mark_w = [&]() {
+        for (int s = t; s < C; s += NT)
+            if (ws[s] >= 0) kref[grp ? gof[ws[s]] : ws[s]] = -INFINITY;
     };
 
     // Check point at the current beta.  lam_end >= 0: the lambda whose
@@ -364,6 +387,7 @@ __device__ __forceinline__ void path_ws_body(const PathDesc &P, int first, int p
                     const bool need = (b != 0.0) || !(sl > 1e-12 * thr);
                     const double kj = need ? -1.0 : fmin(sl * r1[j], DBL_MAX);
                     key[j] = kj;
+                    kref[j] = fabs(u);
                     kid[j] = j;
                     nneed += need ? 1 : 0;
                     if (slot_of[j] < 0) smin = fmin(smin, kj);
@@ -372,7 +396,7 @@ __device__ __forceinline__ void path_ws_body(const PathDesc &P, int first, int p
         } else {
             for (int g = t; g < P.ngroups; g += NT) {
                 const int q0 = gstart[g], q1 = gstart[g + 1];
-                double uu = 0.0, bb = 0.0, gg = 0.0, rr = 0.0;
+                double uu = 0.0, bb = 0.0, gg = 0.0;
                 bool nz = false;
                 for (int qq = q0; qq < q1; ++qq) {
                     const int j = gidx[qq];
@@ -381,7 +405,6 @@ __device__ __forceinline__ void path_ws_body(const PathDesc &P, int first, int p
                     uu += u * u;
                     bb += b * b;
                     gg += (gv - cj) * (gv - cj);
-                    rr += r1[j] * r1[j];
                     nz |= b != 0.0;
                     if (lam_end >= 0.0) {
                         quad += b * gv;
@@ -411,10 +434,12 @@ __device__ __forceinline__ void path_ws_body(const PathDesc &P, int first, int p
                 }
                 if (has_next) {
                     const double thr = cgw[g] * lam_next;
-                    const double sl = thr - sqrt(uu);
+                    const double un = sqrt(uu);
+                    const double sl = thr - un;
                     const bool need = nz || !(sl > 1e-12 * thr);
-                    const double kg = need ? -1.0 : (rr > 0.0 ? fmin(sl / sqrt(rr), DBL_MAX) : DBL_MAX);
+                    const double kg = need ? -1.0 : fmin(sl * r1[g], DBL_MAX);
                     key[g] = kg;
+                    kref[g] = un;
                     kid[g] = g;
                     nneed += need ? (q1 - q0) : 0;
                     if (slot_of[gidx[q0]] < 0) smin = fmin(smin, kg);
@@ -467,6 +492,7 @@ __device__ __forceinline__ void path_ws_body(const PathDesc &P, int first, int p
             S = SM;
             Sthr = S * (1.0 - 1e-9);
             bref = bt;
+            mark_w();
             sync();            // dm and fin are read before they are reused
             return 0;
         }
@@ -591,6 +617,7 @@ __device__ __forceinline__ void path_ws_body(const PathDesc &P, int first, int p
         Sthr = S * (1.0 - 1e-9);
         for (int s = t; s < C; s += NT)
             if (ws[s] >= 0) slot_of[ws[s]] = s;
+        mark_w();
         // both lanes of a slot take its new coordinate; G_WW into registers
         jc = ws[os];
         bt = jc >= 0 ? bfull[jc] : 0.0;
@@ -614,6 +641,156 @@ __device__ __forceinline__ void path_ws_body(const PathDesc &P, int first, int p
         return 0;
     };
 
+    // End of a lambda without forming G beta over all p.  It applies when the
+    // final beta is within the screening bound of the reference (no drift):
+    // then every coordinate outside W is zero with |u_j| below its threshold,
+    // so its stationarity violation is exactly zero, and the outputs need
+    // G beta on W only, which is gfin (the updates' last product G_WW beta_W,
+    // beta being zero outside W).  The bound for the next lambda comes from
+    // the reference's |u_j| (||u_g||) and the new thresholds.  Returns 0 when
+    // W, the reference and the new bound carry on to the next lambda, 2 when
+    // the outputs are written but the next lambda needs a check point first.
+    auto light_end = [&](int l_end, double lam_end, double lam_next, double gfin, int it_end,
+                         bool conv_end) -> int {
+        if (half == 0 && jc >= 0) {
+            bfull[jc] = bt;
+            gfull[jc] = gfin;
+        }
+        const double Dw = slot_max(jc >= 0 ? fabs(bt - bref) : 0.0);
+        sync();
+        const bool has_next = lam_next >= 0.0;
+        double kv = 0.0, penv = 0.0, quad = 0.0, lin = 0.0, smin = INFINITY;
+        int nneed = 0;
+        if (!grp) {
+            for (int j = t; j < p; j += NT) {
+                const size_t o = (size_t)l_end * p + j;
+                if (slot_of[j] >= 0) {
+                    const double b = bfull[j], g = gfull[j], cj = cl[j];
+                    const double lw = wl[j] * lam_end;
+                    const double gr = g - cj;
+                    if (b == 0.0)
+                        kv = nmax(kv, pos(fabs(gr) - thr_scale * lw));
+                    else
+                        kv = nmax(kv, fabs(gr + sgn(b) * pen_deriv(kind, fabs(b), lw, P.alpha, P.gamma)));
+                    penv += pen_value(kind, b, lw, P.alpha, P.gamma);
+                    quad += b * g;
+                    lin += cj * b;
+                    beta_g[o] = b / scl[j];
+                    if (beta_std_g) beta_std_g[o] = b;
+                    bws[j] = b;
+                } else {
+                    beta_g[o] = 0.0;
+                    if (beta_std_g) beta_std_g[o] = 0.0;
+                    bws[j] = 0.0;
+                    if (has_next) {
+                        const double thr = wl[j] * lam_next * thr_scale;
+                        const double sl = thr - kref[j];
+                        nneed += (sl > 1e-12 * thr) ? 0 : 1;
+                        smin = fmin(smin, fmin(sl * r1[j], DBL_MAX));
+                    }
+                }
+            }
+        } else {
+            // coordinates outside W: zero outputs
+            for (int j = t; j < p; j += NT)
+                if (slot_of[j] < 0) {
+                    const size_t o = (size_t)l_end * p + j;
+                    beta_g[o] = 0.0;
+                    if (beta_std_g) beta_std_g[o] = 0.0;
+                    bws[j] = 0.0;
+                }
+            // groups in W (whole groups, members in member order on
+            // consecutive slots): the first slot of each takes its sums
+            for (int s2 = t; s2 < C; s2 += NT) {
+                const int j0 = ws[s2], l2 = s2 % CB, sb = s2 - l2;
+                if (j0 < 0 || gl[2 * s2] != l2) continue;
+                const int m1 = gl[2 * s2 + 1];
+                double bb = 0.0, gg = 0.0;
+                for (int m = l2; m < m1; ++m) {
+                    const int j = ws[sb + m];
+                    const double b = bfull[j], gv = gfull[j], cj = cl[j];
+                    bb += b * b;
+                    gg += (gv - cj) * (gv - cj);
+                    quad += b * gv;
+                    lin += cj * b;
+                    beta_g[(size_t)l_end * p + j] = b / scl[j];
+                    if (beta_std_g) beta_std_g[(size_t)l_end * p + j] = b;
+                    bws[j] = b;
+                }
+                const double lc = lam_end * cgw[gof[j0]];
+                const double bn = sqrt(bb);
+                double v;
+                if (bn > 0.0) {
+                    double ss = 0.0;
+                    for (int m = l2; m < m1; ++m) {
+                        const int j = ws[sb + m];
+                        const double e = (gfull[j] - cl[j]) + lc * bfull[j] / bn;
+                        ss += e * e;
+                    }
+                    v = sqrt(ss);
+                } else {
+                    v = pos(sqrt(gg) - lc);
+                }
+                kv = nmax(kv, v);
+                penv += lc * bn;
+            }
+            // groups outside W (kref = -inf in W): the next lambda's bound
+            if (has_next)
+                for (int g = t; g < P.ngroups; g += NT) {
+                    const double thr = cgw[g] * lam_next;
+                    const double sl = thr - kref[g];
+                    nneed += (sl > 1e-12 * thr) ? 0 : 1;
+                    smin = fmin(smin, fmin(sl * r1[g], DBL_MAX));
+                }
+        }
+        kv = wave_max(kv);
+        penv = wave_sum(penv);
+        quad = wave_sum(quad);
+        lin = wave_sum(lin);
+        smin = -wave_max(-smin);
+        const double nn = wave_sum((double)nneed);
+        if (lane == 0) {
+            fin[0 * NW + wave] = kv;
+            fin[1 * NW + wave] = penv;
+            fin[2 * NW + wave] = quad;
+            fin[3 * NW + wave] = lin;
+            dm[wave * 4 + 0] = smin;      // dm[0][*] is free between updates
+            dm[wave * 4 + 1] = nn;
+            dm[wave * 4 + 2] = Dw;
+        }
+        sync();
+        double SM = dm[0], NN = dm[1], D = dm[2];
+        for (int w = 1; w < NW; ++w) {
+            SM = fmin(SM, dm[w * 4]);
+            NN += dm[w * 4 + 1];
+            D = fmax(D, dm[w * 4 + 2]);
+        }
+        if (t == 0) {
+            double K = fin[0], Pn = fin[NW], Q = fin[2 * NW], Li = fin[3 * NW];
+            for (int w = 1; w < NW; ++w) {
+                K = fmax(K, fin[w]);
+                Pn += fin[NW + w];
+                Q += fin[2 * NW + w];
+                Li += fin[3 * NW + w];
+            }
+            if (kkt_g) kkt_g[l_end] = K;
+            if (obj_g) obj_g[l_end] = 0.5 * Q - Li + 0.5 * yyn + Pn;
+            if (iters_g) iters_g[l_end] = conv_end ? it_end : -it_end;
+        }
+        int rc = 0;
+        if (has_next) {
+            const double St = SM * (1.0 - 1e-9);
+            if (NN == 0.0 && SM > 0.0 && D < St) {
+                S = SM;
+                Sthr = St;
+            } else {
+                rc = 2;
+            }
+        }
+        sync();            // dm and fin are read before they are reused
+        return rc;
+    };
+
     int cur = 0;
     if (checkpoint(-1, -1.0, lambda_g[l0], false, INFINITY, 0, false)) {
         if (t == 0) *P.lstart = l0;
@@ -629,7 +806,7 @@ __device__ __forceinline__ void path_ws_body(const PathDesc &P, int first, int p
         const double lnext = (l + 1 < L) ? lambda_g[l + 1] : -1.0;   // in flight during the updates
         set_upd(lam);
         int it = 0;
-        bool conv = false;
+        bool conv = false, drift = false;
         do {
             const double u = ct + (d * bt - gb);
             double bn;
@@ -641,27 +818,49 @@ __device__ __forceinline__ void path_ws_body(const PathDesc &P, int first, int p
                 double *uq = usq + wave * CB;
                 if (half == 0) uq[lane] = u * u;
                 double ss = 0.0;
+                // the sum in member order (the order of the lambda_max
+                // test); entries past the group are added as 0.0, which
+                // leaves the sum unchanged and keeps the selects off the
+                // chain of dependent additions
                 if (gmaxw <= 16) {
-                    // groups of up to 16: one batch of reads, then the sum in
-                    // member order (the order of the lambda_max test)
+                    // groups of up to 16: one batch of reads
                     double qv[16];
 #pragma unroll
                     for (int k = 0; k < 16; ++k) qv[k] = uq[min(gA + k, CB - 1)];
 #pragma unroll
-                    for (int k = 0; k < 16; ++k)
-                        if (k < gmaxw && gA + k < gB) ss += qv[k];
+                    for (int k = 0; k < 8; ++k) ss += (gA + k < gB) ? qv[k] : 0.0;
+                    if (gmaxw > 8) {
+#pragma unroll
+                        for (int k = 8; k < 12; ++k) ss += (gA + k < gB) ? qv[k] : 0.0;
+                    }
+                    if (gmaxw > 12) {
+#pragma unroll
+                        for (int k = 12; k < 16; ++k) ss += (gA + k < gB) ? qv[k] : 0.0;
+                    }
                 } else {
                     for (int k0 = 0; k0 < gmaxw; k0 += 8) {
                         double qv[8];
 #pragma unroll
                         for (int k = 0; k < 8; ++k) qv[k] = uq[min(gA + k0 + k, CB - 1)];
 #pragma unroll
-                        for (int k = 0; k < 8; ++k)
-                            if (k0 + k < gmaxw && gA + k0 + k < gB) ss += qv[k];
+                        for (int k = 0; k < 8; ++k) ss += (gA + k0 + k < gB) ? qv[k] : 0.0;
                     }
                 }
-                const double nrm = sqrt(ss);
-                const double f = nrm > 0.0 ? 1.0 - lamc / nrm : 0.0;
+                // f = 1 - c_g lambda / ||u_g|| from 1 / ||u_g|| (the hardware
+                // estimate and two Newton steps), which is within a few
+                // units of 1e-16 of the quotient; where f is that close to
+                // zero (or not finite), the exact quotient decides, as in the
+                // lambda_max test
+                double f = 0.0;
+                if (ss > 0.0) {
+                    double y = __builtin_amdgcn_rsq(ss);
+                    const double h0 = 0.5 * y, e0 = fma(-(ss * y), y, 1.0);
+                    y = fma(h0, e0, y);
+                    const double h1 = 0.5 * y, e1 = fma(-(ss * y), y, 1.0);
+                    y = fma(h1, e1, y);
+                    f = fma(-lamc, y, 1.0);
+                    if (!(fabs(f) >= 1e-12)) f = 1.0 - lamc / sqrt(ss);
+                }
                 bn = (jc >= 0 && f > 0.0) ? (u * inv_d) * f : 0.0;
             } else {
                 bn = jc >= 0 ? update_fast(kind, u, q, P.gamma) : 0.0;
@@ -671,7 +870,6 @@ __device__ __forceinline__ void path_ws_body(const PathDesc &P, int first, int p
             ++it;
             const int nxt = cur ^ 1;
             bsl[nxt * C + os] = bn;
-            bool drift;
             if (NW == 1) {
                 sync();
                 // the next product does not depend on the stopping test, so
@@ -727,15 +925,22 @@ __device__ __forceinline__ void path_ws_body(const PathDesc &P, int first, int p
             }
         } while (!conv && it < P.maxit);
         sync();           // dm[cur] is read before the check point reuses dm
-        if (checkpoint(l, lam, lnext, true, 0.0, it, conv)) {
-            if (t == 0) *P.lstart = l + 1;
-            return;
-        }
-        if (l + 1 < L) {
-            // W may have been rebuilt: beta of the (new) slots
-            bsl[cur * C + os] = bt;
-            sync();
-            gb = symv(cur);
+        // the final beta within the bound: outputs from W alone, and the
+        // next lambda keeps W and the reference when the new bound allows
+        const int le = drift ? 1 : light_end(l, lam, lnext, gb, it, conv);
+        if (le != 0) {
+            const int ov = le == 1 ? checkpoint(l, lam, lnext, true, 0.0, it, conv)
+                                   : checkpoint(-1, -1.0, lnext, false, 0.0, 0, false);
+            if (ov) {
+                if (t == 0) *P.lstart = l + 1;
+                return;
+            }
+            if (l + 1 < L) {
+                // W may have been rebuilt: beta of the (new) slots
+                bsl[cur * C + os] = bt;
+                sync();
+                gb = symv(cur);
+            }
         }
         lam_cur = lnext;
     }
