@@ -4,16 +4,17 @@
 // Every update of Section 2.1 leaves a coordinate j at zero exactly when its
 // thresholding input is small: |u_j| <= w_j lambda (lasso, MCP, SCAD; times
 // alpha for the elastic net) or ||u_g|| <= c_g lambda for a group.  For a
-// coordinate that is zero, u_j = c_j - (G beta)_j, and between two iterates
+// coordinate that is zero, u_j = c_j - (G beta)_j.  Only the coordinates of
+// the working set W below move, so between two iterates
 //     |u_j(beta) - u_j(beta')| <= r_j max_k |beta_k - beta'_k|,
-// r_j = sum_k |G_jk|  (for a group, sqrt(sum_{j in g} r_j^2) bounds the change
-// of ||u_g||).  So after an exact evaluation of u at a reference beta, a zero
-// coordinate with slack s_j = threshold - |u_j| stays zero in every update
-// whose input beta is within s_j / r_j of the reference (max norm).
+// r_j = sum_{k in W} |G_jk|  (for a group, sqrt(sum_{j in g} r_j^2) bounds the
+// change of ||u_g||).  So after an exact evaluation of u at a reference beta,
+// a zero coordinate with slack s_j = threshold - |u_j| stays zero in every
+// update whose input beta is within s_j / r_j of the reference (max norm).
 //
 // The kernel keeps a working set W of at most C = 32 NW coordinates (whole
 // groups for the group lasso): the nonzero coordinates and the zero ones
-// closest to their threshold (smallest s_j / r_j).  G restricted to W lives
+// closest to their threshold (smallest s_j).  G restricted to W lives
 // in registers.  Wave w owns slots [32 w, 32 w + 32); lanes l and l + 32 both
 // own slot 32 w + l and hold its row of G_WW, split by columns: lane l the
 // first C / 2 columns, lane l + 32 the rest.  An update reads beta_W from LDS
@@ -88,7 +89,7 @@ __device__ __forceinline__ void path_ws_body(const PathDesc &P, int first, int p
     double *fin = dm + 8 * NW;                // [4][NW] per-wave check-point sums
     double *bfull = fin + 4 * NW;             // [pcap] beta (zero outside W)
     double *gfull = bfull + pcap;             // [pcap] G beta
-    double *r1 = gfull + pcap;                // [pcap] 1 / r of each key: 1 / r_j, r_j = sum_k |G_jk|; a group's 1 / sqrt(sum r_j^2)
+    double *r1 = gfull + pcap;                // [pcap] 1 / r of each key for the current W (r_j = sum_{k in W} |G_jk|; a group's sqrt(sum r_j^2))
     double *key = r1 + pcap;                  // [PSC] s_j / r_j, -1 when j needs W
     double *ab = key + PSC;                   // [C] values of the nonzero coordinates
     double *cl = ab + C;                      // [pcap] c
@@ -159,21 +160,9 @@ __device__ __forceinline__ void path_ws_body(const PathDesc &P, int first, int p
         for (int e = t; e < pp; e += NT) gls[e] = G[e];
         sync();
     }
-    // r_j (G is symmetric: column sums, coalesced), start coefficients, empty W
+    // start coefficients, empty W (r1 is set when W is built)
     for (int j = t; j < p; j += NT) {
-        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-        int k = 0;
-        for (; k + 4 <= p; k += 4) {
-            const double g0 = gat((size_t)k * p + j), g1 = gat((size_t)(k + 1) * p + j);
-            const double g2 = gat((size_t)(k + 2) * p + j), g3 = gat((size_t)(k + 3) * p + j);
-            a0 += fabs(g0);
-            a1 += fabs(g1);
-            a2 += fabs(g2);
-            a3 += fabs(g3);
-        }
-        for (; k < p; ++k) a0 += fabs(gat((size_t)k * p + j));
-        const double rj = (a0 + a1) + (a2 + a3);
-        r1[j] = grp ? rj : 1.0 / rj;   // 1 / r_j (inf for a zero column); groups: r_j for now
+        r1[j] = 0.0;
         bfull[j] = l0 > 0 ? bws[j] : 0.0;
         slot_of[j] = -1;
     }
@@ -185,17 +174,6 @@ __device__ __forceinline__ void path_ws_body(const PathDesc &P, int first, int p
         for (int g = t; g < P.ngroups; g += NT)
             for (int q = gstart[g]; q < gstart[g + 1]; ++q) gof[gidx[q]] = g;
     sync();
-    if (grp) {
-        // a group's bound: ||u_g(beta) - u_g(beta')|| <= sqrt(sum_{j in g} r_j^2) max_k |beta_k - beta'_k|
-        for (int g = t; g < P.ngroups; g += NT) {
-            double rr = 0.0;
-            for (int q = gstart[g]; q < gstart[g + 1]; ++q) rr += r1[gidx[q]] * r1[gidx[q]];
-            kref[g] = 1.0 / sqrt(rr);
-        }
-        sync();
-        for (int g = t; g < P.ngroups; g += NT) r1[g] = kref[g];
-        sync();
-    }
 
     // per-slot state of the owning lanes (the same in both)
     double Gr[HC];                // row W(os) of G_WW, columns [half HC, half HC + HC)
@@ -385,12 +363,11 @@ __device__ __forceinline__ void path_ws_body(const PathDesc &P, int first, int p
                     const double thr = wj * lam_next * thr_scale;
                     const double sl = thr - fabs(u);
                     const bool need = (b != 0.0) || !(sl > 1e-12 * thr);
-                    const double kj = need ? -1.0 : fmin(sl * r1[j], DBL_MAX);
-                    key[j] = kj;
+                    key[j] = need ? -1.0 : sl;
                     kref[j] = fabs(u);
                     kid[j] = j;
                     nneed += need ? 1 : 0;
-                    if (slot_of[j] < 0) smin = fmin(smin, kj);
+                    if (slot_of[j] < 0) smin = fmin(smin, need ? -1.0 : fmin(sl * r1[j], DBL_MAX));
                 }
             }
         } else {
@@ -437,12 +414,11 @@ __device__ __forceinline__ void path_ws_body(const PathDesc &P, int first, int p
                     const double un = sqrt(uu);
                     const double sl = thr - un;
                     const bool need = nz || !(sl > 1e-12 * thr);
-                    const double kg = need ? -1.0 : fmin(sl * r1[g], DBL_MAX);
-                    key[g] = kg;
+                    key[g] = need ? -1.0 : sl;
                     kref[g] = un;
                     kid[g] = g;
                     nneed += need ? (q1 - q0) : 0;
-                    if (slot_of[gidx[q0]] < 0) smin = fmin(smin, kg);
+                    if (slot_of[gidx[q0]] < 0) smin = fmin(smin, need ? -1.0 : fmin(sl * r1[g], DBL_MAX));
                 }
             }
         }
@@ -497,7 +473,6 @@ __device__ __forceinline__ void path_ws_body(const PathDesc &P, int first, int p
             return 0;
         }
         // rebuild W: order the keys ascending, needed ones first
-        double s_out = INFINITY;   // one wave: smallest key left outside W
         if constexpr (NW == 1) {
             // At most 128 keys, two per lane.  Each key gets a 64-bit order
             // code: its bit pattern (keys are -1 for needed coordinates, else
@@ -540,13 +515,6 @@ __device__ __forceinline__ void path_ws_body(const PathDesc &P, int first, int p
                     key[rk[e]] = mk[e];
                     kid[rk[e]] = mi[e];
                 }
-            // the drift bound: the smallest key ranked at C or later (exact,
-            // whatever the order codes did with near-equal keys)
-            double so = INFINITY;
-#pragma unroll
-            for (int e = 0; e < 2; ++e)
-                if (t + 64 * e < PS && rk[e] >= C) so = fmin(so, mk[e]);
-            s_out = -wave_max(-so);
         } else {
             // bitonic sort
             for (int k = 2; k <= PS; k <<= 1)
@@ -574,20 +542,16 @@ __device__ __forceinline__ void path_ws_body(const PathDesc &P, int first, int p
         sync();
         if (!grp) {
             for (int s = t; s < C; s += NT) ws[s] = (s < nkeys) ? kid[s] : -1;
-            if (t == 0) {
-                misc[0] = 0;
-                dm[2] = (NW == 1) ? s_out : ((PS > C) ? key[C] : INFINITY);
-            }
+            if (t == 0) misc[0] = 0;
         } else if (t == 0) {
             // whole groups into waves, first fit, in key order; stop at the
-            // first group that does not fit (its key bounds the drift)
+            // first group that does not fit
             for (int s = 0; s < C; ++s) {
                 ws[s] = -1;
                 gl[2 * s] = gl[2 * s + 1] = s % CB;
             }
             int fill[NW];
             for (int w = 0; w < NW; ++w) fill[w] = 0;
-            double Sn = INFINITY;
             int ovf = 0;
             for (int i = 0; i < nkeys; ++i) {
                 const int g = kid[i];
@@ -597,7 +561,6 @@ __device__ __forceinline__ void path_ws_body(const PathDesc &P, int first, int p
                 while (w < NW && fill[w] + sz > CB) ++w;
                 if (w == NW) {
                     if (key[i] < 0.0) ovf = 1;
-                    Sn = key[i];
                     break;
                 }
                 for (int m = 0; m < sz; ++m) {
@@ -609,14 +572,61 @@ __device__ __forceinline__ void path_ws_body(const PathDesc &P, int first, int p
                 fill[w] += sz;
             }
             misc[0] = ovf;
-            dm[2] = Sn;
         }
         sync();
         if (misc[0]) return 1;
-        S = dm[2];
-        Sthr = S * (1.0 - 1e-9);
         for (int s = t; s < C; s += NT)
             if (ws[s] >= 0) slot_of[ws[s]] = s;
+        // The drift bound of the new W.  Only coordinates in W move, so
+        // r_j = sum_{k in W} |G_jk| bounds |u_j(beta) - u_j(beta')| per unit
+        // of max_k |beta_k - beta'_k| (rows of G for the W coordinates,
+        // coalesced over j; gfull is free here).  S is the smallest s_k / r_k
+        // outside W.
+        for (int j0 = 0; j0 < p; j0 += NT) {
+            const int j = min(j0 + t, p - 1);
+            double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+            for (int s0 = 0; s0 < C; s0 += 16) {
+                double gv[16];
+#pragma unroll
+                for (int u = 0; u < 16; ++u) {
+                    const int jk = ws[s0 + u];
+                    gv[u] = jk >= 0 ? fabs(gat((size_t)jk * p + j)) : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < 16; u += 4) {
+                    a0 += gv[u];
+                    a1 += gv[u + 1];
+                    a2 += gv[u + 2];
+                    a3 += gv[u + 3];
+                }
+            }
+            if (j0 + t < p) gfull[j0 + t] = (a0 + a1) + (a2 + a3);
+        }
+        sync();
+        double sb = INFINITY;
+        if (!grp) {
+            for (int j = t; j < p; j += NT) {
+                const double rinv = 1.0 / gfull[j];
+                r1[j] = rinv;
+                if (slot_of[j] < 0)
+                    sb = fmin(sb, fmin((wl[j] * lam_next * thr_scale - kref[j]) * rinv, DBL_MAX));
+            }
+        } else {
+            for (int g = t; g < P.ngroups; g += NT) {
+                const int q0 = gstart[g], q1 = gstart[g + 1];
+                double rr = 0.0;
+                for (int qq = q0; qq < q1; ++qq) rr += gfull[gidx[qq]] * gfull[gidx[qq]];
+                const double rinv = 1.0 / sqrt(rr);
+                r1[g] = rinv;
+                if (slot_of[gidx[q0]] < 0) sb = fmin(sb, fmin((cgw[g] * lam_next - kref[g]) * rinv, DBL_MAX));
+            }
+        }
+        sb = -wave_max(-sb);
+        if (lane == 0) dm[wave * 4 + 3] = sb;
+        sync();
+        S = dm[3];
+        for (int w = 1; w < NW; ++w) S = fmin(S, dm[w * 4 + 3]);
+        Sthr = S * (1.0 - 1e-9);
         mark_w();
         // both lanes of a slot take its new coordinate; G_WW into registers
         jc = ws[os];
