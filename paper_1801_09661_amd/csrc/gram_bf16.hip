@@ -36,6 +36,9 @@ namespace oem {
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float f32x16_t __attribute__((ext_vector_type(16)));
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
 
 constexpr int kBThreads = 256;
 constexpr int kBTile = 32;                 // MFMA output tile
@@ -70,17 +73,16 @@ __host__ __device__ constexpr int dg_b(int grp, int t)
 // of the 8 rows `row`.  Columns at or past p are read from a valid column
 // instead; they only feed tile entries that are discarded.
 template <bool VEC>
-__device__ inline void load_block(float (&x)[8][4], const float *__restrict__ X, int64_t ldx, int p,
-                                  int col, const int64_t (&row)[8])
+__device__ inline void load_block(float (&x)[8][4], const float *const (&rp)[8], int p, int col)
 {
     // 16-byte loads need only 4-byte alignment on gfx950 (column choice:
-    // gram_col_plan).
+    // gram_col_plan).  rp: the 8 rows.
     const GramColPlan cp = gram_col_plan(VEC, col, p);
     if (cp.vec) {
         const int cv = cp.first;
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
-            const f32x4_t v = *reinterpret_cast<const f32x4_t *>(X + row[e] * ldx + cv);
+            const f32x4_t v = *reinterpret_cast<const f32x4_t *>(rp[e] + cv);
 #pragma unroll
             for (int j = 0; j < 4; ++j) x[e][j] = v[j];
         }
@@ -91,7 +93,7 @@ __device__ inline void load_block(float (&x)[8][4], const float *__restrict__ X,
 #pragma unroll
         for (int e = 0; e < 8; ++e)
 #pragma unroll
-            for (int j = 0; j < 4; ++j) x[e][j] = X[row[e] * ldx + cj[j]];
+            for (int j = 0; j < 4; ++j) x[e][j] = rp[e][cj[j]];
     }
 }
 
@@ -100,18 +102,27 @@ __device__ inline void stage_block(const float (&x)[8][4], __bf16 *hi, __bf16 *l
 {
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-        bf16x8_t h, lw;
+        // two rows per conversion: hi = bf16(v) of a pair in one packed
+        // conversion, its FP32 value by bit operations, lo = bf16(v - hi)
+        // of the pair in another (both round to nearest even)
+        uint32_t hw[4], lw[4];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const float v = x[e][j];
-            const __bf16 hb = (__bf16)v;
-            h[e] = hb;
-            if (SPLIT) lw[e] = (__bf16)(v - (float)hb);
+        for (int e = 0; e < 8; e += 2) {
+            const float v0 = x[e][j], v1 = x[e + 1][j];
+            const bf16x2_t h2 = __builtin_convertvector((f32x2_t){v0, v1}, bf16x2_t);
+            const uint32_t hb = __builtin_bit_cast(uint32_t, h2);
+            hw[e / 2] = hb;
+            if (SPLIT) {
+                const float h0 = __builtin_bit_cast(float, hb << 16);
+                const float h1 = __builtin_bit_cast(float, hb & 0xffff0000u);
+                const bf16x2_t l2 = __builtin_convertvector((f32x2_t){v0 - h0, v1 - h1}, bf16x2_t);
+                lw[e / 2] = __builtin_bit_cast(uint32_t, l2);
+            }
         }
         const int c = 4 * q + j;
         const int off = c * kBRows + 8 * (rg ^ bswz(c));
-        *reinterpret_cast<bf16x8_t *>(hi + off) = h;
-        if (SPLIT) *reinterpret_cast<bf16x8_t *>(lo + off) = lw;
+        *reinterpret_cast<u32x4_t *>(hi + off) = (u32x4_t){hw[0], hw[1], hw[2], hw[3]};
+        if (SPLIT) *reinterpret_cast<u32x4_t *>(lo + off) = (u32x4_t){lw[0], lw[1], lw[2], lw[3]};
     }
 }
 
@@ -191,13 +202,15 @@ __device__ __forceinline__ void gram_bf16_block(
     };
     auto load_chunk = [&](int c, int r) {
         int64_t row[8];
+        const float *rp[8];
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
             if constexpr (LIST) row[e] = nidx[e];
             else row[e] = first + min((int64_t)c * kBRows + 8 * rg + e, count - 1);
+            rp[e] = X + row[e] * ldx;
         }
-        load_block<VEC>(xa[r], X, ldx, g.p, colA, row);
-        if (!DIAG) load_block<VEC>(xb[r], X, ldx, g.p, colB, row);
+        load_block<VEC>(xa[r], rp, g.p, colA);
+        if (!DIAG) load_block<VEC>(xb[r], rp, g.p, colB);
         if (DIAG) {
 #pragma unroll
             for (int e = 0; e < 8; ++e) yv[r][e] = y[row[e]];
@@ -251,47 +264,41 @@ __device__ __forceinline__ void gram_bf16_block(
             const int ks = 2 * kh + ks0;
             if (DIAG) {
                 // group 0 uses tiles 0..3, group 1 tiles 1..3
+                // every pair of the group is formed (pairs past Wi read
+                // staged columns of the panel and are not emitted), so the
+                // accumulators are updated in place
                 bf16x8_t h[kBMaxW], l[kBMaxW];
 #pragma unroll
                 for (int a = 0; a < kBMaxW; ++a) {
-                    if (a < Wi && (pg == 0 || a >= 1)) {
-                        h[a] = operand(hiA, a, ks);
-                        if (SPLIT) l[a] = operand(loA, a, ks);
-                    }
+                    h[a] = operand(hiA, a, ks);
+                    if (SPLIT) l[a] = operand(loA, a, ks);
                 }
                 if (pg == 0) {
 #pragma unroll
                     for (int t = 0; t < 5; ++t)
-                        if (dg_b(0, t) < Wi)
-                            acc[t] = mfma3<SPLIT>(acc[t], h[dg_a(0, t)], l[dg_a(0, t)], h[dg_b(0, t)], l[dg_b(0, t)]);
+                        acc[t] = mfma3<SPLIT>(acc[t], h[dg_a(0, t)], l[dg_a(0, t)], h[dg_b(0, t)], l[dg_b(0, t)]);
                 } else {
 #pragma unroll
                     for (int t = 0; t < 5; ++t)
-                        if (dg_b(1, t) < Wi)
-                            acc[t] = mfma3<SPLIT>(acc[t], h[dg_a(1, t)], l[dg_a(1, t)], h[dg_b(1, t)], l[dg_b(1, t)]);
+                        acc[t] = mfma3<SPLIT>(acc[t], h[dg_a(1, t)], l[dg_a(1, t)], h[dg_b(1, t)], l[dg_b(1, t)]);
                 }
             } else {
                 bf16x8_t ah[2], al[2], bh[kBMaxW], bl[kBMaxW];
 #pragma unroll
                 for (int a = 0; a < 2; ++a) {
-                    if (2 * pg + a < Wi) {
-                        ah[a] = operand(hiA, 2 * pg + a, ks);
-                        if (SPLIT) al[a] = operand(loA, 2 * pg + a, ks);
-                    }
+                    ah[a] = operand(hiA, 2 * pg + a, ks);
+                    if (SPLIT) al[a] = operand(loA, 2 * pg + a, ks);
                 }
 #pragma unroll
                 for (int b = 0; b < kBMaxW; ++b) {
-                    if (b < Wj) {
-                        bh[b] = operand(hiB, b, ks);
-                        if (SPLIT) bl[b] = operand(loB, b, ks);
-                    }
+                    bh[b] = operand(hiB, b, ks);
+                    if (SPLIT) bl[b] = operand(loB, b, ks);
                 }
 #pragma unroll
                 for (int a = 0; a < 2; ++a)
 #pragma unroll
                     for (int b = 0; b < kBMaxW; ++b)
-                        if (2 * pg + a < Wi && b < Wj)
-                            acc[4 * a + b] = mfma3<SPLIT>(acc[4 * a + b], ah[a], al[a], bh[b], bl[b]);
+                        acc[4 * a + b] = mfma3<SPLIT>(acc[4 * a + b], ah[a], al[a], bh[b], bl[b]);
             }
         }
     };
