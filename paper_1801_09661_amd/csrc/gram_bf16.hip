@@ -399,7 +399,7 @@ __device__ __forceinline__ void gram_bf16_block(
 // OFF: the geometry has off-diagonal pairs (p > 128); without them the kernel
 // holds only the diagonal code and its smaller register set.
 template <bool SPLIT, bool LIST, bool VEC, bool OFF>
-__global__ __launch_bounds__(kBThreads) void gram_bf16_kernel(
+__global__ __launch_bounds__(kBThreads, 2) void gram_bf16_kernel(
     const float *__restrict__ X, int64_t n, int64_t ldx, const double *__restrict__ y, GramGeom g,
     RowSource rs, float *__restrict__ partial, double *__restrict__ pvec, double *__restrict__ pscal)
 {
