@@ -196,7 +196,7 @@ __device__ __forceinline__ void path_ws_body(const PathDesc &P, int first, int p
         double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
         // the operand reads of a block of 16 columns are issued together
         // (one LDS latency per block rather than per pair of reads)
-        constexpr int SB = HC < 16 ? HC : 16;
+        constexpr int SB = HC < 32 ? HC : 32;
 #pragma unroll
         for (int c0 = 0; c0 < HC; c0 += SB) {
             double2 vb[SB / 2];
