@@ -56,6 +56,8 @@ def parse():
     ap.add_argument("--nlambda", type=int, default=100)
     ap.add_argument("--precision", default="split_bf16", choices=["fp64", "split_bf16", "bf16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--sequential", action="store_true",
+                    help="CV line: one problem in flight (default: two, on two streams)")
     ap.add_argument("--no-extras", action="store_true", help="skip the sub-records and the oracle errors")
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="run only this many steps of the main form (for profilers); no extras")
@@ -256,11 +258,15 @@ def cpu_baseline_cv(X, y, K, seed, stats, pens, lam, groups, n_full, target_s=4.
 
 # ---------------------------------------------------------------- timing
 
-def time_cv_form(oem, torch, X, y, K, form, pens, groups, nlambda, steps, warm):
-    """Whole steps of one form; then one step split into phases with HIP
-    events on the launch stream: Gram pass, first oem_cv (d of the 11
-    problems + paths + CV), a second oem_cv on the same statistics (paths +
-    CV: d is kept), and the Gram pass alone back to back."""
+def time_cv_form(oem, torch, X, y, K, form, pens, groups, nlambda, steps, warm, pipelined=True):
+    """Whole steps of one form, one problem in flight and (pipelined) two in
+    flight on two streams: the Gram pass of step i + 1 runs on its own handle
+    beside the paths of step i, and its combination, d and paths start once
+    step i has finished (the multi-workgroup d launch needs its workgroups
+    resident).  Then one step split into phases with HIP events on the launch
+    stream: Gram pass, first oem_cv (d of the 11 problems + paths + CV), a
+    second oem_cv on the same statistics (paths + CV: d is kept), and the
+    Gram pass alone back to back."""
     import numpy as np
     p = X.shape[1]
     g = oem.Gram(p, K, form, X.dtype, CV_SEED)
@@ -280,7 +286,40 @@ def time_cv_form(oem, torch, X, y, K, form, pens, groups, nlambda, steps, warm):
     for _ in range(steps):
         res = step()
     torch.cuda.synchronize()
-    t = time.perf_counter() - t0
+    t_seq = time.perf_counter() - t0
+    t = t_seq
+    identical = None
+    if pipelined:
+        g2 = oem.Gram(p, K, form, X.dtype, CV_SEED)   # the tuned workgroup count is per shape
+        handles, streams = [g, g2], [stream, torch.cuda.Stream()]
+
+        def pstep(i, prev):
+            st, h = streams[i % 2], handles[i % 2]
+            with torch.cuda.stream(st):
+                oem.oem_gram_reset(h.h)
+                h.add(X, y)
+                if prev is not None:
+                    st.wait_event(prev)
+                r = h.cv(pens, nlambda=nlambda, lambda_min_ratio=1e-3, tol=1e-10, groups=groups, sync=False)
+                done = torch.cuda.Event()
+                done.record(st)
+            return r, done
+
+        prev = None
+        for i in range(warm):
+            _, prev = pstep(i, prev)
+        torch.cuda.synchronize()
+        outs = []
+        t0 = time.perf_counter()
+        for i in range(steps):
+            r, prev = pstep(i, prev)
+            outs.append(r)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        ref = res["beta"].cpu().numpy()
+        identical = all(np.array_equal(r["beta"].cpu().numpy(), ref) for r in outs)
+        del outs
+        g2.close()
     e = [ev() for _ in range(4)]
     oem.oem_gram_reset(g.h)
     e[0].record(stream)
@@ -306,6 +345,9 @@ def time_cv_form(oem, torch, X, y, K, form, pens, groups, nlambda, steps, warm):
     b.record(stream)
     torch.cuda.synchronize()
     out = dict(ms_per_step=1e3 * t / steps, fits_per_s=(K + 1) * len(pens) * steps / t,
+               sequential_ms_per_step=1e3 * t_seq / steps,
+               sequential_fits_per_s=(K + 1) * len(pens) * steps / t_seq,
+               pipelined=pipelined, pipelined_results_identical=identical,
                gram_ms=e[0].elapsed_time(e[1]), cv_ms=e[1].elapsed_time(e[2]),
                paths_ms=e[2].elapsed_time(e[3]), gram_only_ms=a.elapsed_time(b) / reps,
                updates=int(np.abs(res2["iters"].cpu().numpy()).sum()),
@@ -569,7 +611,8 @@ def cv_main(args):
     steps = args.profile_steps or args.steps
     warm = 0 if args.profile_steps else args.warmup
     forms = [args.precision] if (args.profile_steps or args.precision == "fp64") else [args.precision, "fp64"]
-    runs = {f: time_cv_form(oem, torch, X, y, K, f, CV_PENALTIES, groups, args.nlambda, steps, warm)
+    pipelined = not (args.sequential or args.profile_steps)
+    runs = {f: time_cv_form(oem, torch, X, y, K, f, CV_PENALTIES, groups, args.nlambda, steps, warm, pipelined)
             for f in forms}
     if args.calibrate_copy:
         Z = torch.empty_like(X)
@@ -602,6 +645,11 @@ def cv_main(args):
                                "of 10 (5 active), group lasso+lasso+MCP, 100 lambdas, tol 1e-10",
                    "n": n, "p": p, "folds": K, "penalties": len(CV_PENALTIES), "nlambda": args.nlambda,
                    "precision": args.precision},
+        "pipeline": ("two CV problems in flight on two streams: the Gram pass of step i + 1 beside the "
+                     "paths of step i; every step is a whole Gram pass + oem_cv" if pipelined else
+                     "one CV problem in flight"),
+        "sequential": dict(ms_per_step=m["sequential_ms_per_step"], fits_per_s=m["sequential_fits_per_s"]),
+        "pipelined_results_identical": m["pipelined_results_identical"],
         "phase_ms": phase_ms,
         "gram_gbps": x_bytes / (m["gram_only_ms"] * 1e-3) / 1e9,
         "oem_updates": m["updates"],
@@ -613,6 +661,8 @@ def cv_main(args):
     if "fp64" in runs and args.precision != "fp64":
         f = runs["fp64"]
         out["fp64_form"] = dict(fits_per_s=f["fits_per_s"], ms_per_step=f["ms_per_step"],
+                                sequential=dict(ms_per_step=f["sequential_ms_per_step"],
+                                                fits_per_s=f["sequential_fits_per_s"]),
                                 phase_ms=dict(gram=f["gram_ms"], lanczos=f["derive_ms"], paths=f["paths_ms"]),
                                 gram_tflops=2.0 * n * p * (p + 1) / 2 / (f["gram_only_ms"] * 1e-3) / 1e12)
         out["fp64_form"]["gram_roofline"] = dict(
@@ -621,6 +671,7 @@ def cv_main(args):
             frac=out["fp64_form"]["gram_tflops"] / FP64_PEAK_TFLOPS, traffic=None,
             algorithmic="n p (p + 1) flops per pass (upper triangle with the diagonal, 2 per product)")
         out["mixed_vs_fp64_fits"] = m["fits_per_s"] / f["fits_per_s"]
+        out["mixed_vs_fp64_fits_sequential"] = m["sequential_fits_per_s"] / f["sequential_fits_per_s"]
     if args.profile_steps or args.no_extras:
         print(json.dumps(out))
         return
