@@ -74,6 +74,28 @@ def test_paths_parity_large_p(p, n, pens):
     assert np.all(res["kkt"].cpu().numpy() <= 1e-8)
 
 
+def test_group_lasso_parity_large_p_streaming():
+    """Group lasso at p = 1100 with 16 active groups of 10: the path moves from
+    the two-wave and four-wave working sets (at most 12 groups of 10) to the
+    streaming kernel.  Reference as in the large-p test above: the oracle's
+    path pipeline on a library FP64 Gram, d from a library eigen-solver."""
+    oem = _oem()
+    print("case: group lasso p=1100 n=6000, 16 active groups", flush=True)
+    pr = workloads.cv_grouped(n=6000, p=1100, group_size=10, active_groups=16, seed_tag=251)
+    X64 = pr.X.astype(np.float64)
+    st = oracle.prepare(X64.T @ X64, X64.T @ pr.y, float(pr.y @ pr.y), 6000)
+    d_ref = float(np.linalg.eigvalsh(st["Gs"]).max()) * (1 + 1e-10)
+    pens = ["grp_lasso"]
+    lam = oracle.lambda_sequences(st["cs"], pens, 15, 2e-2, groups=pr.groups)
+    res = oem.fit(_cuda(pr.X), _cuda(pr.y), pens, nlambda=15, lambdas=lam, tol=TOL, groups=pr.groups)
+    torch.cuda.synchronize()
+    assert abs(res["d"].item() - d_ref) <= 1e-12 * d_ref
+    ref = oracle.fit_from_stats(st, pens, lam, groups=pr.groups, tol=TOL, d=d_ref)
+    _assert_paths(res["beta"].cpu().numpy(), ref["beta"], what="grp p=1100", first_is_knife_edge=True)
+    assert (ref["beta"][0, -1] != 0).sum() > 120       # more than 12 groups: the streaming kernel ran
+    assert np.all(res["kkt"].cpu().numpy() <= 1e-8)
+
+
 def test_fp64_x_with_folds():
     """FP64 X and K = 3 hashed folds: CV parity against the oracle."""
     oem = _oem()
