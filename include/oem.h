@@ -38,12 +38,14 @@
  *   - Host waits.  oem_gram, oem_gram_reset, oem_gram_import,
  *     oem_gram_export and oem_batch_run(_graph) enqueue work and return
  *     without waiting for the GPU.  oem_fit_path and oem_cv wait for
- *     `stream` (i) once after the statistics changed, to read back d and
- *     the row counts they validate (penalty conditions gamma d > 1, empty
- *     folds), and (ii) after each upload of their small host tables (lambda
- *     values, groups, path descriptors, a few KB); the path, CV and
- *     selection kernels themselves are enqueued and the call returns before
- *     they finish unless opts->sync = 1.  oem_gram_autotune,
+ *     `stream` once after the statistics changed, to read back d and the
+ *     row counts they validate (penalty conditions gamma d > 1, empty
+ *     folds).  Their small host tables (lambda values, groups, path
+ *     descriptors, a few KB) are copied into the handle and uploaded
+ *     without a wait (a later call waits, if need be, for the previous
+ *     upload of the same table before reusing its host copy); the path, CV
+ *     and selection kernels are enqueued and the call returns before they
+ *     finish unless opts->sync = 1.  oem_gram_autotune,
  *     oem_batch_create, oem_batch_status and the free functions wait for
  *     the device.
  *   - Concurrent streams.  For 128 < p <= 2048 the eigenvalue bound d is

@@ -114,8 +114,8 @@ static int build_groups(oem_gram_s *h, const oem_path_opts *o, bool need_groups,
     const size_t o_gi = put(gp.gidx.data(), gp.gidx.size() * sizeof(int32_t));
     const size_t o_w = put(gp.w.data(), gp.w.size() * sizeof(double));
     const size_t o_cg = put(gp.cg.data(), gp.cg.size() * sizeof(double));
-    OEM_HIP_CHECK(hipMemcpyAsync(h->groupbuf.ptr, host.data(), bytes, hipMemcpyHostToDevice, s));
-    OEM_HIP_CHECK(hipStreamSynchronize(s));   // host staging buffer is released on return
+    rc = stage_upload(h, kUpGroups, h->groupbuf.ptr, host.data(), bytes, s);
+    if (rc) return rc;
     char *base = static_cast<char *>(h->groupbuf.ptr);
     if (!gp.gstart.empty()) {
         gp.d_gstart = reinterpret_cast<const int32_t *>(base + o_gs);
@@ -221,13 +221,11 @@ static int prepare_lambda(oem_gram_s *h, const oem_penalty *pen, int npen,
     if (o->lambda) {
         for (size_t i = 0; i < nl; ++i)
             if (!(o->lambda[i] >= 0.0)) return fail(OEM_E_INVAL, "lambda values must be >= 0");
-        OEM_HIP_CHECK(hipMemcpyAsync(dl, o->lambda, nl * sizeof(double), hipMemcpyHostToDevice, s));
-        OEM_HIP_CHECK(hipStreamSynchronize(s));
-        return OEM_OK;
+        return stage_upload(h, kUpLambda, dl, o->lambda, nl * sizeof(double), s);
     }
     oem_penalty *dpen = reinterpret_cast<oem_penalty *>(dl + nl);
-    OEM_HIP_CHECK(hipMemcpyAsync(dpen, pen, npen * sizeof(oem_penalty), hipMemcpyHostToDevice, s));
-    OEM_HIP_CHECK(hipStreamSynchronize(s));
+    rc = stage_upload(h, kUpLambda, dpen, pen, npen * sizeof(oem_penalty), s);
+    if (rc) return rc;
     return launch_lambda_grid(h->cs.as<double>(), h->p, gp.d_gstart, gp.d_gidx, gp.ngroups, gp.d_w,
                               gp.d_cg, dpen, npen, L, o->lambda_min_ratio, dl, s);
 }
@@ -270,14 +268,39 @@ static PathDesc make_desc(oem_gram_s *h, int q, const oem_penalty &pn, const oem
     return d;
 }
 
+int stage_upload(oem_gram_s *h, int slot, void *dst, const void *src, size_t bytes, hipStream_t s)
+{
+    if (bytes == 0) return OEM_OK;
+    UploadStage &u = h->up;
+    if (u.pending[slot]) {
+        // the previous copy out of this slot has run before its bytes change
+        OEM_HIP_CHECK(hipEventSynchronize(u.done[slot]));
+        u.pending[slot] = false;
+    }
+    if (!u.done[slot]) OEM_HIP_CHECK(hipEventCreateWithFlags(&u.done[slot], hipEventDisableTiming));
+    std::vector<char> &b = u.bytes[slot];
+    b.assign(static_cast<const char *>(src), static_cast<const char *>(src) + bytes);
+    OEM_HIP_CHECK(hipMemcpyAsync(dst, b.data(), bytes, hipMemcpyHostToDevice, s));
+    OEM_HIP_CHECK(hipEventRecord(u.done[slot], s));
+    u.pending[slot] = true;
+    return OEM_OK;
+}
+
+void free_upload_stage(oem_gram_s *h)
+{
+    for (int k = 0; k < kUpSlots; ++k)
+        if (h->up.done[k]) {
+            (void)hipEventDestroy(h->up.done[k]);
+            h->up.done[k] = nullptr;
+            h->up.pending[k] = false;
+        }
+}
+
 static int upload_descs(oem_gram_s *h, const std::vector<PathDesc> &descs, hipStream_t s)
 {
     int rc = h->paths.ensure(descs.size() * sizeof(PathDesc));
     if (rc) return rc;
-    OEM_HIP_CHECK(hipMemcpyAsync(h->paths.ptr, descs.data(), descs.size() * sizeof(PathDesc),
-                                 hipMemcpyHostToDevice, s));
-    OEM_HIP_CHECK(hipStreamSynchronize(s));
-    return OEM_OK;
+    return stage_upload(h, kUpDescs, h->paths.ptr, descs.data(), descs.size() * sizeof(PathDesc), s);
 }
 
 static int finish_sync(const int32_t *d_iters, size_t count, hipStream_t s)
@@ -412,6 +435,7 @@ void oem_gram_free(oem_handle h)
     if (!h) return;
     (void)hipDeviceSynchronize();
     free_host_stage(h);
+    free_upload_stage(h);
     for (DevBuf *b : {&h->Gk, &h->bk, &h->yyk, &h->nk, &h->csk, &h->ysk, &h->xbar, &h->ybar, &h->Gs, &h->cs, &h->sc, &h->yyn,
                       &h->dq, &h->ntrain, &h->lzsteps, &h->partial, &h->partial_n, &h->rowlist, &h->lanczos,
                       &h->paths, &h->order, &h->lam, &h->betaw, &h->groupbuf, &h->cvw, &h->flag, &h->pathws, &h->lzjobs})
@@ -660,7 +684,7 @@ int oem_fit_path(oem_handle h, int32_t fold, const oem_penalty *pen, int32_t npe
     if (rc) return rc;
     rc = upload_descs(h, descs, s);
     if (rc) return rc;
-    rc = launch_paths(h->paths.as<PathDesc>(), descs, h->order, s);
+    rc = launch_paths(h->paths.as<PathDesc>(), descs, h->order, s, h);
     if (rc) return rc;
     if (opts->intercept && opts->beta0) {
         rc = launch_intercepts(h->paths.as<PathDesc>(), (int)descs.size(), s);
@@ -742,7 +766,7 @@ int oem_cv(oem_handle h, const oem_penalty *pen, int32_t npen, const oem_path_op
     if (rc) return rc;
     rc = upload_descs(h, descs, s);
     if (rc) return rc;
-    rc = launch_paths(h->paths.as<PathDesc>(), descs, h->order, s);
+    rc = launch_paths(h->paths.as<PathDesc>(), descs, h->order, s, h);
     if (rc) return rc;
     if (opts->intercept) {
         rc = launch_intercepts(h->paths.as<PathDesc>(), (int)descs.size(), s);

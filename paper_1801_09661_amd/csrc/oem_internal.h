@@ -145,6 +145,18 @@ struct DevBuf {
 
 struct HostStage;   // staging of the out-of-core Gram pass (stream_host.hip)
 
+// Small host tables a call uploads (groups, lambda values and penalties, path
+// descriptors, the launch order).  Each slot keeps its bytes in the handle
+// until the copy has run, so a call enqueues its uploads without waiting;
+// the slot's event, recorded behind its copy, is waited for before the next
+// call rewrites it.
+enum UploadSlot { kUpGroups, kUpLambda, kUpDescs, kUpOrder, kUpSlots };
+struct UploadStage {
+    std::vector<char> bytes[kUpSlots];
+    hipEvent_t done[kUpSlots] = {};
+    bool pending[kUpSlots] = {};
+};
+
 } // namespace oem
 
 struct oem_gram_s {
@@ -168,6 +180,7 @@ struct oem_gram_s {
     // workspaces
     oem::DevBuf partial, partial_n, rowlist, lanczos, paths, order, lam, betaw, groupbuf, cvw, flag, pathws, lzjobs;
     oem::HostStage *stage = nullptr;   // out-of-core staging, created on first use
+    oem::UploadStage up;               // host tables of the path calls
 };
 
 namespace oem {
@@ -209,6 +222,10 @@ int launch_gram_csr(oem_gram_s *h, const int64_t *rowptr, const int32_t *col, co
 int gram_from_host(oem_gram_s *h, const void *X, int64_t n, int64_t ldx, const double *y,
                    int64_t row_offset, const uint8_t *foldid, int64_t chunk_rows, hipStream_t s);
 void free_host_stage(oem_gram_s *h);
+// Enqueue a copy of `bytes` host bytes to `dst` through upload slot `slot`
+// of the handle (no host wait); release the slots' events.
+int stage_upload(oem_gram_s *h, int slot, void *dst, const void *src, size_t bytes, hipStream_t s);
+void free_upload_stage(oem_gram_s *h);
 // Workspace bytes one Gram pass of the handle's shape over n rows carves
 // from a GramWork (the same plan as the pass itself).
 size_t gram_work_bytes(const oem_gram_s *h, int64_t n);
@@ -226,7 +243,7 @@ int launch_lambda_grid(const double *cs_full, int p, const int32_t *gstart, cons
                        int ngroups, const double *w, const double *cg, const oem_penalty *d_pens,
                        int npen, int L, double ratio, double *lambda_out, hipStream_t s);
 int launch_paths(const PathDesc *d_desc, const std::vector<PathDesc> &host, DevBuf &orderbuf,
-                 hipStream_t s);
+                 hipStream_t s, oem_gram_s *stage_owner);
 // The same split into a plan (host: order table grouped by kernel class) and
 // launches that enqueue kernels only (no allocation, no host wait).
 // cls: path kernel; first: offset of its paths in the order table; chain:

@@ -553,16 +553,15 @@ int launch_paths_general(const PathDesc *d_desc, int count, int pmax, hipStream_
 // One set of launches for paths of any p: the order table groups the paths
 // by kernel class.
 int launch_paths(const PathDesc *d_desc, const std::vector<PathDesc> &host, DevBuf &orderbuf,
-                 hipStream_t s)
+                 hipStream_t s, oem_gram_s *stage_owner)
 {
     if (host.empty()) return OEM_OK;
     PathPlan plan;
     plan_paths(host, plan);
     int rc = orderbuf.ensure(plan.order.size() * sizeof(int));
     if (rc) return rc;
-    OEM_HIP_CHECK(hipMemcpyAsync(orderbuf.ptr, plan.order.data(), plan.order.size() * sizeof(int),
-                                 hipMemcpyHostToDevice, s));
-    OEM_HIP_CHECK(hipStreamSynchronize(s));
+    rc = stage_upload(stage_owner, kUpOrder, orderbuf.ptr, plan.order.data(), plan.order.size() * sizeof(int), s);
+    if (rc) return rc;
     return launch_paths_planned(d_desc, orderbuf.as<int>(), plan, s);
 }
 

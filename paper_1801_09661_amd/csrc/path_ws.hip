@@ -61,6 +61,9 @@ static __host__ __device__ inline int ws_pow2(int v)
 // G stays in LDS for the one-wave kernel (p <= 128)
 constexpr int kWsLdsGMaxP = 128;
 
+// LDS a working-set workgroup reserves (more than half of a CU's 160 KB)
+constexpr size_t kWsReserveLds = 100 * 1024;
+
 size_t path_ws_lds_bytes(int NW, int pcap)
 {
     const int C = NW * kWsCB, PSC = ws_pow2(pcap);
@@ -995,7 +998,16 @@ int launch_paths_ws(const PathDesc *d_desc, const int *d_order, int count, int n
     if (pmax > 2048) return fail(OEM_E_INVAL, "working-set path kernel needs p <= 2048");
     if (nw == 1 && pmax > kWsLdsGMaxP) return fail(OEM_E_INVAL, "one-wave working-set kernel needs p <= 128");
     int pcap = pmax;
-    const size_t lds = path_ws_lds_bytes(nw, pcap);
+    // A path is a chain of dependent updates on one CU.  When the launch has
+    // no more paths than the GPU has CUs, each workgroup asks for at least
+    // kWsReserveLds of LDS, so that workgroups of other kernels running at the
+    // same time (the next problem's Gram pass) are not placed beside it, where
+    // they would compete for the LDS and issue slots its chain waits on.
+    int dev = 0, ncu = 0;
+    OEM_HIP_CHECK(hipGetDevice(&dev));
+    OEM_HIP_CHECK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    const size_t need = path_ws_lds_bytes(nw, pcap);
+    const size_t lds = count <= ncu ? std::max(need, kWsReserveLds) : need;
     OEM_HIP_CHECK(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     void *args[] = {(void *)&d_desc, (void *)&d_order, (void *)&first, (void *)&pcap};
     OEM_HIP_CHECK(hipLaunchKernel(kern, dim3(count), dim3(64 * nw), args, lds, s));
