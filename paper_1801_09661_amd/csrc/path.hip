@@ -615,14 +615,21 @@ int launch_intercepts(const PathDesc *d_desc, int count, hipStream_t s)
 // MSE_{k,l} = (yy_k - 2 beta^T b_k + beta^T G_k beta) / n_k from held-out
 // sums; with an intercept b0 the residual is y - b0 - x^T beta, which adds
 // n_k b0^2 - 2 b0 sum_k y + 2 b0 beta^T colsum_k.  One workgroup per (fold,
-// penalty, lambda).
+// penalty, lambda).  Only the nonzero coefficients enter: their indices and
+// values are gathered into LDS (ascending), then beta^T G_k beta is the sum
+// over pairs of them, each thread taking pairs along a row of G_k.
 __global__ __launch_bounds__(kPathThreads) void cv_mse_kernel(
     const double *__restrict__ Gk, const double *__restrict__ bk, const double *__restrict__ yyk,
     const int64_t *__restrict__ nk, const double *__restrict__ csk, const double *__restrict__ ysk,
     const double *__restrict__ beta0_folds, int K, int p, int npen, int L,
     const double *__restrict__ beta_folds, double *__restrict__ mse)
 {
+    extern __shared__ double cv_sm[];
+    double *val = cv_sm;                                        // [p] nonzero values
+    int *idx = reinterpret_cast<int *>(val + p);                // [p] their indices
     __shared__ double red[3 * kPathWaves];
+    __shared__ int wcnt[kPathWaves];
+    const int t = threadIdx.x, lane = t % kWave, wave = t / kWave;
     const int l = blockIdx.x % L;
     const int pen = (blockIdx.x / L) % npen;
     const int k = blockIdx.x / (L * npen);
@@ -630,26 +637,46 @@ __global__ __launch_bounds__(kPathThreads) void cv_mse_kernel(
     const double *beta = beta_folds + path_l * p;
     const double *G = Gk + (size_t)k * p * p;
     double quad = 0.0, lin = 0.0, mix = 0.0;
-    for (int i = threadIdx.x; i < p; i += kPathThreads) {
-        double acc = 0.0;
-        for (int j = 0; j < p; ++j) {
-            const double bj = beta[j];
-            if (bj != 0.0) acc += G[(size_t)j * p + i] * bj;
+    // gather the nonzero coefficients in ascending order
+    int nnz = 0;
+    for (int base = 0; base < p; base += kPathThreads) {
+        const int j = base + t;
+        const double b = j < p ? beta[j] : 0.0;
+        const bool nz = b != 0.0;
+        const uint64_t ball = __ballot(nz);
+        if (lane == 0) wcnt[wave] = __popcll(ball);
+        __syncthreads();
+        int before = 0, total = 0;
+        for (int w = 0; w < kPathWaves; ++w) {
+            before += w < wave ? wcnt[w] : 0;
+            total += wcnt[w];
         }
-        quad += beta[i] * acc;
-        lin += beta[i] * bk[(size_t)k * p + i];
-        if (beta0_folds) mix += beta[i] * csk[(size_t)k * p + i];
+        if (nz) {
+            const int e = nnz + before + __popcll(ball & ((1ull << lane) - 1ull));
+            val[e] = b;
+            idx[e] = j;
+            lin += b * bk[(size_t)k * p + j];
+            if (beta0_folds) mix += b * csk[(size_t)k * p + j];
+        }
+        nnz += total;
+        __syncthreads();
+    }
+    // beta^T G beta over the pairs (a, c) of nonzero coefficients
+    const int pairs = nnz * nnz;
+    for (int e = t; e < pairs; e += kPathThreads) {
+        const int a = e / nnz, c = e - a * nnz;
+        quad += val[a] * (G[(size_t)idx[a] * p + idx[c]] * val[c]);
     }
     quad = wave_sum(quad);
     lin = wave_sum(lin);
     mix = wave_sum(mix);
-    if (threadIdx.x % kWave == 0) {
-        red[threadIdx.x / kWave] = quad;
-        red[kPathWaves + threadIdx.x / kWave] = lin;
-        red[2 * kPathWaves + threadIdx.x / kWave] = mix;
+    if (lane == 0) {
+        red[wave] = quad;
+        red[kPathWaves + wave] = lin;
+        red[2 * kPathWaves + wave] = mix;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (t == 0) {
         double q2 = 0.0, l2 = 0.0, m2 = 0.0;
         for (int w = 0; w < kPathWaves; ++w) {
             q2 += red[w];
@@ -717,7 +744,10 @@ int launch_cv(const double *Gk, const double *bk, const double *yyk, const int64
               int p, int npen, int L, const double *beta_folds, double *mse, double *cvm,
               double *cvsd, int32_t *i_min, int32_t *i_1se, int32_t *best, hipStream_t s)
 {
-    hipLaunchKernelGGL(cv_mse_kernel, dim3(K * npen * L), dim3(kPathThreads), 0, s, Gk, bk, yyk, nk,
+    const size_t lds = (size_t)p * (sizeof(double) + sizeof(int));
+    OEM_HIP_CHECK(hipFuncSetAttribute((const void *)cv_mse_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      (int)lds));
+    hipLaunchKernelGGL(cv_mse_kernel, dim3(K * npen * L), dim3(kPathThreads), lds, s, Gk, bk, yyk, nk,
                        csk, ysk, beta0_folds, K, p, npen, L, beta_folds, mse);
     OEM_HIP_CHECK(hipGetLastError());
     hipLaunchKernelGGL(cv_select_kernel, dim3(1), dim3(256), 0, s, mse, nk, K, npen, L, cvm, cvsd,
