@@ -97,7 +97,7 @@ __device__ __forceinline__ void path_ws_body(const PathDesc &P, int first, int p
     double *ab = key + PSC;                   // [C] values of the nonzero coordinates
     double *cl = ab + C;                      // [pcap] c
     double *scl = cl + pcap;                  // [pcap] column scales
-    double *wl = scl + pcap;                  // [pcap] penalty weights
+    double *wl = scl + pcap;                  // [pcap] penalty weights; group lasso: c_g of each group
     double *usq = wl + pcap;                  // [NW][CB] u^2 of each wave's slots (group lasso)
     double *kref = usq + C;                   // [PSC] |u_j| (||u_g||) of each key at the reference beta
     double *gls = kref + PSC;                 // [pcap pcap] G (one-wave kernel only)
@@ -156,8 +156,11 @@ __device__ __forceinline__ void path_ws_body(const PathDesc &P, int first, int p
     for (int j = t; j < p; j += NT) {
         cl[j] = c_g[j];
         scl[j] = s_g[j];
-        wl[j] = w_g ? w_g[j] : 1.0;
+        if (!grp) wl[j] = w_g ? w_g[j] : 1.0;
     }
+    if (grp)
+        for (int g = t; g < P.ngroups; g += NT) wl[g] = cgw[g];
+    const double *cgl = wl;                   // group weights from LDS
     if constexpr (NW == 1) {
         const int pp = p * p;
         for (int e = t; e < pp; e += NT) gls[e] = G[e];
@@ -230,7 +233,7 @@ __device__ __forceinline__ void path_ws_body(const PathDesc &P, int first, int p
     };
     auto set_upd = [&](double lam) {
         q = make_upd(kind, wt * lam, d, P.alpha, P.gamma);
-        lamc = (grp && jc >= 0) ? cgw[gof[jc]] * lam : 0.0;
+        lamc = (grp && jc >= 0) ? cgl[gof[jc]] * lam : 0.0;
     };
 
     // The keys in W get kref = -inf: no bound for the next lambda comes
@@ -395,7 +398,7 @@ __device__ __forceinline__ void path_ws_body(const PathDesc &P, int first, int p
                     }
                 }
                 if (lam_end >= 0.0) {
-                    const double lc = lam_end * cgw[g];
+                    const double lc = lam_end * cgl[g];
                     const double bn = sqrt(bb);
                     double v;
                     if (bn > 0.0) {
@@ -413,7 +416,7 @@ __device__ __forceinline__ void path_ws_body(const PathDesc &P, int first, int p
                     penv += lc * bn;
                 }
                 if (has_next) {
-                    const double thr = cgw[g] * lam_next;
+                    const double thr = cgl[g] * lam_next;
                     const double un = sqrt(uu);
                     const double sl = thr - un;
                     const bool need = nz || !(sl > 1e-12 * thr);
@@ -621,7 +624,7 @@ __device__ __forceinline__ void path_ws_body(const PathDesc &P, int first, int p
                 for (int qq = q0; qq < q1; ++qq) rr += gfull[gidx[qq]] * gfull[gidx[qq]];
                 const double rinv = 1.0 / sqrt(rr);
                 r1[g] = rinv;
-                if (slot_of[gidx[q0]] < 0) sb = fmin(sb, fmin((cgw[g] * lam_next - kref[g]) * rinv, DBL_MAX));
+                if (slot_of[gidx[q0]] < 0) sb = fmin(sb, fmin((cgl[g] * lam_next - kref[g]) * rinv, DBL_MAX));
             }
         }
         sb = -wave_max(-sb);
@@ -730,7 +733,7 @@ __device__ __forceinline__ void path_ws_body(const PathDesc &P, int first, int p
                     if (beta_std_g) beta_std_g[(size_t)l_end * p + j] = b;
                     bws[j] = b;
                 }
-                const double lc = lam_end * cgw[gof[j0]];
+                const double lc = lam_end * cgl[gof[j0]];
                 const double bn = sqrt(bb);
                 double v;
                 if (bn > 0.0) {
@@ -750,7 +753,7 @@ __device__ __forceinline__ void path_ws_body(const PathDesc &P, int first, int p
             // groups outside W (kref = -inf in W): the next lambda's bound
             if (has_next)
                 for (int g = t; g < P.ngroups; g += NT) {
-                    const double thr = cgw[g] * lam_next;
+                    const double thr = cgl[g] * lam_next;
                     const double sl = thr - kref[g];
                     nneed += (sl > 1e-12 * thr) ? 0 : 1;
                     smin = fmin(smin, fmin(sl * r1[g], DBL_MAX));
