@@ -102,6 +102,9 @@ __device__ __forceinline__ void path_ws_body(const PathDesc &P, int first, int p
     double *kref = usq + C;                   // [PSC] |u_j| (||u_g||) of each key at the reference beta
     double *gls = kref + PSC;                 // [pcap pcap] G (one-wave kernel only)
     int *kid = reinterpret_cast<int *>(gls + (NW == 1 ? pcap * pcap : 0));   // [PSC] coordinate (group) of each key
+    // [2][C] per-slot changes of the updates (more than one wave): the keys'
+    // area, which only a check point uses (PSC >= 2 C whenever NW > 1)
+    double *dls = key;
     int *slot_of = kid + PSC;                 // [pcap] slot of each coordinate, -1 outside W
     int *gof = slot_of + pcap;                // [pcap] group of each coordinate
     int *ws = gof + pcap;                     // [C] coordinate of each slot, -1 when empty
@@ -897,32 +900,29 @@ __device__ __forceinline__ void path_ws_body(const PathDesc &P, int first, int p
                 conv = __ballot(!(dl <= lim)) == 0;
                 drift = __ballot(!(dr < Sthr)) != 0;
             } else {
-                const double DLw = slot_max(dl <= INFINITY ? dl : INFINITY);
-                const double MXw = slot_max(mx);
-                const bool dw = __ballot(!(dr < Sthr)) != 0;
-                if (lane == 0) {
-                    dm[(nxt * NW + wave) * 4 + 0] = DLw;
-                    dm[(nxt * NW + wave) * 4 + 1] = MXw;
-                    dm[(nxt * NW + wave) * 4 + 2] = dw ? 1.0 : 0.0;
-                }
+                // each slot's change goes to LDS beside its new beta, with the
+                // sign bit set when the slot drifted past the bound (a NaN
+                // change counts as infinite, a NaN drift as drifted).  After
+                // the barrier every wave forms max change, max |beta| and
+                // the drift flag over all C slots itself (the same values in
+                // the same lanes, so every wave takes the same decision),
+                // beside the next product's operand reads and products
+                const double dlc = dl <= INFINITY ? dl : INFINITY;
+                dls[nxt * C + os] = (dr < Sthr) ? dlc : -dlc;
                 sync();
-                // the per-wave values are read, and the next product's
-                // operand reads go out with them (neither waits for the other)
-                double dmv[NW][3];
-#pragma unroll
-                for (int w = 0; w < NW; ++w)
-#pragma unroll
-                    for (int e = 0; e < 3; ++e) dmv[w][e] = dm[(nxt * NW + w) * 4 + e];
                 gb = symv(nxt);
-                double DL = dmv[0][0], MX = dmv[0][1], DF = dmv[0][2];
+                double DLv = 0.0, MXv = 0.0;
+                bool drv = false;
 #pragma unroll
-                for (int w = 1; w < NW; ++w) {
-                    DL = fmax(DL, dmv[w][0]);
-                    MX = fmax(MX, dmv[w][1]);
-                    DF = fmax(DF, dmv[w][2]);
+                for (int s2 = lane; s2 < C; s2 += kWave) {
+                    const double v = dls[nxt * C + s2];
+                    DLv = fmax(DLv, fabs(v));
+                    MXv = fmax(MXv, fabs(bsl[nxt * C + s2]));
+                    drv |= signbit(v);
                 }
+                const double DL = wave_max(DLv), MX = wave_max(MXv);
                 conv = DL <= P.tol * MX;
-                drift = DF > 0.0;
+                drift = __ballot(drv) != 0;
             }
             cur = nxt;
             if (!conv && it < P.maxit && drift) {
@@ -1000,6 +1000,10 @@ int launch_paths_ws(const PathDesc *d_desc, const int *d_order, int count, int n
         return fail(OEM_E_INVAL, "working-set path kernel: 1, 2 or 4 waves");
     if (pmax > 2048) return fail(OEM_E_INVAL, "working-set path kernel needs p <= 2048");
     if (nw == 1 && pmax > kWsLdsGMaxP) return fail(OEM_E_INVAL, "one-wave working-set kernel needs p <= 128");
+    // the per-slot changes of the updates share the keys' area
+    if (nw > 1 && ws_pow2(pmax) < 2 * nw * kWsCB)
+        return fail(OEM_E_INVAL, "working-set kernel of " + std::to_string(nw) + " waves needs p > " +
+                                     std::to_string(nw * kWsCB));
     int pcap = pmax;
     // A path is a chain of dependent updates on one CU.  When the launch has
     // no more paths than the GPU has CUs, each workgroup asks for at least
