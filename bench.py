@@ -260,13 +260,14 @@ def cpu_baseline_cv(X, y, K, seed, stats, pens, lam, groups, n_full, target_s=4.
 
 def time_cv_form(oem, torch, X, y, K, form, pens, groups, nlambda, steps, warm, pipelined=True):
     """Whole steps of one form, one problem in flight and (pipelined) two in
-    flight on two streams: the Gram pass of step i + 1 runs on its own handle
-    beside the paths of step i, and its combination, d and paths start once
-    step i has finished (the multi-workgroup d launch needs its workgroups
-    resident).  Then one step split into phases with HIP events on the launch
-    stream: Gram pass, first oem_cv (d of the 11 problems + paths + CV), a
-    second oem_cv on the same statistics (paths + CV: d is kept), and the
-    Gram pass alone back to back."""
+    flight on two streams and two handles: the Gram pass, combination and d
+    of step i + 1 run beside the paths of step i (the paths hold one CU
+    each, 33 in all; a multi-workgroup d launch takes at most half of the
+    CUs, so the two cannot keep each other waiting).  Then one step split
+    into phases with HIP events on the launch stream: Gram pass, first
+    oem_cv (d of the 11 problems + paths + CV), a second oem_cv on the same
+    statistics (paths + CV: d is kept), and the Gram pass alone back to
+    back."""
     import numpy as np
     p = X.shape[1]
     g = oem.Gram(p, K, form, X.dtype, CV_SEED)
@@ -293,27 +294,20 @@ def time_cv_form(oem, torch, X, y, K, form, pens, groups, nlambda, steps, warm, 
         g2 = oem.Gram(p, K, form, X.dtype, CV_SEED)   # the tuned workgroup count is per shape
         handles, streams = [g, g2], [stream, torch.cuda.Stream()]
 
-        def pstep(i, prev):
+        def pstep(i):
             st, h = streams[i % 2], handles[i % 2]
             with torch.cuda.stream(st):
                 oem.oem_gram_reset(h.h)
                 h.add(X, y)
-                if prev is not None:
-                    st.wait_event(prev)
-                r = h.cv(pens, nlambda=nlambda, lambda_min_ratio=1e-3, tol=1e-10, groups=groups, sync=False)
-                done = torch.cuda.Event()
-                done.record(st)
-            return r, done
+                return h.cv(pens, nlambda=nlambda, lambda_min_ratio=1e-3, tol=1e-10, groups=groups, sync=False)
 
-        prev = None
         for i in range(warm):
-            _, prev = pstep(i, prev)
+            pstep(i)
         torch.cuda.synchronize()
         outs = []
         t0 = time.perf_counter()
         for i in range(steps):
-            r, prev = pstep(i, prev)
-            outs.append(r)
+            outs.append(pstep(i))
         torch.cuda.synchronize()
         t = time.perf_counter() - t0
         ref = res["beta"].cpu().numpy()
@@ -645,8 +639,8 @@ def cv_main(args):
                                "of 10 (5 active), group lasso+lasso+MCP, 100 lambdas, tol 1e-10",
                    "n": n, "p": p, "folds": K, "penalties": len(CV_PENALTIES), "nlambda": args.nlambda,
                    "precision": args.precision},
-        "pipeline": ("two CV problems in flight on two streams: the Gram pass of step i + 1 beside the "
-                     "paths of step i; every step is a whole Gram pass + oem_cv" if pipelined else
+        "pipeline": ("two CV problems in flight on two streams: the Gram pass, combination and d of step "
+                     "i + 1 beside the paths of step i; every step is a whole Gram pass + oem_cv" if pipelined else
                      "one CV problem in flight"),
         "sequential": dict(ms_per_step=m["sequential_ms_per_step"], fits_per_s=m["sequential_fits_per_s"]),
         "pipelined_results_identical": m["pipelined_results_identical"],

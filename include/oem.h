@@ -49,17 +49,21 @@
  *     oem_batch_create, oem_batch_status and the free functions wait for
  *     the device.
  *   - Concurrent streams.  For 128 < p <= 2048 the eigenvalue bound d is
- *     computed by one launch whose workgroups exchange data every step, so
- *     all of them must be resident at once; the launcher sizes it from the
- *     occupancy of an otherwise idle device.  When the caller runs other
- *     work on the device at the same time (fits of two handles on two
- *     streams), that work can keep some of those workgroups waiting: their
- *     partners' bounded waits then end and oem_fit_path / oem_cv return
- *     OEM_E_HIP ("timed out waiting for its workgroups"), never a hang or a
- *     wrong d.  Such callers set the environment variable OEM_LANCZOS_MB=0
- *     before the first call (one workgroup per problem, no cross-workgroup
- *     wait); the request loop's workers (oem_server_*) always use one
- *     workgroup per problem.
+ *     computed by launches whose workgroups exchange data every step, so all
+ *     workgroups of a launch must be resident at once; each launch of
+ *     oem_fit_path / oem_cv takes at most half of the CUs (by the occupancy
+ *     of an idle device; a batch's launches take all of them, so a batch
+ *     run has the GPU to itself while it derives d).  Other work
+ *     that runs at the same time and finishes by itself (a Gram pass or the
+ *     paths of another handle on another stream) can delay such a launch
+ *     but not stop it, and two such launches fit side by side.  More than
+ *     two at once (three or more handles deriving d on concurrent streams)
+ *     can keep each other's workgroups waiting: the bounded waits then end
+ *     and oem_fit_path / oem_cv return OEM_E_HIP ("timed out waiting for its
+ *     workgroups"), never a hang or a wrong d.  Such callers set the
+ *     environment variable OEM_LANCZOS_MB=0 before the first call (one
+ *     workgroup per problem, no cross-workgroup wait); the request loop's
+ *     workers (oem_server_*) always use one workgroup per problem.
  *   - Matrices are row-major.  Sizes are element counts.
  */
 #ifndef OEM_H

@@ -1430,7 +1430,7 @@ static bool lanczos_mb_enabled()
 // off the GPU), p outside (kMbMinP, 2048], or the grid cannot be resident at
 // once.  Every job's V must have lanczos_mb_scratch_doubles(p) more doubles
 // after its (mmax + 1) p basis.
-static int launch_lanczos_mb(const LzJob *d_jobs, int count, int pmax, hipStream_t s)
+static int launch_lanczos_mb(const LzJob *d_jobs, int count, int pmax, hipStream_t s, int share)
 {
     if (!lanczos_mb_enabled() || lanczos_single_workgroup || pmax <= kMbMinP || pmax > 2048) return 1;
     const int B = lanczos_mb_blocks(pmax);
@@ -1445,8 +1445,12 @@ static int launch_lanczos_mb(const LzJob *d_jobs, int count, int pmax, hipStream
     OEM_HIP_CHECK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
     OEM_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kMbThreads, lds));
     // every workgroup of a launch must be resident at once: the problems go
-    // in chunks of as many as the GPU holds, one launch after another
-    const long fit = per_cu < 1 ? 0 : (long)per_cu * ncu / B;
+    // in chunks, one launch after another, of as many as 1 / share of the
+    // CUs hold.  share = 2 for the calls of one handle, so that the launch
+    // and work of another handle on another stream (its paths, or its own
+    // d launch) fit side by side; share = 1 for a batch, whose launches
+    // have the GPU to themselves
+    const long fit = per_cu < 1 ? 0 : (long)per_cu * (ncu / share) / B;
     if (fit < 1) return 1;
     for (int c0 = 0; c0 < count; c0 += (int)fit) {
         const int cn = (int)std::min<long>(fit, count - c0);
@@ -1477,7 +1481,7 @@ int launch_lanczos(oem_gram_s *h, hipStream_t s)
             if (rc) return rc;
             OEM_HIP_CHECK(hipMemcpyAsync(h->lzjobs.ptr, jobs.data(), nq * sizeof(LzJob), hipMemcpyHostToDevice, s));
             OEM_HIP_CHECK(hipStreamSynchronize(s));
-            rc = launch_lanczos_mb(h->lzjobs.as<LzJob>(), nq, p, s);
+            rc = launch_lanczos_mb(h->lzjobs.as<LzJob>(), nq, p, s, 2);
             if (rc <= 0) return rc;   // launched, or an error
         }
     }
@@ -1507,7 +1511,7 @@ int launch_lanczos_jobs(const LzJob *d_jobs, const std::vector<LzLaunch> &launch
         // the largest class: one problem over many workgroups when every
         // problem of the launch is above the threshold
         if (L.cls >= 2 && L.cls <= 4) {
-            rc = launch_lanczos_mb(d_jobs + L.first, L.count, L.pmax, s);
+            rc = launch_lanczos_mb(d_jobs + L.first, L.count, L.pmax, s, 1);
             if (rc < 0) return rc;
         }
         if (rc == 1)
