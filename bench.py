@@ -952,7 +952,8 @@ def serve_main(args):
         "dtype": "split-bf16 Gram (f32 acc, f64 reduce) + f64 paths", "data": "synthetic",
         "config": {"workload": f"serving: {args.requests} requests, Poisson {args.rate}/s, p in [10,1000], "
                                "n in [1e4,1e6], AR(1) rho~U(0,0.8) (8 levels), lasso/MCP/SCAD/group lasso, "
-                               "20% 5-fold CV, 100 lambdas", "slots": args.slots},
+                               "20% 5-fold CV, 100 lambdas", "slots": args.slots,
+                                   "hw_queues": os.environ.get("GPU_MAX_HW_QUEUES")},
     }
     print(json.dumps(out))
 
@@ -965,6 +966,9 @@ def main():
                           "n_gpus": args.gpus}))
         sys.exit(2)
     if args.serve:
+        # one hardware queue per worker stream (HIP's default is 4), set
+        # before the runtime starts
+        os.environ["GPU_MAX_HW_QUEUES"] = str(min(32, max(4, args.slots)))
         return serve_main(args)
     if args.batch:
         return batch_main(args)
