@@ -39,11 +39,27 @@ int DevBuf::ensure(size_t need)
     return OEM_OK;
 }
 
+thread_local DeferredFrees *deferred_frees = nullptr;
+
 void DevBuf::release()
 {
-    if (ptr) (void)hipFree(ptr);
+    if (ptr) {
+        if (deferred_frees) {
+            deferred_frees->ptrs.push_back(ptr);
+            deferred_frees->bytes += bytes;
+        } else {
+            (void)hipFree(ptr);
+        }
+    }
     ptr = nullptr;
     bytes = 0;
+}
+
+void flush_deferred_frees(DeferredFrees &d)
+{
+    for (void *q : d.ptrs) (void)hipFree(q);
+    d.ptrs.clear();
+    d.bytes = 0;
 }
 
 static inline hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }

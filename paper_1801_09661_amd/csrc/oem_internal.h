@@ -143,6 +143,18 @@ struct DevBuf {
     template <typename T> T *as() const { return static_cast<T *>(ptr); }
 };
 
+// Device frees held back on one thread.  hipFree waits for the whole device,
+// so a thread whose stream runs beside other streams (a worker of the request
+// loop) would wait for their kernels each time it grows a buffer.  While a
+// thread's deferred_frees is set, DevBuf::release hands its memory to the list
+// instead; flush_deferred_frees frees it all (one wait for the device).
+struct DeferredFrees {
+    std::vector<void *> ptrs;
+    size_t bytes = 0;
+};
+extern thread_local DeferredFrees *deferred_frees;
+void flush_deferred_frees(DeferredFrees &d);
+
 struct HostStage;   // staging of the out-of-core Gram pass (stream_host.hip)
 
 // Small host tables a call uploads (groups, lambda values and penalties, path

@@ -28,6 +28,7 @@ struct oem_server_s {
     int32_t prec = OEM_FP64;
     oem_path_opts opts{};
     int64_t budget = 0;
+    int nslots = 1;
     int64_t in_use = 0;
     int running = 0;
     bool stop = false;
@@ -144,6 +145,12 @@ void worker_main(oem_server_s *S, int slot)
 {
     (void)hipSetDevice(S->device);
     oem::lanczos_single_workgroup = true;   // several workers run on the GPU at once
+    // buffers that a request outgrows are freed only between requests, once
+    // they add up to a quarter of this worker's share of the byte budget:
+    // each hipFree waits for every worker's kernels
+    oem::DeferredFrees held;
+    oem::deferred_frees = &held;
+    const size_t held_cap = (size_t)(S->budget / (4 * (int64_t)S->nslots));
     Worker W;
     W.h = new oem_gram_s();
     W.h->device = S->device;
@@ -163,6 +170,7 @@ void worker_main(oem_server_s *S, int slot)
             S->in_use += job.bytes;
             ++S->running;
         }
+        if (held.bytes > held_cap) oem::flush_deferred_frees(held);
         const double t_admit = now_s();
         const int status = ok ? run_request(S, W, job.r) : OEM_E_HIP;
         const double t_done = now_s();
@@ -176,6 +184,8 @@ void worker_main(oem_server_s *S, int slot)
         S->cv_done.notify_all();
     }
     if (W.st) (void)hipStreamSynchronize(W.st);
+    oem::deferred_frees = nullptr;
+    oem::flush_deferred_frees(held);
     for (DevBuf *b : {&W.xbuf, &W.ybuf, &W.outb}) b->release();
     oem_gram_free(W.h);
     if (W.st) (void)hipStreamDestroy(W.st);
@@ -211,6 +221,7 @@ int oem_server_create(int32_t nslots, int64_t device_bytes, int32_t precision,
     S->prec = precision;
     S->opts = *opts;
     S->budget = device_bytes;
+    S->nslots = nslots;
     for (int i = 0; i < nslots; ++i) S->workers.emplace_back(worker_main, S, i);
     *out = S;
     return OEM_OK;
