@@ -106,6 +106,13 @@ def test_server_admission_by_bytes():
         keep = _submit_all(srv, reqs)
         done = srv.drain()
     assert len(done) == len(reqs) and all(r["status"] == oem.OEM_OK for r in done)
+    # a small budget also makes the workers free the buffers their requests
+    # outgrew between requests (held-back frees past their cap): the results
+    # are those of the first server
+    ref = {r["id"]: r for r in first}
+    for r in done:
+        for key in ("beta", "lambda_", "cvm", "i_min"):
+            assert np.array_equal(r[key], ref[r["id"]][key]), f"request {r['id']} {key}"
     # at every admission, the bytes in flight stayed within the budget
     for r in done:
         t = r["t_admit"]
