@@ -459,7 +459,15 @@ void oem_batch_free(oem_batch b);
  * host memory), Gram pass (with fold statistics for CV), and the full-data
  * path of oem_fit_path or the cross validation of oem_cv, outputs copied to
  * the caller's host arrays.  Requests in flight overlap on the device; each
- * result is the one the request gives alone (same kernels, same inputs). */
+ * result is the one the request gives alone (same kernels, same inputs).
+ * Device memory: a worker keeps its buffers between requests.  Its staging
+ * of X, y and the outputs is released after a request when it passes the
+ * worker's share of the budget (device_bytes / nslots); its Gram statistics
+ * and path workspace, which grow with p^2 and the folds but not with n, keep
+ * the size of the largest request it has seen.  hipFree waits for the whole
+ * device, so the buffers a request outgrows are freed between requests, once
+ * they pass a quarter of that share, and during a request only when an
+ * allocation fails without them. */
 typedef struct {
     int64_t id;                /* caller's tag, returned in the completion */
     int32_t p;                 /* columns, 1..4096 */

@@ -29,7 +29,14 @@ int DevBuf::ensure(size_t need)
     if (need <= bytes && ptr) return OEM_OK;
     release();
     if (need == 0) need = 8;
-    if (hipMalloc(&ptr, need) != hipSuccess) {
+    bool ok = hipMalloc(&ptr, need) == hipSuccess;
+    if (!ok && deferred_frees && !deferred_frees->ptrs.empty()) {
+        // the held-back frees may be what is missing
+        (void)hipGetLastError();
+        flush_deferred_frees(*deferred_frees);
+        ok = hipMalloc(&ptr, need) == hipSuccess;
+    }
+    if (!ok) {
         ptr = nullptr;
         bytes = 0;
         (void)hipGetLastError();

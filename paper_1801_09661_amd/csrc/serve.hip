@@ -150,7 +150,8 @@ void worker_main(oem_server_s *S, int slot)
     // each hipFree waits for every worker's kernels
     oem::DeferredFrees held;
     oem::deferred_frees = &held;
-    const size_t held_cap = (size_t)(S->budget / (4 * (int64_t)S->nslots));
+    const size_t share = (size_t)(S->budget / S->nslots);
+    const size_t held_cap = share / 4;
     Worker W;
     W.h = new oem_gram_s();
     W.h->device = S->device;
@@ -174,6 +175,10 @@ void worker_main(oem_server_s *S, int slot)
         const double t_admit = now_s();
         const int status = ok ? run_request(S, W, job.r) : OEM_E_HIP;
         const double t_done = now_s();
+        // an idle worker's staging of X, y and the outputs stays within its
+        // share of the budget
+        if (W.xbuf.bytes + W.ybuf.bytes + W.outb.bytes > share)
+            for (DevBuf *b : {&W.xbuf, &W.ybuf, &W.outb}) b->release();
         {
             std::lock_guard<std::mutex> lk(S->mu);
             S->in_use -= job.bytes;
