@@ -152,6 +152,33 @@ __device__ inline double split_sum(const T *__restrict__ base, size_t stride, in
     const int h = threadIdx.x / kWave;
     double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
     int s = h;
+    // eight or four steps of the last loop at once, their 32 or 16 loads
+    // issued together (one load round trip instead of eight or four; each
+    // accumulator adds the same values in the same order)
+    for (; s + 124 < S; s += 128) {
+        double v[32];
+#pragma unroll
+        for (int j = 0; j < 32; ++j) v[j] = (double)base[(size_t)(s + 4 * j) * stride];
+#pragma unroll
+        for (int j = 0; j < 32; j += 4) {
+            a0 += v[j];
+            a1 += v[j + 1];
+            a2 += v[j + 2];
+            a3 += v[j + 3];
+        }
+    }
+    for (; s + 60 < S; s += 64) {
+        double v[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) v[j] = (double)base[(size_t)(s + 4 * j) * stride];
+#pragma unroll
+        for (int j = 0; j < 16; j += 4) {
+            a0 += v[j];
+            a1 += v[j + 1];
+            a2 += v[j + 2];
+            a3 += v[j + 3];
+        }
+    }
     for (; s + 12 < S; s += 16) {
         a0 += (double)base[(size_t)s * stride];
         a1 += (double)base[(size_t)(s + 4) * stride];
