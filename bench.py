@@ -780,7 +780,27 @@ def batch_main(args):
         x_bytes += n * p * X.element_size() + 8 * n
     rest_ms = max(main_run["ms_per_step"] - gram_ms, 1e-9)
     psq = sum(X.shape[1] ** 2 for X, _ in dev) / len(dev)
-    g_roof = gram_roofline(x_bytes, gram_ms, None, "Gram passes of the 64 problems (one after another)")
+    # Most of the passes' time is matrix-core work: a problem's pass is bound
+    # by the matrix cores when its products outweigh its bytes at the peak
+    # rates (p above about 420 for split-BF16), and those problems carry most
+    # of the flops.  The line reports the passes against the matrix-core peak,
+    # with the HBM figure and the per-problem roofline time beside it.
+    g_hbm = gram_roofline(x_bytes, gram_ms, None, "Gram passes of the 64 problems (one after another)")
+    nprod = {"split_bf16": 3, "bf16": 1, "fp64": 1}[args.precision]
+    mpeak = FP64_PEAK_TFLOPS if args.precision == "fp64" else MFMA_BF16_PEAK_TFLOPS
+    pflops = [nprod * float(X.shape[0]) * X.shape[1] * (X.shape[1] + 1) for X, _ in dev]
+    pbytes = [float(X.shape[0]) * X.shape[1] * X.element_size() + 8.0 * X.shape[0] for X, _ in dev]
+    t_roof = [max(fb / (HBM_PEAK_GBS * 1e9), ff / (mpeak * 1e12)) for ff, fb in zip(pflops, pbytes)]
+    g_tf = sum(pflops) / (gram_ms * 1e-3) / 1e12
+    g_roof = dict(bound="mfma", kernel="Gram passes of the 64 problems (one after another)", achieved=g_tf,
+                  peak=mpeak, unit="TFLOP/s", frac=g_tf / mpeak, traffic=None,
+                  algorithmic=f"{nprod} x n p (p + 1) flops per problem (the upper triangle with the diagonal, "
+                              f"2 per product; {nprod} products), {sum(pflops):.4e} in all",
+                  mfma_bound_problems=sum(1 for ff, fb in zip(pflops, pbytes)
+                                          if ff / (mpeak * 1e12) > fb / (HBM_PEAK_GBS * 1e9)),
+                  roofline_ms=1e3 * sum(t_roof), frac_of_roofline_time=1e3 * sum(t_roof) / gram_ms,
+                  hbm=dict(achieved=g_hbm["achieved"], peak=HBM_PEAK_GBS, unit="GB/s", frac=g_hbm["frac"],
+                           algorithmic=g_hbm["algorithmic"]))
     p_roof = dict(bound="alu", kernel="d and path kernels of the 64 problems (the rest of the step)",
                   achieved=2.0 * psq * main_run["updates"] / (rest_ms * 1e-3) / 1e12, peak=FP64_PEAK_TFLOPS,
                   unit="TFLOP/s", traffic=None,
