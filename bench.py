@@ -360,6 +360,16 @@ def gram_roofline(x_bytes, ms, traffic, kernel):
                 algorithmic=f"{x_bytes} B per pass: X read once and y")
 
 
+def gram_mfma_side(n, p, ms, precision):
+    """The same Gram pass as matrix-core work: n p (p + 1) flops per product
+    (the upper triangle with the diagonal), three products for split-BF16."""
+    nprod = {"split_bf16": 3, "bf16": 1, "fp64": 1}[precision]
+    peak = FP64_PEAK_TFLOPS if precision == "fp64" else MFMA_BF16_PEAK_TFLOPS
+    tf = nprod * float(n) * p * (p + 1) / (ms * 1e-3) / 1e12
+    return dict(achieved=tf, peak=peak, unit="TFLOP/s", frac=tf / peak,
+                algorithmic=f"{nprod} x n p (p + 1) flops per pass")
+
+
 def path_roofline(p, updates, ms, kernel):
     tf = 2.0 * p * p * updates / (ms * 1e-3) / 1e12
     return dict(bound="alu", kernel=kernel, achieved=tf, peak=FP64_PEAK_TFLOPS, unit="TFLOP/s",
@@ -451,8 +461,9 @@ def tall_record(oem, torch, args, with_errors=True):
                         "tol 1e-10", n=n, p=p,
                fits_per_s=m["fits_per_s"], ms_per_step=m["ms_per_step"], gram_ms_in_step=m["gram_ms"],
                fit_ms_in_step=m["fit_ms"], oem_updates=m["updates"],
-               gram_roofline=gram_roofline(x_bytes, m["gram_only_ms"], traffic,
-                                           "Gram pass (split-BF16 kernel + fixed-order reduction)"),
+               gram_roofline=dict(gram_roofline(x_bytes, m["gram_only_ms"], traffic,
+                                                "Gram pass (split-BF16 kernel + fixed-order reduction)"),
+                                  mfma=gram_mfma_side(n, p, m["gram_only_ms"], args.precision)),
                path_roofline=path_roofline(p, m["updates"], m["fit_ms"],
                                            "path kernels (+ combine, Lanczos d, lambda grid)"))
     if "fp64" in runs and args.precision != "fp64":
@@ -616,8 +627,9 @@ def cv_main(args):
     m = runs[args.precision]
     x_bytes = n * p * X.element_size() + n * 8
     traffic = stored_traffic("cv_grouped").get("gram") if args.precision == "split_bf16" else None
-    roofs = dict(gram=gram_roofline(x_bytes, m["gram_only_ms"], traffic,
-                                    "Gram pass with fold sums (split-BF16 kernels + fixed-order reduction)"),
+    roofs = dict(gram=dict(gram_roofline(x_bytes, m["gram_only_ms"], traffic,
+                                         "Gram pass with fold sums (split-BF16 kernels + fixed-order reduction)"),
+                           mfma=gram_mfma_side(n, p, m["gram_only_ms"], args.precision)),
                  lanczos=lanczos_roofline(p, m["lanczos_steps"], m["derive_ms"]),
                  paths=path_roofline(p, m["updates"], m["paths_ms"], "path kernels + CV error"))
     phase_ms = dict(gram=m["gram_ms"], lanczos=m["derive_ms"], paths=m["paths_ms"])
