@@ -35,6 +35,11 @@ METRIC = "Gram GB/s of X; λ-path fits/s mixed vs FP64; serve p50/p99 at 1e-6 er
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 MFMA_BF16_PEAK_TFLOPS = 2500.0
+# CV steps in flight in the default line (--in-flight): each step's oem_cv
+# waits for its d, so the host enqueues a step's Gram pass only once the
+# previous step's d is in; a fourth step in flight measured no faster than
+# three
+CV_IN_FLIGHT = 3
 DTYPE = {"fp64": "f64", "split_bf16": "split-bf16 Gram (f32 acc, f64 reduce) + f64 paths",
          "bf16": "bf16 Gram (f32 acc, f64 reduce) + f64 paths"}
 
@@ -49,15 +54,17 @@ CV_SEED = 180109661
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--in-flight", type=int, default=CV_IN_FLIGHT,
+                    help="CV line: problems in flight on as many streams and handles")
     ap.add_argument("--n", type=int, default=0, help="rows (default: the workload's)")
     ap.add_argument("--p", type=int, default=0, help="columns (default: the workload's)")
     ap.add_argument("--nlambda", type=int, default=100)
     ap.add_argument("--precision", default="split_bf16", choices=["fp64", "split_bf16", "bf16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sequential", action="store_true",
-                    help="CV line: one problem in flight (default: two, on two streams)")
+                    help="CV line: one problem in flight (default: three, on three streams)")
     ap.add_argument("--no-extras", action="store_true", help="skip the sub-records and the oracle errors")
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="run only this many steps of the main form (for profilers); no extras")
@@ -258,12 +265,14 @@ def cpu_baseline_cv(X, y, K, seed, stats, pens, lam, groups, n_full, target_s=4.
 
 # ---------------------------------------------------------------- timing
 
-def time_cv_form(oem, torch, X, y, K, form, pens, groups, nlambda, steps, warm, pipelined=True):
-    """Whole steps of one form, one problem in flight and (pipelined) two in
-    flight on two streams and two handles: the Gram pass, combination and d
-    of step i + 1 run beside the paths of step i (the paths hold one CU
-    each, 33 in all; a multi-workgroup d launch takes at most half of the
-    CUs, so the two cannot keep each other waiting).  Then one step split
+def time_cv_form(oem, torch, X, y, K, form, pens, groups, nlambda, steps, warm, pipelined=True,
+                 depth=CV_IN_FLIGHT):
+    """Whole steps of one form, one problem in flight and (pipelined) three
+    in flight on three streams and three handles: the Gram pass, combination
+    and d of step i + 1 run beside the paths of steps i and i - 1 (the paths
+    hold one CU each, 33 a step; oem_cv waits for its d, so one d launch runs
+    at a time, on at most half of the CUs, and the paths beside it finish by
+    themselves).  Then one step split
     into phases with HIP events on the launch stream: Gram pass, first
     oem_cv (d of the 11 problems + paths + CV), a second oem_cv on the same
     statistics (paths + CV: d is kept), and the Gram pass alone back to
@@ -291,17 +300,21 @@ def time_cv_form(oem, torch, X, y, K, form, pens, groups, nlambda, steps, warm, 
     t = t_seq
     identical = None
     if pipelined:
-        g2 = oem.Gram(p, K, form, X.dtype, CV_SEED)   # the tuned workgroup count is per shape
-        handles, streams = [g, g2], [stream, torch.cuda.Stream()]
+        # the tuned workgroup count is per shape, so the extra handles use it too
+        extra = [oem.Gram(p, K, form, X.dtype, CV_SEED) for _ in range(depth - 1)]
+        handles = [g] + extra
+        streams = [stream] + [torch.cuda.Stream() for _ in extra]
 
         def pstep(i):
-            st, h = streams[i % 2], handles[i % 2]
+            st, h = streams[i % depth], handles[i % depth]
             with torch.cuda.stream(st):
                 oem.oem_gram_reset(h.h)
                 h.add(X, y)
                 return h.cv(pens, nlambda=nlambda, lambda_min_ratio=1e-3, tol=1e-10, groups=groups, sync=False)
 
-        for i in range(warm):
+        # every handle runs at least once before the timed steps (its first
+        # call sizes its buffers)
+        for i in range(max(warm, depth)):
             pstep(i)
         torch.cuda.synchronize()
         outs = []
@@ -313,7 +326,8 @@ def time_cv_form(oem, torch, X, y, K, form, pens, groups, nlambda, steps, warm, 
         ref = res["beta"].cpu().numpy()
         identical = all(np.array_equal(r["beta"].cpu().numpy(), ref) for r in outs)
         del outs
-        g2.close()
+        for h in extra:
+            h.close()
     e = [ev() for _ in range(4)]
     oem.oem_gram_reset(g.h)
     e[0].record(stream)
@@ -617,7 +631,8 @@ def cv_main(args):
     warm = 0 if args.profile_steps else args.warmup
     forms = [args.precision] if (args.profile_steps or args.precision == "fp64") else [args.precision, "fp64"]
     pipelined = not (args.sequential or args.profile_steps)
-    runs = {f: time_cv_form(oem, torch, X, y, K, f, CV_PENALTIES, groups, args.nlambda, steps, warm, pipelined)
+    runs = {f: time_cv_form(oem, torch, X, y, K, f, CV_PENALTIES, groups, args.nlambda, steps, warm, pipelined,
+                            args.in_flight)
             for f in forms}
     if args.calibrate_copy:
         Z = torch.empty_like(X)
@@ -651,9 +666,9 @@ def cv_main(args):
                                "of 10 (5 active), group lasso+lasso+MCP, 100 lambdas, tol 1e-10",
                    "n": n, "p": p, "folds": K, "penalties": len(CV_PENALTIES), "nlambda": args.nlambda,
                    "precision": args.precision},
-        "pipeline": ("two CV problems in flight on two streams: the Gram pass, combination and d of step "
-                     "i + 1 beside the paths of step i; every step is a whole Gram pass + oem_cv" if pipelined else
-                     "one CV problem in flight"),
+        "pipeline": (f"{args.in_flight} CV problems in flight on {args.in_flight} streams: the Gram pass, "
+                     "combination and d of step i + 1 beside the paths of the steps before it; every step is a "
+                     "whole Gram pass + oem_cv" if pipelined else "one CV problem in flight"),
         "sequential": dict(ms_per_step=m["sequential_ms_per_step"], fits_per_s=m["sequential_fits_per_s"]),
         "pipelined_results_identical": m["pipelined_results_identical"],
         "phase_ms": phase_ms,
@@ -996,6 +1011,9 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}))
+        sys.exit(2)
+    if args.in_flight < 1:
+        print(json.dumps({"error": "--in-flight must be >= 1"}))
         sys.exit(2)
     if args.serve:
         # one hardware queue per worker stream (HIP's default is 4), set
