@@ -26,8 +26,8 @@ def _oem():
     return oem
 
 
-@pytest.mark.parametrize("in_flight", [2, 3])
-def test_cv_steps_in_flight_match_one_handle(in_flight):
+@pytest.mark.parametrize("in_flight,precision", [(2, "fp64"), (3, "fp64"), (3, "split_bf16")])
+def test_cv_steps_in_flight_match_one_handle(in_flight, precision):
     oem = _oem()
     # p > 128: d from the multi-workgroup Lanczos
     pr = workloads.cv_grouped(n=60_000, p=200, group_size=10, active_groups=4, seed_tag=77)
@@ -36,9 +36,9 @@ def test_cv_steps_in_flight_match_one_handle(in_flight):
     y = torch.from_numpy(pr.y).cuda()
     pens = ["grp_lasso", "lasso", dict(kind="mcp", gamma=3.0)]
     kw = dict(nlambda=30, lambda_min_ratio=1e-2, tol=TOL, groups=pr.groups, sync=False)
-    print(f"case: n={n} p={p} K={K}, {in_flight} handles in flight", flush=True)
+    print(f"case: n={n} p={p} K={K}, {precision}, {in_flight} handles in flight", flush=True)
 
-    ref_h = oem.Gram(p, K, "fp64", X.dtype, SEED)
+    ref_h = oem.Gram(p, K, precision, X.dtype, SEED)
     ref_h.add(X, y)
     ref = ref_h.cv(pens, **kw)
     torch.cuda.synchronize()
@@ -46,7 +46,7 @@ def test_cv_steps_in_flight_match_one_handle(in_flight):
     ref_cvm = ref["cvm"].cpu().numpy()
     ref_h.close()
 
-    handles = [oem.Gram(p, K, "fp64", X.dtype, SEED) for _ in range(in_flight)]
+    handles = [oem.Gram(p, K, precision, X.dtype, SEED) for _ in range(in_flight)]
     streams = [torch.cuda.Stream() for _ in range(in_flight)]
     outs = []
     for i in range(3 * in_flight):
@@ -62,6 +62,8 @@ def test_cv_steps_in_flight_match_one_handle(in_flight):
     for h in handles:
         h.close()
 
+    if precision != "fp64":
+        return   # the mixed forms' error against the oracle is tested with the single fits
     # the one-handle run against the oracle's held-out error (group lasso)
     ref_o = oracle.cv(pr.X, pr.y, K, SEED, ["grp_lasso"], groups=pr.groups, nlambda=30,
                       lambda_min_ratio=1e-2, tol=TOL)
