@@ -268,11 +268,11 @@ def cpu_baseline_cv(X, y, K, seed, stats, pens, lam, groups, n_full, target_s=4.
 def time_cv_form(oem, torch, X, y, K, form, pens, groups, nlambda, steps, warm, pipelined=True,
                  depth=CV_IN_FLIGHT):
     """Whole steps of one form, one problem in flight and (pipelined) three
-    in flight on three streams and three handles: the Gram pass, combination
-    and d of step i + 1 run beside the paths of steps i and i - 1 (the paths
-    hold one CU each, 33 a step; oem_cv waits for its d, so one d launch runs
-    at a time, on at most half of the CUs, and the paths beside it finish by
-    themselves).  Then one step split
+    in flight on three streams and three handles: the Gram pass of step i + 1
+    is enqueued before oem_cv of step i and runs beside its combination and
+    d, and both run beside the paths of the steps before (the paths hold one
+    CU each, 33 a step; oem_cv waits for its d, so one d launch runs at a
+    time, on at most half of the CUs, beside work that finishes by itself).  Then one step split
     into phases with HIP events on the launch stream: Gram pass, first
     oem_cv (d of the 11 problems + paths + CV), a second oem_cv on the same
     statistics (paths + CV: d is kept), and the Gram pass alone back to
@@ -305,22 +305,34 @@ def time_cv_form(oem, torch, X, y, K, form, pens, groups, nlambda, steps, warm, 
         handles = [g] + extra
         streams = [stream] + [torch.cuda.Stream() for _ in extra]
 
-        def pstep(i):
+        def gram_step(i):
             st, h = streams[i % depth], handles[i % depth]
             with torch.cuda.stream(st):
                 oem.oem_gram_reset(h.h)
                 h.add(X, y)
+
+        def cv_step(i):
+            st, h = streams[i % depth], handles[i % depth]
+            with torch.cuda.stream(st):
                 return h.cv(pens, nlambda=nlambda, lambda_min_ratio=1e-3, tol=1e-10, groups=groups, sync=False)
+
+        def run(count):
+            # the Gram pass of step i + 1 is enqueued before oem_cv of step i,
+            # so it runs beside step i's d instead of after it
+            outs = []
+            gram_step(0)
+            for i in range(count):
+                if i + 1 < count:
+                    gram_step(i + 1)
+                outs.append(cv_step(i))
+            return outs
 
         # every handle runs at least once before the timed steps (its first
         # call sizes its buffers)
-        for i in range(max(warm, depth)):
-            pstep(i)
+        run(max(warm, depth))
         torch.cuda.synchronize()
-        outs = []
         t0 = time.perf_counter()
-        for i in range(steps):
-            outs.append(pstep(i))
+        outs = run(steps)
         torch.cuda.synchronize()
         t = time.perf_counter() - t0
         ref = res["beta"].cpu().numpy()
@@ -666,9 +678,10 @@ def cv_main(args):
                                "of 10 (5 active), group lasso+lasso+MCP, 100 lambdas, tol 1e-10",
                    "n": n, "p": p, "folds": K, "penalties": len(CV_PENALTIES), "nlambda": args.nlambda,
                    "precision": args.precision},
-        "pipeline": (f"{args.in_flight} CV problems in flight on {args.in_flight} streams: the Gram pass, "
-                     "combination and d of step i + 1 beside the paths of the steps before it; every step is a "
-                     "whole Gram pass + oem_cv" if pipelined else "one CV problem in flight"),
+        "pipeline": (f"{args.in_flight} CV problems in flight on {args.in_flight} streams: the Gram pass of "
+                     "step i + 1 enqueued before oem_cv of step i (beside its d), both beside the paths of the "
+                     "steps before; every step is a whole Gram pass + oem_cv" if pipelined
+                     else "one CV problem in flight"),
         "sequential": dict(ms_per_step=m["sequential_ms_per_step"], fits_per_s=m["sequential_fits_per_s"]),
         "pipelined_results_identical": m["pipelined_results_identical"],
         "phase_ms": phase_ms,
