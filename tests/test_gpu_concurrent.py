@@ -1,6 +1,7 @@
 """GPU test: several handles, each on its own stream, running whole CV steps
 (Gram pass with fold sums + oem_cv) one after another without waiting for
-each other, as a caller that keeps several problems in flight does.
+each other, as a caller that keeps several problems in flight does (also
+with each next Gram pass enqueued before the current oem_cv).
 
 Each oem_cv waits for its own d, so one multi-workgroup d launch runs at a
 time, beside the paths of the steps before it.  Every step runs the same
@@ -26,8 +27,9 @@ def _oem():
     return oem
 
 
-@pytest.mark.parametrize("in_flight,precision", [(2, "fp64"), (3, "fp64"), (3, "split_bf16")])
-def test_cv_steps_in_flight_match_one_handle(in_flight, precision):
+@pytest.mark.parametrize("in_flight,precision,early", [(2, "fp64", False), (3, "fp64", True),
+                                                       (3, "split_bf16", True)])
+def test_cv_steps_in_flight_match_one_handle(in_flight, precision, early):
     oem = _oem()
     # p > 128: d from the multi-workgroup Lanczos
     pr = workloads.cv_grouped(n=60_000, p=200, group_size=10, active_groups=4, seed_tag=77)
@@ -36,7 +38,7 @@ def test_cv_steps_in_flight_match_one_handle(in_flight, precision):
     y = torch.from_numpy(pr.y).cuda()
     pens = ["grp_lasso", "lasso", dict(kind="mcp", gamma=3.0)]
     kw = dict(nlambda=30, lambda_min_ratio=1e-2, tol=TOL, groups=pr.groups, sync=False)
-    print(f"case: n={n} p={p} K={K}, {precision}, {in_flight} handles in flight", flush=True)
+    print(f"case: n={n} p={p} K={K}, {precision}, {in_flight} handles in flight, early Gram {early}", flush=True)
 
     ref_h = oem.Gram(p, K, precision, X.dtype, SEED)
     ref_h.add(X, y)
@@ -48,13 +50,31 @@ def test_cv_steps_in_flight_match_one_handle(in_flight, precision):
 
     handles = [oem.Gram(p, K, precision, X.dtype, SEED) for _ in range(in_flight)]
     streams = [torch.cuda.Stream() for _ in range(in_flight)]
-    outs = []
-    for i in range(3 * in_flight):
+    def gram_step(i):
         h, st = handles[i % in_flight], streams[i % in_flight]
         with torch.cuda.stream(st):
             oem.oem_gram_reset(h.h, stream=st)
             h.add(X, y, stream=st)
-            outs.append(h.cv(pens, stream=st, **kw))
+
+    def cv_step(i):
+        h, st = handles[i % in_flight], streams[i % in_flight]
+        with torch.cuda.stream(st):
+            return h.cv(pens, stream=st, **kw)
+
+    outs = []
+    steps = 3 * in_flight
+    if early:
+        # the next step's Gram pass enqueued before this step's oem_cv: it
+        # runs beside this step's d
+        gram_step(0)
+        for i in range(steps):
+            if i + 1 < steps:
+                gram_step(i + 1)
+            outs.append(cv_step(i))
+    else:
+        for i in range(steps):
+            gram_step(i)
+            outs.append(cv_step(i))
     torch.cuda.synchronize()
     for i, r in enumerate(outs):
         assert np.array_equal(r["beta"].cpu().numpy(), ref_beta), f"step {i} beta"
